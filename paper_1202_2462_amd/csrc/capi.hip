@@ -1,0 +1,255 @@
+// C ABI entry points: argument checks, context and workspace management, and
+// dispatch to the kernel launchers. No C++ exception leaves this file.
+#include <cstdarg>
+#include <cstdio>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "mgdd_internal.h"
+
+namespace mgdd {
+
+int fail(Ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_check(Ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess) return MGDD_OK;
+    return fail(c, MGDD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dalloc(Ctx *c, size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(c, MGDD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return nullptr;
+    }
+    c->owned.push_back(p);
+    return p;
+}
+
+void dfree(Ctx *c, void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < c->owned.size(); i++)
+        if (c->owned[i] == p) {
+            c->owned[i] = c->owned.back();
+            c->owned.pop_back();
+            break;
+        }
+    (void)hipFree(p);
+}
+
+void *ensure_stage(Ctx *c, size_t bytes) {
+    if (c->stage_bytes >= bytes) return c->stage;
+    if (c->stage) {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(c, c->stage);
+    }
+    c->stage = dalloc(c, bytes);
+    c->stage_bytes = c->stage ? bytes : 0;
+    return c->stage;
+}
+
+void *ensure_scratch(Ctx *c, size_t bytes) {
+    if (c->scratch_bytes >= bytes) return c->scratch;
+    if (c->scratch) {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(c, c->scratch);
+    }
+    c->scratch = dalloc(c, bytes);
+    c->scratch_bytes = c->scratch ? bytes : 0;
+    return c->scratch;
+}
+
+double *ensure_red(Ctx *c, size_t n) {
+    if (c->red_doubles >= n) return c->red;
+    if (c->red) {
+        (void)hipStreamSynchronize(c->stream);
+        dfree(c, c->red);
+        (void)hipHostFree(c->red_host);
+        c->red_host = nullptr;
+    }
+    c->red = (double *)dalloc(c, n * sizeof(double));
+    if (!c->red) return nullptr;
+    if (hipHostMalloc((void **)&c->red_host, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        fail(c, MGDD_ENOMEM, "hipHostMalloc failed");
+        return nullptr;
+    }
+    c->red_doubles = n;
+    return c->red;
+}
+
+static int setup_geometry(Ctx *c, const int *dims, const int *block) {
+    std::vector<uint32_t> coord;
+    std::vector<int> nbr;
+    std::string e = geometry_tables(dims, block, c->g, coord, nbr);
+    if (!e.empty()) return fail(c, MGDD_ESHAPE, e);
+    c->d_blk_coord = (uint32_t *)dalloc(c, coord.size() * sizeof(uint32_t));
+    c->d_blk_nbr = (int *)dalloc(c, nbr.size() * sizeof(int));
+    if (!c->d_blk_coord || !c->d_blk_nbr) return MGDD_ENOMEM;
+    int rc = hip_check(c, hipMemcpy(c->d_blk_coord, coord.data(), coord.size() * sizeof(uint32_t), hipMemcpyHostToDevice), "copy");
+    if (rc) return rc;
+    rc = hip_check(c, hipMemcpy(c->d_blk_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+    if (rc) return rc;
+    c->g.blk_coord = c->d_blk_coord;
+    c->g.blk_nbr = c->d_blk_nbr;
+    return MGDD_OK;
+}
+
+static bool valid_prec(int p) { return p == MGDD_F64 || p == MGDD_F32; }
+
+}  // namespace mgdd
+
+using namespace mgdd;
+
+struct mgdd_ctx {
+    Ctx c;
+};
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                         \
+    }                                                                     \
+    catch (const std::bad_alloc &) {                                      \
+        return fail(ctx ? &ctx->c : nullptr, MGDD_ENOMEM, "host allocation failed"); \
+    }                                                                     \
+    catch (...) {                                                         \
+        return fail(ctx ? &ctx->c : nullptr, MGDD_EINVAL, "internal error"); \
+    }
+
+extern "C" {
+
+int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ctx **out) {
+    if (!dims || !block || !out) return MGDD_EINVAL;
+    *out = nullptr;
+    mgdd_ctx *ctx = nullptr;
+    GUARD_BEGIN
+    ctx = new mgdd_ctx();
+    ctx->c.stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&ctx->c.dev);
+    int rc = setup_geometry(&ctx->c, dims, block);
+    if (rc) {
+        // keep the context so that the caller can read the error, then free it
+        std::string msg = ctx->c.err;
+        for (void *p : ctx->c.owned) (void)hipFree(p);
+        delete ctx;
+        fprintf(stderr, "mgdd_create: %s\n", msg.c_str());
+        return rc;
+    }
+    *out = ctx;
+    return MGDD_OK;
+    GUARD_END
+}
+
+int mgdd_destroy(mgdd_ctx *ctx) {
+    if (!ctx) return MGDD_OK;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    for (void *p : ctx->c.owned) (void)hipFree(p);
+    if (ctx->c.red_host) (void)hipHostFree(ctx->c.red_host);
+    delete ctx;
+    return MGDD_OK;
+}
+
+const char *mgdd_last_error(const mgdd_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level) {
+    if (!ctx || !valid_prec(prec) || nrhs < 0) return 0;
+    if (level == 0) return csize(prec) * fine_elems(&ctx->c, nrhs);
+    if (level == 1 && ctx->c.c.ready) return csize(prec) * (size_t)nrhs * ctx->c.c.Vc * 2 * ctx->c.c.N;
+    return 0;
+}
+
+int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, double m0, double csw) {
+    if (!ctx || !U) return MGDD_EINVAL;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    const size_t V = c->g.V;
+    for (size_t i = 0; i < V * 4 * 18; i++)
+        if (!std::isfinite(U[i])) return fail(c, MGDD_ENAN, "gauge field holds NaN or Inf");
+    if (!std::isfinite(m0) || !std::isfinite(csw)) return fail(c, MGDD_ENAN, "m0 or csw not finite");
+    if (!c->U64) {
+        c->U64 = dalloc(c, V * 36 * 16);
+        c->U32 = dalloc(c, V * 36 * 8);
+        c->A64 = dalloc(c, V * 72 * 8);
+        c->A32 = dalloc(c, V * 72 * 4);
+        c->Ainv64 = dalloc(c, V * 72 * 8);
+        if (!c->U64 || !c->U32 || !c->A64 || !c->A32 || !c->Ainv64) return MGDD_ENOMEM;
+    }
+    c->m0 = m0;
+    c->csw = csw;
+    c->c.ready = false;
+    void *st = ensure_stage(c, V * 36 * 16);
+    if (!st) return MGDD_ENOMEM;
+    int rc = hip_check(c, hipMemcpyAsync(st, U, V * 36 * 16, hipMemcpyHostToDevice, c->stream), "copy gauge");
+    if (rc) return rc;
+    rc = launch_gauge_ingest(c, (const double2 *)st);
+    if (rc) return rc;
+    c->gauge_ready = true;
+    return MGDD_OK;
+    GUARD_END
+}
+
+int mgdd_pack(mgdd_ctx *ctx, int prec, int nrhs, const double *src, int src_on_device, void *dst) {
+    if (!ctx || !src || !dst || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    size_t bytes = (size_t)nrhs * 12 * c->g.V * 16;
+    const double2 *canon = (const double2 *)src;
+    if (!src_on_device) {
+        void *st = ensure_stage(c, bytes);
+        if (!st) return MGDD_ENOMEM;
+        int rc = hip_check(c, hipMemcpyAsync(st, src, bytes, hipMemcpyHostToDevice, c->stream), "copy field");
+        if (rc) return rc;
+        canon = (const double2 *)st;
+    }
+    int rc = launch_pack(c, prec, nrhs, canon, dst);
+    if (rc) return rc;
+    if (!src_on_device) return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    return MGDD_OK;
+    GUARD_END
+}
+
+int mgdd_unpack(mgdd_ctx *ctx, int prec, int nrhs, const void *src, double *dst, int dst_on_device) {
+    if (!ctx || !src || !dst || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    size_t bytes = (size_t)nrhs * 12 * c->g.V * 16;
+    double2 *canon = (double2 *)dst;
+    if (!dst_on_device) {
+        canon = (double2 *)ensure_stage(c, bytes);
+        if (!canon) return MGDD_ENOMEM;
+    }
+    int rc = launch_unpack(c, prec, nrhs, src, canon);
+    if (rc) return rc;
+    if (!dst_on_device) {
+        rc = hip_check(c, hipMemcpyAsync(dst, canon, bytes, hipMemcpyDeviceToHost, c->stream), "copy field");
+        if (rc) return rc;
+        return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    }
+    return MGDD_OK;
+    GUARD_END
+}
+
+int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out) {
+    if (!ctx || !in || !out || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (in == out) return fail(&ctx->c, MGDD_EINVAL, "in and out alias");
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    GUARD_BEGIN
+    return launch_dirac(&ctx->c, prec, nrhs, in, out);
+    GUARD_END
+}
+
+int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, double shift_re, double shift_im,
+             const void *b, void *z) {
+    if (!ctx || !b || !z || !valid_prec(prec) || nrhs <= 0 || nsweeps < 0 || mr_iters < 0) return MGDD_EINVAL;
+    if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    GUARD_BEGIN
+    return launch_sap(&ctx->c, prec, nrhs, nsweeps, mr_iters, shift_re, shift_im, b, z);
+    GUARD_END
+}
+
+}  // extern "C"

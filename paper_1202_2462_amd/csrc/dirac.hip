@@ -1,0 +1,52 @@
+// Wilson-clover operator D = A - 1/2 H (Section 1): one thread per site,
+// site-major loads of the 8 neighbour spinors and links, spin projection to
+// half spinors before the SU(3) products.
+#include "stencil.h"
+
+namespace mgdd {
+
+namespace {
+
+constexpr int TPB = 256;
+
+// One thread per (site, right-hand side). Workgroup w covers TPB sites of one
+// right-hand side; the right-hand sides of one range of sites are consecutive
+// workgroups on one XCD, so the links and the clover term of those sites come
+// from HBM once and from L2 for the other right-hand sides.
+template <typename T>
+__global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restrict__ Up, const C<T> *__restrict__ Ap,
+                                                    const C<T> *__restrict__ in, C<T> *__restrict__ out, int nrhs,
+                                                    int nwg) {
+    const int w = xcd_block(nwg);
+    const int r = w % nrhs;
+    const int d = (w / nrhs) * TPB + threadIdx.x;
+    if (d >= g.V) return;
+    int nbr[8];
+    site_neighbours(g, d, nbr);
+    const size_t V = g.V;
+    LinkViews<T> U(Up, V);
+    CloverViews<T> A(Ap, V);
+    FieldView<T> f(in + (size_t)r * 12 * V, V, 12), o(out + (size_t)r * 12 * V, V, 12);
+    C<T> acc[12], psi[12], res[12];
+    hop_sum<T>(U, f, d, nbr, acc);
+    load_spinor<T>(f, d, psi);
+    clover_mv<T>(A, d, psi, res);
+#pragma unroll
+    for (int k = 0; k < 12; k++) res[k] = csub(res[k], cscale(acc[k], (T)0.5));
+    store_spinor<T>(o, d, res);
+}
+
+}  // namespace
+
+int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
+    int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
+    if (prec == MGDD_F64)
+        dirac_kernel<double><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
+                                                         (const double2 *)in, (double2 *)out, nrhs, nwg);
+    else
+        dirac_kernel<float><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32, (const float2 *)c->A32,
+                                                        (const float2 *)in, (float2 *)out, nrhs, nwg);
+    return hip_check(c, hipGetLastError(), "dirac kernel");
+}
+
+}  // namespace mgdd

@@ -1,0 +1,124 @@
+// Internal declarations of the gfx950 library: device geometry, complex
+// helpers, the context, and the launch entry points of each kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mgdd.h"
+
+namespace mgdd {
+
+// ------------------------------------------------------------------ complex arithmetic
+
+template <typename T> struct cx;
+template <> struct cx<double> { using t = double2; };
+template <> struct cx<float> { using t = float2; };
+template <typename T> using C = typename cx<T>::t;
+
+template <typename T> __host__ __device__ inline C<T> mk(T r, T i) { C<T> z; z.x = r; z.y = i; return z; }
+template <typename V> __host__ __device__ inline V cadd(V a, V b) { V z; z.x = a.x + b.x; z.y = a.y + b.y; return z; }
+template <typename V> __host__ __device__ inline V csub(V a, V b) { V z; z.x = a.x - b.x; z.y = a.y - b.y; return z; }
+template <typename V> __host__ __device__ inline V cmul(V a, V b) {
+    V z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z;
+}
+// conj(a) * b
+template <typename V> __host__ __device__ inline V cmulc(V a, V b) {
+    V z; z.x = a.x * b.x + a.y * b.y; z.y = a.x * b.y - a.y * b.x; return z;
+}
+// acc += a * b
+template <typename V> __host__ __device__ inline void cfma(V &acc, V a, V b) {
+    acc.x += a.x * b.x - a.y * b.y; acc.y += a.x * b.y + a.y * b.x;
+}
+// acc += conj(a) * b
+template <typename V> __host__ __device__ inline void cfmac(V &acc, V a, V b) {
+    acc.x += a.x * b.x + a.y * b.y; acc.y += a.x * b.y - a.y * b.x;
+}
+template <typename V, typename S> __host__ __device__ inline V cscale(V a, S s) { V z; z.x = a.x * s; z.y = a.y * s; return z; }
+// i * a
+template <typename V> __host__ __device__ inline V ci(V a) { V z; z.x = -a.y; z.y = a.x; return z; }
+template <typename V> __host__ __device__ inline V cneg(V a) { V z; z.x = -a.x; z.y = -a.y; return z; }
+
+}  // namespace mgdd
+
+#include "geometry.h"
+
+namespace mgdd {
+
+// Remaps the workgroup index so that consecutive ranges of workgroups (and so
+// of lattice sites) land on the same XCD: the hardware hands workgroups to the
+// 8 XCDs round-robin, each XCD with its own L2.
+__device__ inline int xcd_block(int nwg) {
+    int b = blockIdx.x;
+    int per = nwg >> 3;
+    if (per == 0 || (nwg & 7)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ------------------------------------------------------------------ the context
+
+struct Level1 {  // coarse level of the current P
+    bool ready = false;
+    int agg[4] = {0, 0, 0, 0};
+    int Lc[4] = {0, 0, 0, 0};
+    int Vc = 0, N = 0;
+    void *P64 = nullptr, *P32 = nullptr;    // N fine fields, device layout
+    void *Dc64 = nullptr, *Dc32 = nullptr;  // [Vc][9][2N (col)][2N (row)] complex
+    int *nbr = nullptr;                     // [Vc][9] coarse neighbour (self first)
+    int *agg_sites = nullptr;               // [Vc][Va] device fine site of local site of aggregate
+};
+
+struct Ctx {
+    Geom g{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int dev = 0;
+    // geometry tables
+    uint32_t *d_blk_coord = nullptr;
+    int *d_blk_nbr = nullptr;
+    // operator
+    bool gauge_ready = false;
+    double m0 = 0, csw = 0;
+    void *U64 = nullptr, *U32 = nullptr;    // [4][9][V] complex
+    void *A64 = nullptr, *A32 = nullptr;    // [72][V] real (packed Hermitian 6x6 x 2 chiralities)
+    void *Ainv64 = nullptr;                 // [72][V] inverse of A (even-odd)
+    Level1 c;
+    // workspace
+    std::vector<void *> owned;
+    void *stage = nullptr;                  // canonical staging buffer
+    size_t stage_bytes = 0;
+    double *red = nullptr;                  // reduction partials
+    size_t red_doubles = 0;
+    double *red_host = nullptr;             // pinned
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+int fail(Ctx *c, int code, const std::string &msg);
+int hip_check(Ctx *c, hipError_t e, const char *what);
+void *dalloc(Ctx *c, size_t bytes);
+void dfree(Ctx *c, void *p);
+void *ensure_stage(Ctx *c, size_t bytes);
+void *ensure_scratch(Ctx *c, size_t bytes);
+double *ensure_red(Ctx *c, size_t ndoubles);
+inline size_t csize(int prec) { return prec == MGDD_F64 ? 16 : 8; }
+inline size_t fine_elems(const Ctx *c, int nrhs) { return (size_t)nrhs * 12 * c->g.V; }
+
+// ------------------------------------------------------------------ launchers (one per kernel family)
+
+// layout.hip
+int launch_pack(Ctx *c, int prec, int nrhs, const double2 *canon, void *dst);
+int launch_unpack(Ctx *c, int prec, int nrhs, const void *src, double2 *canon);
+int launch_gauge_ingest(Ctx *c, const double2 *Ucanon);
+int launch_convert(Ctx *c, int from, int to, size_t n, const void *src, void *dst);
+
+// dirac.hip
+int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out);
+
+// sap.hip
+int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, double sim, const void *b, void *z);
+
+}  // namespace mgdd

@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libmgdd.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls, and does no
+arithmetic of its own: PyTorch supplies device memory and the stream. The
+library must have been built (python -m paper_1202_2462_amd.build); importing
+this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgdd.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mgdd.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1202_2462_amd.build`")
+
+# PyTorch ships its own HIP runtime (same soname as the system one). It is
+# loaded first, so that libmgdd.so binds to that copy and the process holds a
+# single HIP runtime, whose device memory and streams both sides share.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ESHAPE, ERANK, ENOTREADY, ENOCONV, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+F64, F32 = 0, 1
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ERANK", -4: "ENOTREADY", -5: "ENOCONV", -6: "EBREAKDOWN",
+          -7: "ENAN", -8: "EHIP", -9: "ENOMEM"}
+
+
+class MgddError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_vp = ctypes.c_void_p
+_i4 = ctypes.c_int * 4
+
+
+def _sig(name, restype, *args):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_sig("mgdd_create", ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _vp, ctypes.POINTER(_vp))
+_sig("mgdd_destroy", ctypes.c_int, _vp)
+_sig("mgdd_last_error", ctypes.c_char_p, _vp)
+_sig("mgdd_field_bytes", ctypes.c_size_t, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int)
+_sig("mgdd_set_gauge", ctypes.c_int, _vp, _vp, ctypes.c_double, ctypes.c_double)
+_sig("mgdd_pack", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp)
+_sig("mgdd_unpack", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
+_sig("mgdd_dirac_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+     ctypes.c_double, _vp, _vp)
+
+
+def declared_symbols() -> list[str]:
+    """Names of the entry points declared in include/mgdd.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mgdd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+def _check(ctx, rc):
+    if rc != OK:
+        msg = _lib.mgdd_last_error(ctx).decode() if ctx else ""
+        raise MgddError(rc, msg)
+    return rc
+
+
+# --------------------------------------------------------------------- entry points
+
+def mgdd_create(dims, block, stream=None):
+    """Returns the context handle. stream: a torch.cuda.Stream, a raw
+    hipStream_t int, or None for torch's current stream."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    out = _vp()
+    rc = _lib.mgdd_create(_i4(*dims), _i4(*block), stream, ctypes.byref(out))
+    if rc != OK:
+        raise MgddError(rc, "mgdd_create failed (dims/block do not fit)")
+    return out.value
+
+
+def mgdd_destroy(ctx):
+    return _lib.mgdd_destroy(ctx)
+
+
+def mgdd_last_error(ctx) -> str:
+    return _lib.mgdd_last_error(ctx).decode()
+
+
+def mgdd_field_bytes(ctx, prec, nrhs, level=0) -> int:
+    return int(_lib.mgdd_field_bytes(ctx, prec, nrhs, level))
+
+
+def mgdd_set_gauge(ctx, U: np.ndarray, m0: float, csw: float):
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    return _check(ctx, _lib.mgdd_set_gauge(ctx, _ptr(U), m0, csw))
+
+
+def mgdd_pack(ctx, prec, nrhs, src, dst):
+    """src: canonical complex128 fields (numpy on the host, or a torch tensor on the device)."""
+    on_dev = 0 if isinstance(src, np.ndarray) else 1
+    if on_dev == 0:
+        src = np.ascontiguousarray(src, dtype=np.complex128)
+    return _check(ctx, _lib.mgdd_pack(ctx, prec, nrhs, _ptr(src), on_dev, _ptr(dst)))
+
+
+def mgdd_unpack(ctx, prec, nrhs, src, dst):
+    on_dev = 0 if isinstance(dst, np.ndarray) else 1
+    return _check(ctx, _lib.mgdd_unpack(ctx, prec, nrhs, _ptr(src), _ptr(dst), on_dev))
+
+
+def mgdd_dirac_apply(ctx, prec, nrhs, x, y):
+    return _check(ctx, _lib.mgdd_dirac_apply(ctx, prec, nrhs, _ptr(x), _ptr(y)))
+
+
+def mgdd_sap(ctx, prec, nrhs, nsweeps, mr_iters, shift, b, z):
+    shift = complex(shift)
+    return _check(ctx, _lib.mgdd_sap(ctx, prec, nrhs, nsweeps, mr_iters, shift.real, shift.imag, _ptr(b), _ptr(z)))
+
+
+# --------------------------------------------------------------------- convenience wrapper
+
+class Lattice:
+    """Owns one context; fields are torch tensors shaped (nrhs, 12, V, 2) of
+    float64 (F64) or float32 (F32) in the device layout."""
+
+    def __init__(self, dims, block, stream=None):
+        import torch
+        self.torch = torch
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.ctx = mgdd_create(self.dims, block, stream)
+
+    def close(self):
+        if self.ctx:
+            mgdd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field(self, prec=F64, nrhs=1):
+        t = self.torch
+        dt = t.float64 if prec == F64 else t.float32
+        return t.zeros((nrhs, 12, self.V, 2), dtype=dt, device="cuda")
+
+    def set_gauge(self, U, m0, csw):
+        mgdd_set_gauge(self.ctx, U, m0, csw)
+
+    def pack(self, canon: np.ndarray, prec=F64):
+        canon = np.asarray(canon, dtype=np.complex128)
+        if canon.ndim == 3:
+            canon = canon[None]
+        f = self.field(prec, canon.shape[0])
+        mgdd_pack(self.ctx, prec, canon.shape[0], canon, f)
+        return f
+
+    def unpack(self, f, prec=None) -> np.ndarray:
+        prec = (F64 if f.dtype == self.torch.float64 else F32) if prec is None else prec
+        nrhs = f.shape[0]
+        out = np.zeros((nrhs, self.V, 4, 3), dtype=np.complex128)
+        mgdd_unpack(self.ctx, prec, nrhs, f, out)
+        return out
+
+    @staticmethod
+    def prec_of(f):
+        import torch
+        return F64 if f.dtype == torch.float64 else F32
+
+    def dirac(self, x, y=None):
+        y = self.torch.empty_like(x) if y is None else y
+        mgdd_dirac_apply(self.ctx, self.prec_of(x), x.shape[0], x, y)
+        return y
+
+    def sap(self, b, z, nsweeps, mr_iters, shift=0.0):
+        mgdd_sap(self.ctx, self.prec_of(b), b.shape[0], nsweeps, mr_iters, shift, b, z)
+        return z

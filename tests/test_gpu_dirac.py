@@ -1,0 +1,94 @@
+"""GPU parity of the layout conversion, the Wilson-clover apply and the SAP
+sweep (through the C ABI) against the oracle, element by element."""
+import numpy as np
+import pytest
+
+import latgen
+from gpu_common import TOL32, TOL64, lattice, problem, rel, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((8, 8, 8, 8), (4, 4, 4, 4)),      # 16 blocks, 2 per direction
+    ((4, 8, 4, 16), (4, 4, 2, 4)),     # one block in x (wrap kept), uneven shape
+    ((8, 4, 4, 8), (2, 4, 4, 2)),      # block of 64 sites, one block in y and z
+]
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+def test_pack_roundtrip(dims, block):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("pack roundtrip", dims, block)
+    op = problem(dims)
+    lat = lattice(op, block)
+    psi = latgen.gaussian_fields(dims, 2, 1)
+    f = lat.pack(psi, F64)
+    assert np.array_equal(lat.unpack(f), psi)
+    f32 = lat.pack(psi, F32)
+    assert np.array_equal(lat.unpack(f32), psi.astype(np.complex64).astype(np.complex128))
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+def test_dirac_apply_parity(dims, block):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("dirac parity", dims, block)
+    op = problem(dims, seed=5)
+    lat = lattice(op, block)
+    psi = latgen.gaussian_fields(dims, 3, 2)
+    want = np.stack([op.apply(p) for p in psi])
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        got = lat.unpack(lat.dirac(lat.pack(psi, prec)))
+        for r in range(3):
+            assert rel(got[r], want[r]) < tol, (prec, r, rel(got[r], want[r]))
+        # element-wise: the largest deviation relative to the field's scale
+        assert np.max(np.abs(got - want)) < 50 * tol * np.max(np.abs(want))
+
+
+def test_dirac_point_source_and_zero():
+    """A point source touches exactly the 9 stencil sites; zero maps to zero."""
+    from paper_1202_2462_amd.mgdd import F64
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    say("dirac point source", dims)
+    op = problem(dims, seed=9)
+    lat = lattice(op, block)
+    src = latgen.point_sources(dims, 11)
+    got = lat.unpack(lat.dirac(lat.pack(src, F64)))
+    want = np.stack([op.apply(p) for p in src])
+    assert rel(got, want) < TOL64
+    nz = np.nonzero(np.abs(got[0]).sum(axis=(1, 2)))[0]
+    assert len(nz) == 9
+    z = lat.unpack(lat.dirac(lat.field(F64, 1)))
+    assert np.all(z == 0)
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+@pytest.mark.parametrize("shift", [0.0, 0.2 - 0.15j])
+def test_sap_parity(dims, block, shift):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("sap parity", dims, block, shift)
+    op = problem(dims, seed=7, m0=0.2)
+    lat = lattice(op, block)
+    b = latgen.gaussian_fields(dims, 2, 3)
+    z0 = latgen.gaussian_fields(dims, 2, 4)
+    want = np.stack([op.sap(block, b[r], z0[r], 2, 4, shift) for r in range(2)])
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        z = lat.pack(z0, prec)
+        lat.sap(lat.pack(b, prec), z, 2, 4, shift)
+        got = lat.unpack(z)
+        for r in range(2):
+            assert rel(got[r], want[r]) < tol, (prec, r, rel(got[r], want[r]))
+
+
+def test_sap_zero_rhs_and_zero_iterations():
+    from paper_1202_2462_amd.mgdd import F64
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    say("sap degenerate", dims)
+    op = problem(dims, seed=2)
+    lat = lattice(op, block)
+    z = lat.field(F64, 1)
+    lat.sap(lat.field(F64, 1), z, 3, 4)          # b = 0, z0 = 0: MR stops at q = 0
+    assert np.all(lat.unpack(z) == 0)
+    z0 = latgen.gaussian_fields(dims, 1, 5)
+    z = lat.pack(z0, F64)
+    lat.sap(lat.pack(z0, F64), z, 1, 0)          # zero MR steps leave z unchanged
+    assert np.array_equal(lat.unpack(z), z0)

@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the SAP + aggregation two-level solver on one MI355X.
+
+One step = one pass of the whole hot path on the 16^3 x 32 workload: gauge
+ingest with the clover term, the bootstrap setup (Schwarz sweeps in FP32,
+P and D_c, harmonic Ritz vectors, second setup part) and the mixed-precision
+FGMRES solve of one Gaussian right-hand side to ||b - D z|| <= 1e-10 ||b||.
+`value` is solves per second (setup included). Beside it the same JSON line
+carries the Wilson-clover apply rates (Dirac applies/s and HBM GB/s), the
+time-to-1e-10 of the plain FP64 two-level solve and of plain FP64 GCR (also
+even-odd), the roofline of the dominant kernel, and the oracle on the host
+cores as a CPU baseline.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --kernel-only sap      (short run for hardware counters)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c1"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_m0(name):
+    path = os.path.join(ROOT, "tests", "golden", "m0.json")
+    with open(path) as f:
+        return float(json.load(f)[name]["m0"])
+
+
+class Bench:
+    def __init__(self, name=WORKLOAD, m0=None):
+        import torch
+
+        import latgen
+        from paper_1202_2462_amd import mgdd
+        self.torch, self.mgdd, self.latgen = torch, mgdd, latgen
+        w = latgen.WORKLOADS[name]
+        self.name, self.w = name, w
+        self.dims, self.block, self.agg, self.N = tuple(w["dims"]), tuple(w["block"]), tuple(w["agg"]), w["ntv"]
+        self.V = int(np.prod(self.dims))
+        self.m0, self.csw = (load_m0(name) if m0 is None else m0), w["csw"]
+        k = int(name[1:])
+        t0 = time.time()
+        U = latgen.workload_gauge(name)
+        log(f"gauge field {self.dims} generated in {time.time() - t0:.1f} s")
+        self.U_host = U
+        self.lat = mgdd.Lattice(self.dims, self.block)
+        F64 = mgdd.F64
+        # inputs resident in HBM before any timed region
+        self.U_dev = torch.tensor(U.view(np.float64), device="cuda")
+        self.rnd = self.lat.pack(latgen.gaussian_fields(self.dims, self.N, 1000 * k + latgen.TAG_TV), F64)
+        self.Vc = self.V // int(np.prod(self.agg))
+        st = latgen.gaussian_vector(self.Vc * 2 * self.N, 1000 * k + latgen.TAG_ARNOLDI)
+        self.start = torch.tensor(np.stack([st.real, st.imag], -1), dtype=torch.float64, device="cuda")
+        self.b_host = latgen.gaussian_fields(self.dims, 1, 1000 * k + latgen.TAG_RHS)
+        self.b = self.lat.pack(self.b_host, F64)
+        torch.cuda.synchronize()
+
+    # one pass of the hot path
+    def step(self, setup_prec=None, solve_prec=None, split=None):
+        mg = self.mgdd
+        w = self.w
+        setup_prec = mg.F32 if setup_prec is None else setup_prec
+        solve_prec = mg.MIXED if solve_prec is None else solve_prec
+        t0 = time.perf_counter()
+        self.lat.set_gauge(self.U_dev, self.m0, self.csw)
+        self.lat.setup(self.agg, self.rnd, self.start, nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], prec=setup_prec)
+        t1 = time.perf_counter()
+        z, stats = self.lat.solve(self.b, precision=solve_prec, restart=w["restart"], tol=w["tol"], maxit=2000,
+                                  coarse_iters=12, nu=1, mr_iters=w["mr"])
+        t2 = time.perf_counter()
+        if split is not None:
+            split.update(setup_s=t1 - t0, solve_s=t2 - t1, iters=stats[0].iters, restarts=stats[0].restarts,
+                         relres=stats[0].relres)
+        return z, stats[0]
+
+    def gcr(self, even_odd):
+        mg = self.mgdd
+        t0 = time.perf_counter()
+        z, stats = self.lat.solve(self.b, solver=mg.SOLVER_GCR_EO if even_odd else mg.SOLVER_GCR, restart=16,
+                                  tol=self.w["tol"], maxit=100000)
+        return dict(seconds=time.perf_counter() - t0, iters=stats[0].iters, relres=stats[0].relres,
+                    converged=bool(stats[0].converged)), z
+
+    def time_calls(self, fn, n, warm=3):
+        torch = self.torch
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()   # the stream the library was created on
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(n):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / n
+
+    def dirac_rates(self):
+        mg = self.mgdd
+        out = {}
+        for prec, name, bps in ((mg.F64, "f64", 1536), (mg.F32, "f32", 768)):
+            x = self.lat.field(prec, 1)
+            x.normal_()
+            y = self.lat.field(prec, 1)
+            t = self.time_calls(lambda: mg.mgdd_dirac_apply(self.lat.ctx, prec, 1, x, y), 50)
+            out[name] = dict(applies_per_s=1.0 / t, us_per_apply=t * 1e6, gbs=bps * self.V / t / 1e9)
+        return out
+
+    def sap_launch_time(self):
+        """Average duration of one colour step of the FP32 Schwarz kernel
+        (mgdd_sap with one sweep launches one kernel per colour)."""
+        mg = self.mgdd
+        b = self.lat.field(mg.F32, 1)
+        b.normal_()
+        z = self.lat.field(mg.F32, 1)
+        t = self.time_calls(lambda: mg.mgdd_sap(self.lat.ctx, mg.F32, 1, 1, self.w["mr"], 0.0, b, z), 50)
+        return t / 2.0
+
+
+def cpu_baseline(bench, gpu_split):
+    """Oracle on the host cores. The full oracle pipeline at this size takes
+    minutes, so it is timed per component on this workload and the components
+    are added up with the counts of the GPU step (test vectors, sweeps,
+    outer iterations)."""
+    import oracle
+    from oracle import solvers
+    w = bench.w
+    dims, block, agg, N = bench.dims, bench.block, bench.agg, bench.N
+    op = solvers.Operator(dims, bench.U_host, bench.m0, bench.csw)
+    psi = bench.latgen.gaussian_fields(dims, 1, 5)[0]
+    zero = np.zeros_like(psi)
+    t = {}
+    t0 = time.perf_counter(); op.apply(psi); t["dirac"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); op.sap(block, zero, psi, 1, w["mr"]); t["sap_sweep"] = time.perf_counter() - t0
+    tv = bench.latgen.gaussian_fields(dims, N, 7)
+    t0 = time.perf_counter(); tl = solvers.TwoLevel(op, agg, tv, block, mr_iters=w["mr"])
+    t["P_and_Dc"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); tl.precond(psi); t["precond"] = time.perf_counter() - t0
+    iters = gpu_split["iters"]
+    restarts = gpu_split["restarts"]
+    setup = (w["nu"] * N + w["iota"] * N) * t["sap_sweep"] + 2 * t["P_and_Dc"] + 2 * N * t["dirac"]
+    solve = iters * (t["precond"] + t["dirac"]) + (restarts + 1) * t["dirac"]
+    total = setup + solve
+    sample = ("oracle FP64 on the same workload, timed per component (one Wilson-clover apply, one Schwarz sweep, "
+              "one P + D_c build, one two-level preconditioner application: %.1f s of CPU work) and composed with "
+              "the GPU step's counts (%d test vectors, nu=%d, iota=%d, %d outer iterations)"
+              % (sum(t.values()), N, w["nu"], w["iota"], iters))
+    return dict(value=1.0 / total, unit="solves/s", cores=oracle.num_threads(), kind="oracle", sample=sample,
+                seconds_per_solve=total, components_s={k: round(v, 4) for k, v in t.items()})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--kernel-only", choices=["sap", "dirac", "copy"], default=None)
+    ap.add_argument("--m0", type=float, default=None, help="override the tuned bare mass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    bench = Bench(m0=args.m0)
+    mg = bench.mgdd
+
+    if args.kernel_only:
+        # short run of one kernel for hardware counters (rocprofv3 --pmc)
+        bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
+        if args.kernel_only == "sap":
+            bench.sap_launch_time()
+        elif args.kernel_only == "dirac":
+            bench.dirac_rates()
+        x = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda").normal_()
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)    # reference copy kernel: 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": args.kernel_only, "copy_bytes_each_way": x.numel() * 4}))
+        return
+
+    log("warmup")
+    for _ in range(args.warmup):
+        bench.step()
+    torch.cuda.synchronize()
+    log("timed steps")
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(args.steps):
+        _, last = bench.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = elapsed / args.steps * 1e3
+    split = {}
+    bench.step(split=split)
+    log("split", split)
+
+    result = {
+        "metric": "Dirac applies/s + HBM GB/s; time-to-1e-10 solve vs plain FP64 GCR (1 GPU)",
+        "value": 1000.0 / ms,
+        "unit": "solves/s (bootstrap setup + mixed-precision FGMRES to 1e-10, 1 RHS)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (smoother, transfers, coarse solve) + f64 (outer FGMRES, true residual)",
+        "data": "synthetic (seeded SU(3) links exp(i eps H) + 2 APE steps, Gaussian RHS)",
+        "config": {"workload": "16^3x32 Wilson-clover c_sw=1.0, min Re eig(D) = %.2f, SAP blocks 4^4 with 4 MR "
+                               "steps and 1 sweep, aggregates 4^4, 20 test vectors, FGMRES(20), tol 1e-10"
+                               % bench.w["target"],
+                   "lattice": list(bench.dims), "m0": bench.m0, "global_batch": 1, "parallelism": "single GPU"},
+        "time_to_solution": {"mg_mixed": split},
+    }
+    if last is not None:
+        result["time_to_solution"]["mg_mixed"]["converged"] = bool(last.converged)
+
+    if not args.no_compare:
+        log("plain FP64 multilevel")
+        s64 = {}
+        bench.step(setup_prec=mg.F64, solve_prec=mg.PLAIN_F64, split=s64)
+        result["time_to_solution"]["mg_fp64"] = s64
+        log("plain FP64 GCR")
+        result["time_to_solution"]["gcr_fp64"], _ = bench.gcr(False)
+        log("even-odd FP64 GCR")
+        result["time_to_solution"]["gcr_eo_fp64"], _ = bench.gcr(True)
+        tts = result["time_to_solution"]
+        mgt = tts["mg_mixed"]["setup_s"] + tts["mg_mixed"]["solve_s"]
+        result["speedup_vs_gcr_fp64"] = {"solve_only": tts["gcr_fp64"]["seconds"] / tts["mg_mixed"]["solve_s"],
+                                         "with_setup": tts["gcr_fp64"]["seconds"] / mgt}
+
+    bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
+    result["dirac"] = bench.dirac_rates()
+    # roofline of the FP32 Schwarz colour kernel (the dominant kernel of the step):
+    # algorithmic bytes per site 864 = z in 96 + b 96 + links 288 + clover 288 + z out 96,
+    # V/2 sites per launch (one colour)
+    t_launch = bench.sap_launch_time()
+    bytes_launch = 864 * bench.V / 2
+    achieved = bytes_launch / t_launch / 1e9
+    result["roofline"] = {"bound": "hbm", "kernel": "sap_colour_kernel<float>", "achieved": achieved,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                          "us_per_launch": t_launch * 1e6, "algorithmic_bytes_per_launch": bytes_launch}
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(bench, split)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -96,11 +96,13 @@ const char *mgdd_last_error(const mgdd_ctx *ctx);
 size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level);
 
 /* Sets the gauge field and mass of D = D(U) + m (Section 1): U is the
- * canonical host array [V][4][3][3] of complex double (read only, copied).
- * Builds on the device the links in FP64 and FP32 and the clover term
- * A(x) = (4+m0) + c_sw (i/4) sum sigma F (both chiral 6x6 blocks, FP64 and
- * FP32) and the inverse of A on even sites (FP64). Synchronous. Drops any P. */
-int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, double m0, double csw);
+ * canonical array [V][4][3][3] of complex double (read only), in host memory
+ * or, if src_on_device, in device memory. Builds on the device the links in
+ * FP64 and FP32 and the clover term A(x) = (4+m0) + c_sw (i/4) sum sigma F
+ * (both chiral 6x6 blocks, FP64 and FP32) and the inverse of A (FP64, for the
+ * even-odd comparator). Synchronous. Drops any P. Errors: MGDD_ENAN (NaN or
+ * Inf in U, m0 or csw), MGDD_EINVAL (singular clover block). */
+int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, int src_on_device, double m0, double csw);
 
 /* Canonical complex-double fields (nrhs of them, host or device memory as
  * src_on_device says) -> device layout of precision prec (round to nearest
@@ -122,6 +124,109 @@ int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *ou
  * second setup part use shift = lambda). Asynchronous. */
 int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, double shift_re, double shift_im,
              const void *b, void *z);
+
+/* ------------------------------------------------------------------ coarse level (Section 3) */
+
+/* Builds the aggregation interpolation P from ntv test vectors (Section 3,
+ * "Aggregation Based Interpolation"): the vectors are cut up over the
+ * aggregates, which form a block decomposition of extents agg (each dividing
+ * L) and are split by chirality (spins 0,1 and 2,3) so that
+ * gamma_5 P = P gamma_5^c; each (aggregate, chirality) piece is
+ * orthonormalised by modified Gram-Schmidt in column order (P^H P = 1, the
+ * unique thin QR with positive diagonal of R). Then builds the coarse operator
+ * D_c = P^H D P (a 9-point stencil of 2N x 2N blocks) in FP64, with FP32
+ * copies of P and D_c. test_vectors: ntv FP64 device fields (read only).
+ * Synchronous. Errors: MGDD_ERANK (ntv > 6 * vol(agg) or a piece is rank
+ * deficient), MGDD_ESHAPE, MGDD_EINVAL (ntv not in 1..32). */
+int mgdd_build_P(mgdd_ctx *ctx, const int agg[4], int ntv, const void *test_vectors);
+
+/* Copies the ntv test vectors that define the current P (FP64 device fields)
+ * to dst (device, ntv fine FP64 fields). */
+int mgdd_get_test_vectors(mgdd_ctx *ctx, void *dst);
+
+/* coarse = P^H fine (restriction R = P^H, Section 3); nrhs fields. */
+int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coarse);
+
+/* fine = P coarse (interpolation, Section 3); nrhs fields. */
+int mgdd_prolong(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *fine);
+
+/* out = D_c in, D_c = P^H D P (eq. (3.1)); nrhs coarse fields. */
+int mgdd_coarse_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out);
+
+/* x = approximate D_c^{-1} b by `iters` steps of GMRES from x = 0 without
+ * restart (the coarse solve of Section 4 uses 12). nrhs coarse fields;
+ * synchronous (one host read of the Hessenberg matrix per field). */
+int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x);
+
+/* Two-level preconditioner (Section 3: smoother and coarse-grid correction
+ * alternate): z = P GMRES_iters(D_c, P^H r) followed by nu Schwarz sweeps
+ * (mr_iters MR steps per block) on D z = r. r: FP64 fine fields; z: fine
+ * fields of precision prec (the precision the preconditioner computes in). */
+int mgdd_precondition(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, int coarse_iters, const void *r,
+                      void *z);
+
+/* ------------------------------------------------------------------ setup and solve */
+
+typedef struct {
+    int agg[4];       /* aggregate extents */
+    int ntv;          /* number of test vectors N */
+    int nu;           /* first part: rounds of one Schwarz sweep (b = 0) + orthonormalisation */
+    int iota;         /* second part: shifted Schwarz sweeps on each interpolated Ritz vector */
+    int mr_iters;     /* minimal residual steps per block solve */
+    int arnoldi_m;    /* Arnoldi steps for the harmonic Ritz pairs; 0 = min(dim D_c, 2N + 10) */
+    int n_part2;      /* repetitions of the second part (the paper runs it once) */
+    int prec;         /* precision of the Schwarz sweeps: MGDD_F64 or MGDD_F32 */
+} mgdd_setup_params;
+
+/* Bootstrap setup (Section 3, "Bootstrap Setup"). Part 1: the ntv random
+ * fields (random_vectors: ntv FP64 device fields, read only) get nu rounds of
+ * one Schwarz sweep with b = 0, each followed by a global modified
+ * Gram-Schmidt in index order; then P and D_c. Part 2 (n_part2 times):
+ * harmonic Ritz pairs (lambda_i, phi_i) of D_c (target 0, the ntv of smallest
+ * modulus, from arnoldi_m Arnoldi steps started at arnoldi_start: one FP64
+ * coarse field, device), w_i = P phi_i smoothed by iota sweeps of Schwarz with
+ * block inverses of D - lambda_i, then the 2N vectors {w_i} u {v_j} are
+ * orthonormalised and replaced by the N combinations given by the N smallest
+ * eigenpairs of the Gram matrix (DV)^H DV; then P and D_c again.
+ * Synchronous. */
+int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const void *random_vectors,
+                         const void *arnoldi_start);
+
+enum { MGDD_SOLVER_FGMRES_MG = 0, MGDD_SOLVER_GCR = 1, MGDD_SOLVER_GCR_EO = 2 };
+enum { MGDD_PLAIN_F64 = 0, MGDD_MIXED = 1 };
+
+typedef struct {
+    int solver;        /* MGDD_SOLVER_* */
+    int precision;     /* MGDD_PLAIN_F64, or MGDD_MIXED: the preconditioner (SAP,
+                          restriction, prolongation, coarse solve) in FP32, the
+                          outer orthogonalisation, true residual and solution
+                          update in FP64 */
+    int restart;       /* Krylov restart length m */
+    double tol;        /* stop when ||b - D z|| <= tol ||b|| (true residual, FP64) */
+    int maxit;         /* maximal number of outer iterations */
+    int coarse_iters;  /* GMRES steps on D_c per preconditioner application */
+    int nu;            /* Schwarz sweeps per preconditioner application */
+    int mr_iters;      /* MR steps per block solve */
+} mgdd_solve_params;
+
+typedef struct {
+    int iters;         /* outer iterations */
+    int restarts;      /* true-residual recomputations */
+    int converged;     /* 1 if ||b - D z|| <= tol ||b|| */
+    double relres;     /* final ||b - D z|| / ||b|| in FP64 */
+    double seconds;    /* wall time of this right-hand side */
+} mgdd_solve_stats;
+
+/* Solves D z = b (eq. (1.1)) for nrhs FP64 device fields b; z (FP64 device
+ * fields) holds the initial guess on entry and the solution on exit.
+ * FGMRES_MG: flexible GMRES(restart) right-preconditioned by the two-level
+ * method (Section 4). GCR: plain GCR(restart) on D. GCR_EO: GCR(restart) on
+ * the even-odd Schur complement, convergence judged on the full system.
+ * stats: array of nrhs entries (may be NULL). Synchronous. Errors:
+ * MGDD_ENOCONV (maxit reached; z and stats written), MGDD_ENAN,
+ * MGDD_ENOTREADY (no gauge field; no P for FGMRES_MG). */
+int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const void *b, void *z,
+               mgdd_solve_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -311,7 +311,9 @@ class EvenOdd:
 def harmonic_ritz(apply, v0, m, nkeep):
     """Harmonic Ritz pairs for target 0 from m Arnoldi steps: eigenpairs of
     H_m + |h_{m+1,m}|^2 H_m^{-H} e_m e_m^T; the nkeep of smallest modulus
-    (ties by index). Returns (theta[nkeep], vectors list)."""
+    (ties broken by real part, then imaginary part, so that the choice does
+    not depend on the order an eigensolver returns them in).
+    Returns (theta[nkeep], vectors list)."""
     V, H, k = arnoldi(apply, v0, m)
     Hm = H[:k, :k]
     T = Hm.copy()
@@ -322,7 +324,7 @@ def harmonic_ritz(apply, v0, m, nkeep):
         f = np.linalg.solve(Hm.conj().T, em)
         T = T + abs(hk) ** 2 * np.outer(f, em)
     theta, Y = np.linalg.eig(T)
-    order = sorted(range(k), key=lambda i: (abs(theta[i]), i))[:nkeep]
+    order = sorted(range(k), key=lambda i: (abs(theta[i]), theta[i].real, theta[i].imag))[:nkeep]
     vecs = []
     for i in order:
         y = Y[:, i]

@@ -25,13 +25,13 @@ from oracle.solvers import Operator
 GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden", "m0.json")
 
 
-def leftmost(dims, U, csw, tol=1e-6, k=6):
+def leftmost(dims, U, csw, tol=1e-6, k=6, ncv=40):
     op = Operator(dims, U, 0.0, csw)
     n = int(np.prod(dims)) * 12
     shape = (int(np.prod(dims)), 4, 3)
     L = sla.LinearOperator((n, n), matvec=lambda v: op.apply(v.reshape(shape)).ravel(), dtype=np.complex128)
     v0 = latgen.gaussian_vector(n, 12345)
-    vals, vecs = sla.eigs(L, k=k, which="SR", tol=tol, v0=v0, ncv=max(40, 3 * k), maxiter=5000)
+    vals, vecs = sla.eigs(L, k=k, which="SR", tol=tol, v0=v0, ncv=max(ncv, 3 * k), maxiter=5000)
     i = int(np.argmin(vals.real))
     lam = vals[i]
     v = vecs[:, i]
@@ -43,17 +43,20 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="+")
     ap.add_argument("--write", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--k", type=int, default=6)
+    ap.add_argument("--ncv", type=int, default=40)
     args = ap.parse_args()
     data = json.load(open(GOLDEN)) if os.path.exists(GOLDEN) else {}
     for name in args.configs:
         w = latgen.WORKLOADS[name]
         t0 = time.time()
         U = latgen.workload_gauge(name)
-        lam, res = leftmost(w["dims"], U, w["csw"])
+        lam, res = leftmost(w["dims"], U, w["csw"], tol=args.tol, k=args.k, ncv=args.ncv)
         m0 = w["target"] - lam.real
         data[name] = dict(m0=m0, leftmost_D0=[lam.real, lam.imag], residual=res, target=w["target"],
                           dims=list(w["dims"]), csw=w["csw"],
-                          recipe="m0 = target - min Re spec D(0); ARPACK 'SR' on the oracle operator",
+                          recipe=f"m0 = target - min Re spec D(0); ARPACK 'SR' on the oracle operator, tol {args.tol}, k {args.k}, ncv {args.ncv}",
                           seconds=round(time.time() - t0, 1))
         print(name, data[name], flush=True)
     if args.write:

@@ -1,0 +1,201 @@
+// Level-1 kernels on flat complex arrays for the Krylov methods: multi-dot
+// products (several vectors against one, in one pass over memory), linear
+// combinations y = beta y + alpha sum_i c_i x_i with the coefficients read
+// from device memory (so that Gram-Schmidt needs no host round trip), and
+// scaling. Reductions are deterministic: a fixed grid for a given length, a
+// fixed butterfly inside each wave, per-workgroup partials summed in index
+// order by a second kernel. Sums are accumulated in double.
+#include "blas.h"
+
+namespace mgdd {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline int red_grid(size_t n) {
+    size_t g = (n + TPB * 4 - 1) / (TPB * 4);
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// part[i * nwg + blockIdx.x] = sum over this workgroup's elements of conj(x_i) w
+template <typename TX, typename TW, int NV>
+__global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PtrList xs, int nvec, const C<TW> *__restrict__ w,
+                                                       double2 *__restrict__ part) {
+    __shared__ double red[TPB / 64][2 * NV];
+    double2 acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) acc[i] = make_double2(0, 0);
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
+        C<TW> wv = w[e];
+        double2 wd = make_double2((double)wv.x, (double)wv.y);
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            if (i < nvec) {
+                C<TX> xv = ((const C<TX> *)xs.p[i])[e];
+                cfmac(acc[i], make_double2((double)xv.x, (double)xv.y), wd);
+            }
+        }
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        if (i < nvec) {
+            double a = wave_sum(acc[i].x), b = wave_sum(acc[i].y);
+            if (lane == 0) { red[wv][2 * i] = a; red[wv][2 * i + 1] = b; }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nvec) {
+        int i = threadIdx.x;
+        double a = 0, b = 0;
+        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * i]; b += red[k][2 * i + 1]; }
+        part[(size_t)i * gridDim.x + blockIdx.x] = make_double2(a, b);
+    }
+}
+
+// out[i] = sum_k part[i * nwg + k] (fixed order), optionally plus add[i]
+__global__ void finish_kernel(int nvec, int nwg, const double2 *__restrict__ part, double2 *__restrict__ out) {
+    int i = blockIdx.x;
+    __shared__ double sa[64], sb[64];
+    double a = 0, b = 0;
+    for (int k = threadIdx.x; k < nwg; k += 64) { a += part[(size_t)i * nwg + k].x; b += part[(size_t)i * nwg + k].y; }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0, B = 0;
+        for (int k = 0; k < 64; k++) { A += sa[k]; B += sb[k]; }
+        out[i] = make_double2(A, B);
+    }
+}
+
+// y = beta y + alpha sum_i coef[i] x_i
+template <typename TX, typename TY, int NV>
+__global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int nvec, const double2 *__restrict__ coef,
+                                                      double alpha, double beta, C<TY> *__restrict__ y) {
+    double2 c[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) c[i] = i < nvec ? cscale(coef[i], alpha) : make_double2(0, 0);
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
+        double2 acc = make_double2(0, 0);
+        if (beta != 0.0) {
+            C<TY> yv = y[e];
+            acc = make_double2(beta * (double)yv.x, beta * (double)yv.y);
+        }
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            if (i < nvec) {
+                C<TX> xv = ((const C<TX> *)xs.p[i])[e];
+                cfma(acc, c[i], make_double2((double)xv.x, (double)xv.y));
+            }
+        }
+        y[e] = mk<TY>((TY)acc.x, (TY)acc.y);
+    }
+}
+
+// y = s * x, s = alpha * coef[0] (device) or alpha when coef == nullptr; x and y may alias
+template <typename TX, typename TY>
+__global__ __launch_bounds__(TPB) void scale_kernel(size_t n, const C<TX> *x, const double2 *__restrict__ coef,
+                                                    double2 alpha, C<TY> *y) {
+    double2 s = coef ? cmul(coef[0], alpha) : alpha;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
+        C<TX> xv = x[e];
+        double2 v = cmul(s, make_double2((double)xv.x, (double)xv.y));
+        y[e] = mk<TY>((TY)v.x, (TY)v.y);
+    }
+}
+
+// coef[0] = 1 / sqrt(re(v[0])) (normalisation from a squared norm)
+__global__ void rsqrt_kernel(const double2 *v, double2 *coef) {
+    double n = sqrt(v[0].x);
+    coef[0] = make_double2(n > 0 ? 1.0 / n : 0.0, 0.0);
+}
+
+int lin_grid(size_t n) {
+    size_t g = (n + TPB - 1) / TPB;
+    if (g > 8192) g = 8192;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int nvec, const void *w, double2 *out) {
+    int nwg = red_grid(n);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * nvec * nwg + 16);
+    if (!part) return MGDD_ENOMEM;
+    for (int i0 = 0; i0 < nvec; i0 += MAXV) {
+        int nv = nvec - i0 < MAXV ? nvec - i0 : MAXV;
+        PtrList pl{};
+        for (int i = 0; i < nv; i++) pl.p[i] = xs[i0 + i];
+#define MD(TX, TW) multidot_kernel<TX, TW, MAXV><<<nwg, TPB, 0, c->stream>>>(n, pl, nv, (const C<TW> *)w, part)
+        if (px == MGDD_F64 && pw == MGDD_F64) MD(double, double);
+        else if (px == MGDD_F32 && pw == MGDD_F32) MD(float, float);
+        else if (px == MGDD_F32 && pw == MGDD_F64) MD(float, double);
+        else MD(double, float);
+#undef MD
+        finish_kernel<<<nv, 64, 0, c->stream>>>(nv, nwg, part, out + i0);
+        int rc = hip_check(c, hipGetLastError(), "multidot");
+        if (rc) return rc;
+    }
+    return MGDD_OK;
+}
+
+int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nvec, const double2 *coef, double alpha,
+                 double beta, void *y) {
+    int nwg = lin_grid(n);
+    if (nvec == 0) {
+        if (beta == 1.0) return MGDD_OK;
+        PtrList pl{};
+#define LC(TX, TY) lincomb_kernel<TX, TY, 1><<<nwg, TPB, 0, c->stream>>>(n, pl, 0, coef, alpha, beta, (C<TY> *)y)
+        if (py == MGDD_F64) LC(double, double); else LC(float, float);
+        return hip_check(c, hipGetLastError(), "lincomb");
+    }
+    for (int i0 = 0; i0 < nvec; i0 += MAXV) {
+        int nv = nvec - i0 < MAXV ? nvec - i0 : MAXV;
+        PtrList pl{};
+        for (int i = 0; i < nv; i++) pl.p[i] = xs[i0 + i];
+        double b = i0 == 0 ? beta : 1.0;
+#define LC2(TX, TY) lincomb_kernel<TX, TY, MAXV><<<nwg, TPB, 0, c->stream>>>(n, pl, nv, coef + i0, alpha, b, (C<TY> *)y)
+        if (px == MGDD_F64 && py == MGDD_F64) LC2(double, double);
+        else if (px == MGDD_F32 && py == MGDD_F32) LC2(float, float);
+        else if (px == MGDD_F32 && py == MGDD_F64) LC2(float, double);
+        else LC2(double, float);
+#undef LC2
+#undef LC
+        int rc = hip_check(c, hipGetLastError(), "lincomb");
+        if (rc) return rc;
+    }
+    return MGDD_OK;
+}
+
+int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y) {
+    int nwg = lin_grid(n);
+    if (px == MGDD_F64 && py == MGDD_F64)
+        scale_kernel<double, double><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, (double2 *)y);
+    else if (px == MGDD_F32 && py == MGDD_F32)
+        scale_kernel<float, float><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, (float2 *)y);
+    else if (px == MGDD_F64)
+        scale_kernel<double, float><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, (float2 *)y);
+    else
+        scale_kernel<float, double><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, (double2 *)y);
+    return hip_check(c, hipGetLastError(), "scale");
+}
+
+int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef) {
+    rsqrt_kernel<<<1, 1, 0, c->stream>>>(v, coef);
+    return hip_check(c, hipGetLastError(), "rsqrt");
+}
+
+}  // namespace mgdd

@@ -7,6 +7,8 @@
 #include <new>
 
 #include "mgdd_internal.h"
+#include "solver.h"
+#include "transfer.h"
 
 namespace mgdd {
 
@@ -149,6 +151,7 @@ int mgdd_destroy(mgdd_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->c.stream);
     for (void *p : ctx->c.owned) (void)hipFree(p);
     if (ctx->c.red_host) (void)hipHostFree(ctx->c.red_host);
+    if (ctx->c.hbuf) (void)hipHostFree(ctx->c.hbuf);
     delete ctx;
     return MGDD_OK;
 }
@@ -162,13 +165,11 @@ size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level) {
     return 0;
 }
 
-int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, double m0, double csw) {
+int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, int src_on_device, double m0, double csw) {
     if (!ctx || !U) return MGDD_EINVAL;
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     const size_t V = c->g.V;
-    for (size_t i = 0; i < V * 4 * 18; i++)
-        if (!std::isfinite(U[i])) return fail(c, MGDD_ENAN, "gauge field holds NaN or Inf");
     if (!std::isfinite(m0) || !std::isfinite(csw)) return fail(c, MGDD_ENAN, "m0 or csw not finite");
     if (!c->U64) {
         c->U64 = dalloc(c, V * 36 * 16);
@@ -181,11 +182,17 @@ int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, double m0, double csw) {
     c->m0 = m0;
     c->csw = csw;
     c->c.ready = false;
-    void *st = ensure_stage(c, V * 36 * 16);
-    if (!st) return MGDD_ENOMEM;
-    int rc = hip_check(c, hipMemcpyAsync(st, U, V * 36 * 16, hipMemcpyHostToDevice, c->stream), "copy gauge");
-    if (rc) return rc;
-    rc = launch_gauge_ingest(c, (const double2 *)st);
+    c->gauge_ready = false;
+    const double2 *src = (const double2 *)U;
+    int rc = MGDD_OK;
+    if (!src_on_device) {
+        void *st = ensure_stage(c, V * 36 * 16);
+        if (!st) return MGDD_ENOMEM;
+        rc = hip_check(c, hipMemcpyAsync(st, U, V * 36 * 16, hipMemcpyHostToDevice, c->stream), "copy gauge");
+        if (rc) return rc;
+        src = (const double2 *)st;
+    }
+    rc = launch_gauge_ingest(c, src);
     if (rc) return rc;
     c->gauge_ready = true;
     return MGDD_OK;
@@ -249,6 +256,145 @@ int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, doubl
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     GUARD_BEGIN
     return launch_sap(&ctx->c, prec, nrhs, nsweeps, mr_iters, shift_re, shift_im, b, z);
+    GUARD_END
+}
+
+static int need_coarse(mgdd_ctx *ctx) {
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    if (!ctx->c.c.ready) return fail(&ctx->c, MGDD_ENOTREADY, "no interpolation P (call mgdd_build_P or mgdd_setup_bootstrap)");
+    return MGDD_OK;
+}
+
+int mgdd_build_P(mgdd_ctx *ctx, const int agg[4], int ntv, const void *test_vectors) {
+    if (!ctx || !agg || !test_vectors) return MGDD_EINVAL;
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    c->c.ready = false;
+    int rc = transfer_setup(c, agg, ntv);
+    if (!rc) rc = launch_build_P(c, test_vectors);
+    if (!rc) rc = launch_coarse_build(c);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc) c->c.ready = true;
+    return rc;
+    GUARD_END
+}
+
+int mgdd_get_test_vectors(mgdd_ctx *ctx, void *dst) {
+    if (!ctx || !dst) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    Ctx *c = &ctx->c;
+    return hip_check(c, hipMemcpyAsync(dst, c->c.tv64, (size_t)c->c.N * 12 * c->g.V * 16, hipMemcpyDeviceToDevice,
+                                       c->stream), "copy");
+}
+
+int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coarse) {
+    if (!ctx || !fine || !coarse || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_restrict(&ctx->c, prec, nrhs, fine, coarse);
+    GUARD_END
+}
+
+int mgdd_prolong(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *fine) {
+    if (!ctx || !fine || !coarse || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_prolong(&ctx->c, prec, nrhs, coarse, fine);
+    GUARD_END
+}
+
+int mgdd_coarse_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out) {
+    if (!ctx || !in || !out || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (in == out) return fail(&ctx->c, MGDD_EINVAL, "in and out alias");
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_coarse_apply(&ctx->c, prec, nrhs, in, out);
+    GUARD_END
+}
+
+int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x) {
+    if (!ctx || !b || !x || !valid_prec(prec) || nrhs <= 0 || iters < 1 || iters > 1000) return MGDD_EINVAL;
+    if (b == x) return fail(&ctx->c, MGDD_EINVAL, "b and x alias");
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    Arena A;
+    rc = arena_open(c, coarse_gmres_bytes(c, prec, iters), A);
+    size_t nc = (size_t)c->c.Vc * 2 * c->c.N * csize(prec);
+    for (int r = 0; r < nrhs && !rc; r++)
+        rc = coarse_gmres(c, prec, iters, (const char *)b + r * nc, (char *)x + r * nc, A);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    return rc;
+    GUARD_END
+}
+
+int mgdd_precondition(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, int coarse_iters, const void *r,
+                      void *z) {
+    if (!ctx || !r || !z || !valid_prec(prec) || nrhs <= 0 || nu < 0 || mr_iters < 0 || coarse_iters < 1)
+        return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    Arena A;
+    rc = arena_open(c, precond_bytes(c, prec, coarse_iters), A);
+    size_t n = (size_t)12 * c->g.V;
+    for (int k = 0; k < nrhs && !rc; k++)
+        rc = mg_precond(c, prec, (const char *)r + k * n * 16, (char *)z + k * n * csize(prec), nu, mr_iters,
+                        coarse_iters, A);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    return rc;
+    GUARD_END
+}
+
+int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const void *random_vectors,
+                         const void *arnoldi_start) {
+    if (!ctx || !params || !random_vectors || !arnoldi_start) return MGDD_EINVAL;
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    const mgdd_setup_params *sp = params;
+    if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0)
+        return fail(&ctx->c, MGDD_EINVAL, "bad setup parameters");
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    c->c.ready = false;
+    int rc = bootstrap(c, sp, random_vectors, arnoldi_start);
+    if (!rc) c->c.ready = true;
+    return rc;
+    GUARD_END
+}
+
+int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const void *b, void *z,
+               mgdd_solve_stats *stats) {
+    if (!ctx || !params || !b || !z || nrhs <= 0) return MGDD_EINVAL;
+    const mgdd_solve_params *sp = params;
+    if (sp->restart < 1 || sp->restart > 256 || sp->maxit < 0 || !(sp->tol > 0) ||
+        (sp->solver != MGDD_SOLVER_FGMRES_MG && sp->solver != MGDD_SOLVER_GCR && sp->solver != MGDD_SOLVER_GCR_EO) ||
+        (sp->precision != MGDD_PLAIN_F64 && sp->precision != MGDD_MIXED))
+        return fail(&ctx->c, MGDD_EINVAL, "bad solve parameters");
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    if (sp->solver == MGDD_SOLVER_FGMRES_MG) {
+        int rc = need_coarse(ctx);
+        if (rc) return rc;
+        if (sp->coarse_iters < 1 || sp->nu < 0 || sp->mr_iters < 0) return fail(&ctx->c, MGDD_EINVAL, "bad solve parameters");
+    }
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    size_t n = (size_t)12 * c->g.V * 16;
+    int result = MGDD_OK;
+    for (int r = 0; r < nrhs; r++) {
+        mgdd_solve_stats st{};
+        int rc = solve_one(c, sp, (const char *)b + r * n, (char *)z + r * n, &st);
+        if (stats) stats[r] = st;
+        if (rc == MGDD_ENOCONV) { result = rc; continue; }
+        if (rc) return rc;
+    }
+    return result;
     GUARD_END
 }
 

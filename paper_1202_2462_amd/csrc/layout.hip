@@ -43,7 +43,8 @@ __global__ void convert_kernel(size_t n, const C<S> *__restrict__ src, C<D> *__r
 
 // ---------------------------------------------------------------- gauge ingest
 
-__global__ void links_kernel(Geom g, const double2 *__restrict__ Uc, double2 *__restrict__ U64, float2 *__restrict__ U32) {
+__global__ void links_kernel(Geom g, const double2 *__restrict__ Uc, double2 *__restrict__ U64, float2 *__restrict__ U32,
+                             int *__restrict__ bad) {
     int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= g.V) return;
     int X[4];
@@ -54,6 +55,7 @@ __global__ void links_kernel(Geom g, const double2 *__restrict__ Uc, double2 *__
         double sg = (mu == 3 && X[3] == g.L[3] - 1) ? -1.0 : 1.0;
         for (int k = 0; k < 9; k++) {
             double2 u = Uc[((size_t)s * 4 + mu) * 9 + k];
+            if (!isfinite(u.x) || !isfinite(u.y)) atomicOr(bad, 2);
             u.x *= sg;
             u.y *= sg;
             U64[((size_t)mu * 9 + k) * g.V + d] = u;
@@ -211,7 +213,7 @@ __global__ void clover_kernel(Geom g, const double2 *__restrict__ Uc, double m0,
             A32[(size_t)(chi * 18 + k) * g.V + d] = make_float2((float)m[2 * k], (float)m[2 * k + 1]);
         }
         double2 Ai[6][6];
-        if (!inv6(Am, Ai)) { atomicExch(bad, 1); continue; }
+        if (!inv6(Am, Ai)) { atomicOr(bad, 1); continue; }
         for (int i = 0; i < 6; i++) m[i] = Ai[i][i].x;
         for (int i = 0; i < 6; i++)
             for (int j = i + 1; j < 6; j++) {
@@ -253,12 +255,12 @@ int launch_convert(Ctx *c, int from, int to, size_t n, const void *src, void *ds
 }
 
 int launch_gauge_ingest(Ctx *c, const double2 *Ucanon) {
-    links_kernel<<<nblk(c->g.V), TPB, 0, c->stream>>>(c->g, Ucanon, (double2 *)c->U64, (float2 *)c->U32);
-    int rc = hip_check(c, hipGetLastError(), "links kernel");
-    if (rc) return rc;
     int *bad = (int *)ensure_scratch(c, sizeof(int));
     if (!bad) return MGDD_ENOMEM;
-    rc = hip_check(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream), "memset");
+    int rc = hip_check(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream), "memset");
+    if (rc) return rc;
+    links_kernel<<<nblk(c->g.V), TPB, 0, c->stream>>>(c->g, Ucanon, (double2 *)c->U64, (float2 *)c->U32, bad);
+    rc = hip_check(c, hipGetLastError(), "links kernel");
     if (rc) return rc;
     clover_kernel<<<nblk(c->g.V, 128), 128, 0, c->stream>>>(c->g, Ucanon, c->m0, c->csw, (double2 *)c->A64,
                                                           (float2 *)c->A32, (double2 *)c->Ainv64, bad);
@@ -269,6 +271,7 @@ int launch_gauge_ingest(Ctx *c, const double2 *Ucanon) {
     if (rc) return rc;
     rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     if (rc) return rc;
+    if (hbad & 2) return fail(c, MGDD_ENAN, "gauge field holds NaN or Inf");
     if (hbad) return fail(c, MGDD_EINVAL, "clover term is singular on some site");
     return MGDD_OK;
 }

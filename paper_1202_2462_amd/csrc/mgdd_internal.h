@@ -64,11 +64,13 @@ struct Level1 {  // coarse level of the current P
     bool ready = false;
     int agg[4] = {0, 0, 0, 0};
     int Lc[4] = {0, 0, 0, 0};
-    int Vc = 0, N = 0;
+    int Vc = 0, Va = 0, N = 0;
     void *P64 = nullptr, *P32 = nullptr;    // N fine fields, device layout
     void *Dc64 = nullptr, *Dc32 = nullptr;  // [Vc][9][2N (col)][2N (row)] complex
-    int *nbr = nullptr;                     // [Vc][9] coarse neighbour (self first)
-    int *agg_sites = nullptr;               // [Vc][Va] device fine site of local site of aggregate
+    int *cnbr = nullptr;                    // [Vc][9] coarse neighbour (self first)
+    int *agg_sites = nullptr;               // [Vc][Va] device site of each local site of an aggregate
+    int *site_agg = nullptr;                // [V] aggregate of each device site
+    void *tv64 = nullptr;                   // the N test vectors P was built from
 };
 
 struct Ctx {
@@ -83,8 +85,8 @@ struct Ctx {
     bool gauge_ready = false;
     double m0 = 0, csw = 0;
     void *U64 = nullptr, *U32 = nullptr;    // [4][9][V] complex
-    void *A64 = nullptr, *A32 = nullptr;    // [72][V] real (packed Hermitian 6x6 x 2 chiralities)
-    void *Ainv64 = nullptr;                 // [72][V] inverse of A (even-odd)
+    void *A64 = nullptr, *A32 = nullptr;    // [36][V] complex pairs (packed Hermitian 6x6 x 2 chiralities)
+    void *Ainv64 = nullptr;                 // [36][V] the same for the inverse of A (even-odd)
     Level1 c;
     // workspace
     std::vector<void *> owned;
@@ -95,6 +97,9 @@ struct Ctx {
     double *red_host = nullptr;             // pinned
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    void *ws = nullptr;                     // solver / setup workspace
+    size_t ws_bytes = 0;
+    void *hbuf = nullptr;                   // pinned scalars (see host_buf)
 };
 
 int fail(Ctx *c, int code, const std::string &msg);

@@ -1,0 +1,27 @@
+// Host-driven solvers and setup (see solver.hip).
+#pragma once
+
+#include <complex>
+
+#include "mgdd_internal.h"
+
+namespace mgdd {
+
+// Bump allocator over the context workspace. take() returns nullptr (and
+// records the size needed) when the workspace is too small.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, off = 0, need = 0;
+    void *take(size_t bytes);
+};
+int arena_open(Ctx *c, size_t bytes, Arena &a);
+std::complex<double> *host_buf(Ctx *c, size_t n);
+
+size_t coarse_gmres_bytes(const Ctx *c, int p, int m);
+size_t precond_bytes(const Ctx *c, int p, int cit);
+int coarse_gmres(Ctx *c, int p, int m, const void *b, void *x, Arena &A);
+int mg_precond(Ctx *c, int p, const void *r64, void *z, int nu, int mr, int cit, Arena &A);
+int solve_one(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st);
+int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64);
+
+}  // namespace mgdd

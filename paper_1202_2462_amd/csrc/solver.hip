@@ -1,0 +1,687 @@
+// Host-driven solvers on top of the kernels: the fixed-step GMRES on D_c, the
+// two-level preconditioner, flexible GMRES (Section 4), plain and even-odd
+// GCR (comparators), and the bootstrap setup (Section 3). Vectors stay on the
+// device; Gram-Schmidt coefficients are produced and consumed on the device,
+// and the host reads back only the small Hessenberg or Gram matrices it needs
+// for Givens rotations and eigenproblems.
+#include <chrono>
+#include <cmath>
+
+#include "blas.h"
+#include "eo.h"
+#include "linalg.h"
+#include "solver.h"
+#include "transfer.h"
+
+namespace mgdd {
+
+using la::cd;
+
+// ---------------------------------------------------------------- workspace
+
+void *Arena::take(size_t bytes) {
+    size_t b = (bytes + 255) & ~(size_t)255;
+    if (off + b > cap) {
+        need = off + b > need ? off + b : need;
+        off += b;
+        return nullptr;
+    }
+    void *p = base + off;
+    off += b;
+    return p;
+}
+
+int arena_open(Ctx *c, size_t bytes, Arena &a) {
+    if (c->ws_bytes < bytes) {
+        if (c->ws) {
+            (void)hipStreamSynchronize(c->stream);
+            dfree(c, c->ws);
+        }
+        c->ws = dalloc(c, bytes);
+        c->ws_bytes = c->ws ? bytes : 0;
+        if (!c->ws) return MGDD_ENOMEM;
+    }
+    a.base = (char *)c->ws;
+    a.cap = c->ws_bytes;
+    a.off = 0;
+    a.need = 0;
+    return MGDD_OK;
+}
+
+// Pinned host buffer for scalars (fixed capacity, allocated once per context,
+// never moved). Every host write into it follows a stream synchronisation, so
+// that no copy queued earlier still reads the old contents.
+cd *host_buf(Ctx *c, size_t n) {
+    const size_t cap = (size_t)1 << 16;
+    if (n > cap) return nullptr;
+    if (!c->hbuf) {
+        if (hipHostMalloc((void **)&c->hbuf, cap * sizeof(cd), hipHostMallocDefault) != hipSuccess) {
+            c->hbuf = nullptr;
+            return nullptr;
+        }
+    }
+    return (cd *)c->hbuf;
+}
+
+// copies n device double2 to host (synchronous)
+static int read_dev(Ctx *c, const double2 *src, size_t n, cd *dst) {
+    int rc = hip_check(c, hipMemcpyAsync(dst, src, n * sizeof(double2), hipMemcpyDeviceToHost, c->stream), "read");
+    if (rc) return rc;
+    return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+// copies n host values to device (asynchronous; src must stay valid until the
+// next synchronisation, which every caller performs before reusing it)
+static int write_dev(Ctx *c, const cd *src, size_t n, double2 *dst) {
+    return hip_check(c, hipMemcpyAsync(dst, src, n * sizeof(double2), hipMemcpyHostToDevice, c->stream), "write");
+}
+
+static bool finite(cd z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
+
+// Solves min || beta e1 - H y || for the (k+1) x k upper Hessenberg H (column
+// major, ld = ldh) by Givens rotations; returns y (k values).
+static void hessenberg_lsq(int k, const std::vector<cd> &Hcol, int ldh, double beta, std::vector<cd> &y) {
+    std::vector<cd> R((size_t)(k + 1) * k);
+    for (int j = 0; j < k; j++)
+        for (int i = 0; i <= j + 1; i++) R[(size_t)j * (k + 1) + i] = Hcol[(size_t)j * ldh + i];
+    std::vector<cd> g(k + 1, 0.0);
+    g[0] = beta;
+    for (int j = 0; j < k; j++) {
+        cd *col = &R[(size_t)j * (k + 1)];
+        // earlier rotations were applied column by column as they were formed
+        double c;
+        cd s, rho;
+        la::givens(col[j], col[j + 1], c, s, rho);
+        col[j] = rho;
+        col[j + 1] = 0.0;
+        cd gj = g[j];
+        g[j] = c * gj;
+        g[j + 1] = -std::conj(s) * gj;
+        for (int l = j + 1; l < k; l++) {
+            cd *cl = &R[(size_t)l * (k + 1)];
+            cd a = cl[j], b = cl[j + 1];
+            cl[j] = c * a + s * b;
+            cl[j + 1] = -std::conj(s) * a + c * b;
+        }
+    }
+    y.assign(k, 0.0);
+    for (int i = k - 1; i >= 0; i--) {
+        cd s = g[i];
+        for (int l = i + 1; l < k; l++) s -= R[(size_t)l * (k + 1) + i] * y[l];
+        y[i] = s / R[(size_t)i * (k + 1) + i];
+    }
+}
+
+// ---------------------------------------------------------------- Gram-Schmidt steps on the device
+
+// w <- w - V (V^H w), twice (classical Gram-Schmidt with one re-orthogonalisation);
+// h1 and h2 receive the two coefficient vectors, nrm the squared norm of w after.
+static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm) {
+    int rc = blas_multidot(c, p, p, n, V, k, w, h1);
+    if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h1, -1.0, 1.0, w);
+    if (!rc) rc = blas_multidot(c, p, p, n, V, k, w, h2);
+    if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h2, -1.0, 1.0, w);
+    const void *wp = w;
+    if (!rc) rc = blas_multidot(c, p, p, n, &wp, 1, w, nrm);
+    return rc;
+}
+
+// modified Gram-Schmidt of nv vectors in index order (global orthonormalisation)
+static int mgs_device(Ctx *c, int p, size_t n, void *const *X, int nv, double2 *scal) {
+    for (int k = 0; k < nv; k++) {
+        for (int j = 0; j < k; j++) {
+            const void *xj = X[j];
+            int rc = blas_multidot(c, p, p, n, &xj, 1, X[k], scal);
+            if (!rc) rc = blas_lincomb(c, p, p, n, &xj, 1, scal, -1.0, 1.0, X[k]);
+            if (rc) return rc;
+        }
+        const void *xk = X[k];
+        int rc = blas_multidot(c, p, p, n, &xk, 1, X[k], scal);
+        if (!rc) rc = blas_rsqrt(c, scal, scal + 1);
+        if (!rc) rc = blas_scale(c, p, p, n, X[k], scal + 1, make_double2(1, 0), X[k]);
+        if (rc) return rc;
+    }
+    return MGDD_OK;
+}
+
+// ---------------------------------------------------------------- coarse GMRES
+
+size_t coarse_gmres_bytes(const Ctx *c, int p, int m) {
+    size_t n = (size_t)c->c.Vc * 2 * c->c.N;
+    return (size_t)(m + 2) * (n * csize(p) + 256) + 4 * (size_t)(m + 2) * (m + 2) * 16 + 4096;
+}
+
+// x = GMRES_m(D_c, b) from x = 0, no restart, one host synchronisation.
+int coarse_gmres(Ctx *c, int p, int m, const void *b, void *x, Arena &A) {
+    const size_t n = (size_t)c->c.Vc * 2 * c->c.N, cs = csize(p);
+    const size_t mark = A.off;
+    std::vector<void *> V(m + 1);
+    for (int i = 0; i <= m; i++) V[i] = A.take(n * cs);
+    void *w = A.take(n * cs);
+    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * (m + 1) * 16);
+    double2 *h2 = (double2 *)A.take((size_t)(m + 1) * (m + 1) * 16);
+    double2 *nr = (double2 *)A.take((size_t)(m + 2) * 16);
+    double2 *coef = (double2 *)A.take((size_t)(m + 2) * 16);
+    if (!coef) return fail(c, MGDD_ENOMEM, "coarse GMRES workspace");
+    const void *bp = b;
+    int rc = blas_multidot(c, p, p, n, &bp, 1, b, nr);
+    if (!rc) rc = blas_rsqrt(c, nr, coef);
+    if (!rc) rc = blas_scale(c, p, p, n, b, coef, make_double2(1, 0), V[0]);
+    for (int j = 0; j < m && !rc; j++) {
+        rc = launch_coarse_apply(c, p, 1, V[j], w);
+        if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1), h2 + (size_t)j * (m + 1), nr + j + 1);
+        if (!rc) rc = blas_rsqrt(c, nr + j + 1, coef + j + 1);
+        if (!rc) rc = blas_scale(c, p, p, n, w, coef + j + 1, make_double2(1, 0), V[j + 1]);
+    }
+    if (rc) return rc;
+    const size_t hs = (size_t)(m + 1) * (m + 1);
+    cd *hb = host_buf(c, 2 * hs + m + 2 + m + 1);
+    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+    rc = hip_check(c, hipMemcpyAsync(hb, h1, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(hb + hs, h2, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = read_dev(c, nr, m + 1, hb + 2 * hs);
+    if (rc) return rc;
+    const cd *H1 = hb, *H2 = hb + hs, *NR = hb + 2 * hs;
+    double beta = std::sqrt(NR[0].real());
+    if (!std::isfinite(beta)) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
+    if (beta == 0.0) {
+        A.off = mark;
+        return blas_lincomb(c, p, p, n, nullptr, 0, nullptr, 0.0, 0.0, x);
+    }
+    std::vector<cd> Hc((size_t)m * (m + 1), 0.0);
+    int k = m;
+    for (int j = 0; j < m; j++) {
+        for (int i = 0; i <= j; i++) Hc[(size_t)j * (m + 1) + i] = H1[(size_t)j * (m + 1) + i] + H2[(size_t)j * (m + 1) + i];
+        double hn = std::sqrt(std::max(NR[j + 1].real(), 0.0));
+        Hc[(size_t)j * (m + 1) + j + 1] = hn;
+        if (hn == 0.0) { k = j + 1; break; }
+    }
+    std::vector<cd> y;
+    hessenberg_lsq(k, Hc, m + 1, beta, y);
+    cd *yb = hb + 2 * hs + m + 2;
+    for (int i = 0; i < k; i++) {
+        if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
+        yb[i] = y[i];
+    }
+    rc = write_dev(c, yb, k, coef);
+    if (!rc) rc = blas_lincomb(c, p, p, n, V.data(), k, coef, 1.0, 0.0, x);
+    A.off = mark;
+    return rc;
+}
+
+// ---------------------------------------------------------------- two-level preconditioner
+
+size_t precond_bytes(const Ctx *c, int p, int cit) {
+    size_t n = (size_t)12 * c->g.V, nc = (size_t)c->c.Vc * 2 * c->c.N;
+    return n * 8 + 2 * nc * csize(p) + coarse_gmres_bytes(c, p, cit) + 4096;
+}
+
+// z = SAP^nu(D, r, z0 = P GMRES_cit(D_c, P^H r)); r in FP64, z in precision p.
+int mg_precond(Ctx *c, int p, const void *r64, void *z, int nu, int mr, int cit, Arena &A) {
+    const size_t n = (size_t)12 * c->g.V, nc = (size_t)c->c.Vc * 2 * c->c.N;
+    const size_t mark = A.off;
+    const void *rp = r64;
+    int rc = MGDD_OK;
+    if (p == MGDD_F32) {
+        void *r32 = A.take(n * 8);
+        if (!r32) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
+        rc = launch_convert(c, MGDD_F64, MGDD_F32, n, r64, r32);
+        rp = r32;
+    }
+    void *cb = A.take(nc * csize(p)), *cx = A.take(nc * csize(p));
+    if (!cx) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
+    if (!rc) rc = launch_restrict(c, p, 1, rp, cb);
+    if (!rc) rc = coarse_gmres(c, p, cit, cb, cx, A);
+    if (!rc) rc = launch_prolong(c, p, 1, cx, z);
+    if (!rc && nu > 0) rc = launch_sap(c, p, 1, nu, mr, 0.0, 0.0, rp, z);
+    A.off = mark;
+    return rc;
+}
+
+// ---------------------------------------------------------------- FGMRES with the two-level preconditioner
+
+static int fgmres(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st, Arena &A) {
+    const int m = sp->restart, p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
+    const size_t n = (size_t)12 * c->g.V, cs = csize(p);
+    std::vector<void *> V(m + 1), Z(m);
+    for (int i = 0; i <= m; i++) V[i] = A.take(n * 16);
+    for (int i = 0; i < m; i++) Z[i] = A.take(n * cs);
+    void *w = A.take(n * 16), *r = A.take(n * 16);
+    void *z64 = p == MGDD_F32 ? A.take(n * 16) : nullptr;
+    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * 16), *h2 = (double2 *)A.take((size_t)(m + 1) * 16);
+    double2 *nr = (double2 *)A.take(64), *coef = (double2 *)A.take((size_t)(m + 2) * 16);
+    double2 *pm = (double2 *)A.take(32);
+    if (!pm) return fail(c, MGDD_ENOMEM, "FGMRES workspace");
+    cd *hb = host_buf(c, 4 * (size_t)(m + 2) + 8);
+    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+    hb[0] = 1.0;
+    hb[1] = -1.0;
+    int rc = write_dev(c, hb, 2, pm);
+    const void *bp = b;
+    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &bp, 1, b, nr);
+    if (!rc) rc = read_dev(c, nr, 1, hb + 4);
+    if (rc) return rc;
+    const double bn = std::sqrt(hb[4].real());
+    if (!std::isfinite(bn)) return fail(c, MGDD_ENAN, "right-hand side holds NaN or Inf");
+    st->iters = st->restarts = 0;
+    st->converged = 0;
+    if (bn == 0.0) {
+        st->converged = 1;
+        st->relres = 0.0;
+        return blas_lincomb(c, MGDD_F64, MGDD_F64, n, nullptr, 0, nullptr, 0.0, 0.0, z);
+    }
+    for (;;) {
+        // true residual r = b - D z
+        rc = launch_dirac(c, MGDD_F64, 1, z, w);
+        const void *bw[2] = {b, w};
+        if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, bw, 2, pm, 1.0, 0.0, r);
+        const void *rp = r;
+        if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &rp, 1, r, nr);
+        if (!rc) rc = read_dev(c, nr, 1, hb + 4);
+        if (rc) return rc;
+        const double rn = std::sqrt(hb[4].real());
+        if (!std::isfinite(rn)) return fail(c, MGDD_ENAN, "NaN in the residual");
+        st->relres = rn / bn;
+        if (rn <= sp->tol * bn) { st->converged = 1; return MGDD_OK; }
+        if (st->iters >= sp->maxit) return MGDD_OK;
+        rc = blas_scale(c, MGDD_F64, MGDD_F64, n, r, nullptr, make_double2(1.0 / rn, 0), V[0]);
+        if (rc) return rc;
+        std::vector<cd> Hc((size_t)m * (m + 1), 0.0), g(m + 1, 0.0), sn(m);
+        std::vector<double> cs_(m);
+        g[0] = rn;
+        int k = 0;
+        for (int j = 0; j < m; j++) {
+            rc = mg_precond(c, p, V[j], Z[j], sp->nu, sp->mr_iters, sp->coarse_iters, A);
+            if (!rc && p == MGDD_F32) {
+                rc = launch_convert(c, MGDD_F32, MGDD_F64, n, Z[j], z64);
+                if (!rc) rc = launch_dirac(c, MGDD_F64, 1, z64, w);
+            } else if (!rc) {
+                rc = launch_dirac(c, MGDD_F64, 1, Z[j], w);
+            }
+            if (!rc) rc = cgs2(c, MGDD_F64, n, V.data(), j + 1, w, h1, h2, nr);
+            if (rc) return rc;
+            rc = hip_check(c, hipMemcpyAsync(hb, h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, c->stream), "read");
+            if (!rc) rc = hip_check(c, hipMemcpyAsync(hb + m + 2, h2, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, c->stream), "read");
+            if (!rc) rc = read_dev(c, nr, 1, hb + 2 * (m + 2));
+            if (rc) return rc;
+            cd *col = &Hc[(size_t)j * (m + 1)];
+            for (int i = 0; i <= j; i++) col[i] = hb[i] + hb[m + 2 + i];
+            const double hn = std::sqrt(std::max(hb[2 * (m + 2)].real(), 0.0));
+            if (!std::isfinite(hn)) return fail(c, MGDD_ENAN, "NaN in the Arnoldi step");
+            col[j + 1] = hn;
+            for (int i = 0; i < j; i++) {
+                cd a = col[i], bb = col[i + 1];
+                col[i] = cs_[i] * a + sn[i] * bb;
+                col[i + 1] = -std::conj(sn[i]) * a + cs_[i] * bb;
+            }
+            cd rho;
+            la::givens(col[j], col[j + 1], cs_[j], sn[j], rho);
+            col[j] = rho;
+            col[j + 1] = 0.0;
+            cd gj = g[j];
+            g[j] = cs_[j] * gj;
+            g[j + 1] = -std::conj(sn[j]) * gj;
+            st->iters++;
+            k = j + 1;
+            if (std::abs(g[j + 1]) <= sp->tol * bn || hn == 0.0 || st->iters >= sp->maxit) break;
+            rc = blas_scale(c, MGDD_F64, MGDD_F64, n, w, nullptr, make_double2(1.0 / hn, 0), V[j + 1]);
+            if (rc) return rc;
+        }
+        // R y = g (R upper triangular after the rotations)
+        std::vector<cd> y(k);
+        for (int i = k - 1; i >= 0; i--) {
+            cd s = g[i];
+            for (int l = i + 1; l < k; l++) s -= Hc[(size_t)l * (m + 1) + i] * y[l];
+            y[i] = s / Hc[(size_t)i * (m + 1) + i];
+            if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the least-squares solve");
+        }
+        cd *yb = hb + 3 * (m + 2);
+        for (int i = 0; i < k; i++) yb[i] = y[i];
+        rc = write_dev(c, yb, k, coef);
+        if (!rc) rc = blas_lincomb(c, p, MGDD_F64, n, Z.data(), k, coef, 1.0, 1.0, z);
+        if (rc) return rc;
+        st->restarts++;
+    }
+}
+
+// ---------------------------------------------------------------- GCR (plain and even-odd)
+
+// Operator of a GCR solve: the full D or the even-odd Schur complement.
+struct GcrOp {
+    Ctx *c;
+    bool eo;
+    void *t;  // half-field temporary for the Schur complement
+    int apply(const void *x, void *y) const {
+        if (!eo) return launch_dirac(c, MGDD_F64, 1, x, y);
+        int rc = launch_eo(c, 0, 0, 1, x, nullptr, 0.0, 1.0, t);   // t = A_ee^-1 H_eo x
+        if (!rc) rc = launch_eo(c, 1, 1, 0, t, x, 1.0, -0.25, y);    // y = A_oo x - 1/4 H_oe t
+        return rc;
+    }
+};
+
+// GCR(m) on op x = rhs from x (in/out), until ||rhs - op x|| <= thr, or maxit.
+// Returns the true residual norm in *res.
+static int gcr_core(Ctx *c, const GcrOp &op, size_t n, int m, const void *rhs, void *x, double thr, int maxit,
+                    int &iters, int &restarts, double *res, Arena &A) {
+    const size_t mark = A.off;
+    std::vector<void *> P(m), Q(m);
+    for (int i = 0; i < m; i++) { P[i] = A.take(n * 16); Q[i] = A.take(n * 16); }
+    void *r = A.take(n * 16), *w = A.take(n * 16);
+    double2 *b1 = (double2 *)A.take((size_t)m * 16), *b2 = (double2 *)A.take((size_t)m * 16);
+    double2 *sc = (double2 *)A.take(128), *pm = (double2 *)A.take(32);
+    if (!pm) return fail(c, MGDD_ENOMEM, "GCR workspace");
+    cd *hb = host_buf(c, 8);
+    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+    hb[0] = 1.0;
+    hb[1] = -1.0;
+    int rc = write_dev(c, hb, 2, pm);
+    for (;;) {
+        if (!rc) rc = op.apply(x, w);
+        const void *bw[2] = {rhs, w};
+        if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, bw, 2, pm, 1.0, 0.0, r);
+        const void *rp = r;
+        if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &rp, 1, r, sc);
+        if (!rc) rc = read_dev(c, sc, 1, hb + 2);
+        if (rc) return rc;
+        double rn = std::sqrt(hb[2].real());
+        if (!std::isfinite(rn)) return fail(c, MGDD_ENAN, "NaN in the GCR residual");
+        *res = rn;
+        if (rn <= thr || iters >= maxit) break;
+        for (int i = 0; i < m; i++) {
+            rc = hip_check(c, hipMemcpyAsync(P[i], r, n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+            if (!rc) rc = op.apply(P[i], Q[i]);
+            for (int pass = 0; pass < 2 && i > 0 && !rc; pass++) {
+                double2 *bb = pass ? b2 : b1;
+                rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, Q.data(), i, Q[i], bb);
+                if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, Q.data(), i, bb, -1.0, 1.0, Q[i]);
+                if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, P.data(), i, bb, -1.0, 1.0, P[i]);
+            }
+            const void *qi = Q[i];
+            if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &qi, 1, Q[i], sc);
+            if (!rc) rc = blas_rsqrt(c, sc, sc + 1);
+            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, Q[i], sc + 1, make_double2(1, 0), Q[i]);
+            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, P[i], sc + 1, make_double2(1, 0), P[i]);
+            if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &qi, 1, r, sc + 2);   // alpha = <q, r>
+            const void *pi = P[i];
+            if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &pi, 1, sc + 2, 1.0, 1.0, x);
+            if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &qi, 1, sc + 2, -1.0, 1.0, r);
+            if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &rp, 1, r, sc + 3);
+            if (!rc) rc = read_dev(c, sc + 3, 1, hb + 3);
+            if (rc) return rc;
+            iters++;
+            double rr = std::sqrt(hb[3].real());
+            if (!std::isfinite(rr)) return fail(c, MGDD_ENAN, "NaN in GCR");
+            if (rr <= thr || iters >= maxit) break;
+        }
+        restarts++;
+    }
+    A.off = mark;
+    return rc;
+}
+
+static int gcr_solve(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st, Arena &A) {
+    const size_t n = (size_t)12 * c->g.V;
+    double2 *sc = (double2 *)A.take(64);
+    void *w = A.take(n * 16);
+    if (!w) return fail(c, MGDD_ENOMEM, "GCR workspace");
+    const void *bp = b;
+    cd *hb = host_buf(c, 8);
+    int rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &bp, 1, b, sc);
+    if (!rc) rc = read_dev(c, sc, 1, hb + 4);
+    if (rc) return rc;
+    const double bn = std::sqrt(hb[4].real());
+    if (!std::isfinite(bn)) return fail(c, MGDD_ENAN, "right-hand side holds NaN or Inf");
+    st->iters = st->restarts = 0;
+    st->converged = 0;
+    if (bn == 0.0) {
+        st->converged = 1;
+        st->relres = 0;
+        return blas_lincomb(c, MGDD_F64, MGDD_F64, n, nullptr, 0, nullptr, 0.0, 0.0, z);
+    }
+    double res = 0;
+    if (sp->solver == MGDD_SOLVER_GCR) {
+        GcrOp op{c, false, nullptr};
+        rc = gcr_core(c, op, n, sp->restart, b, z, sp->tol * bn, sp->maxit, st->iters, st->restarts, &res, A);
+        if (rc) return rc;
+        st->relres = res / bn;
+        st->converged = res <= sp->tol * bn;
+        return MGDD_OK;
+    }
+    // even-odd: solve the Schur complement on the odd sites, then reconstruct
+    const size_t nh = n / 2;
+    void *be = A.take(nh * 16), *bo = A.take(nh * 16), *ze = A.take(nh * 16), *zo = A.take(nh * 16);
+    void *t = A.take(nh * 16), *bh = A.take(nh * 16), *rfull = A.take(n * 16);
+    if (!rfull) return fail(c, MGDD_ENOMEM, "GCR workspace");
+    GcrOp op{c, true, t};
+    rc = launch_eo_split(c, b, be, bo);
+    if (!rc) rc = launch_eo_split(c, z, ze, zo);
+    if (!rc) rc = launch_eo(c, 0, 0, 1, nullptr, be, 1.0, 0.0, t);      // t = A_ee^-1 b_e
+    if (!rc) rc = launch_eo(c, 1, 0, 0, t, bo, 1.0, 0.5, bh);           // b_hat = b_o + 1/2 H_oe t
+    double thr = sp->tol * bn;
+    for (;;) {
+        if (rc) return rc;
+        rc = gcr_core(c, op, nh, sp->restart, bh, zo, thr, sp->maxit, st->iters, st->restarts, &res, A);
+        if (!rc) rc = launch_eo(c, 0, 0, 1, zo, be, 1.0, 0.5, ze);      // z_e = A_ee^-1 (b_e + 1/2 H_eo z_o)
+        if (!rc) rc = launch_eo_merge(c, ze, zo, z);
+        if (!rc) rc = launch_dirac(c, MGDD_F64, 1, z, w);
+        // full residual ||b - D z||
+        if (!rc) {
+            double2 *pm = sc + 2;
+            cd *h = host_buf(c, 8);
+            h[0] = 1.0;
+            h[1] = -1.0;
+            rc = write_dev(c, h, 2, pm);
+            const void *bw2[2] = {b, w};
+            if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, bw2, 2, pm, 1.0, 0.0, rfull);
+            const void *rf = rfull;
+            if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &rf, 1, rfull, sc);
+            if (!rc) rc = read_dev(c, sc, 1, h + 4);
+            if (rc) return rc;
+            double full = std::sqrt(h[4].real());
+            st->relres = full / bn;
+            if (full <= sp->tol * bn) { st->converged = 1; return MGDD_OK; }
+            if (st->iters >= sp->maxit) return MGDD_OK;
+            thr *= 0.1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- solve entry
+
+size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp) {
+    const size_t n = (size_t)12 * c->g.V;
+    const int m = sp->restart;
+    if (sp->solver == MGDD_SOLVER_FGMRES_MG) {
+        int p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
+        return (size_t)(m + 4) * (n * 16 + 256) + (size_t)m * (n * csize(p) + 256) + 8 * (size_t)(m + 2) * 16 +
+               precond_bytes(c, p, sp->coarse_iters) + 65536;
+    }
+    return (size_t)(2 * m + 10) * (n * 16 + 256) + 65536;
+}
+
+int solve_one(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st) {
+    Arena A;
+    int rc = arena_open(c, solve_bytes(c, sp), A);
+    if (rc) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    if (sp->solver == MGDD_SOLVER_FGMRES_MG) rc = fgmres(c, sp, b, z, st, A);
+    else rc = gcr_solve(c, sp, b, z, st, A);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (A.need) return fail(c, MGDD_ENOMEM, "solver workspace estimate too small");
+    if (!rc && !st->converged) return fail(c, MGDD_ENOCONV, "maxit reached before the tolerance");
+    return rc;
+}
+
+// ---------------------------------------------------------------- bootstrap setup
+
+static int arnoldi_host(Ctx *c, int m, const void *v0, std::vector<void *> &Qv, std::vector<cd> &H, int &k, Arena &A) {
+    const size_t n = (size_t)c->c.Vc * 2 * c->c.N;
+    void *w = A.take(n * 16);
+    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * (m + 1) * 16), *h2 = (double2 *)A.take((size_t)(m + 1) * (m + 1) * 16);
+    double2 *nr = (double2 *)A.take((size_t)(m + 2) * 16), *coef = (double2 *)A.take((size_t)(m + 2) * 16);
+    Qv.resize(m + 1);
+    for (int i = 0; i <= m; i++) Qv[i] = A.take(n * 16);
+    if (!Qv[m]) return fail(c, MGDD_ENOMEM, "Arnoldi workspace");
+    const void *vp = v0;
+    int rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &vp, 1, v0, nr);
+    if (!rc) rc = blas_rsqrt(c, nr, coef);
+    if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, v0, coef, make_double2(1, 0), Qv[0]);
+    for (int j = 0; j < m && !rc; j++) {
+        rc = launch_coarse_apply(c, MGDD_F64, 1, Qv[j], w);
+        if (!rc) rc = cgs2(c, MGDD_F64, n, Qv.data(), j + 1, w, h1 + (size_t)j * (m + 1), h2 + (size_t)j * (m + 1), nr + j + 1);
+        if (!rc) rc = blas_rsqrt(c, nr + j + 1, coef + j + 1);
+        if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, w, coef + j + 1, make_double2(1, 0), Qv[j + 1]);
+    }
+    if (rc) return rc;
+    const size_t hs = (size_t)(m + 1) * (m + 1);
+    std::vector<cd> b1(hs), b2(hs), nn(m + 1);
+    rc = hip_check(c, hipMemcpyAsync(b1.data(), h1, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(b2.data(), h2, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(nn.data(), nr, (m + 1) * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (rc) return rc;
+    if (!(nn[0].real() > 0)) return fail(c, MGDD_EINVAL, "Arnoldi start vector is zero");
+    // H (m+1) x m, row-major
+    H.assign((size_t)(m + 1) * m, 0.0);
+    k = m;
+    for (int j = 0; j < m; j++) {
+        for (int i = 0; i <= j; i++) H[(size_t)i * m + j] = b1[(size_t)j * (m + 1) + i] + b2[(size_t)j * (m + 1) + i];
+        double hn = std::sqrt(std::max(nn[j + 1].real(), 0.0));
+        H[(size_t)(j + 1) * m + j] = hn;
+        if (hn == 0.0) { k = j + 1; break; }
+    }
+    return MGDD_OK;
+}
+
+int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64) {
+    const int N = sp->ntv, p = sp->prec;
+    const size_t n = (size_t)12 * c->g.V;
+    int rc = transfer_setup(c, sp->agg, N);
+    if (rc) return rc;
+    const size_t nc = (size_t)c->c.Vc * 2 * N;
+    const int mA = sp->arnoldi_m > 0 ? sp->arnoldi_m : (int)std::min<size_t>(nc, 2 * (size_t)N + 10);
+    size_t bytes = (size_t)N * n * 16 * 2 + (p == MGDD_F32 ? (size_t)N * n * 8 * 2 : (size_t)N * n * 16) +
+                   (size_t)4 * N * n * 16 + (size_t)(mA + 3 + N) * nc * 16 + 64 * (size_t)(mA + 2) * (mA + 2) + (1 << 20);
+    Arena A;
+    rc = arena_open(c, bytes, A);
+    if (rc) return rc;
+    std::vector<void *> Vt(N);
+    void *vt = A.take((size_t)N * n * 16);
+    void *vs = p == MGDD_F32 ? A.take((size_t)N * n * 8) : vt;
+    void *zero = A.take((size_t)N * n * csize(p));
+    double2 *scal = (double2 *)A.take(4096);
+    if (!scal) return fail(c, MGDD_ENOMEM, "setup workspace");
+    for (int i = 0; i < N; i++) Vt[i] = (char *)vt + (size_t)i * n * 16;
+    rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+    if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, (size_t)N * n * csize(p), c->stream), "memset");
+    // part 1: nu rounds of (one SAP sweep with b = 0 on all vectors, global MGS)
+    for (int it = 0; it < sp->nu && !rc; it++) {
+        if (p == MGDD_F32) rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)N * n, vt, vs);
+        if (!rc) rc = launch_sap(c, p, N, 1, sp->mr_iters, 0.0, 0.0, zero, vs);
+        if (!rc && p == MGDD_F32) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)N * n, vs, vt);
+        if (!rc) rc = mgs_device(c, MGDD_F64, n, Vt.data(), N, scal);
+    }
+    if (!rc) rc = launch_build_P(c, vt);
+    if (!rc) rc = launch_coarse_build(c);
+    if (rc) return rc;
+    // part 2
+    std::vector<void *> W(2 * N), DW(2 * N);
+    void *wbuf = A.take((size_t)2 * N * n * 16), *dwbuf = A.take((size_t)2 * N * n * 16);
+    void *tmp32 = p == MGDD_F32 ? A.take(n * 8) : nullptr;
+    std::vector<void *> phi(N);
+    for (int i = 0; i < N; i++) phi[i] = A.take(nc * 16);
+    double2 *gdev = (double2 *)A.take((size_t)4 * N * N * 16 + 256), *ydev = (double2 *)A.take((size_t)4 * N * N * 16 + 256);
+    if (!ydev || !dwbuf || !phi[N - 1]) return fail(c, MGDD_ENOMEM, "setup workspace");
+    for (int i = 0; i < 2 * N; i++) {
+        W[i] = (char *)wbuf + (size_t)i * n * 16;
+        DW[i] = (char *)dwbuf + (size_t)i * n * 16;
+    }
+    for (int rep = 0; rep < sp->n_part2; rep++) {
+        const size_t mark = A.off;
+        std::vector<void *> Qv;
+        std::vector<cd> H;
+        int k = 0;
+        rc = arnoldi_host(c, mA, start64, Qv, H, k, A);
+        if (rc) return rc;
+        // harmonic Ritz pairs of D_c for target 0
+        la::Mat T((size_t)k * k);
+        for (int i = 0; i < k; i++)
+            for (int j = 0; j < k; j++) T[(size_t)i * k + j] = H[(size_t)i * mA + j];
+        if (k == mA) {
+            cd hk = H[(size_t)mA * mA + mA - 1];
+            la::Mat HmH((size_t)k * k);
+            for (int i = 0; i < k; i++)
+                for (int j = 0; j < k; j++) HmH[(size_t)i * k + j] = std::conj(T[(size_t)j * k + i]);
+            std::vector<cd> f(k, 0.0);
+            f[k - 1] = 1.0;
+            if (!la::lu_solve(k, HmH, f)) return fail(c, MGDD_EBREAKDOWN, "singular Hessenberg matrix in the setup");
+            for (int i = 0; i < k; i++) T[(size_t)i * k + k - 1] += std::norm(hk) * f[i];
+        }
+        std::vector<cd> th;
+        la::Mat Y;
+        if (!la::eig(k, T, th, Y)) return fail(c, MGDD_EBREAKDOWN, "eigenvalue iteration did not converge");
+        std::vector<int> order(k);
+        for (int i = 0; i < k; i++) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int a, int b) {
+            double ma = std::abs(th[a]), mb = std::abs(th[b]);
+            if (ma != mb) return ma < mb;
+            if (th[a].real() != th[b].real()) return th[a].real() < th[b].real();
+            return th[a].imag() < th[b].imag();
+        });
+        const int nk = std::min(N, k);
+        // phi_i = Q y_i / ||Q y_i||, w_i = P phi_i, then iota sweeps of SAP with shift theta_i
+        cd *hb = host_buf(c, (size_t)k * nk + 8);
+        if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+        for (int i = 0; i < nk; i++)
+            for (int j = 0; j < k; j++) hb[(size_t)i * k + j] = Y[(size_t)j * k + order[i]];
+        rc = write_dev(c, hb, (size_t)k * nk, ydev);
+        for (int i = 0; i < nk && !rc; i++) {
+            rc = blas_lincomb(c, MGDD_F64, MGDD_F64, nc, Qv.data(), k, ydev + (size_t)i * k, 1.0, 0.0, phi[i]);
+            const void *pp = phi[i];
+            if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, nc, &pp, 1, phi[i], scal);
+            if (!rc) rc = blas_rsqrt(c, scal, scal + 1);
+            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, nc, phi[i], scal + 1, make_double2(1, 0), phi[i]);
+            if (!rc) rc = launch_prolong(c, MGDD_F64, 1, phi[i], W[i]);
+            cd lam = th[order[i]];
+            if (p == MGDD_F32) {
+                if (!rc) rc = launch_convert(c, MGDD_F64, MGDD_F32, n, W[i], tmp32);
+                if (!rc) rc = launch_sap(c, p, 1, sp->iota, sp->mr_iters, lam.real(), lam.imag(), zero, tmp32);
+                if (!rc) rc = launch_convert(c, MGDD_F32, MGDD_F64, n, tmp32, W[i]);
+            } else if (!rc) {
+                rc = launch_sap(c, p, 1, sp->iota, sp->mr_iters, lam.real(), lam.imag(), zero, W[i]);
+            }
+        }
+        if (rc) return rc;
+        const int nw = nk + N;
+        for (int j = 0; j < N && !rc; j++)
+            rc = hip_check(c, hipMemcpyAsync(W[nk + j], Vt[j], n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+        if (!rc) rc = mgs_device(c, MGDD_F64, n, W.data(), nw, scal);
+        if (!rc) rc = launch_dirac(c, MGDD_F64, nw, wbuf, dwbuf);
+        for (int j = 0; j < nw && !rc; j++) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, DW.data(), nw, DW[j], gdev + (size_t)j * nw);
+        std::vector<cd> G((size_t)nw * nw);
+        if (!rc) rc = read_dev(c, gdev, (size_t)nw * nw, G.data());
+        if (rc) return rc;
+        // column j of the device result holds <DW_i, DW_j>: G[i][j]
+        la::Mat Gm((size_t)nw * nw);
+        for (int i = 0; i < nw; i++)
+            for (int j = 0; j < nw; j++) Gm[(size_t)i * nw + j] = G[(size_t)j * nw + i];
+        std::vector<double> sig;
+        la::Mat Z;
+        la::eigh(nw, Gm, sig, Z);
+        hb = host_buf(c, (size_t)nw * N + 8);
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < nw; j++) hb[(size_t)i * nw + j] = Z[(size_t)j * nw + i];
+        rc = write_dev(c, hb, (size_t)nw * N, ydev);
+        for (int i = 0; i < N && !rc; i++) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, W.data(), nw, ydev + (size_t)i * nw, 1.0, 0.0, Vt[i]);
+        if (!rc) rc = launch_build_P(c, vt);
+        if (!rc) rc = launch_coarse_build(c);
+        if (rc) return rc;
+        A.off = mark;
+    }
+    rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (A.need) return fail(c, MGDD_ENOMEM, "setup workspace estimate too small");
+    return rc;
+}
+
+}  // namespace mgdd

@@ -1,0 +1,24 @@
+// Aggregation interpolation, restriction, prolongation and the coarse
+// operator (see transfer.hip).
+#pragma once
+
+#include "mgdd_internal.h"
+
+namespace mgdd {
+
+struct AggGeom {
+    int a[4];
+};
+
+// tables and buffers of the coarse level for aggregates agg and N test vectors
+int transfer_setup(Ctx *c, const int *agg, int N);
+// P from N FP64 fine fields (device layout); FP32 copy made too. MGDD_ERANK if rank deficient.
+int launch_build_P(Ctx *c, const void *tv64);
+int launch_restrict(Ctx *c, int prec, int nrhs, const void *fine, void *coarse);
+int launch_restrict_ex(Ctx *c, int prec, int nrhs, const void *P, const void *fine, void *out, size_t ostride,
+                       size_t rstride);
+int launch_prolong(Ctx *c, int prec, int nrhs, const void *coarse, void *fine);
+int launch_coarse_build(Ctx *c);
+int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out);
+
+}  // namespace mgdd

@@ -1,0 +1,441 @@
+// Aggregation interpolation (Section 3): P from test vectors by a local
+// orthonormalisation per (aggregate, chirality), restriction P^H,
+// prolongation P, and the coarse operator D_c = P^H D P built column by
+// column from the terms of D (self term plus the hops that cross each face of
+// an aggregate) followed by a restriction. The coarse stencil apply lives here
+// as well.
+#include "stencil.h"
+#include "transfer.h"
+
+namespace mgdd {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <typename T> __device__ inline T wsum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// sum of (a, b) over the workgroup, identical in every thread (fixed order)
+__device__ inline double2 block_sum2(double a, double b, double *red) {
+    a = wsum(a);
+    b = wsum(b);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+    __syncthreads();
+    double A = 0, B = 0;
+    for (int i = 0; i < nw; i++) { A += red[2 * i]; B += red[2 * i + 1]; }
+    __syncthreads();
+    return make_double2(A, B);
+}
+
+// ---------------------------------------------------------------- P: local modified Gram-Schmidt
+//
+// One workgroup per (aggregate, chirality); the (6 * Va) x N block of the test
+// vectors is orthonormalised in place, in column order, so that P^H P = 1 on
+// the block with a positive real diagonal of R (the unique thin QR).
+__global__ __launch_bounds__(TPB) void build_P_kernel(int V, int Va, int N, const int *__restrict__ agg_sites,
+                                                      double2 *__restrict__ P, int *__restrict__ flag) {
+    __shared__ double red[2 * (TPB / 64)];
+    const int a = blockIdx.x, chi = blockIdx.y;
+    const int *sites = agg_sites + (size_t)a * Va;
+    const size_t fs = (size_t)12 * V;  // field stride
+    for (int k = 0; k < N; k++) {
+        double2 *w = P + (size_t)k * fs;
+        double n0 = 0;
+        for (int l = threadIdx.x; l < Va; l += blockDim.x)
+            for (int c = 6 * chi; c < 6 * chi + 6; c++) {
+                double2 v = w[(size_t)c * V + sites[l]];
+                n0 += v.x * v.x + v.y * v.y;
+            }
+        n0 = block_sum2(n0, 0, red).x;
+        for (int j = 0; j < k; j++) {
+            const double2 *q = P + (size_t)j * fs;
+            double ra = 0, rb = 0;
+            for (int l = threadIdx.x; l < Va; l += blockDim.x)
+                for (int c = 6 * chi; c < 6 * chi + 6; c++) {
+                    size_t e = (size_t)c * V + sites[l];
+                    double2 qv = q[e], wv = w[e];
+                    ra += qv.x * wv.x + qv.y * wv.y;
+                    rb += qv.x * wv.y - qv.y * wv.x;
+                }
+            double2 r = block_sum2(ra, rb, red);
+            for (int l = threadIdx.x; l < Va; l += blockDim.x)
+                for (int c = 6 * chi; c < 6 * chi + 6; c++) {
+                    size_t e = (size_t)c * V + sites[l];
+                    w[e] = csub(w[e], cmul(r, q[e]));
+                }
+        }
+        double nn = 0;
+        for (int l = threadIdx.x; l < Va; l += blockDim.x)
+            for (int c = 6 * chi; c < 6 * chi + 6; c++) {
+                double2 v = w[(size_t)c * V + sites[l]];
+                nn += v.x * v.x + v.y * v.y;
+            }
+        nn = block_sum2(nn, 0, red).x;
+        double rkk = sqrt(nn);
+        if (!(rkk > 1e-12 * sqrt(n0)) || n0 == 0.0) {
+            if (threadIdx.x == 0) atomicExch(flag, 1);
+            rkk = 1.0;
+        }
+        double inv = 1.0 / rkk;
+        for (int l = threadIdx.x; l < Va; l += blockDim.x)
+            for (int c = 6 * chi; c < 6 * chi + 6; c++) {
+                size_t e = (size_t)c * V + sites[l];
+                w[e] = cscale(w[e], inv);
+            }
+    }
+}
+
+// ---------------------------------------------------------------- restriction c = P^H f
+//
+// One workgroup per (aggregate, field). out[a * ostride + r * rstride + chi * N + k].
+template <typename T>
+__global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, const int *__restrict__ agg_sites,
+                                                       const C<T> *__restrict__ P, const C<T> *__restrict__ f,
+                                                       C<T> *__restrict__ out, size_t ostride, size_t rstride) {
+    extern __shared__ unsigned char smem[];
+    T *red = (T *)smem;  // [waves][N][4]
+    const int a = blockIdx.x, r = blockIdx.y;
+    const int *sites = agg_sites + (size_t)a * Va;
+    const size_t fs = (size_t)12 * V;
+    const C<T> *fr = f + (size_t)r * fs;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k < N; k++) {
+        const C<T> *pk = P + (size_t)k * fs;
+        T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+        for (int l = threadIdx.x; l < Va; l += blockDim.x) {
+            int d = sites[l];
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                C<T> pv = pk[(size_t)c * V + d], fv = fr[(size_t)c * V + d];
+                T re = pv.x * fv.x + pv.y * fv.y, im = pv.x * fv.y - pv.y * fv.x;
+                if (c < 6) { p0 += re; p1 += im; } else { p2 += re; p3 += im; }
+            }
+        }
+        p0 = wsum(p0); p1 = wsum(p1); p2 = wsum(p2); p3 = wsum(p3);
+        if (lane == 0) {
+            T *o = red + ((size_t)w * N + k) * 4;
+            o[0] = p0; o[1] = p1; o[2] = p2; o[3] = p3;
+        }
+    }
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+        int chi = i / N, k = i % N;
+        T re = 0, im = 0;
+        for (int q = 0; q < nw; q++) {
+            re += red[((size_t)q * N + k) * 4 + 2 * chi];
+            im += red[((size_t)q * N + k) * 4 + 2 * chi + 1];
+        }
+        out[(size_t)a * ostride + (size_t)r * rstride + i] = mk<T>(re, im);
+    }
+}
+
+// ---------------------------------------------------------------- prolongation f = P c
+template <typename T>
+__global__ __launch_bounds__(TPB) void prolong_kernel(int V, int Vc, int N, const int *__restrict__ site_agg,
+                                                      const C<T> *__restrict__ P, const C<T> *__restrict__ cin,
+                                                      C<T> *__restrict__ f, int nrhs) {
+    const size_t i = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= (size_t)V * nrhs) return;
+    const int r = (int)(i / V), d = (int)(i % V);
+    const int a = site_agg[d];
+    const size_t fs = (size_t)12 * V;
+    const C<T> *x = cin + ((size_t)r * Vc + a) * 2 * N;
+    C<T> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = mk<T>(0, 0);
+    for (int k = 0; k < N; k++) {
+        const C<T> *pk = P + (size_t)k * fs;
+        C<T> x0 = x[k], x1 = x[N + k];
+#pragma unroll
+        for (int c = 0; c < 12; c++) cfma(acc[c], pk[(size_t)c * V + d], c < 6 ? x0 : x1);
+    }
+    C<T> *fr = f + (size_t)r * fs;
+#pragma unroll
+    for (int c = 0; c < 12; c++) fr[(size_t)c * V + d] = acc[c];
+}
+
+// ---------------------------------------------------------------- terms of D for one column of D_c
+//
+// For the prolonged unit vector P_j (test vector k restricted to chirality
+// chi), W_0 = A P_j - 1/2 (hops that stay inside the aggregate) and, for each
+// face direction dd = 1 + 2 mu (+mu) or 2 + 2 mu (-mu), W_dd = the single hop of
+// D that leaves the aggregate through that face (zero elsewhere). Written as 9
+// fine fields [dd][12][V].
+template <int MU, bool FWD>
+__device__ inline void face_term(const LinkViews<double> &U, const FieldView<double> &pj, int chi, int d, int dn,
+                                 bool crosses, double2 *self, double2 *Wdir, size_t V) {
+    double2 psi[12], u[9], t[12];
+    load_spinor<double>(pj, dn, psi);
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        if ((c >= 6) != (chi != 0)) psi[c] = make_double2(0, 0);
+        t[c] = make_double2(0, 0);
+    }
+    load_link<double, MU>(U, FWD ? d : dn, u);
+    hop<double, MU, FWD>(t, u, psi);
+    FieldView<double> w(Wdir, V, 12);
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        if (crosses) {
+            w.st(c, d, cscale(t[c], -0.5));
+        } else {
+            self[c] = cadd(self[c], t[c]);
+            w.st(c, d, make_double2(0, 0));
+        }
+    }
+}
+
+__global__ __launch_bounds__(TPB) void dc_terms_kernel(Geom g, AggGeom ag, const double2 *__restrict__ Up,
+                                                       const double2 *__restrict__ Ap, const double2 *__restrict__ Pk,
+                                                       int chi, double2 *__restrict__ W) {
+    const int d = blockIdx.x * TPB + threadIdx.x;
+    if (d >= g.V) return;
+    const size_t V = g.V;
+    int X[4], nbr[8];
+    site_coords(g, d, X);
+    site_neighbours(g, d, nbr);
+    LinkViews<double> U(Up, V);
+    CloverViews<double> A(Ap, V);
+    FieldView<double> pj(Pk, V, 12);
+    double2 self[12], psi[12], ap[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) self[c] = make_double2(0, 0);
+    bool last[4], first[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        int r = X[m] % ag.a[m];
+        last[m] = r == ag.a[m] - 1;   // the +m hop leaves the aggregate
+        first[m] = r == 0;            // the -m hop leaves the aggregate
+    }
+    const size_t fs = (size_t)12 * V;
+    face_term<0, true>(U, pj, chi, d, nbr[0], last[0], self, W + 1 * fs, V);
+    face_term<0, false>(U, pj, chi, d, nbr[1], first[0], self, W + 2 * fs, V);
+    face_term<1, true>(U, pj, chi, d, nbr[2], last[1], self, W + 3 * fs, V);
+    face_term<1, false>(U, pj, chi, d, nbr[3], first[1], self, W + 4 * fs, V);
+    face_term<2, true>(U, pj, chi, d, nbr[4], last[2], self, W + 5 * fs, V);
+    face_term<2, false>(U, pj, chi, d, nbr[5], first[2], self, W + 6 * fs, V);
+    face_term<3, true>(U, pj, chi, d, nbr[6], last[3], self, W + 7 * fs, V);
+    face_term<3, false>(U, pj, chi, d, nbr[7], first[3], self, W + 8 * fs, V);
+    // self term: A P_j - 1/2 (hops that stay inside the aggregate)
+    load_spinor<double>(pj, d, psi);
+#pragma unroll
+    for (int c = 0; c < 12; c++) if ((c >= 6) != (chi != 0)) psi[c] = make_double2(0, 0);
+    clover_mv<double>(A, d, psi, ap);
+    FieldView<double> w0(W, V, 12);
+#pragma unroll
+    for (int c = 0; c < 12; c++) w0.st(c, d, csub(ap[c], cscale(self[c], 0.5)));
+}
+
+// ---------------------------------------------------------------- coarse stencil y = D_c x
+//
+// One 64-lane workgroup per (coarse site, right-hand side); lane i < 2N forms
+// row i. Blocks are stored column-major, B[a][dir][col][row], so that the
+// lanes read consecutive rows of one column.
+template <typename T>
+__global__ __launch_bounds__(64) void coarse_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
+                                                          const C<T> *__restrict__ Dc, const C<T> *__restrict__ x,
+                                                          C<T> *__restrict__ y) {
+    const int a = blockIdx.x, r = blockIdx.y, i = threadIdx.x;
+    const int n2 = 2 * N;
+    __shared__ C<T> xs[9][64];
+    const C<T> *xr = x + (size_t)r * Vc * n2;
+    for (int dd = 0; dd < 9; dd++) {
+        int b = cnbr[a * 9 + dd];
+        if (i < n2) xs[dd][i] = xr[(size_t)b * n2 + i];
+    }
+    __syncthreads();
+    if (i >= n2) return;
+    C<T> acc = mk<T>(0, 0);
+    const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
+    for (int dd = 0; dd < 9; dd++)
+        for (int j = 0; j < n2; j++) cfma(acc, B[((size_t)dd * n2 + j) * n2 + i], xs[dd][j]);
+    y[((size_t)r * Vc + a) * n2 + i] = acc;
+}
+
+template <typename T>
+__global__ void dc_to_f32(int Vc, int n2, const double2 *__restrict__ src, C<T> *__restrict__ dst) {
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t n = (size_t)Vc * 9 * n2 * n2;
+    if (e < n) dst[e] = mk<T>((T)src[e].x, (T)src[e].y);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+int transfer_setup(Ctx *c, const int *agg, int N) {
+    Level1 &L1 = c->c;
+    const Geom &g = c->g;
+    for (int m = 0; m < 4; m++)
+        if (agg[m] <= 0 || g.L[m] % agg[m]) return fail(c, MGDD_ESHAPE, "aggregates must divide the lattice");
+    int Va = agg[0] * agg[1] * agg[2] * agg[3];
+    if (N <= 0 || N > 32) return fail(c, MGDD_EINVAL, "number of test vectors must be in 1..32");
+    if (N > 6 * Va) return fail(c, MGDD_ERANK, "more test vectors than dof per aggregate and chirality");
+    int Lc[4];
+    for (int m = 0; m < 4; m++) Lc[m] = g.L[m] / agg[m];
+    int Vc = Lc[0] * Lc[1] * Lc[2] * Lc[3];
+    bool same = L1.agg_sites && L1.N == N && L1.Vc == Vc;
+    for (int m = 0; m < 4 && same; m++) same = L1.agg[m] == agg[m];
+    if (same) return MGDD_OK;
+    // free the previous level
+    void *old[] = {L1.P64, L1.P32, L1.Dc64, L1.Dc32, L1.cnbr, L1.agg_sites, L1.site_agg, L1.tv64};
+    (void)hipStreamSynchronize(c->stream);
+    for (void *p : old) dfree(c, p);
+    L1 = Level1();
+    // tables: fine sites of each aggregate (local lexicographic order), aggregate of each site
+    std::vector<int> agg_sites((size_t)Vc * Va), site_agg(g.V), cnbr((size_t)Vc * 9);
+    std::vector<uint32_t> coord;
+    std::vector<int> bn;
+    Geom hg{};
+    int block[4] = {1 << g.lb[0], 1 << g.lb[1], 1 << g.lb[2], 1 << g.lb[3]};
+    geometry_tables(g.L, block, hg, coord, bn);
+    hg.blk_coord = coord.data();
+    hg.blk_nbr = bn.data();
+    std::vector<int> dev_of_lex(g.V);
+    for (int d = 0; d < g.V; d++) dev_of_lex[lex_of(hg, d)] = d;
+    for (int a = 0; a < Vc; a++) {
+        int t = a, ac[4];
+        for (int m = 0; m < 4; m++) { ac[m] = t % Lc[m]; t /= Lc[m]; }
+        int l = 0;
+        for (int x3 = 0; x3 < agg[3]; x3++)
+            for (int x2 = 0; x2 < agg[2]; x2++)
+                for (int x1 = 0; x1 < agg[1]; x1++)
+                    for (int x0 = 0; x0 < agg[0]; x0++) {
+                        int X[4] = {ac[0] * agg[0] + x0, ac[1] * agg[1] + x1, ac[2] * agg[2] + x2, ac[3] * agg[3] + x3};
+                        int s = X[0] + g.L[0] * (X[1] + g.L[1] * (X[2] + g.L[2] * X[3]));
+                        int d = dev_of_lex[s];
+                        agg_sites[(size_t)a * Va + l++] = d;
+                        site_agg[d] = a;
+                    }
+        cnbr[(size_t)a * 9] = a;
+        for (int m = 0; m < 4; m++)
+            for (int dir = 0; dir < 2; dir++) {
+                int y[4] = {ac[0], ac[1], ac[2], ac[3]};
+                y[m] = (y[m] + (dir == 0 ? 1 : -1) + Lc[m]) % Lc[m];
+                cnbr[(size_t)a * 9 + 1 + 2 * m + dir] = y[0] + Lc[0] * (y[1] + Lc[1] * (y[2] + Lc[2] * y[3]));
+            }
+    }
+    size_t fsz = (size_t)N * 12 * g.V;
+    size_t dsz = (size_t)Vc * 9 * 4 * N * N;
+    L1.P64 = dalloc(c, fsz * 16);
+    L1.tv64 = dalloc(c, fsz * 16);
+    L1.P32 = dalloc(c, fsz * 8);
+    L1.Dc64 = dalloc(c, dsz * 16);
+    L1.Dc32 = dalloc(c, dsz * 8);
+    L1.cnbr = (int *)dalloc(c, cnbr.size() * sizeof(int));
+    L1.agg_sites = (int *)dalloc(c, agg_sites.size() * sizeof(int));
+    L1.site_agg = (int *)dalloc(c, site_agg.size() * sizeof(int));
+    if (!L1.P64 || !L1.tv64 || !L1.P32 || !L1.Dc64 || !L1.Dc32 || !L1.cnbr || !L1.agg_sites || !L1.site_agg) return MGDD_ENOMEM;
+    int rc = hip_check(c, hipMemcpy(L1.cnbr, cnbr.data(), cnbr.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+    if (!rc) rc = hip_check(c, hipMemcpy(L1.agg_sites, agg_sites.data(), agg_sites.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+    if (!rc) rc = hip_check(c, hipMemcpy(L1.site_agg, site_agg.data(), site_agg.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+    if (rc) return rc;
+    for (int m = 0; m < 4; m++) { L1.agg[m] = agg[m]; L1.Lc[m] = Lc[m]; }
+    L1.Vc = Vc;
+    L1.Va = Va;
+    L1.N = N;
+    return MGDD_OK;
+}
+
+int launch_build_P(Ctx *c, const void *tv64) {
+    Level1 &L1 = c->c;
+    const Geom &g = c->g;
+    size_t fsz = (size_t)L1.N * 12 * g.V;
+    int rc = hip_check(c, hipMemcpyAsync(L1.P64, tv64, fsz * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+    if (!rc && tv64 != L1.tv64)
+        rc = hip_check(c, hipMemcpyAsync(L1.tv64, tv64, fsz * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+    if (rc) return rc;
+    int *flag = (int *)ensure_scratch(c, sizeof(int));
+    if (!flag) return MGDD_ENOMEM;
+    rc = hip_check(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream), "memset");
+    if (rc) return rc;
+    build_P_kernel<<<dim3(L1.Vc, 2), TPB, 0, c->stream>>>(g.V, L1.Va, L1.N, L1.agg_sites, (double2 *)L1.P64, flag);
+    rc = hip_check(c, hipGetLastError(), "build_P kernel");
+    if (rc) return rc;
+    int hflag = 0;
+    rc = hip_check(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "copy");
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (rc) return rc;
+    if (hflag) return fail(c, MGDD_ERANK, "test vectors are rank deficient on some aggregate");
+    return launch_convert(c, MGDD_F64, MGDD_F32, fsz, L1.P64, L1.P32);
+}
+
+int launch_restrict_ex(Ctx *c, int prec, int nrhs, const void *P, const void *fine, void *out, size_t ostride,
+                       size_t rstride) {
+    const Level1 &L1 = c->c;
+    size_t lds = (size_t)(TPB / 64) * L1.N * 4 * (prec == MGDD_F64 ? 8 : 4);
+    dim3 grid(L1.Vc, nrhs);
+    if (prec == MGDD_F64)
+        restrict_kernel<double><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const double2 *)P,
+                                                               (const double2 *)fine, (double2 *)out, ostride, rstride);
+    else
+        restrict_kernel<float><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const float2 *)P,
+                                                              (const float2 *)fine, (float2 *)out, ostride, rstride);
+    return hip_check(c, hipGetLastError(), "restrict kernel");
+}
+
+int launch_restrict(Ctx *c, int prec, int nrhs, const void *fine, void *coarse) {
+    const Level1 &L1 = c->c;
+    size_t n2 = 2 * (size_t)L1.N;
+    return launch_restrict_ex(c, prec, nrhs, prec == MGDD_F64 ? L1.P64 : L1.P32, fine, coarse, n2, n2 * L1.Vc);
+}
+
+int launch_prolong(Ctx *c, int prec, int nrhs, const void *coarse, void *fine) {
+    const Level1 &L1 = c->c;
+    size_t n = (size_t)c->g.V * nrhs;
+    unsigned nwg = (unsigned)((n + TPB - 1) / TPB);
+    if (prec == MGDD_F64)
+        prolong_kernel<double><<<nwg, TPB, 0, c->stream>>>(c->g.V, L1.Vc, L1.N, L1.site_agg, (const double2 *)L1.P64,
+                                                           (const double2 *)coarse, (double2 *)fine, nrhs);
+    else
+        prolong_kernel<float><<<nwg, TPB, 0, c->stream>>>(c->g.V, L1.Vc, L1.N, L1.site_agg, (const float2 *)L1.P32,
+                                                          (const float2 *)coarse, (float2 *)fine, nrhs);
+    return hip_check(c, hipGetLastError(), "prolong kernel");
+}
+
+int launch_coarse_build(Ctx *c) {
+    Level1 &L1 = c->c;
+    const Geom &g = c->g;
+    const int N = L1.N, n2 = 2 * N;
+    double2 *W = (double2 *)ensure_scratch(c, (size_t)9 * 12 * g.V * 16);
+    if (!W) return MGDD_ENOMEM;
+    AggGeom ag{};
+    for (int m = 0; m < 4; m++) ag.a[m] = L1.agg[m];
+    unsigned nwg = (unsigned)((g.V + TPB - 1) / TPB);
+    const size_t blk = (size_t)n2 * n2;
+    for (int chi = 0; chi < 2; chi++)
+        for (int k = 0; k < N; k++) {
+            int j = chi * N + k;
+            dc_terms_kernel<<<nwg, TPB, 0, c->stream>>>(g, ag, (const double2 *)c->U64, (const double2 *)c->A64,
+                                                       (const double2 *)L1.P64 + (size_t)k * 12 * g.V, chi, W);
+            int rc = hip_check(c, hipGetLastError(), "D_c terms kernel");
+            if (rc) return rc;
+            // column j of the 9 blocks of every coarse site: out[a][dd][j][row]
+            rc = launch_restrict_ex(c, MGDD_F64, 9, L1.P64, W, (double2 *)L1.Dc64 + (size_t)j * n2, 9 * blk, blk);
+            if (rc) return rc;
+        }
+    size_t n = (size_t)L1.Vc * 9 * blk;
+    dc_to_f32<float><<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(L1.Vc, n2, (const double2 *)L1.Dc64,
+                                                                                       (float2 *)L1.Dc32);
+    return hip_check(c, hipGetLastError(), "D_c convert");
+}
+
+int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out) {
+    const Level1 &L1 = c->c;
+    dim3 grid(L1.Vc, nrhs);
+    if (prec == MGDD_F64)
+        coarse_apply_kernel<double><<<grid, 64, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,
+                                                                (const double2 *)in, (double2 *)out);
+    else
+        coarse_apply_kernel<float><<<grid, 64, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const float2 *)L1.Dc32,
+                                                               (const float2 *)in, (float2 *)out);
+    return hip_check(c, hipGetLastError(), "coarse apply kernel");
+}
+
+}  // namespace mgdd

@@ -54,7 +54,7 @@ _sig("mgdd_create", ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(c
 _sig("mgdd_destroy", ctypes.c_int, _vp)
 _sig("mgdd_last_error", ctypes.c_char_p, _vp)
 _sig("mgdd_field_bytes", ctypes.c_size_t, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int)
-_sig("mgdd_set_gauge", ctypes.c_int, _vp, _vp, ctypes.c_double, ctypes.c_double)
+_sig("mgdd_set_gauge", ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double)
 _sig("mgdd_pack", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp)
 _sig("mgdd_unpack", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
 _sig("mgdd_dirac_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
@@ -62,10 +62,45 @@ _sig("mgdd_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ct
      ctypes.c_double, _vp, _vp)
 
 
+class SetupParams(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_int * 4), ("ntv", ctypes.c_int), ("nu", ctypes.c_int), ("iota", ctypes.c_int),
+                ("mr_iters", ctypes.c_int), ("arnoldi_m", ctypes.c_int), ("n_part2", ctypes.c_int),
+                ("prec", ctypes.c_int)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("coarse_iters", ctypes.c_int),
+                ("nu", ctypes.c_int), ("mr_iters", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO = 0, 1, 2
+PLAIN_F64, MIXED = 0, 1
+
+_sig("mgdd_build_P", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp)
+_sig("mgdd_get_test_vectors", ctypes.c_int, _vp, _vp)
+_sig("mgdd_restrict", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_prolong", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_coarse_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_coarse_solve", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_precondition", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     _vp, _vp)
+_sig("mgdd_setup_bootstrap", ctypes.c_int, _vp, ctypes.POINTER(SetupParams), _vp, _vp)
+_sig("mgdd_solve", ctypes.c_int, _vp, ctypes.POINTER(SolveParams), ctypes.c_int, _vp, _vp, ctypes.POINTER(SolveStats))
+
+
 def declared_symbols() -> list[str]:
     """Names of the entry points declared in include/mgdd.h."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(mgdd_[a-z0-9_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(mgdd_[A-Za-z0-9_]+)\s*\(", txt)))
 
 
 def _ptr(x):
@@ -117,9 +152,13 @@ def mgdd_field_bytes(ctx, prec, nrhs, level=0) -> int:
     return int(_lib.mgdd_field_bytes(ctx, prec, nrhs, level))
 
 
-def mgdd_set_gauge(ctx, U: np.ndarray, m0: float, csw: float):
-    U = np.ascontiguousarray(U, dtype=np.complex128)
-    return _check(ctx, _lib.mgdd_set_gauge(ctx, _ptr(U), m0, csw))
+def mgdd_set_gauge(ctx, U, m0: float, csw: float):
+    """U: canonical complex128 [V,4,3,3] (numpy on the host) or the same bytes
+    as a float64 torch tensor on the device."""
+    on_dev = 0 if isinstance(U, np.ndarray) else 1
+    if on_dev == 0:
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+    return _check(ctx, _lib.mgdd_set_gauge(ctx, _ptr(U), on_dev, m0, csw))
 
 
 def mgdd_pack(ctx, prec, nrhs, src, dst):
@@ -142,6 +181,47 @@ def mgdd_dirac_apply(ctx, prec, nrhs, x, y):
 def mgdd_sap(ctx, prec, nrhs, nsweeps, mr_iters, shift, b, z):
     shift = complex(shift)
     return _check(ctx, _lib.mgdd_sap(ctx, prec, nrhs, nsweeps, mr_iters, shift.real, shift.imag, _ptr(b), _ptr(z)))
+
+
+def mgdd_build_P(ctx, agg, ntv, test_vectors):
+    return _check(ctx, _lib.mgdd_build_P(ctx, _i4(*agg), ntv, _ptr(test_vectors)))
+
+
+def mgdd_get_test_vectors(ctx, dst):
+    return _check(ctx, _lib.mgdd_get_test_vectors(ctx, _ptr(dst)))
+
+
+def mgdd_restrict(ctx, prec, nrhs, fine, coarse):
+    return _check(ctx, _lib.mgdd_restrict(ctx, prec, nrhs, _ptr(fine), _ptr(coarse)))
+
+
+def mgdd_prolong(ctx, prec, nrhs, coarse, fine):
+    return _check(ctx, _lib.mgdd_prolong(ctx, prec, nrhs, _ptr(coarse), _ptr(fine)))
+
+
+def mgdd_coarse_apply(ctx, prec, nrhs, x, y):
+    return _check(ctx, _lib.mgdd_coarse_apply(ctx, prec, nrhs, _ptr(x), _ptr(y)))
+
+
+def mgdd_coarse_solve(ctx, prec, nrhs, iters, b, x):
+    return _check(ctx, _lib.mgdd_coarse_solve(ctx, prec, nrhs, iters, _ptr(b), _ptr(x)))
+
+
+def mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, r, z):
+    return _check(ctx, _lib.mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, _ptr(r), _ptr(z)))
+
+
+def mgdd_setup_bootstrap(ctx, params: SetupParams, random_vectors, arnoldi_start):
+    return _check(ctx, _lib.mgdd_setup_bootstrap(ctx, ctypes.byref(params), _ptr(random_vectors), _ptr(arnoldi_start)))
+
+
+def mgdd_solve(ctx, params: SolveParams, nrhs, b, z, allow_noconv=False):
+    """Returns a list of SolveStats (one per right-hand side)."""
+    stats = (SolveStats * nrhs)()
+    rc = _lib.mgdd_solve(ctx, ctypes.byref(params), nrhs, _ptr(b), _ptr(z), stats)
+    if not (rc == ENOCONV and allow_noconv):
+        _check(ctx, rc)
+    return [stats[i] for i in range(nrhs)]
 
 
 # --------------------------------------------------------------------- convenience wrapper
@@ -204,3 +284,63 @@ class Lattice:
     def sap(self, b, z, nsweeps, mr_iters, shift=0.0):
         mgdd_sap(self.ctx, self.prec_of(b), b.shape[0], nsweeps, mr_iters, shift, b, z)
         return z
+
+    # coarse level -------------------------------------------------------
+    def build_P(self, agg, test_vectors):
+        """test_vectors: (N, 12, V, 2) float64 device tensor."""
+        mgdd_build_P(self.ctx, agg, test_vectors.shape[0], test_vectors)
+        self.agg = tuple(agg)
+        self.N = test_vectors.shape[0]
+        self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
+        self.Vc = int(np.prod(self.cdims))
+
+    def coarse_field(self, prec=F64, nrhs=1):
+        t = self.torch
+        dt = t.float64 if prec == F64 else t.float32
+        return t.zeros((nrhs, self.Vc, 2, self.N, 2), dtype=dt, device="cuda")
+
+    def restrict(self, f, c=None):
+        c = self.coarse_field(self.prec_of(f), f.shape[0]) if c is None else c
+        mgdd_restrict(self.ctx, self.prec_of(f), f.shape[0], f, c)
+        return c
+
+    def prolong(self, c, f=None):
+        f = self.field(self.prec_of(c), c.shape[0]) if f is None else f
+        mgdd_prolong(self.ctx, self.prec_of(c), c.shape[0], c, f)
+        return f
+
+    def coarse_apply(self, x, y=None):
+        y = self.torch.empty_like(x) if y is None else y
+        mgdd_coarse_apply(self.ctx, self.prec_of(x), x.shape[0], x, y)
+        return y
+
+    def coarse_solve(self, b, iters=12, x=None):
+        x = self.torch.empty_like(b) if x is None else x
+        mgdd_coarse_solve(self.ctx, self.prec_of(b), b.shape[0], iters, b, x)
+        return x
+
+    def precondition(self, r, prec=F64, nu=1, mr_iters=4, coarse_iters=12):
+        z = self.field(prec, r.shape[0])
+        mgdd_precondition(self.ctx, prec, r.shape[0], nu, mr_iters, coarse_iters, r, z)
+        return z
+
+    def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64):
+        N = random_vectors.shape[0]
+        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, arnoldi_m, n_part2, prec)
+        mgdd_setup_bootstrap(self.ctx, sp, random_vectors, arnoldi_start)
+        self.agg = tuple(agg)
+        self.N = N
+        self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
+        self.Vc = int(np.prod(self.cdims))
+
+    def test_vectors(self):
+        out = self.field(F64, self.N)
+        mgdd_get_test_vectors(self.ctx, out)
+        return out
+
+    def solve(self, b, z=None, solver=SOLVER_FGMRES_MG, precision=PLAIN_F64, restart=20, tol=1e-10, maxit=1000,
+              coarse_iters=12, nu=1, mr_iters=4, allow_noconv=False):
+        z = self.torch.zeros_like(b) if z is None else z
+        sp = SolveParams(solver, precision, restart, tol, maxit, coarse_iters, nu, mr_iters)
+        stats = mgdd_solve(self.ctx, sp, b.shape[0], b, z, allow_noconv=allow_noconv)
+        return z, stats

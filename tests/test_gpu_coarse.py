@@ -1,0 +1,120 @@
+"""GPU parity of the aggregation interpolation, restriction, prolongation,
+coarse operator, coarse GMRES and two-level preconditioner (through the C ABI)
+against the oracle."""
+import numpy as np
+import pytest
+
+import latgen
+import oracle
+from gpu_common import TOL32, TOL64, lattice, problem, rel, say
+from oracle import solvers
+
+pytestmark = pytest.mark.gpu
+
+# (lattice, SAP block, aggregate, N): coarse extents 2 (the +/- neighbours
+# coincide), 1 and 2 mixed, and 4
+CASES = [
+    ((8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 4, 4), 8),
+    ((8, 8, 4, 8), (4, 4, 4, 4), (4, 4, 4, 2), 6),
+    ((8, 8, 8, 8), (4, 4, 4, 4), (2, 2, 2, 2), 4),
+]
+
+
+def to_np_coarse(t):
+    a = t.detach().cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def to_dev_coarse(lat, c, prec):
+    import torch
+    from paper_1202_2462_amd.mgdd import F64
+    arr = np.stack([c.real, c.imag], axis=-1)
+    return torch.tensor(arr, dtype=torch.float64 if prec == F64 else torch.float32, device="cuda")
+
+
+def setup(dims, block, agg, N, seed=3):
+    from paper_1202_2462_amd.mgdd import F64
+    op = problem(dims, seed=seed, m0=0.1)
+    lat = lattice(op, block)
+    tv = latgen.gaussian_fields(dims, N, seed + 40)
+    lat.build_P(agg, lat.pack(tv, F64))
+    tl = solvers.TwoLevel(op, agg, tv, block, mr_iters=4)
+    return op, lat, tl, tv
+
+
+@pytest.mark.parametrize("dims,block,agg,N", CASES)
+def test_transfer_parity(dims, block, agg, N):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("transfer parity", dims, agg, N)
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    f = latgen.gaussian_fields(dims, 2, 5)
+    Vc = lat.Vc
+    c = latgen.gaussian_vector(2 * Vc * 2 * N, 6).reshape(2, Vc, 2, N)
+    want_r = np.stack([tl.restrict(f[i]) for i in range(2)])
+    want_p = np.stack([tl.prolong(c[i]) for i in range(2)])
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        got_r = to_np_coarse(lat.restrict(lat.pack(f, prec)))
+        assert rel(got_r, want_r) < tol, (prec, rel(got_r, want_r))
+        got_p = lat.unpack(lat.prolong(to_dev_coarse(lat, c, prec)))
+        assert rel(got_p, want_p) < tol, (prec, rel(got_p, want_p))
+    # the test vectors define P: P P^H v = v on the GPU too
+    v = lat.pack(tv[:2], F64)
+    back = lat.unpack(lat.prolong(lat.restrict(v)))
+    assert rel(back, tv[:2]) < 1e-12
+    # stored test vectors come back unchanged
+    assert np.array_equal(lat.unpack(lat.test_vectors()), tv)
+
+
+@pytest.mark.parametrize("dims,block,agg,N", CASES)
+def test_coarse_operator_parity(dims, block, agg, N):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("coarse operator parity", dims, agg, N)
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    Vc = lat.Vc
+    x = latgen.gaussian_vector(3 * Vc * 2 * N, 8).reshape(3, Vc, 2, N)
+    want = np.stack([tl.coarse_apply(x[i]) for i in range(3)])
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        got = to_np_coarse(lat.coarse_apply(to_dev_coarse(lat, x, prec)))
+        assert rel(got, want) < tol, (prec, rel(got, want))
+
+
+@pytest.mark.parametrize("dims,block,agg,N", CASES[:2])
+def test_coarse_gmres_parity(dims, block, agg, N):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("coarse gmres parity", dims, agg, N)
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    Vc = lat.Vc
+    b = latgen.gaussian_vector(2 * Vc * 2 * N, 9).reshape(2, Vc, 2, N)
+    want = np.stack([solvers.gmres_fixed(tl.coarse_apply, b[i], 12) for i in range(2)])
+    for prec, tol in ((F64, 1e-10), (F32, 1e-4)):
+        got = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, b, prec), 12))
+        assert rel(got, want) < tol, (prec, rel(got, want))
+    # zero right-hand side gives zero
+    z = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, 0 * b, F64), 12))
+    assert np.all(z == 0)
+
+
+@pytest.mark.parametrize("dims,block,agg,N", CASES[:2])
+def test_preconditioner_parity(dims, block, agg, N):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("preconditioner parity", dims, agg, N)
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    r = latgen.gaussian_fields(dims, 1, 10)
+    want = tl.precond(r[0])
+    r64 = lat.pack(r, F64)
+    for prec, tol in ((F64, 1e-10), (F32, 1e-4)):
+        got = lat.unpack(lat.precondition(r64, prec=prec))[0]
+        assert rel(got, want) < tol, (prec, rel(got, want))
+
+
+def test_rank_deficient_test_vectors_rejected():
+    from paper_1202_2462_amd.mgdd import ERANK, F64, MgddError
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    say("rank deficiency")
+    op = problem(dims)
+    lat = lattice(op, block)
+    tv = latgen.gaussian_fields(dims, 4, 1)
+    tv[3] = tv[1] * (2 - 1j)
+    with pytest.raises(MgddError) as e:
+        lat.build_P((4, 4, 4, 4), lat.pack(tv, F64))
+    assert e.value.code == ERANK

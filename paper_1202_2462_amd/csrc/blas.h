@@ -17,6 +17,8 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
                  double beta, void *y);
 // y = (coef ? coef[0] * alpha : alpha) x   (x and y may alias)
 int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y);
+// y = x / sqrt(re nrm2[0]) (y = 0 when that is 0); x and y may alias
+int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y);
 // coef[0] = 1/sqrt(re v[0])
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef);
 

@@ -3,7 +3,7 @@
 // combinations y = beta y + alpha sum_i c_i x_i with the coefficients read
 // from device memory (so that Gram-Schmidt needs no host round trip), and
 // scaling. Reductions are deterministic: a fixed grid for a given length, a
-// fixed butterfly inside each wave, per-workgroup partials summed in index
+// fixed butterfly inside each wave, per-workgroup partials summed in a fixed
 // order by a second kernel. Sums are accumulated in double.
 #include "blas.h"
 
@@ -26,7 +26,11 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// part[i * nwg + blockIdx.x] = sum over this workgroup's elements of conj(x_i) w
+// part[i * nwg + wg] = sum over the elements of workgroup wg of conj(x_i) w.
+// (A single-kernel variant in which the last workgroup adds the partials
+// needs a device-scope release by every workgroup, which writes back L2 on
+// every XCD and made the kernel five times slower; a second small kernel
+// adds the partials instead.)
 template <typename TX, typename TW, int NV>
 __global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PtrList xs, int nvec, const C<TW> *__restrict__ w,
                                                        double2 *__restrict__ part) {
@@ -63,20 +67,19 @@ __global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PtrList xs, int
     }
 }
 
-// out[i] = sum_k part[i * nwg + k] (fixed order), optionally plus add[i]
-__global__ void finish_kernel(int nvec, int nwg, const double2 *__restrict__ part, double2 *__restrict__ out) {
-    int i = blockIdx.x;
-    __shared__ double sa[64], sb[64];
+// out[i] = sum_k part[i * nwg + k]: one 64-lane wave per i, lane l adding the
+// partials k = l, l + 64, ... in order, then a butterfly.
+__global__ __launch_bounds__(64) void finish_kernel(int nwg, const double2 *__restrict__ part, double2 *__restrict__ out) {
+    const int i = blockIdx.x, lane = threadIdx.x;
     double a = 0, b = 0;
-    for (int k = threadIdx.x; k < nwg; k += 64) { a += part[(size_t)i * nwg + k].x; b += part[(size_t)i * nwg + k].y; }
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double A = 0, B = 0;
-        for (int k = 0; k < 64; k++) { A += sa[k]; B += sb[k]; }
-        out[i] = make_double2(A, B);
+    for (int k = lane; k < nwg; k += 64) {
+        double2 v = part[(size_t)i * nwg + k];
+        a += v.x;
+        b += v.y;
     }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) out[i] = make_double2(a, b);
 }
 
 // y = beta y + alpha sum_i coef[i] x_i
@@ -104,11 +107,19 @@ __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int 
     }
 }
 
-// y = s * x, s = alpha * coef[0] (device) or alpha when coef == nullptr; x and y may alias
+// y = s * x with s = alpha * coef[0] (coef on the device), or
+// s = alpha / sqrt(re nrm2[0]) (0 when that is 0) when inv_norm, or s = alpha
+// when coef == nullptr; x and y may alias
 template <typename TX, typename TY>
 __global__ __launch_bounds__(TPB) void scale_kernel(size_t n, const C<TX> *x, const double2 *__restrict__ coef,
-                                                    double2 alpha, C<TY> *y) {
-    double2 s = coef ? cmul(coef[0], alpha) : alpha;
+                                                    double2 alpha, int inv_norm, C<TY> *y) {
+    double2 s = alpha;
+    if (coef && inv_norm) {
+        double nn = sqrt(coef[0].x);
+        s = nn > 0 ? cscale(alpha, 1.0 / nn) : make_double2(0, 0);
+    } else if (coef) {
+        s = cmul(coef[0], alpha);
+    }
     const size_t stride = (size_t)gridDim.x * TPB;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
         C<TX> xv = x[e];
@@ -145,7 +156,7 @@ int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int n
         else if (px == MGDD_F32 && pw == MGDD_F64) MD(float, double);
         else MD(double, float);
 #undef MD
-        finish_kernel<<<nv, 64, 0, c->stream>>>(nv, nwg, part, out + i0);
+        finish_kernel<<<nv, 64, 0, c->stream>>>(nwg, part, out + i0);
         int rc = hip_check(c, hipGetLastError(), "multidot");
         if (rc) return rc;
     }
@@ -180,17 +191,26 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
     return MGDD_OK;
 }
 
-int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y) {
+static int scale_launch(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha,
+                        int inv_norm, void *y) {
     int nwg = lin_grid(n);
     if (px == MGDD_F64 && py == MGDD_F64)
-        scale_kernel<double, double><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, (double2 *)y);
+        scale_kernel<double, double><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, inv_norm, (double2 *)y);
     else if (px == MGDD_F32 && py == MGDD_F32)
-        scale_kernel<float, float><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, (float2 *)y);
+        scale_kernel<float, float><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, inv_norm, (float2 *)y);
     else if (px == MGDD_F64)
-        scale_kernel<double, float><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, (float2 *)y);
+        scale_kernel<double, float><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, inv_norm, (float2 *)y);
     else
-        scale_kernel<float, double><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, (double2 *)y);
+        scale_kernel<float, double><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, inv_norm, (double2 *)y);
     return hip_check(c, hipGetLastError(), "scale");
+}
+
+int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y) {
+    return scale_launch(c, px, py, n, x, coef, alpha, 0, y);
+}
+
+int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y) {
+    return scale_launch(c, px, py, n, x, nrm2, make_double2(1, 0), 1, y);
 }
 
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef) {

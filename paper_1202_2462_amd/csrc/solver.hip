@@ -137,8 +137,7 @@ static int mgs_device(Ctx *c, int p, size_t n, void *const *X, int nv, double2 *
         }
         const void *xk = X[k];
         int rc = blas_multidot(c, p, p, n, &xk, 1, X[k], scal);
-        if (!rc) rc = blas_rsqrt(c, scal, scal + 1);
-        if (!rc) rc = blas_scale(c, p, p, n, X[k], scal + 1, make_double2(1, 0), X[k]);
+        if (!rc) rc = blas_normalize(c, p, p, n, X[k], scal, X[k]);
         if (rc) return rc;
     }
     return MGDD_OK;
@@ -165,13 +164,11 @@ int coarse_gmres(Ctx *c, int p, int m, const void *b, void *x, Arena &A) {
     if (!coef) return fail(c, MGDD_ENOMEM, "coarse GMRES workspace");
     const void *bp = b;
     int rc = blas_multidot(c, p, p, n, &bp, 1, b, nr);
-    if (!rc) rc = blas_rsqrt(c, nr, coef);
-    if (!rc) rc = blas_scale(c, p, p, n, b, coef, make_double2(1, 0), V[0]);
+    if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0]);
     for (int j = 0; j < m && !rc; j++) {
         rc = launch_coarse_apply(c, p, 1, V[j], w);
         if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1), h2 + (size_t)j * (m + 1), nr + j + 1);
-        if (!rc) rc = blas_rsqrt(c, nr + j + 1, coef + j + 1);
-        if (!rc) rc = blas_scale(c, p, p, n, w, coef + j + 1, make_double2(1, 0), V[j + 1]);
+        if (!rc) rc = blas_normalize(c, p, p, n, w, nr + j + 1, V[j + 1]);
     }
     if (rc) return rc;
     const size_t hs = (size_t)(m + 1) * (m + 1);
@@ -398,9 +395,8 @@ static int gcr_core(Ctx *c, const GcrOp &op, size_t n, int m, const void *rhs, v
             }
             const void *qi = Q[i];
             if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &qi, 1, Q[i], sc);
-            if (!rc) rc = blas_rsqrt(c, sc, sc + 1);
-            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, Q[i], sc + 1, make_double2(1, 0), Q[i]);
-            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, P[i], sc + 1, make_double2(1, 0), P[i]);
+            if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, n, P[i], sc, P[i]);
+            if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, n, Q[i], sc, Q[i]);
             if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &qi, 1, r, sc + 2);   // alpha = <q, r>
             const void *pi = P[i];
             if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &pi, 1, sc + 2, 1.0, 1.0, x);
@@ -525,13 +521,11 @@ static int arnoldi_host(Ctx *c, int m, const void *v0, std::vector<void *> &Qv, 
     if (!Qv[m]) return fail(c, MGDD_ENOMEM, "Arnoldi workspace");
     const void *vp = v0;
     int rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &vp, 1, v0, nr);
-    if (!rc) rc = blas_rsqrt(c, nr, coef);
-    if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, v0, coef, make_double2(1, 0), Qv[0]);
+    if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, n, v0, nr, Qv[0]);
     for (int j = 0; j < m && !rc; j++) {
         rc = launch_coarse_apply(c, MGDD_F64, 1, Qv[j], w);
         if (!rc) rc = cgs2(c, MGDD_F64, n, Qv.data(), j + 1, w, h1 + (size_t)j * (m + 1), h2 + (size_t)j * (m + 1), nr + j + 1);
-        if (!rc) rc = blas_rsqrt(c, nr + j + 1, coef + j + 1);
-        if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, w, coef + j + 1, make_double2(1, 0), Qv[j + 1]);
+        if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, n, w, nr + j + 1, Qv[j + 1]);
     }
     if (rc) return rc;
     const size_t hs = (size_t)(m + 1) * (m + 1);
@@ -640,8 +634,7 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
             rc = blas_lincomb(c, MGDD_F64, MGDD_F64, nc, Qv.data(), k, ydev + (size_t)i * k, 1.0, 0.0, phi[i]);
             const void *pp = phi[i];
             if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, nc, &pp, 1, phi[i], scal);
-            if (!rc) rc = blas_rsqrt(c, scal, scal + 1);
-            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, nc, phi[i], scal + 1, make_double2(1, 0), phi[i]);
+            if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, nc, phi[i], scal, phi[i]);
             if (!rc) rc = launch_prolong(c, MGDD_F64, 1, phi[i], W[i]);
             cd lam = th[order[i]];
             if (p == MGDD_F32) {

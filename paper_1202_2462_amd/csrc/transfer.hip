@@ -104,6 +104,14 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
     const size_t fs = (size_t)12 * V;
     const C<T> *fr = f + (size_t)r * fs;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // one site per thread when Va <= blockDim (the field values stay in registers)
+    C<T> f0[12];
+    const bool one = Va <= (int)blockDim.x;
+    if (one) {
+        int d = threadIdx.x < Va ? sites[threadIdx.x] : 0;
+#pragma unroll
+        for (int c = 0; c < 12; c++) f0[c] = threadIdx.x < Va ? fr[(size_t)c * V + d] : mk<T>(0, 0);
+    }
     for (int k = 0; k < N; k++) {
         const C<T> *pk = P + (size_t)k * fs;
         T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
@@ -111,7 +119,7 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
             int d = sites[l];
 #pragma unroll
             for (int c = 0; c < 12; c++) {
-                C<T> pv = pk[(size_t)c * V + d], fv = fr[(size_t)c * V + d];
+                C<T> pv = pk[(size_t)c * V + d], fv = one ? f0[c] : fr[(size_t)c * V + d];
                 T re = pv.x * fv.x + pv.y * fv.y, im = pv.x * fv.y - pv.y * fv.x;
                 if (c < 6) { p0 += re; p1 += im; } else { p2 += re; p3 += im; }
             }
@@ -232,30 +240,175 @@ __global__ __launch_bounds__(TPB) void dc_terms_kernel(Geom g, AggGeom ag, const
     for (int c = 0; c < 12; c++) w0.st(c, d, csub(ap[c], cscale(self[c], 0.5)));
 }
 
-// ---------------------------------------------------------------- coarse stencil y = D_c x
-//
-// One 64-lane workgroup per (coarse site, right-hand side); lane i < 2N forms
-// row i. Blocks are stored column-major, B[a][dir][col][row], so that the
-// lanes read consecutive rows of one column.
-template <typename T>
-__global__ __launch_bounds__(64) void coarse_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
-                                                          const C<T> *__restrict__ Dc, const C<T> *__restrict__ x,
-                                                          C<T> *__restrict__ y) {
-    const int a = blockIdx.x, r = blockIdx.y, i = threadIdx.x;
+// One workgroup per (aggregate a, column j = (chi', k')), one thread per
+// site x of a: the thread forms the 9 terms of D applied to the prolonged unit
+// vector P e_j at x (self term: clover plus the hops that stay in a; one face
+// term per direction, nonzero on that face only), then projects all 9 on every
+// P_k(x) of both chiralities in one pass over P. Wave butterflies and one LDS
+// exchange sum over the sites. Block layout [a][dir][col][row].
+template <int MU, bool FWD>
+__device__ inline void term_hop(const LinkViews<double> &U, const FieldView<double> &pj, int chi, int d, int dn,
+                                double2 *acc) {
+    double2 psi[12], u[9];
+    load_spinor<double>(pj, dn, psi);
+#pragma unroll
+    for (int c = 0; c < 12; c++)
+        if ((c >= 6) != (chi != 0)) psi[c] = make_double2(0, 0);
+    load_link<double, MU>(U, FWD ? d : dn, u);
+    hop<double, MU, FWD>(acc, u, psi);
+}
+
+// the hop of one direction: into the face term when it leaves the aggregate
+// (scaled by -1/2), else added to the self sum
+template <int MU, bool FWD>
+__device__ inline void term_into(const LinkViews<double> &U, const FieldView<double> &pj, int chi, int d, int dn,
+                                 bool crosses, double2 *self, double2 *face) {
+    double2 t[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) t[c] = make_double2(0, 0);
+    term_hop<MU, FWD>(U, pj, chi, d, dn, t);
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        face[c] = crosses ? cscale(t[c], -0.5) : make_double2(0, 0);
+        self[c] = crosses ? self[c] : cadd(self[c], t[c]);
+    }
+}
+
+__global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N, int Va, const int *__restrict__ agg_sites,
+                                                       const double2 *__restrict__ Up, const double2 *__restrict__ Ap,
+                                                       const double2 *__restrict__ P, double2 *__restrict__ Dc,
+                                                       int nwg) {
+    extern __shared__ double dred[];  // [waves][N][9][4]
     const int n2 = 2 * N;
-    __shared__ C<T> xs[9][64];
-    const C<T> *xr = x + (size_t)r * Vc * n2;
-    for (int dd = 0; dd < 9; dd++) {
-        int b = cnbr[a * 9 + dd];
-        if (i < n2) xs[dd][i] = xr[(size_t)b * n2 + i];
+    const int w = xcd_block(nwg);
+    const int a = w / n2, j = w % n2, chi = j / N, kk = j % N;
+    const size_t V = g.V;
+    const int l = threadIdx.x;
+    const bool active = l < Va;
+    double2 wt[9][12];
+#pragma unroll
+    for (int t = 0; t < 9; t++)
+#pragma unroll
+        for (int c = 0; c < 12; c++) wt[t][c] = make_double2(0, 0);
+    int d = 0;
+    if (active) {
+        d = agg_sites[(size_t)a * Va + l];
+        int X[4], nbr[8];
+        site_coords(g, d, X);
+        site_neighbours(g, d, nbr);
+        LinkViews<double> U(Up, V);
+        CloverViews<double> A(Ap, V);
+        FieldView<double> pj(P + (size_t)kk * 12 * V, V, 12);
+        double2 self[12];
+#pragma unroll
+        for (int c = 0; c < 12; c++) self[c] = make_double2(0, 0);
+        bool last[4], first[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            int r = X[m] % ag.a[m];
+            last[m] = r == ag.a[m] - 1;   // the +m hop leaves the aggregate
+            first[m] = r == 0;            // the -m hop leaves the aggregate
+        }
+        term_into<0, true>(U, pj, chi, d, nbr[0], last[0], self, wt[1]);
+        term_into<0, false>(U, pj, chi, d, nbr[1], first[0], self, wt[2]);
+        term_into<1, true>(U, pj, chi, d, nbr[2], last[1], self, wt[3]);
+        term_into<1, false>(U, pj, chi, d, nbr[3], first[1], self, wt[4]);
+        term_into<2, true>(U, pj, chi, d, nbr[4], last[2], self, wt[5]);
+        term_into<2, false>(U, pj, chi, d, nbr[5], first[2], self, wt[6]);
+        term_into<3, true>(U, pj, chi, d, nbr[6], last[3], self, wt[7]);
+        term_into<3, false>(U, pj, chi, d, nbr[7], first[3], self, wt[8]);
+        double2 psi[12], ap[12];
+        load_spinor<double>(pj, d, psi);
+#pragma unroll
+        for (int c = 0; c < 12; c++)
+            if ((c >= 6) != (chi != 0)) psi[c] = make_double2(0, 0);
+        clover_mv<double>(A, d, psi, ap);
+#pragma unroll
+        for (int c = 0; c < 12; c++) wt[0][c] = csub(ap[c], cscale(self[c], 0.5));
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k < N; k++) {
+        double2 pk[12];
+        if (active) {
+            FieldView<double> fk(P + (size_t)k * 12 * V, V, 12);
+            load_spinor<double>(fk, d, pk);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; c++) pk[c] = make_double2(0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; t++) {
+            double p[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                double re = pk[c].x * wt[t][c].x + pk[c].y * wt[t][c].y;
+                double im = pk[c].x * wt[t][c].y - pk[c].y * wt[t][c].x;
+                p[c < 6 ? 0 : 2] += re;
+                p[c < 6 ? 1 : 3] += im;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) p[q] = wsum(p[q]);
+            if (lane == 0) {
+                double *o = dred + (((size_t)wv * N + k) * 9 + t) * 4;
+                o[0] = p[0]; o[1] = p[1]; o[2] = p[2]; o[3] = p[3];
+            }
+        }
     }
     __syncthreads();
-    if (i >= n2) return;
-    C<T> acc = mk<T>(0, 0);
-    const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
-    for (int dd = 0; dd < 9; dd++)
-        for (int j = 0; j < n2; j++) cfma(acc, B[((size_t)dd * n2 + j) * n2 + i], xs[dd][j]);
-    y[((size_t)r * Vc + a) * n2 + i] = acc;
+    const int nw = blockDim.x >> 6;
+    const size_t blk = (size_t)n2 * n2;
+    for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
+        int t = e / n2, i = e % n2;
+        int rchi = i / N, k = i % N;
+        double re = 0, im = 0;
+        for (int q = 0; q < nw; q++) {
+            const double *o = dred + (((size_t)q * N + k) * 9 + t) * 4;
+            re += o[2 * rchi];
+            im += o[2 * rchi + 1];
+        }
+        Dc[((size_t)a * 9 + t) * blk + (size_t)j * n2 + i] = make_double2(re, im);
+    }
+}
+
+// ---------------------------------------------------------------- coarse stencil y = D_c x
+//
+// One workgroup of 256 threads per (coarse site, right-hand side): wave q
+// handles the directions q, q+4, q+8 and lane i < 2N forms row i of their
+// products; the four partial rows are added in wave order through LDS. Blocks
+// are stored column-major, B[a][dir][col][row], so the lanes of a wave read
+// consecutive rows of one column.
+template <typename T>
+__global__ __launch_bounds__(256) void coarse_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
+                                                           const C<T> *__restrict__ Dc, const C<T> *__restrict__ x,
+                                                           C<T> *__restrict__ y) {
+    const int a = blockIdx.x, r = blockIdx.y;
+    const int n2 = 2 * N;
+    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
+    __shared__ C<T> xs[9][64];
+    __shared__ C<T> part[4][64];
+    const C<T> *xr = x + (size_t)r * Vc * n2;
+    for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
+        int dd = e / n2, j = e % n2;
+        xs[dd][j] = xr[(size_t)cnbr[a * 9 + dd] * n2 + j];
+    }
+    __syncthreads();
+    C<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+    if (i < n2) {
+        const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
+        for (int dd = q; dd < 9; dd += 4) {
+            const C<T> *Bd = B + (size_t)dd * n2 * n2 + i;
+            int j = 0;
+            for (; j + 1 < n2; j += 2) {
+                cfma(acc0, Bd[(size_t)j * n2], xs[dd][j]);
+                cfma(acc1, Bd[(size_t)(j + 1) * n2], xs[dd][j + 1]);
+            }
+            if (j < n2) cfma(acc0, Bd[(size_t)j * n2], xs[dd][j]);
+        }
+    }
+    part[q][i] = cadd(acc0, acc1);
+    __syncthreads();
+    if (q == 0 && i < n2)
+        y[((size_t)r * Vc + a) * n2 + i] = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
 }
 
 template <typename T>
@@ -403,6 +556,24 @@ int launch_coarse_build(Ctx *c) {
     Level1 &L1 = c->c;
     const Geom &g = c->g;
     const int N = L1.N, n2 = 2 * N;
+    if (L1.Va <= 256) {
+        AggGeom ag{};
+        for (int m = 0; m < 4; m++) ag.a[m] = L1.agg[m];
+        int threads = ((L1.Va + 63) / 64) * 64;
+        int nwg = L1.Vc * n2;
+        size_t lds = (size_t)(threads / 64) * N * 9 * 4 * sizeof(double);
+        dc_build_kernel<<<nwg, threads, lds, c->stream>>>(g, ag, N, L1.Va, L1.agg_sites, (const double2 *)c->U64,
+                                                           (const double2 *)c->A64, (const double2 *)L1.P64,
+                                                           (double2 *)L1.Dc64, nwg);
+        int rc = hip_check(c, hipGetLastError(), "D_c build kernel");
+        if (rc) return rc;
+        size_t n = (size_t)L1.Vc * 9 * n2 * n2;
+        dc_to_f32<float><<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(L1.Vc, n2, (const double2 *)L1.Dc64,
+                                                                            (float2 *)L1.Dc32);
+        return hip_check(c, hipGetLastError(), "D_c convert");
+    }
+    // aggregates of more than 256 sites: terms of each column as 9 fine
+    // fields, then a restriction of those fields
     double2 *W = (double2 *)ensure_scratch(c, (size_t)9 * 12 * g.V * 16);
     if (!W) return MGDD_ENOMEM;
     AggGeom ag{};
@@ -430,10 +601,10 @@ int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     const Level1 &L1 = c->c;
     dim3 grid(L1.Vc, nrhs);
     if (prec == MGDD_F64)
-        coarse_apply_kernel<double><<<grid, 64, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,
+        coarse_apply_kernel<double><<<grid, 256, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,
                                                                 (const double2 *)in, (double2 *)out);
     else
-        coarse_apply_kernel<float><<<grid, 64, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const float2 *)L1.Dc32,
+        coarse_apply_kernel<float><<<grid, 256, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const float2 *)L1.Dc32,
                                                                (const float2 *)in, (float2 *)out);
     return hip_check(c, hipGetLastError(), "coarse apply kernel");
 }

@@ -87,12 +87,16 @@ double *ensure_red(Ctx *c, size_t n) {
 
 static int setup_geometry(Ctx *c, const int *dims, const int *block) {
     std::vector<uint32_t> coord;
-    std::vector<int> nbr;
-    std::string e = geometry_tables(dims, block, c->g, coord, nbr);
+    std::vector<int> nbr, lexpos;
+    std::string e = geometry_tables(dims, block, c->g, coord, nbr, &lexpos);
     if (!e.empty()) return fail(c, MGDD_ESHAPE, e);
     c->d_blk_coord = (uint32_t *)dalloc(c, coord.size() * sizeof(uint32_t));
     c->d_blk_nbr = (int *)dalloc(c, nbr.size() * sizeof(int));
-    if (!c->d_blk_coord || !c->d_blk_nbr) return MGDD_ENOMEM;
+    int *d_lexpos = (int *)dalloc(c, lexpos.size() * sizeof(int));
+    if (!c->d_blk_coord || !c->d_blk_nbr || !d_lexpos) return MGDD_ENOMEM;
+    int rc0 = hip_check(c, hipMemcpy(d_lexpos, lexpos.data(), lexpos.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
+    if (rc0) return rc0;
+    c->g.pos_of_lex = d_lexpos;
     int rc = hip_check(c, hipMemcpy(c->d_blk_coord, coord.data(), coord.size() * sizeof(uint32_t), hipMemcpyHostToDevice), "copy");
     if (rc) return rc;
     rc = hip_check(c, hipMemcpy(c->d_blk_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
@@ -132,6 +136,11 @@ int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ct
     ctx = new mgdd_ctx();
     ctx->c.stream = (hipStream_t)hip_stream;
     (void)hipGetDevice(&ctx->c.dev);
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->c.dev) == hipSuccess && v > 0)
+            ctx->c.lds_max = (size_t)v;
+    }
     int rc = setup_geometry(&ctx->c, dims, block);
     if (rc) {
         // keep the context so that the caller can read the error, then free it

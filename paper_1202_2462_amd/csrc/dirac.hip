@@ -19,8 +19,9 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
                                                     int nwg) {
     const int w = xcd_block(nwg);
     const int r = w % nrhs;
-    const int d = (w / nrhs) * TPB + threadIdx.x;
-    if (d >= g.V) return;
+    const int i = (w / nrhs) * TPB + threadIdx.x;
+    if (i >= g.V) return;
+    const int d = site_in_lex_block_order(g, i);
     int nbr[8];
     site_neighbours(g, d, nbr);
     const size_t V = g.V;

@@ -24,7 +24,17 @@ struct Geom {
     int V, Vb, lgVb, nblocks, ncol0;
     const uint32_t *blk_coord;   // [nblocks] packed block coords of position pos (8 bits each)
     const int *blk_nbr;          // [nblocks][8] position of the neighbour block, dir = 2*mu + (0:+,1:-)
+    const int *pos_of_lex;       // [nblocks] position of the block with lexicographic block index b
 };
+
+// Device site of the i-th site in lexicographic block order (blocks in
+// lexicographic order of their coordinates, sites in device order inside a
+// block): kernels that visit every site use this order so that a range of
+// consecutive workgroups covers a compact slab of the lattice with both
+// colours, and neighbour faces are reused from cache.
+__host__ __device__ inline int site_in_lex_block_order(const Geom &g, int i) {
+    return (g.pos_of_lex[i >> g.lgVb] << g.lgVb) + (i & (g.Vb - 1));
+}
 
 __host__ __device__ inline int local_index(const Geom &g, const int *x) {
     int lex = x[0] + (x[1] << g.lb[0]) + (x[2] << (g.lb[0] + g.lb[1])) + (x[3] << (g.lb[0] + g.lb[1] + g.lb[2]));
@@ -87,7 +97,7 @@ __host__ __device__ inline int lex_of(const Geom &g, int d) {
 // even or 1 (two-colouring), fewer than 256 blocks per direction.
 // coord[pos] and nbr[pos*8 + dir] are filled; returns "" or the error text.
 inline std::string geometry_tables(const int *dims, const int *block, Geom &g, std::vector<uint32_t> &coord,
-                                   std::vector<int> &nbr) {
+                                   std::vector<int> &nbr, std::vector<int> *lexpos = nullptr) {
     auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
     auto ilog2 = [](int v) { int r = 0; while ((1 << r) < v) r++; return r; };
     for (int mu = 0; mu < 4; mu++) {
@@ -137,6 +147,7 @@ inline std::string geometry_tables(const int *dims, const int *block, Geom &g, s
                 nbr[(size_t)p * 8 + 2 * mu + dir] = pos_of_lex[lex];
             }
     }
+    if (lexpos) *lexpos = pos_of_lex;
     return "";
 }
 

@@ -51,12 +51,11 @@ namespace mgdd {
 // Remaps the workgroup index so that consecutive ranges of workgroups (and so
 // of lattice sites) land on the same XCD: the hardware hands workgroups to the
 // 8 XCDs round-robin, each XCD with its own L2.
-__device__ inline int xcd_block(int nwg) {
-    int b = blockIdx.x;
-    int per = nwg >> 3;
-    if (per == 0 || (nwg & 7)) return b;
-    return (b & 7) * per + (b >> 3);
+__host__ __device__ inline int xcd_remap(int b, int nwg) {
+    const int q = nwg >> 3, r = nwg & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
 }
+__device__ inline int xcd_block(int nwg) { return xcd_remap(blockIdx.x, nwg); }
 
 // ------------------------------------------------------------------ the context
 
@@ -78,6 +77,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int dev = 0;
+    size_t lds_max = 65536;                 // LDS bytes one workgroup may take
     // geometry tables
     uint32_t *d_blk_coord = nullptr;
     int *d_blk_nbr = nullptr;

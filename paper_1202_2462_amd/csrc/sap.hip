@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void sap_colour_kernel(Geom g, const C<T> *__r
     C<T> *rho_lds = (C<T> *)smem;                        // [12][Vb]
     T *red = (T *)(smem + sizeof(C<T>) * 12 * Vb);      // [3 * waves]
     const size_t V = g.V;
-    const int pos = (colour ? g.ncol0 : 0) + blockIdx.x;
+    const int pos = (colour ? g.ncol0 : 0) + xcd_block(gridDim.x);
     const int l = threadIdx.x;
     const int d = (pos << g.lgVb) + l;
     const size_t roff = (size_t)blockIdx.y * 12 * V;
@@ -150,6 +150,281 @@ __global__ __launch_bounds__(256) void sap_colour_kernel(Geom g, const C<T> *__r
     store_spinor<T>(zf, d, zs);
 }
 
+// ---------------------------------------------------------------- four lanes per site
+//
+// Lane m = threadIdx & 3 of a site handles the two hops along direction m,
+// the rows of the clover term that belong to spin m, and owns spin m
+// (components 3m..3m+2) of r, rho, e and q. The hop partial sums of the four
+// lanes are combined by a two-step reduce-scatter over lane pairs (xor 2,
+// then xor 1), so that every spin's sum is formed by one lane in a fixed
+// order. The spin projection is branch-free: in the chiral basis
+// gamma_mu = [[0, B],[B^H, 0]] with (B l)_s = beta_s l_pi(s), pi a swap for
+// x, y and the identity for z, t, and beta_s in {+-1, +-i}.
+struct Proj {
+    bool swap;
+    float2 b0, b1;  // beta_0, beta_1 (exact in any precision)
+};
+
+// beta_0 = -i (x, z), -1 (y, t); beta_1 = -i (x), +1 (y), +i (z), -1 (t);
+// written as arithmetic of mu (a table of constants indexed by a lane value
+// would be placed in scratch memory)
+__device__ inline Proj proj_of(int mu) {
+    Proj p;
+    const int odd = mu & 1, hi = (mu >> 1) & 1;
+    p.swap = mu < 2;
+    p.b0 = make_float2(odd ? -1.f : 0.f, odd ? 0.f : -1.f);
+    p.b1 = make_float2(odd ? (float)(1 - 2 * hi) : 0.f, odd ? 0.f : (float)(2 * hi - 1));
+    return p;
+}
+
+template <typename T> __device__ inline C<T> cmulp(float2 beta, C<T> v) {
+    return mk<T>((T)beta.x * v.x - (T)beta.y * v.y, (T)beta.x * v.y + (T)beta.y * v.x);
+}
+template <typename T> __device__ inline C<T> cmulpc(float2 beta, C<T> v) {  // conj(beta) v
+    return mk<T>((T)beta.x * v.x + (T)beta.y * v.y, (T)beta.x * v.y - (T)beta.y * v.x);
+}
+
+// acc += (1 -+ gamma_mu) U^(H) psi for a runtime direction (FWD: 1 - gamma, U)
+template <typename T, bool FWD>
+__device__ inline void hop_rt(C<T> *acc, const Proj &p, const C<T> *u, const C<T> *psi) {
+    C<T> h0[3], h1[3], w0[3], w1[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        C<T> l0 = psi[6 + a], l1 = psi[9 + a];
+        C<T> bl0 = cmulp<T>(p.b0, p.swap ? l1 : l0);
+        C<T> bl1 = cmulp<T>(p.b1, p.swap ? l0 : l1);
+        h0[a] = FWD ? csub(psi[a], bl0) : cadd(psi[a], bl0);
+        h1[a] = FWD ? csub(psi[3 + a], bl1) : cadd(psi[3 + a], bl1);
+    }
+    su3_mv<T, !FWD>(u, h0, w0);
+    su3_mv<T, !FWD>(u, h1, w1);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc[a] = cadd(acc[a], w0[a]);
+        acc[3 + a] = cadd(acc[3 + a], w1[a]);
+        // (B^H w)_s = conj(beta_pi(s)) w_pi(s); forward subtracts, backward adds
+        C<T> bw0 = p.swap ? cmulpc<T>(p.b1, w1[a]) : cmulpc<T>(p.b0, w0[a]);
+        C<T> bw1 = p.swap ? cmulpc<T>(p.b0, w0[a]) : cmulpc<T>(p.b1, w1[a]);
+        acc[6 + a] = FWD ? csub(acc[6 + a], bw0) : cadd(acc[6 + a], bw0);
+        acc[9 + a] = FWD ? csub(acc[9 + a], bw1) : cadd(acc[9 + a], bw1);
+    }
+}
+
+// sum of a 12-component partial over the 4 lanes of a site, returned for
+// spin m only (3 components) in out
+template <typename T> __device__ inline void reduce_scatter4(const C<T> *acc, int m, C<T> *out) {
+    C<T> kept[2][3];
+    const bool hi = m & 2;
+#pragma unroll
+    for (int k = 0; k < 2; k++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            C<T> mine = hi ? acc[(2 + k) * 3 + c] : acc[k * 3 + c];
+            C<T> send = hi ? acc[k * 3 + c] : acc[(2 + k) * 3 + c];
+            C<T> recv = mk<T>(__shfl_xor(send.x, 2, 64), __shfl_xor(send.y, 2, 64));
+            kept[k][c] = cadd(mine, recv);
+        }
+    const bool odd = m & 1;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        C<T> mine = odd ? kept[1][c] : kept[0][c];
+        C<T> send = odd ? kept[0][c] : kept[1][c];
+        C<T> recv = mk<T>(__shfl_xor(send.x, 1, 64), __shfl_xor(send.y, 1, 64));
+        out[c] = cadd(mine, recv);
+    }
+}
+
+// rows of spin m of the clover block of chirality m/2: y = A x, x = the 6
+// components of that chirality
+template <typename T>
+__device__ inline void clover_rows(const FieldView<T> &A, unsigned aoff, int d, int m, const C<T> *x, C<T> *y,
+                                   unsigned salt) {
+    T a[36];
+#pragma unroll
+    for (int k = 0; k < 18; k++) {
+        C<T> v = A.ld_lane(k, d, aoff, salt);
+        a[2 * k] = v.x;
+        a[2 * k + 1] = v.y;
+    }
+    // rows r0..r0+2 with r0 = 3 (m & 1): every entry is picked by a select
+    // between the two compile-time candidates, so no array index depends on
+    // the lane
+    const bool up = m & 1;
+#pragma unroll
+    for (int rr = 0; rr < 3; rr++) {
+        C<T> acc = mk<T>(0, 0);
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            C<T> e0, e1;
+            {
+                const int i = rr;
+                if (j == i) e0 = mk<T>(a[i], (T)0);
+                else if (i < j) e0 = mk<T>(a[hpack(i, j)], a[hpack(i, j) + 1]);
+                else e0 = mk<T>(a[hpack(j, i)], -a[hpack(j, i) + 1]);
+            }
+            {
+                const int i = 3 + rr;
+                if (j == i) e1 = mk<T>(a[i], (T)0);
+                else if (i < j) e1 = mk<T>(a[hpack(i, j)], a[hpack(i, j) + 1]);
+                else e1 = mk<T>(a[hpack(j, i)], -a[hpack(j, i) + 1]);
+            }
+            cfma(acc, up ? e1 : e0, x[j]);
+        }
+        y[rr] = acc;
+    }
+}
+
+// The forward links of the block's sites (4 x 9 complex per site) are staged
+// in LDS once, next to rho: every hop inside the block (forward: the site's
+// own link; backward: the neighbour's forward link) reads its link from LDS.
+// With links + rho resident a workgroup takes about 100 KB of LDS, so one
+// block runs per CU and the clover term re-read at every MR step stays in
+// the XCD's L2.
+template <typename T>
+__global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restrict__ Up, const C<T> *__restrict__ Ap,
+                                                    const C<T> *__restrict__ b, C<T> *__restrict__ z, int colour,
+                                                    int mr, T sre, T sim) {
+    extern __shared__ unsigned char smem[];
+    const int Vb = g.Vb;
+    C<T> *rho_lds = (C<T> *)smem;                        // [12][Vb]
+    C<T> *lnk_lds = rho_lds + 12 * Vb;                   // [4 * 9][Vb]
+    T *red = (T *)(lnk_lds + 36 * Vb);                   // [3 * waves]
+    const size_t V = g.V;
+    const int pos = (colour ? g.ncol0 : 0) + xcd_block(gridDim.x);
+    const int m = threadIdx.x & 3, l = threadIdx.x >> 2;
+    const int d = (pos << g.lgVb) + l;
+    const size_t roff = (size_t)blockIdx.y * 12 * V;
+    // one uniform descriptor for all links and one for the clover term; the
+    // lane's direction / chirality enters through the 32-bit vector offset
+    const FieldView<T> Uall(Up, V, 36), Aall(Ap, V, 36);
+    const unsigned uoff = (unsigned)m * 9u * Uall.cs, aoff = (unsigned)(m >> 1) * 18u * Aall.cs;
+    const FieldView<T> bf(b + roff, V, 12), zf(z + roff, V, 12);
+    const C<T> shift = mk<T>(sre, sim);
+    const Proj pr = proj_of(m);
+
+    // neighbours along the lane's direction m, with every array index a
+    // compile-time constant (a lane-dependent index into a private array
+    // would put the array in scratch memory)
+    int x[4];
+    local_coords(g, l, x);
+    int nf, nbk, lnf, lnb;
+    {
+        int xm = 0, lbm = 0, nbm = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++)
+            if (mu == m) { xm = x[mu]; lbm = g.lb[mu]; nbm = g.nb[mu]; }
+        const int bm = 1 << lbm;
+        const bool wrap = nbm == 1;
+        int yf = xm + 1, yb = xm - 1;
+        const bool fin = yf < bm, bin = yb >= 0;       // stays in the block without wrapping
+        const int yfw = yf & (bm - 1), ybw = (yb + bm) & (bm - 1);
+        int xf[4], xb[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            xf[mu] = mu == m ? yfw : x[mu];
+            xb[mu] = mu == m ? ybw : x[mu];
+        }
+        const int lf = local_index(g, xf), lb = local_index(g, xb);
+        lnf = (fin || wrap) ? lf : -1;
+        lnb = (bin || wrap) ? lb : -1;
+        const int pf = fin ? pos : g.blk_nbr[pos * 8 + 2 * m];
+        const int pb = bin ? pos : g.blk_nbr[pos * 8 + 2 * m + 1];
+        nf = (pf << g.lgVb) + lf;
+        nbk = (pb << g.lgVb) + lb;
+    }
+    const int ch = m >> 1;  // chirality of spin m
+
+    // stage the forward link of direction m of this site
+#pragma unroll
+    for (int k = 0; k < 9; k++) lnk_lds[(m * 9 + k) * Vb + l] = Uall.ld_lane(k, d, uoff);
+    __syncthreads();
+
+    // r = b - (D - shift) z, spin m
+    C<T> rho[3], e[3], q[3];
+    {
+        C<T> acc[12], psi[12], u[9];
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
+        load_spinor<T>(zf, nf, psi);
+#pragma unroll
+        for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + l];
+        hop_rt<T, true>(acc, pr, u, psi);
+        load_spinor<T>(zf, nbk, psi);
+        if (lnb >= 0) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + lnb];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, nbk, uoff);
+        }
+        hop_rt<T, false>(acc, pr, u, psi);
+        C<T> hs[3], zc[6], az[3], zs[3], bs[3];
+        reduce_scatter4<T>(acc, m, hs);
+#pragma unroll
+        for (int c = 0; c < 6; c++) zc[c] = zf.ld_lane(c, d, 6u * ch * zf.cs);
+        clover_rows<T>(Aall, aoff, d, m, zc, az, 0);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            zs[c] = zc[(m & 1) * 3 + c];
+            bs[c] = bf.ld_lane(c, d, 3u * m * bf.cs);
+            C<T> dz = csub(csub(az[c], cscale(hs[c], (T)0.5)), cmul(shift, zs[c]));
+            rho[c] = csub(bs[c], dz);
+            e[c] = mk<T>(0, 0);
+            rho_lds[(3 * m + c) * Vb + l] = rho[c];
+        }
+    }
+    __syncthreads();
+
+    for (int it = 0; it < mr; it++) {
+        const unsigned salt = opaque_zero();
+        C<T> acc[12], psi[12], u[9];
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
+        if (lnf >= 0) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) psi[k] = rho_lds[k * Vb + lnf];
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + l];
+            hop_rt<T, true>(acc, pr, u, psi);
+        }
+        if (lnb >= 0) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) psi[k] = rho_lds[k * Vb + lnb];
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + lnb];
+            hop_rt<T, false>(acc, pr, u, psi);
+        }
+        C<T> hs[3], xc[6], ax[3];
+        reduce_scatter4<T>(acc, m, hs);
+#pragma unroll
+        for (int c = 0; c < 6; c++) xc[c] = rho_lds[(6 * ch + c) * Vb + l];
+        clover_rows<T>(Aall, aoff, d, m, xc, ax, salt);
+        Red3<T> part{0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            q[c] = csub(csub(ax[c], cscale(hs[c], (T)0.5)), cmul(shift, rho[c]));
+            part.a += q[c].x * q[c].x + q[c].y * q[c].y;
+            part.b += q[c].x * rho[c].x + q[c].y * rho[c].y;   // conj(q) rho
+            part.c += q[c].x * rho[c].y - q[c].y * rho[c].x;
+        }
+        Red3<T> s = block_sum3<T>(part, red);
+        if (s.a == (T)0) break;
+        C<T> alpha = mk<T>(s.b / s.a, s.c / s.a);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            cfma(e[c], alpha, rho[c]);
+            rho[c] = csub(rho[c], cmul(alpha, q[c]));
+        }
+        if (it + 1 < mr) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) rho_lds[(3 * m + c) * Vb + l] = rho[c];
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) zf.st_lane(c, d, 3u * m * zf.cs, cadd(zf.ld_lane(c, d, 3u * m * zf.cs), e[c]));
+}
+
 }  // namespace
 
 int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, double sim, const void *b, void *z) {
@@ -157,19 +432,26 @@ int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, doub
     if (g.Vb < 64 || g.Vb > 256)
         return fail(c, MGDD_ESHAPE, "the Schwarz kernel needs 64 <= block volume <= 256");
     size_t lds = (prec == MGDD_F64 ? 16 : 8) * 12 * (size_t)g.Vb + (prec == MGDD_F64 ? 8 : 4) * 3 * (g.Vb / 64);
+    // four lanes per site with the block's links staged in LDS (FP32)
+    const size_t lds4 = 8 * (12 + 36) * (size_t)g.Vb + 4 * 3 * (4 * g.Vb / 64);
     for (int s = 0; s < nsweeps; s++)
         for (int col = 0; col < 2; col++) {
             int nblocks = col ? g.nblocks - g.ncol0 : g.ncol0;
             if (nblocks == 0) continue;
             dim3 grid(nblocks, nrhs);
-            if (prec == MGDD_F64)
+            if (prec == MGDD_F64) {
                 sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64,
                                                                           (const double2 *)c->A64, (const double2 *)b,
                                                                           (double2 *)z, col, mr, sre, sim);
-            else
+            } else if (lds4 <= c->lds_max) {
+                sap4_kernel<float><<<grid, 4 * g.Vb, lds4, c->stream>>>(g, (const float2 *)c->U32,
+                                                                        (const float2 *)c->A32, (const float2 *)b,
+                                                                        (float2 *)z, col, mr, (float)sre, (float)sim);
+            } else {
                 sap_colour_kernel<float><<<grid, g.Vb, lds, c->stream>>>(g, (const float2 *)c->U32,
                                                                          (const float2 *)c->A32, (const float2 *)b,
                                                                          (float2 *)z, col, mr, (float)sre, (float)sim);
+            }
             int rc = hip_check(c, hipGetLastError(), "sap kernel");
             if (rc) return rc;
         }

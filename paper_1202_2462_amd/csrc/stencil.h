@@ -54,6 +54,15 @@ template <typename T> struct FieldView {
     __device__ void st(int comp, int site, C<T> v) const {
         BIO<T>::st(v, r, (unsigned)site * (unsigned)sizeof(C<T>), comp * cs);
     }
+    // load / store with an extra per-lane byte offset (the descriptor and the
+    // scalar offset stay wave-uniform; a lane-dependent scalar offset would
+    // make the compiler loop over the distinct values)
+    __device__ C<T> ld_lane(int comp, int site, unsigned lane_off, unsigned salt = 0) const {
+        return BIO<T>::ld(r, (unsigned)site * (unsigned)sizeof(C<T>) + lane_off, comp * cs + salt);
+    }
+    __device__ void st_lane(int comp, int site, unsigned lane_off, C<T> v) const {
+        BIO<T>::st(v, r, (unsigned)site * (unsigned)sizeof(C<T>) + lane_off, comp * cs);
+    }
 };
 
 template <typename T> __device__ inline void load_spinor(const FieldView<T> &f, int d, C<T> *s) {

@@ -444,12 +444,13 @@ int transfer_setup(Ctx *c, const int *agg, int N) {
     // tables: fine sites of each aggregate (local lexicographic order), aggregate of each site
     std::vector<int> agg_sites((size_t)Vc * Va), site_agg(g.V), cnbr((size_t)Vc * 9);
     std::vector<uint32_t> coord;
-    std::vector<int> bn;
+    std::vector<int> bn, lp;
     Geom hg{};
     int block[4] = {1 << g.lb[0], 1 << g.lb[1], 1 << g.lb[2], 1 << g.lb[3]};
-    geometry_tables(g.L, block, hg, coord, bn);
+    geometry_tables(g.L, block, hg, coord, bn, &lp);
     hg.blk_coord = coord.data();
     hg.blk_nbr = bn.data();
+    hg.pos_of_lex = lp.data();
     std::vector<int> dev_of_lex(g.V);
     for (int d = 0; d < g.V; d++) dev_of_lex[lex_of(hg, d)] = d;
     for (int a = 0; a < Vc; a++) {

@@ -11,21 +11,15 @@
 #include <cstdlib>
 #include <vector>
 
-#include "../paper_1202_2462_amd/csrc/geometry.h"
+#include "../paper_1202_2462_amd/csrc/mgdd_internal.h"
 
 using namespace mgdd;
-
-static int xcd_remap(int b, int nwg) {
-    int per = nwg >> 3;
-    if (per == 0 || (nwg & 7)) return b;
-    return (b & 7) * per + (b >> 3);
-}
 
 static int check(const int *dims, const int *block, bool expect_ok) {
     Geom g{};
     std::vector<uint32_t> coord;
-    std::vector<int> nbr;
-    std::string e = geometry_tables(dims, block, g, coord, nbr);
+    std::vector<int> nbr, lexpos;
+    std::string e = geometry_tables(dims, block, g, coord, nbr, &lexpos);
     if (!expect_ok) {
         if (e.empty()) { printf("FAIL: shape accepted but should be rejected\n"); return 1; }
         return 0;
@@ -33,7 +27,13 @@ static int check(const int *dims, const int *block, bool expect_ok) {
     if (!e.empty()) { printf("FAIL: %s\n", e.c_str()); return 1; }
     g.blk_coord = coord.data();
     g.blk_nbr = nbr.data();
-    std::vector<int> seen(g.V, 0);
+    g.pos_of_lex = lexpos.data();
+    std::vector<int> seen(g.V, 0), seen2(g.V, 0);
+    for (int i = 0; i < g.V; i++) {
+        int d = site_in_lex_block_order(g, i);
+        if (d < 0 || d >= g.V || seen2[d]) { printf("FAIL lexicographic block order\n"); return 1; }
+        seen2[d] = 1;
+    }
     for (int d = 0; d < g.V; d++) {
         int X[4];
         site_coords(g, d, X);
@@ -87,7 +87,7 @@ static int check(const int *dims, const int *block, bool expect_ok) {
             if (q != p && cq == col) { printf("FAIL two neighbouring blocks share a colour\n"); return 1; }
         }
     }
-    for (int nwg : {1, 7, 8, 16, 24, 8 * 37, 1000}) {
+    for (int nwg : {1, 2, 7, 8, 9, 15, 16, 24, 8 * 37, 1000, 1001}) {
         std::vector<int> hit(nwg, 0);
         for (int b = 0; b < nwg; b++) {
             int w = xcd_remap(b, nwg);

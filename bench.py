@@ -12,7 +12,9 @@ even-odd), the roofline of the dominant kernel, and the oracle on the host
 cores as a CPU baseline.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       python bench.py --kernel-only sap      (short run for hardware counters)
+       python bench.py --kernel-only step|sap|dirac|copy   (short runs for hardware counters:
+           one step, Schwarz sweeps alone, Wilson-clover applies alone; each followed
+           by a 256 MiB copy that calibrates the traffic counters)
 """
 from __future__ import annotations
 
@@ -28,7 +30,50 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions (the library is built with
+# them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
 WORKLOAD = "c1"
+# algorithmic cost of one site update of a Schwarz colour step with k MR steps
+# (FP32): bytes = z in 96 + b 96 + links 288 + clover 288 + z out 96;
+# flops = (1 + k) operator applications of 1896 + k MR updates of 336
+SAP_BYTES_PER_SITE = 864
+
+
+def sap_flops_per_site(k):
+    return (1 + k) * 1896 + k * 336
+
+
+# HBM traffic of the FP32 Schwarz kernel from hardware counters, and the
+# sources it was taken from (the figure is dropped when they have changed)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sap4_kernel_f32_16x16x16x32_hbm_traffic.md")
+SAP_SOURCES = ["paper_1202_2462_amd/csrc/sap.hip", "paper_1202_2462_amd/csrc/stencil.h",
+               "paper_1202_2462_amd/csrc/mgdd_internal.h", "paper_1202_2462_amd/csrc/geometry.h"]
+
+
+def sap_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SAP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def sap_traffic_per_site():
+    """HBM bytes per site update from the committed counter summary, or None
+    when there is none or the kernel's sources differ from the measured ones."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.split(":", 1)[0].strip() in ("hbm_bytes_per_site_update", "kernel_sources_sha256"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != sap_sources_digest() or "hbm_bytes_per_site_update" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_site_update"])
 
 
 def log(*a):
@@ -171,7 +216,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--kernel-only", choices=["sap", "dirac", "copy"], default=None)
+    ap.add_argument("--kernel-only", choices=["step", "sap", "dirac", "copy"], default=None)
     ap.add_argument("--m0", type=float, default=None, help="override the tuned bare mass")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -185,7 +230,9 @@ def main():
     if args.kernel_only:
         # short run of one kernel for hardware counters (rocprofv3 --pmc)
         bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
-        if args.kernel_only == "sap":
+        if args.kernel_only == "step":
+            bench.step()
+        elif args.kernel_only == "sap":
             bench.sap_launch_time()
         elif args.kernel_only == "dirac":
             bench.dirac_rates()
@@ -202,12 +249,19 @@ def main():
         bench.step()
     torch.cuda.synchronize()
     log("timed steps")
+    ctx = bench.lat.ctx
+    for kern, prec in ((mg.KERNEL_SAP, mg.F32), (mg.KERNEL_DIRAC, mg.F64)):
+        mg.mgdd_timing_read(ctx, kern, prec, reset=True)
+    mg.mgdd_timing_enable(ctx, True)    # HIP events around each launch, on the library's stream
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
         _, last = bench.step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    mg.mgdd_timing_enable(ctx, False)
+    sap_ms, sap_units, sap_n = mg.mgdd_timing_read(ctx, mg.KERNEL_SAP, mg.F32, reset=True)
+    d_ms, d_units, d_n = mg.mgdd_timing_read(ctx, mg.KERNEL_DIRAC, mg.F64, reset=True)
     ms = elapsed / args.steps * 1e3
     split = {}
     bench.step(split=split)
@@ -246,15 +300,30 @@ def main():
 
     bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
     result["dirac"] = bench.dirac_rates()
-    # roofline of the FP32 Schwarz colour kernel (the dominant kernel of the step):
-    # algorithmic bytes per site 864 = z in 96 + b 96 + links 288 + clover 288 + z out 96,
-    # V/2 sites per launch (one colour)
-    t_launch = bench.sap_launch_time()
-    bytes_launch = 864 * bench.V / 2
-    achieved = bytes_launch / t_launch / 1e9
-    result["roofline"] = {"bound": "hbm", "kernel": "sap_colour_kernel<float>", "achieved": achieved,
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                          "us_per_launch": t_launch * 1e6, "algorithmic_bytes_per_launch": bytes_launch}
+    if d_n:
+        result["dirac"]["f64_in_solves"] = {"launches": d_n, "us_per_launch": d_ms * 1e3 / d_n,
+                                            "gbs": 1536 * d_units / (d_ms * 1e-3) / 1e9}
+    # roofline of the dominant kernel of the step, the FP32 Schwarz colour
+    # kernel, from its launches in the timed steps (HIP events around each
+    # launch on the library's stream). At k MR steps it performs
+    # sap_flops_per_site(k) flops on 864 algorithmic bytes per site update,
+    # above the FP32 ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B): ALU-bound.
+    if sap_n:
+        t_launch = sap_ms * 1e-3 / sap_n
+        units_launch = sap_units / sap_n
+        flops_launch = sap_flops_per_site(bench.w["mr"]) * units_launch
+        achieved = flops_launch / t_launch / 1e12
+        tps = sap_traffic_per_site()
+        result["roofline"] = {
+            "bound": "alu", "kernel": "sap4_kernel<float> (Schwarz colour step, 4 MR steps)",
+            "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VALU_PEAK_TFLOPS,
+            "traffic": None if tps is None else tps * units_launch,
+            "launches": sap_n, "us_per_launch": t_launch * 1e6, "site_updates_per_launch": units_launch,
+            "algorithmic_flops_per_launch": flops_launch,
+            "algorithmic_bytes_per_launch": SAP_BYTES_PER_SITE * units_launch,
+            "hbm_gbs": SAP_BYTES_PER_SITE * units_launch / t_launch / 1e9,
+            "hbm_frac": SAP_BYTES_PER_SITE * units_launch / t_launch / 1e9 / HBM_PEAK_GBS}
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -154,8 +154,9 @@ int mgdd_prolong(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *fi
 int mgdd_coarse_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out);
 
 /* x = approximate D_c^{-1} b by `iters` steps of GMRES from x = 0 without
- * restart (the coarse solve of Section 4 uses 12). nrhs coarse fields;
- * synchronous (one host read of the Hessenberg matrix per field). */
+ * restart (the coarse solve of Section 4 uses 12). nrhs coarse fields, each
+ * with its own Krylov basis and Hessenberg matrix, computed together in
+ * shared launches; synchronous (one host read of the Hessenberg matrices). */
 int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x);
 
 /* Two-level preconditioner (Section 3: smoother and coarse-grid correction
@@ -214,7 +215,7 @@ typedef struct {
     int restarts;      /* true-residual recomputations */
     int converged;     /* 1 if ||b - D z|| <= tol ||b|| */
     double relres;     /* final ||b - D z|| / ||b|| in FP64 */
-    double seconds;    /* wall time of this right-hand side */
+    double seconds;    /* wall time of the solve this right-hand side was part of */
 } mgdd_solve_stats;
 
 /* Solves D z = b (eq. (1.1)) for nrhs FP64 device fields b; z (FP64 device
@@ -222,11 +223,42 @@ typedef struct {
  * FGMRES_MG: flexible GMRES(restart) right-preconditioned by the two-level
  * method (Section 4). GCR: plain GCR(restart) on D. GCR_EO: GCR(restart) on
  * the even-odd Schur complement, convergence judged on the full system.
+ * With FGMRES_MG the nrhs right-hand sides are solved together: one Krylov
+ * basis, Hessenberg matrix, restart and stopping test each, with D, the
+ * preconditioner and the Gram-Schmidt steps applied to all of them in shared
+ * launches (a right-hand side that has converged stops changing). If the
+ * workspace for all of them does not fit in device memory they are split
+ * into smaller batches. GCR and GCR_EO solve them one after the other.
  * stats: array of nrhs entries (may be NULL). Synchronous. Errors:
  * MGDD_ENOCONV (maxit reached; z and stats written), MGDD_ENAN,
  * MGDD_ENOTREADY (no gauge field; no P for FGMRES_MG). */
 int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const void *b, void *z,
                mgdd_solve_stats *stats);
+
+/* ------------------------------------------------------------------ kernel timing
+ * Instrumentation, not part of the method. While timing is enabled the
+ * library brackets every launch of the Wilson-clover kernel
+ * (MGDD_KERNEL_DIRAC, used by mgdd_dirac_apply and inside the solvers) and
+ * of the Schwarz colour kernel (MGDD_KERNEL_SAP, one launch per colour step
+ * of Alg. 2.1) with a pair of HIP events on the context's stream, and adds up
+ * the durations per kernel family and precision. Enabling creates a fixed
+ * pool of events (owned by the context, released by mgdd_destroy);
+ * disabling keeps the totals. The pool is drained with a stream
+ * synchronisation when it is full or when the totals are read. */
+enum { MGDD_KERNEL_DIRAC = 0, MGDD_KERNEL_SAP = 1 };
+
+/* on: nonzero to enable, 0 to disable. Errors: MGDD_EHIP (event creation). */
+int mgdd_timing_enable(mgdd_ctx *ctx, int on);
+
+/* Totals for one kernel family (MGDD_KERNEL_*) and precision (MGDD_F64 or
+ * MGDD_F32), after a synchronisation of the context's stream. Outputs (each
+ * may be NULL): total_ms = sum of launch durations in milliseconds;
+ * site_updates = sum over launches of sites times right-hand sides processed
+ * (the sites of one colour for a Schwarz launch); launches = number of
+ * launches. reset: nonzero to zero these totals afterwards. Errors:
+ * MGDD_EINVAL (bad kernel or precision). */
+int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *total_ms, double *site_updates,
+                     long long *launches);
 
 #ifdef __cplusplus
 }

@@ -10,15 +10,20 @@ struct PtrList {
     const void *p[MAXV];
 };
 
-// out[i] = <x_i, w> = sum conj(x_i) w for i < nvec (device double2 array).
-int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int nvec, const void *w, double2 *out);
-// y = beta y + alpha sum_i coef[i] x_i   (coef: device double2 array)
+// Every array holds nseg segments of n complex numbers (segment s at offset
+// s * n); the operation is applied to each segment independently.
+//
+// out[i * nseg + s] = <x_i, w>_s = sum conj(x_i) w over segment s, i < nvec
+int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int nvec, const void *w, double2 *out,
+                  int nseg = 1);
+// y_s = beta y_s + alpha sum_i coef[i * nseg + s] x_i,s   (coef on the device)
 int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nvec, const double2 *coef, double alpha,
-                 double beta, void *y);
-// y = (coef ? coef[0] * alpha : alpha) x   (x and y may alias)
-int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y);
-// y = x / sqrt(re nrm2[0]) (y = 0 when that is 0); x and y may alias
-int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y);
+                 double beta, void *y, int nseg = 1);
+// y_s = (coef ? coef[s] * alpha : alpha) x_s   (x and y may alias)
+int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y,
+               int nseg = 1);
+// y_s = x_s / sqrt(re nrm2[s]) (y_s = 0 when that is 0); x and y may alias
+int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y, int nseg = 1);
 // coef[0] = 1/sqrt(re v[0])
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef);
 

@@ -2,9 +2,12 @@
 // products (several vectors against one, in one pass over memory), linear
 // combinations y = beta y + alpha sum_i c_i x_i with the coefficients read
 // from device memory (so that Gram-Schmidt needs no host round trip), and
-// scaling. Reductions are deterministic: a fixed grid for a given length, a
-// fixed butterfly inside each wave, per-workgroup partials summed in a fixed
-// order by a second kernel. Sums are accumulated in double.
+// scaling. Every operation works on nseg independent segments of length n at
+// once (the right-hand sides of a batched solve, segment s at offset s * n
+// of every array; coefficients and results indexed [i][s]); the segment is
+// the second grid dimension. Reductions are deterministic: a fixed grid for a
+// given length, a fixed butterfly inside each wave, per-workgroup partials
+// summed in a fixed order by a second kernel. Sums are accumulated in double.
 #include "blas.h"
 
 namespace mgdd {
@@ -38,14 +41,14 @@ __global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PtrList xs, int
     double2 acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; i++) acc[i] = make_double2(0, 0);
-    const size_t stride = (size_t)gridDim.x * TPB;
+    const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
-        C<TW> wv = w[e];
+        C<TW> wv = w[so + e];
         double2 wd = make_double2((double)wv.x, (double)wv.y);
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             if (i < nvec) {
-                C<TX> xv = ((const C<TX> *)xs.p[i])[e];
+                C<TX> xv = ((const C<TX> *)xs.p[i])[so + e];
                 cfmac(acc[i], make_double2((double)xv.x, (double)xv.y), wd);
             }
         }
@@ -63,12 +66,12 @@ __global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PtrList xs, int
         int i = threadIdx.x;
         double a = 0, b = 0;
         for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * i]; b += red[k][2 * i + 1]; }
-        part[(size_t)i * gridDim.x + blockIdx.x] = make_double2(a, b);
+        part[((size_t)i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
     }
 }
 
-// out[i] = sum_k part[i * nwg + k]: one 64-lane wave per i, lane l adding the
-// partials k = l, l + 64, ... in order, then a butterfly.
+// out[q] = sum_k part[q * nwg + k] (q = i * nseg + s): one 64-lane wave per q,
+// lane l adding the partials k = l, l + 64, ... in order, then a butterfly.
 __global__ __launch_bounds__(64) void finish_kernel(int nwg, const double2 *__restrict__ part, double2 *__restrict__ out) {
     const int i = blockIdx.x, lane = threadIdx.x;
     double a = 0, b = 0;
@@ -83,27 +86,29 @@ __global__ __launch_bounds__(64) void finish_kernel(int nwg, const double2 *__re
 }
 
 // y = beta y + alpha sum_i coef[i] x_i
+// (coefficient of vector i for segment s: coef[i * cstride + s])
 template <typename TX, typename TY, int NV>
 __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int nvec, const double2 *__restrict__ coef,
-                                                      double alpha, double beta, C<TY> *__restrict__ y) {
+                                                      int cstride, double alpha, double beta, C<TY> *__restrict__ y) {
     double2 c[NV];
 #pragma unroll
-    for (int i = 0; i < NV; i++) c[i] = i < nvec ? cscale(coef[i], alpha) : make_double2(0, 0);
-    const size_t stride = (size_t)gridDim.x * TPB;
+    for (int i = 0; i < NV; i++)
+        c[i] = i < nvec ? cscale(coef[(size_t)i * cstride + blockIdx.y], alpha) : make_double2(0, 0);
+    const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
         double2 acc = make_double2(0, 0);
         if (beta != 0.0) {
-            C<TY> yv = y[e];
+            C<TY> yv = y[so + e];
             acc = make_double2(beta * (double)yv.x, beta * (double)yv.y);
         }
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             if (i < nvec) {
-                C<TX> xv = ((const C<TX> *)xs.p[i])[e];
+                C<TX> xv = ((const C<TX> *)xs.p[i])[so + e];
                 cfma(acc, c[i], make_double2((double)xv.x, (double)xv.y));
             }
         }
-        y[e] = mk<TY>((TY)acc.x, (TY)acc.y);
+        y[so + e] = mk<TY>((TY)acc.x, (TY)acc.y);
     }
 }
 
@@ -115,16 +120,16 @@ __global__ __launch_bounds__(TPB) void scale_kernel(size_t n, const C<TX> *x, co
                                                     double2 alpha, int inv_norm, C<TY> *y) {
     double2 s = alpha;
     if (coef && inv_norm) {
-        double nn = sqrt(coef[0].x);
+        double nn = sqrt(coef[blockIdx.y].x);
         s = nn > 0 ? cscale(alpha, 1.0 / nn) : make_double2(0, 0);
     } else if (coef) {
-        s = cmul(coef[0], alpha);
+        s = cmul(coef[blockIdx.y], alpha);
     }
-    const size_t stride = (size_t)gridDim.x * TPB;
+    const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
-        C<TX> xv = x[e];
+        C<TX> xv = x[so + e];
         double2 v = cmul(s, make_double2((double)xv.x, (double)xv.y));
-        y[e] = mk<TY>((TY)v.x, (TY)v.y);
+        y[so + e] = mk<TY>((TY)v.x, (TY)v.y);
     }
 }
 
@@ -142,21 +147,23 @@ int lin_grid(size_t n) {
 
 }  // namespace
 
-int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int nvec, const void *w, double2 *out) {
+int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int nvec, const void *w, double2 *out,
+                  int nseg) {
     int nwg = red_grid(n);
-    double2 *part = (double2 *)ensure_red(c, (size_t)2 * nvec * nwg + 16);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * MAXV * nseg * nwg + 16);
     if (!part) return MGDD_ENOMEM;
     for (int i0 = 0; i0 < nvec; i0 += MAXV) {
         int nv = nvec - i0 < MAXV ? nvec - i0 : MAXV;
         PtrList pl{};
         for (int i = 0; i < nv; i++) pl.p[i] = xs[i0 + i];
-#define MD(TX, TW) multidot_kernel<TX, TW, MAXV><<<nwg, TPB, 0, c->stream>>>(n, pl, nv, (const C<TW> *)w, part)
+        dim3 grid(nwg, nseg);
+#define MD(TX, TW) multidot_kernel<TX, TW, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nv, (const C<TW> *)w, part)
         if (px == MGDD_F64 && pw == MGDD_F64) MD(double, double);
         else if (px == MGDD_F32 && pw == MGDD_F32) MD(float, float);
         else if (px == MGDD_F32 && pw == MGDD_F64) MD(float, double);
         else MD(double, float);
 #undef MD
-        finish_kernel<<<nv, 64, 0, c->stream>>>(nwg, part, out + i0);
+        finish_kernel<<<nv * nseg, 64, 0, c->stream>>>(nwg, part, out + (size_t)i0 * nseg);
         int rc = hip_check(c, hipGetLastError(), "multidot");
         if (rc) return rc;
     }
@@ -164,12 +171,13 @@ int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int n
 }
 
 int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nvec, const double2 *coef, double alpha,
-                 double beta, void *y) {
+                 double beta, void *y, int nseg) {
     int nwg = lin_grid(n);
+    dim3 grid(nwg, nseg);
     if (nvec == 0) {
         if (beta == 1.0) return MGDD_OK;
         PtrList pl{};
-#define LC(TX, TY) lincomb_kernel<TX, TY, 1><<<nwg, TPB, 0, c->stream>>>(n, pl, 0, coef, alpha, beta, (C<TY> *)y)
+#define LC(TX, TY) lincomb_kernel<TX, TY, 1><<<grid, TPB, 0, c->stream>>>(n, pl, 0, coef, nseg, alpha, beta, (C<TY> *)y)
         if (py == MGDD_F64) LC(double, double); else LC(float, float);
         return hip_check(c, hipGetLastError(), "lincomb");
     }
@@ -178,7 +186,8 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
         PtrList pl{};
         for (int i = 0; i < nv; i++) pl.p[i] = xs[i0 + i];
         double b = i0 == 0 ? beta : 1.0;
-#define LC2(TX, TY) lincomb_kernel<TX, TY, MAXV><<<nwg, TPB, 0, c->stream>>>(n, pl, nv, coef + i0, alpha, b, (C<TY> *)y)
+#define LC2(TX, TY) lincomb_kernel<TX, TY, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nv, coef + (size_t)i0 * nseg, nseg, \
+                                                                                 alpha, b, (C<TY> *)y)
         if (px == MGDD_F64 && py == MGDD_F64) LC2(double, double);
         else if (px == MGDD_F32 && py == MGDD_F32) LC2(float, float);
         else if (px == MGDD_F32 && py == MGDD_F64) LC2(float, double);
@@ -192,25 +201,25 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
 }
 
 static int scale_launch(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha,
-                        int inv_norm, void *y) {
-    int nwg = lin_grid(n);
+                        int inv_norm, void *y, int nseg) {
+    dim3 grid(lin_grid(n), nseg);
     if (px == MGDD_F64 && py == MGDD_F64)
-        scale_kernel<double, double><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, inv_norm, (double2 *)y);
+        scale_kernel<double, double><<<grid, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, inv_norm, (double2 *)y);
     else if (px == MGDD_F32 && py == MGDD_F32)
-        scale_kernel<float, float><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, inv_norm, (float2 *)y);
+        scale_kernel<float, float><<<grid, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, inv_norm, (float2 *)y);
     else if (px == MGDD_F64)
-        scale_kernel<double, float><<<nwg, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, inv_norm, (float2 *)y);
+        scale_kernel<double, float><<<grid, TPB, 0, c->stream>>>(n, (const double2 *)x, coef, alpha, inv_norm, (float2 *)y);
     else
-        scale_kernel<float, double><<<nwg, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, inv_norm, (double2 *)y);
+        scale_kernel<float, double><<<grid, TPB, 0, c->stream>>>(n, (const float2 *)x, coef, alpha, inv_norm, (double2 *)y);
     return hip_check(c, hipGetLastError(), "scale");
 }
 
-int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y) {
-    return scale_launch(c, px, py, n, x, coef, alpha, 0, y);
+int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y, int nseg) {
+    return scale_launch(c, px, py, n, x, coef, alpha, 0, y, nseg);
 }
 
-int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y) {
-    return scale_launch(c, px, py, n, x, nrm2, make_double2(1, 0), 1, y);
+int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y, int nseg) {
+    return scale_launch(c, px, py, n, x, nrm2, make_double2(1, 0), 1, y, nseg);
 }
 
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef) {

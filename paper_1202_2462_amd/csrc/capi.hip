@@ -4,7 +4,9 @@
 #include <cstdio>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "mgdd_internal.h"
 #include "solver.h"
@@ -85,6 +87,54 @@ double *ensure_red(Ctx *c, size_t n) {
     return c->red;
 }
 
+// ------------------------------------------------------------------ kernel timing
+
+constexpr int KT_SLOTS = 2048;
+
+int kt_flush(Ctx *c) {
+    KTimer &k = c->kt;
+    if (k.used == 0) return MGDD_OK;
+    int rc = hip_check(c, hipEventSynchronize(k.ev[2 * (k.used - 1) + 1]), "timing");
+    for (int i = 0; i < k.used && !rc; i++) {
+        float ms = 0;
+        rc = hip_check(c, hipEventElapsedTime(&ms, k.ev[2 * i], k.ev[2 * i + 1]), "timing");
+        const int f = k.fam[i] >> 1, p = k.fam[i] & 1;
+        k.ms[f][p] += ms;
+        k.usum[f][p] += k.units[i];
+        k.launches[f][p]++;
+    }
+    k.used = 0;
+    return rc;
+}
+
+int kt_begin(Ctx *c) {
+    KTimer &k = c->kt;
+    if (!k.on) return -1;
+    if (k.used == KT_SLOTS && kt_flush(c)) return -1;
+    const int s = k.used++;
+    if (hipEventRecord(k.ev[2 * s], c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        k.used--;
+        return -1;
+    }
+    return s;
+}
+
+void kt_end(Ctx *c, int slot, int family, int prec, double units) {
+    if (slot < 0) return;
+    KTimer &k = c->kt;
+    (void)hipEventRecord(k.ev[2 * slot + 1], c->stream);
+    k.fam[slot] = family * 2 + (prec == MGDD_F32 ? 1 : 0);
+    k.units[slot] = units;
+}
+
+static void kt_release(Ctx *c) {
+    for (hipEvent_t e : c->kt.ev) (void)hipEventDestroy(e);
+    c->kt.ev.clear();
+    c->kt.on = false;
+    c->kt.used = 0;
+}
+
 static int setup_geometry(Ctx *c, const int *dims, const int *block) {
     std::vector<uint32_t> coord;
     std::vector<int> nbr, lexpos;
@@ -107,6 +157,13 @@ static int setup_geometry(Ctx *c, const int *dims, const int *block) {
 }
 
 static bool valid_prec(int p) { return p == MGDD_F64 || p == MGDD_F32; }
+
+// true when the last error was a failed device allocation (then a smaller
+// batch may fit); clears the HIP error state
+static bool alloc_failed(Ctx *c) {
+    (void)hipGetLastError();
+    return c->err.rfind("hipMalloc", 0) == 0;
+}
 
 }  // namespace mgdd
 
@@ -158,6 +215,7 @@ int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ct
 int mgdd_destroy(mgdd_ctx *ctx) {
     if (!ctx) return MGDD_OK;
     (void)hipStreamSynchronize(ctx->c.stream);
+    kt_release(&ctx->c);
     for (void *p : ctx->c.owned) (void)hipFree(p);
     if (ctx->c.red_host) (void)hipHostFree(ctx->c.red_host);
     if (ctx->c.hbuf) (void)hipHostFree(ctx->c.hbuf);
@@ -334,10 +392,8 @@ int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     Arena A;
-    rc = arena_open(c, coarse_gmres_bytes(c, prec, iters), A);
-    size_t nc = (size_t)c->c.Vc * 2 * c->c.N * csize(prec);
-    for (int r = 0; r < nrhs && !rc; r++)
-        rc = coarse_gmres(c, prec, iters, (const char *)b + r * nc, (char *)x + r * nc, A);
+    rc = arena_open(c, coarse_gmres_bytes(c, prec, iters, nrhs), A);
+    if (!rc) rc = coarse_gmres(c, prec, iters, nrhs, b, x, A);
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     return rc;
     GUARD_END
@@ -352,11 +408,8 @@ int mgdd_precondition(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, i
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     Arena A;
-    rc = arena_open(c, precond_bytes(c, prec, coarse_iters), A);
-    size_t n = (size_t)12 * c->g.V;
-    for (int k = 0; k < nrhs && !rc; k++)
-        rc = mg_precond(c, prec, (const char *)r + k * n * 16, (char *)z + k * n * csize(prec), nu, mr_iters,
-                        coarse_iters, A);
+    rc = arena_open(c, precond_bytes(c, prec, coarse_iters, nrhs), A);
+    if (!rc) rc = mg_precond(c, prec, nrhs, r, z, nu, mr_iters, coarse_iters, A);
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     return rc;
     GUARD_END
@@ -394,16 +447,74 @@ int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const v
     }
     GUARD_BEGIN
     Ctx *c = &ctx->c;
-    size_t n = (size_t)12 * c->g.V * 16;
-    int result = MGDD_OK;
-    for (int r = 0; r < nrhs; r++) {
-        mgdd_solve_stats st{};
-        int rc = solve_one(c, sp, (const char *)b + r * n, (char *)z + r * n, &st);
-        if (stats) stats[r] = st;
-        if (rc == MGDD_ENOCONV) { result = rc; continue; }
-        if (rc) return rc;
+    const size_t n = (size_t)12 * c->g.V * 16;
+    std::vector<mgdd_solve_stats> st(nrhs);
+    // all right-hand sides in one batched solve; when the workspace for that
+    // does not fit in device memory, in batches of half the size, and so on
+    int batch = nrhs, result = MGDD_OK;
+    for (int r0 = 0; r0 < nrhs;) {
+        const int nb = nrhs - r0 < batch ? nrhs - r0 : batch;
+        int rc = solve_batch(c, sp, nb, (const char *)b + r0 * n, (char *)z + r0 * n, st.data() + r0);
+        if (rc == MGDD_ENOMEM && nb > 1 && alloc_failed(c)) {
+            batch = (nb + 1) / 2;
+            continue;
+        }
+        if (rc == MGDD_ENOCONV) result = rc;
+        else if (rc) {
+            if (stats) std::copy(st.begin(), st.end(), stats);
+            return rc;
+        }
+        r0 += nb;
     }
+    if (stats) std::copy(st.begin(), st.end(), stats);
     return result;
+    GUARD_END
+}
+
+int mgdd_timing_enable(mgdd_ctx *ctx, int on) {
+    if (!ctx) return MGDD_EINVAL;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    if (!on) {
+        int rc = kt_flush(c);
+        c->kt.on = false;
+        return rc;
+    }
+    if (c->kt.ev.empty()) {
+        c->kt.ev.resize(2 * KT_SLOTS);
+        for (auto &e : c->kt.ev) {
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                e = nullptr;
+                kt_release(c);
+                return fail(c, MGDD_EHIP, "hipEventCreate failed");
+            }
+        }
+        c->kt.fam.assign(KT_SLOTS, 0);
+        c->kt.units.assign(KT_SLOTS, 0.0);
+    }
+    c->kt.on = true;
+    return MGDD_OK;
+    GUARD_END
+}
+
+int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *total_ms, double *site_updates,
+                     long long *launches) {
+    if (!ctx || kernel < 0 || kernel >= KF_COUNT || !valid_prec(prec)) return MGDD_EINVAL;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    int rc = kt_flush(c);
+    if (rc) return rc;
+    const int p = prec == MGDD_F32 ? 1 : 0;
+    if (total_ms) *total_ms = c->kt.ms[kernel][p];
+    if (site_updates) *site_updates = c->kt.usum[kernel][p];
+    if (launches) *launches = c->kt.launches[kernel][p];
+    if (reset) {
+        c->kt.ms[kernel][p] = 0;
+        c->kt.usum[kernel][p] = 0;
+        c->kt.launches[kernel][p] = 0;
+    }
+    return MGDD_OK;
     GUARD_END
 }
 

@@ -41,12 +41,14 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
 
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
+    const int slot = kt_begin(c);
     if (prec == MGDD_F64)
         dirac_kernel<double><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
                                                          (const double2 *)in, (double2 *)out, nrhs, nwg);
     else
         dirac_kernel<float><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32, (const float2 *)c->A32,
                                                         (const float2 *)in, (float2 *)out, nrhs, nwg);
+    kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs);
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
 

@@ -72,6 +72,21 @@ struct Level1 {  // coarse level of the current P
     void *tv64 = nullptr;                   // the N test vectors P was built from
 };
 
+// Optional timing of kernel families with HIP events on the context's stream:
+// each launch is bracketed by an event pair from a fixed pool; durations are
+// added up when the pool is full or when the caller reads them.
+enum KernelFamily { KF_DIRAC = 0, KF_SAP = 1, KF_COUNT = 2 };
+struct KTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;      // 2 per slot
+    std::vector<int> fam;            // family * 2 + precision, per used slot
+    std::vector<double> units;       // site-rhs updates, per used slot
+    int used = 0;
+    double ms[KF_COUNT][2] = {};
+    double usum[KF_COUNT][2] = {};
+    long long launches[KF_COUNT][2] = {};
+};
+
 struct Ctx {
     Geom g{};
     hipStream_t stream = nullptr;
@@ -100,6 +115,7 @@ struct Ctx {
     void *ws = nullptr;                     // solver / setup workspace
     size_t ws_bytes = 0;
     void *hbuf = nullptr;                   // pinned scalars (see host_buf)
+    KTimer kt;
 };
 
 int fail(Ctx *c, int code, const std::string &msg);
@@ -109,6 +125,10 @@ void dfree(Ctx *c, void *p);
 void *ensure_stage(Ctx *c, size_t bytes);
 void *ensure_scratch(Ctx *c, size_t bytes);
 double *ensure_red(Ctx *c, size_t ndoubles);
+// kt_begin returns a slot (or -1 when timing is off); kt_end closes it.
+int kt_begin(Ctx *c);
+void kt_end(Ctx *c, int slot, int family, int prec, double units);
+int kt_flush(Ctx *c);
 inline size_t csize(int prec) { return prec == MGDD_F64 ? 16 : 8; }
 inline size_t fine_elems(const Ctx *c, int nrhs) { return (size_t)nrhs * 12 * c->g.V; }
 

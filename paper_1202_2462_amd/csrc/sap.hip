@@ -439,6 +439,7 @@ int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, doub
             int nblocks = col ? g.nblocks - g.ncol0 : g.ncol0;
             if (nblocks == 0) continue;
             dim3 grid(nblocks, nrhs);
+            const int slot = kt_begin(c);
             if (prec == MGDD_F64) {
                 sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64,
                                                                           (const double2 *)c->A64, (const double2 *)b,
@@ -452,6 +453,7 @@ int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, doub
                                                                          (const float2 *)c->A32, (const float2 *)b,
                                                                          (float2 *)z, col, mr, (float)sre, (float)sim);
             }
+            kt_end(c, slot, KF_SAP, prec, (double)nblocks * g.Vb * nrhs);
             int rc = hip_check(c, hipGetLastError(), "sap kernel");
             if (rc) return rc;
         }

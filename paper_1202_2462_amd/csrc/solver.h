@@ -17,11 +17,13 @@ struct Arena {
 int arena_open(Ctx *c, size_t bytes, Arena &a);
 std::complex<double> *host_buf(Ctx *c, size_t n);
 
-size_t coarse_gmres_bytes(const Ctx *c, int p, int m);
-size_t precond_bytes(const Ctx *c, int p, int cit);
-int coarse_gmres(Ctx *c, int p, int m, const void *b, void *x, Arena &A);
-int mg_precond(Ctx *c, int p, const void *r64, void *z, int nu, int mr, int cit, Arena &A);
-int solve_one(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st);
+// nb: number of right-hand sides handled together (stacked fields)
+size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb);
+size_t precond_bytes(const Ctx *c, int p, int cit, int nb);
+size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb);
+int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A);
+int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, int nu, int mr, int cit, Arena &A);
+int solve_batch(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st);
 int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64);
 
 }  // namespace mgdd

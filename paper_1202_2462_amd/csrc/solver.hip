@@ -114,15 +114,18 @@ static void hessenberg_lsq(int k, const std::vector<cd> &Hcol, int ldh, double b
 
 // ---------------------------------------------------------------- Gram-Schmidt steps on the device
 
-// w <- w - V (V^H w), twice (classical Gram-Schmidt with one re-orthogonalisation);
-// h1 and h2 receive the two coefficient vectors, nrm the squared norm of w after.
-static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm) {
-    int rc = blas_multidot(c, p, p, n, V, k, w, h1);
-    if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h1, -1.0, 1.0, w);
-    if (!rc) rc = blas_multidot(c, p, p, n, V, k, w, h2);
-    if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h2, -1.0, 1.0, w);
+// w <- w - V (V^H w), twice (classical Gram-Schmidt with one re-orthogonalisation),
+// for each of the nb segments (right-hand sides) independently; h1 and h2
+// receive the two coefficient vectors ([i][segment]), nrm the squared norms
+// of w after.
+static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm,
+                int nb = 1) {
+    int rc = blas_multidot(c, p, p, n, V, k, w, h1, nb);
+    if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h1, -1.0, 1.0, w, nb);
+    if (!rc) rc = blas_multidot(c, p, p, n, V, k, w, h2, nb);
+    if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h2, -1.0, 1.0, w, nb);
     const void *wp = w;
-    if (!rc) rc = blas_multidot(c, p, p, n, &wp, 1, w, nrm);
+    if (!rc) rc = blas_multidot(c, p, p, n, &wp, 1, w, nrm, nb);
     return rc;
 }
 
@@ -145,77 +148,83 @@ static int mgs_device(Ctx *c, int p, size_t n, void *const *X, int nv, double2 *
 
 // ---------------------------------------------------------------- coarse GMRES
 
-size_t coarse_gmres_bytes(const Ctx *c, int p, int m) {
-    size_t n = (size_t)c->c.Vc * 2 * c->c.N;
-    return (size_t)(m + 2) * (n * csize(p) + 256) + 4 * (size_t)(m + 2) * (m + 2) * 16 + 4096;
+size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb) {
+    size_t n = (size_t)c->c.Vc * 2 * c->c.N * nb;
+    return (size_t)(m + 2) * (n * csize(p) + 256) + (4 * (size_t)(m + 2) * (m + 2) + 2 * (size_t)(m + 2)) * nb * 16 + 4096;
 }
 
-// x = GMRES_m(D_c, b) from x = 0, no restart, one host synchronisation.
-int coarse_gmres(Ctx *c, int p, int m, const void *b, void *x, Arena &A) {
+// x_s = GMRES_m(D_c, b_s) from x = 0, no restart, for nb right-hand sides at
+// once (one Krylov basis and one Hessenberg matrix each, shared launches);
+// one host synchronisation.
+int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A) {
     const size_t n = (size_t)c->c.Vc * 2 * c->c.N, cs = csize(p);
     const size_t mark = A.off;
     std::vector<void *> V(m + 1);
-    for (int i = 0; i <= m; i++) V[i] = A.take(n * cs);
-    void *w = A.take(n * cs);
-    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * (m + 1) * 16);
-    double2 *h2 = (double2 *)A.take((size_t)(m + 1) * (m + 1) * 16);
-    double2 *nr = (double2 *)A.take((size_t)(m + 2) * 16);
-    double2 *coef = (double2 *)A.take((size_t)(m + 2) * 16);
+    for (int i = 0; i <= m; i++) V[i] = A.take(n * nb * cs);
+    void *w = A.take(n * nb * cs);
+    const size_t hs = (size_t)(m + 1) * (m + 1) * nb;   // column j at j (m + 1) nb, entry [i][s]
+    double2 *h1 = (double2 *)A.take(hs * 16);
+    double2 *h2 = (double2 *)A.take(hs * 16);
+    double2 *nr = (double2 *)A.take((size_t)(m + 2) * nb * 16);
+    double2 *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
     if (!coef) return fail(c, MGDD_ENOMEM, "coarse GMRES workspace");
     const void *bp = b;
-    int rc = blas_multidot(c, p, p, n, &bp, 1, b, nr);
-    if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0]);
+    int rc = blas_multidot(c, p, p, n, &bp, 1, b, nr, nb);
+    if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0], nb);
     for (int j = 0; j < m && !rc; j++) {
-        rc = launch_coarse_apply(c, p, 1, V[j], w);
-        if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1), h2 + (size_t)j * (m + 1), nr + j + 1);
-        if (!rc) rc = blas_normalize(c, p, p, n, w, nr + j + 1, V[j + 1]);
+        rc = launch_coarse_apply(c, p, nb, V[j], w);
+        if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1) * nb, h2 + (size_t)j * (m + 1) * nb,
+                           nr + (size_t)(j + 1) * nb, nb);
+        if (!rc) rc = blas_normalize(c, p, p, n, w, nr + (size_t)(j + 1) * nb, V[j + 1], nb);
     }
     if (rc) return rc;
-    const size_t hs = (size_t)(m + 1) * (m + 1);
-    cd *hb = host_buf(c, 2 * hs + m + 2 + m + 1);
+    cd *hb = host_buf(c, 2 * hs + (size_t)(m + 1) * nb + (size_t)m * nb);
     if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
     rc = hip_check(c, hipMemcpyAsync(hb, h1, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
     if (!rc) rc = hip_check(c, hipMemcpyAsync(hb + hs, h2, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
-    if (!rc) rc = read_dev(c, nr, m + 1, hb + 2 * hs);
+    if (!rc) rc = read_dev(c, nr, (size_t)(m + 1) * nb, hb + 2 * hs);
     if (rc) return rc;
     const cd *H1 = hb, *H2 = hb + hs, *NR = hb + 2 * hs;
-    double beta = std::sqrt(NR[0].real());
-    if (!std::isfinite(beta)) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
-    if (beta == 0.0) {
-        A.off = mark;
-        return blas_lincomb(c, p, p, n, nullptr, 0, nullptr, 0.0, 0.0, x);
+    cd *yb = hb + 2 * hs + (size_t)(m + 1) * nb;   // [i][s]
+    for (size_t q = 0; q < (size_t)m * nb; q++) yb[q] = 0.0;
+    std::vector<cd> Hc((size_t)m * (m + 1)), y;
+    for (int sg = 0; sg < nb; sg++) {
+        const double beta = std::sqrt(NR[sg].real());
+        if (!std::isfinite(beta)) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
+        if (beta == 0.0) continue;   // x_s = 0
+        std::fill(Hc.begin(), Hc.end(), cd(0.0));
+        int k = m;
+        for (int j = 0; j < m; j++) {
+            const size_t cj = (size_t)j * (m + 1) * nb;
+            for (int i = 0; i <= j; i++)
+                Hc[(size_t)j * (m + 1) + i] = H1[cj + (size_t)i * nb + sg] + H2[cj + (size_t)i * nb + sg];
+            double hn = std::sqrt(std::max(NR[(size_t)(j + 1) * nb + sg].real(), 0.0));
+            Hc[(size_t)j * (m + 1) + j + 1] = hn;
+            if (hn == 0.0) { k = j + 1; break; }
+        }
+        hessenberg_lsq(k, Hc, m + 1, beta, y);
+        for (int i = 0; i < k; i++) {
+            if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
+            yb[(size_t)i * nb + sg] = y[i];
+        }
     }
-    std::vector<cd> Hc((size_t)m * (m + 1), 0.0);
-    int k = m;
-    for (int j = 0; j < m; j++) {
-        for (int i = 0; i <= j; i++) Hc[(size_t)j * (m + 1) + i] = H1[(size_t)j * (m + 1) + i] + H2[(size_t)j * (m + 1) + i];
-        double hn = std::sqrt(std::max(NR[j + 1].real(), 0.0));
-        Hc[(size_t)j * (m + 1) + j + 1] = hn;
-        if (hn == 0.0) { k = j + 1; break; }
-    }
-    std::vector<cd> y;
-    hessenberg_lsq(k, Hc, m + 1, beta, y);
-    cd *yb = hb + 2 * hs + m + 2;
-    for (int i = 0; i < k; i++) {
-        if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
-        yb[i] = y[i];
-    }
-    rc = write_dev(c, yb, k, coef);
-    if (!rc) rc = blas_lincomb(c, p, p, n, V.data(), k, coef, 1.0, 0.0, x);
+    rc = write_dev(c, yb, (size_t)m * nb, coef);
+    if (!rc) rc = blas_lincomb(c, p, p, n, V.data(), m, coef, 1.0, 0.0, x, nb);
     A.off = mark;
     return rc;
 }
 
 // ---------------------------------------------------------------- two-level preconditioner
 
-size_t precond_bytes(const Ctx *c, int p, int cit) {
-    size_t n = (size_t)12 * c->g.V, nc = (size_t)c->c.Vc * 2 * c->c.N;
-    return n * 8 + 2 * nc * csize(p) + coarse_gmres_bytes(c, p, cit) + 4096;
+size_t precond_bytes(const Ctx *c, int p, int cit, int nb) {
+    size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
+    return n * 8 + 2 * nc * csize(p) + coarse_gmres_bytes(c, p, cit, nb) + 4096;
 }
 
-// z = SAP^nu(D, r, z0 = P GMRES_cit(D_c, P^H r)); r in FP64, z in precision p.
-int mg_precond(Ctx *c, int p, const void *r64, void *z, int nu, int mr, int cit, Arena &A) {
-    const size_t n = (size_t)12 * c->g.V, nc = (size_t)c->c.Vc * 2 * c->c.N;
+// z = SAP^nu(D, r, z0 = P GMRES_cit(D_c, P^H r)) for nb right-hand sides at
+// once; r in FP64, z in precision p.
+int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, int nu, int mr, int cit, Arena &A) {
+    const size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
     const size_t mark = A.off;
     const void *rp = r64;
     int rc = MGDD_OK;
@@ -227,117 +236,181 @@ int mg_precond(Ctx *c, int p, const void *r64, void *z, int nu, int mr, int cit,
     }
     void *cb = A.take(nc * csize(p)), *cx = A.take(nc * csize(p));
     if (!cx) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
-    if (!rc) rc = launch_restrict(c, p, 1, rp, cb);
-    if (!rc) rc = coarse_gmres(c, p, cit, cb, cx, A);
-    if (!rc) rc = launch_prolong(c, p, 1, cx, z);
-    if (!rc && nu > 0) rc = launch_sap(c, p, 1, nu, mr, 0.0, 0.0, rp, z);
+    if (!rc) rc = launch_restrict(c, p, nb, rp, cb);
+    if (!rc) rc = coarse_gmres(c, p, cit, nb, cb, cx, A);
+    if (!rc) rc = launch_prolong(c, p, nb, cx, z);
+    if (!rc && nu > 0) rc = launch_sap(c, p, nb, nu, mr, 0.0, 0.0, rp, z);
     A.off = mark;
     return rc;
 }
 
 // ---------------------------------------------------------------- FGMRES with the two-level preconditioner
 
-static int fgmres(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st, Arena &A) {
+// Flexible GMRES(m) for nb right-hand sides at once: each has its own Krylov
+// basis, Hessenberg matrix, Givens rotations, restarts and stopping test;
+// the preconditioner, D and the Gram-Schmidt kernels run on all of them in
+// shared launches. A right-hand side that has converged (or ended its
+// cycle) gets zero coefficients, so its vectors stay zero until the next
+// restart and its iterate no longer changes.
+static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st,
+                  Arena &A) {
     const int m = sp->restart, p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
-    const size_t n = (size_t)12 * c->g.V, cs = csize(p);
+    const size_t n = (size_t)12 * c->g.V, cs = csize(p), nn = n * nb;
     std::vector<void *> V(m + 1), Z(m);
-    for (int i = 0; i <= m; i++) V[i] = A.take(n * 16);
-    for (int i = 0; i < m; i++) Z[i] = A.take(n * cs);
-    void *w = A.take(n * 16), *r = A.take(n * 16);
-    void *z64 = p == MGDD_F32 ? A.take(n * 16) : nullptr;
-    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * 16), *h2 = (double2 *)A.take((size_t)(m + 1) * 16);
-    double2 *nr = (double2 *)A.take(64), *coef = (double2 *)A.take((size_t)(m + 2) * 16);
-    double2 *pm = (double2 *)A.take(32);
+    for (int i = 0; i <= m; i++) V[i] = A.take(nn * 16);
+    for (int i = 0; i < m; i++) Z[i] = A.take(nn * cs);
+    void *w = A.take(nn * 16), *r = A.take(nn * 16);
+    void *z64 = p == MGDD_F32 ? A.take(nn * 16) : nullptr;
+    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * nb * 16), *h2 = (double2 *)A.take((size_t)(m + 1) * nb * 16);
+    double2 *nr = (double2 *)A.take((size_t)nb * 16), *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
+    double2 *pm = (double2 *)A.take((size_t)2 * nb * 16);
     if (!pm) return fail(c, MGDD_ENOMEM, "FGMRES workspace");
-    cd *hb = host_buf(c, 4 * (size_t)(m + 2) + 8);
-    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
-    hb[0] = 1.0;
-    hb[1] = -1.0;
-    int rc = write_dev(c, hb, 2, pm);
-    const void *bp = b;
-    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &bp, 1, b, nr);
-    if (!rc) rc = read_dev(c, nr, 1, hb + 4);
-    if (rc) return rc;
-    const double bn = std::sqrt(hb[4].real());
-    if (!std::isfinite(bn)) return fail(c, MGDD_ENAN, "right-hand side holds NaN or Inf");
-    st->iters = st->restarts = 0;
-    st->converged = 0;
-    if (bn == 0.0) {
-        st->converged = 1;
-        st->relres = 0.0;
-        return blas_lincomb(c, MGDD_F64, MGDD_F64, n, nullptr, 0, nullptr, 0.0, 0.0, z);
+    // pinned scalars: [pm 2nb | h1 (m+1)nb | h2 (m+1)nb | norms nb | coefficients (m+1)nb]
+    cd *hb = host_buf(c, (size_t)nb * (3 * (size_t)m + 6));
+    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer (too many right-hand sides for this restart length)");
+    cd *Hb1 = hb + 2 * nb, *Hb2 = Hb1 + (size_t)(m + 1) * nb, *Nb = Hb2 + (size_t)(m + 1) * nb,
+       *Cb = Nb + nb;
+    for (int sg = 0; sg < nb; sg++) {
+        hb[sg] = 1.0;
+        hb[nb + sg] = -1.0;
     }
+    int rc = write_dev(c, hb, 2 * (size_t)nb, pm);
+    const void *bp = b;
+    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &bp, 1, b, nr, nb);
+    if (!rc) rc = read_dev(c, nr, nb, Nb);
+    if (rc) return rc;
+    std::vector<double> bn(nb), hn(nb);
+    std::vector<char> active(nb, 1), incycle(nb);
+    bool zero_rhs = false;
+    for (int sg = 0; sg < nb; sg++) {
+        bn[sg] = std::sqrt(Nb[sg].real());
+        if (!std::isfinite(bn[sg])) return fail(c, MGDD_ENAN, "right-hand side holds NaN or Inf");
+        st[sg].iters = st[sg].restarts = 0;
+        st[sg].converged = 0;
+        st[sg].relres = 0.0;
+        if (bn[sg] == 0.0) {
+            st[sg].converged = 1;
+            active[sg] = 0;
+            zero_rhs = true;
+        }
+    }
+    if (zero_rhs) {   // z_s = 0 for b_s = 0
+        for (int sg = 0; sg < nb; sg++) Cb[sg] = active[sg] ? 1.0 : 0.0;
+        rc = write_dev(c, Cb, nb, coef);
+        if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, z, coef, make_double2(1, 0), z, nb);
+        if (rc) return rc;
+    }
+    std::vector<std::vector<cd>> Hc(nb), g(nb), sn(nb);
+    std::vector<std::vector<double>> cs_(nb);
+    std::vector<int> k(nb);
     for (;;) {
-        // true residual r = b - D z
-        rc = launch_dirac(c, MGDD_F64, 1, z, w);
+        // true residuals r = b - D z
+        rc = launch_dirac(c, MGDD_F64, nb, z, w);
         const void *bw[2] = {b, w};
-        if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, bw, 2, pm, 1.0, 0.0, r);
+        if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, bw, 2, pm, 1.0, 0.0, r, nb);
         const void *rp = r;
-        if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &rp, 1, r, nr);
-        if (!rc) rc = read_dev(c, nr, 1, hb + 4);
+        if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &rp, 1, r, nr, nb);
+        if (!rc) rc = read_dev(c, nr, nb, Nb);
         if (rc) return rc;
-        const double rn = std::sqrt(hb[4].real());
-        if (!std::isfinite(rn)) return fail(c, MGDD_ENAN, "NaN in the residual");
-        st->relres = rn / bn;
-        if (rn <= sp->tol * bn) { st->converged = 1; return MGDD_OK; }
-        if (st->iters >= sp->maxit) return MGDD_OK;
-        rc = blas_scale(c, MGDD_F64, MGDD_F64, n, r, nullptr, make_double2(1.0 / rn, 0), V[0]);
+        bool any = false;
+        for (int sg = 0; sg < nb; sg++) {
+            Cb[sg] = 0.0;
+            if (!active[sg]) continue;
+            const double rn = std::sqrt(Nb[sg].real());
+            if (!std::isfinite(rn)) return fail(c, MGDD_ENAN, "NaN in the residual");
+            st[sg].relres = rn / bn[sg];
+            if (rn <= sp->tol * bn[sg]) {
+                st[sg].converged = 1;
+                active[sg] = 0;
+            } else if (st[sg].iters >= sp->maxit) {
+                active[sg] = 0;
+            } else {
+                Cb[sg] = 1.0 / rn;
+                any = true;
+            }
+        }
+        if (!any) return MGDD_OK;
+        rc = write_dev(c, Cb, nb, coef);
+        if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, r, coef, make_double2(1, 0), V[0], nb);
         if (rc) return rc;
-        std::vector<cd> Hc((size_t)m * (m + 1), 0.0), g(m + 1, 0.0), sn(m);
-        std::vector<double> cs_(m);
-        g[0] = rn;
-        int k = 0;
+        for (int sg = 0; sg < nb; sg++) {
+            incycle[sg] = active[sg];
+            Hc[sg].assign((size_t)m * (m + 1), 0.0);
+            g[sg].assign(m + 1, 0.0);
+            g[sg][0] = std::sqrt(Nb[sg].real());
+            sn[sg].assign(m, 0.0);
+            cs_[sg].assign(m, 0.0);
+            k[sg] = 0;
+        }
+        int kmax = 0;
         for (int j = 0; j < m; j++) {
-            rc = mg_precond(c, p, V[j], Z[j], sp->nu, sp->mr_iters, sp->coarse_iters, A);
+            rc = mg_precond(c, p, nb, V[j], Z[j], sp->nu, sp->mr_iters, sp->coarse_iters, A);
             if (!rc && p == MGDD_F32) {
-                rc = launch_convert(c, MGDD_F32, MGDD_F64, n, Z[j], z64);
-                if (!rc) rc = launch_dirac(c, MGDD_F64, 1, z64, w);
+                rc = launch_convert(c, MGDD_F32, MGDD_F64, nn, Z[j], z64);
+                if (!rc) rc = launch_dirac(c, MGDD_F64, nb, z64, w);
             } else if (!rc) {
-                rc = launch_dirac(c, MGDD_F64, 1, Z[j], w);
+                rc = launch_dirac(c, MGDD_F64, nb, Z[j], w);
             }
-            if (!rc) rc = cgs2(c, MGDD_F64, n, V.data(), j + 1, w, h1, h2, nr);
+            if (!rc) rc = cgs2(c, MGDD_F64, n, V.data(), j + 1, w, h1, h2, nr, nb);
             if (rc) return rc;
-            rc = hip_check(c, hipMemcpyAsync(hb, h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, c->stream), "read");
-            if (!rc) rc = hip_check(c, hipMemcpyAsync(hb + m + 2, h2, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, c->stream), "read");
-            if (!rc) rc = read_dev(c, nr, 1, hb + 2 * (m + 2));
+            rc = hip_check(c, hipMemcpyAsync(Hb1, h1, (size_t)(j + 1) * nb * 16, hipMemcpyDeviceToHost, c->stream), "read");
+            if (!rc) rc = hip_check(c, hipMemcpyAsync(Hb2, h2, (size_t)(j + 1) * nb * 16, hipMemcpyDeviceToHost, c->stream), "read");
+            if (!rc) rc = read_dev(c, nr, nb, Nb);
             if (rc) return rc;
-            cd *col = &Hc[(size_t)j * (m + 1)];
-            for (int i = 0; i <= j; i++) col[i] = hb[i] + hb[m + 2 + i];
-            const double hn = std::sqrt(std::max(hb[2 * (m + 2)].real(), 0.0));
-            if (!std::isfinite(hn)) return fail(c, MGDD_ENAN, "NaN in the Arnoldi step");
-            col[j + 1] = hn;
-            for (int i = 0; i < j; i++) {
-                cd a = col[i], bb = col[i + 1];
-                col[i] = cs_[i] * a + sn[i] * bb;
-                col[i + 1] = -std::conj(sn[i]) * a + cs_[i] * bb;
+            kmax = j + 1;
+            bool more = false;
+            for (int sg = 0; sg < nb; sg++) {
+                Cb[sg] = 0.0;
+                if (!incycle[sg]) continue;
+                cd *col = &Hc[sg][(size_t)j * (m + 1)];
+                for (int i = 0; i <= j; i++) col[i] = Hb1[(size_t)i * nb + sg] + Hb2[(size_t)i * nb + sg];
+                const double h = std::sqrt(std::max(Nb[sg].real(), 0.0));
+                if (!std::isfinite(h)) return fail(c, MGDD_ENAN, "NaN in the Arnoldi step");
+                col[j + 1] = h;
+                for (int i = 0; i < j; i++) {
+                    cd a = col[i], bb = col[i + 1];
+                    col[i] = cs_[sg][i] * a + sn[sg][i] * bb;
+                    col[i + 1] = -std::conj(sn[sg][i]) * a + cs_[sg][i] * bb;
+                }
+                cd rho;
+                la::givens(col[j], col[j + 1], cs_[sg][j], sn[sg][j], rho);
+                col[j] = rho;
+                col[j + 1] = 0.0;
+                cd gj = g[sg][j];
+                g[sg][j] = cs_[sg][j] * gj;
+                g[sg][j + 1] = -std::conj(sn[sg][j]) * gj;
+                st[sg].iters++;
+                k[sg] = j + 1;
+                if (std::abs(g[sg][j + 1]) <= sp->tol * bn[sg] || h == 0.0 || st[sg].iters >= sp->maxit) {
+                    incycle[sg] = 0;
+                } else {
+                    Cb[sg] = 1.0 / h;
+                    more = true;
+                }
             }
-            cd rho;
-            la::givens(col[j], col[j + 1], cs_[j], sn[j], rho);
-            col[j] = rho;
-            col[j + 1] = 0.0;
-            cd gj = g[j];
-            g[j] = cs_[j] * gj;
-            g[j + 1] = -std::conj(sn[j]) * gj;
-            st->iters++;
-            k = j + 1;
-            if (std::abs(g[j + 1]) <= sp->tol * bn || hn == 0.0 || st->iters >= sp->maxit) break;
-            rc = blas_scale(c, MGDD_F64, MGDD_F64, n, w, nullptr, make_double2(1.0 / hn, 0), V[j + 1]);
+            if (!more || j + 1 == m) break;
+            rc = write_dev(c, Cb, nb, coef);
+            if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, w, coef, make_double2(1, 0), V[j + 1], nb);
             if (rc) return rc;
         }
-        // R y = g (R upper triangular after the rotations)
-        std::vector<cd> y(k);
-        for (int i = k - 1; i >= 0; i--) {
-            cd s = g[i];
-            for (int l = i + 1; l < k; l++) s -= Hc[(size_t)l * (m + 1) + i] * y[l];
-            y[i] = s / Hc[(size_t)i * (m + 1) + i];
-            if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the least-squares solve");
+        // R y = g (R upper triangular after the rotations), per right-hand side
+        for (size_t q = 0; q < (size_t)kmax * nb; q++) Cb[q] = 0.0;
+        for (int sg = 0; sg < nb; sg++) {
+            if (!active[sg]) continue;
+            const int kk = k[sg];
+            std::vector<cd> y(kk);
+            for (int i = kk - 1; i >= 0; i--) {
+                cd sacc = g[sg][i];
+                for (int l = i + 1; l < kk; l++) sacc -= Hc[sg][(size_t)l * (m + 1) + i] * y[l];
+                y[i] = sacc / Hc[sg][(size_t)i * (m + 1) + i];
+                if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the least-squares solve");
+            }
+            for (int i = 0; i < kk; i++) Cb[(size_t)i * nb + sg] = y[i];
+            st[sg].restarts++;
         }
-        cd *yb = hb + 3 * (m + 2);
-        for (int i = 0; i < k; i++) yb[i] = y[i];
-        rc = write_dev(c, yb, k, coef);
-        if (!rc) rc = blas_lincomb(c, p, MGDD_F64, n, Z.data(), k, coef, 1.0, 1.0, z);
+        rc = write_dev(c, Cb, (size_t)kmax * nb, coef);
+        if (!rc) rc = blas_lincomb(c, p, MGDD_F64, n, Z.data(), kmax, coef, 1.0, 1.0, z, nb);
         if (rc) return rc;
-        st->restarts++;
     }
 }
 
@@ -484,29 +557,41 @@ static int gcr_solve(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z
 
 // ---------------------------------------------------------------- solve entry
 
-size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp) {
+size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb) {
     const size_t n = (size_t)12 * c->g.V;
     const int m = sp->restart;
     if (sp->solver == MGDD_SOLVER_FGMRES_MG) {
         int p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
-        return (size_t)(m + 4) * (n * 16 + 256) + (size_t)m * (n * csize(p) + 256) + 8 * (size_t)(m + 2) * 16 +
-               precond_bytes(c, p, sp->coarse_iters) + 65536;
+        return (size_t)(m + 4) * (n * nb * 16 + 256) + (size_t)m * (n * nb * csize(p) + 256) +
+               (3 * (size_t)m + 8) * nb * 16 + precond_bytes(c, p, sp->coarse_iters, nb) + 65536;
     }
     return (size_t)(2 * m + 10) * (n * 16 + 256) + 65536;
 }
 
-int solve_one(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st) {
+// nb right-hand sides: one batched FGMRES, or GCR one after the other
+int solve_batch(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st) {
     Arena A;
-    int rc = arena_open(c, solve_bytes(c, sp), A);
+    const bool batched = sp->solver == MGDD_SOLVER_FGMRES_MG;
+    int rc = arena_open(c, solve_bytes(c, sp, batched ? nb : 1), A);
     if (rc) return rc;
     auto t0 = std::chrono::steady_clock::now();
-    if (sp->solver == MGDD_SOLVER_FGMRES_MG) rc = fgmres(c, sp, b, z, st, A);
-    else rc = gcr_solve(c, sp, b, z, st, A);
+    if (batched) {
+        rc = fgmres(c, sp, nb, b, z, st, A);
+    } else {
+        const size_t fb = (size_t)12 * c->g.V * 16;
+        for (int r = 0; r < nb && !rc; r++) {
+            A.off = 0;
+            rc = gcr_solve(c, sp, (const char *)b + r * fb, (char *)z + r * fb, &st[r], A);
+        }
+    }
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
-    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nb; r++) st[r].seconds = secs;
     if (A.need) return fail(c, MGDD_ENOMEM, "solver workspace estimate too small");
-    if (!rc && !st->converged) return fail(c, MGDD_ENOCONV, "maxit reached before the tolerance");
-    return rc;
+    if (rc) return rc;
+    for (int r = 0; r < nb; r++)
+        if (!st[r].converged) return fail(c, MGDD_ENOCONV, "maxit reached before the tolerance");
+    return MGDD_OK;
 }
 
 // ---------------------------------------------------------------- bootstrap setup

@@ -29,6 +29,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ESHAPE, ERANK, ENOTREADY, ENOCONV, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 F64, F32 = 0, 1
+KERNEL_DIRAC, KERNEL_SAP = 0, 1
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ERANK", -4: "ENOTREADY", -5: "ENOCONV", -6: "EBREAKDOWN",
           -7: "ENAN", -8: "EHIP", -9: "ENOMEM"}
 
@@ -95,6 +96,9 @@ _sig("mgdd_precondition", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.
      _vp, _vp)
 _sig("mgdd_setup_bootstrap", ctypes.c_int, _vp, ctypes.POINTER(SetupParams), _vp, _vp)
 _sig("mgdd_solve", ctypes.c_int, _vp, ctypes.POINTER(SolveParams), ctypes.c_int, _vp, _vp, ctypes.POINTER(SolveStats))
+_sig("mgdd_timing_enable", ctypes.c_int, _vp, ctypes.c_int)
+_sig("mgdd_timing_read", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong))
 
 
 def declared_symbols() -> list[str]:
@@ -222,6 +226,18 @@ def mgdd_solve(ctx, params: SolveParams, nrhs, b, z, allow_noconv=False):
     if not (rc == ENOCONV and allow_noconv):
         _check(ctx, rc)
     return [stats[i] for i in range(nrhs)]
+
+
+def mgdd_timing_enable(ctx, on=True):
+    return _check(ctx, _lib.mgdd_timing_enable(ctx, 1 if on else 0))
+
+
+def mgdd_timing_read(ctx, kernel, prec, reset=False):
+    """Returns (total_ms, site_updates, launches) for one kernel family."""
+    ms, units, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+    _check(ctx, _lib.mgdd_timing_read(ctx, kernel, prec, 1 if reset else 0, ctypes.byref(ms), ctypes.byref(units),
+                                      ctypes.byref(n)))
+    return ms.value, units.value, n.value
 
 
 # --------------------------------------------------------------------- convenience wrapper

@@ -52,6 +52,57 @@ def test_fgmres_mixed_reaches_tolerance():
         assert np.linalg.norm(b[r] - op.apply(got[r])) <= 1e-10 * np.linalg.norm(b[r])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_fgmres_equals_single_solves(precision):
+    """Several right-hand sides in one batched FGMRES: each has its own
+    Krylov space and stopping test, so every solution and iteration count
+    equals that of solving it alone (the per-segment reductions use the same
+    grid and order). The batch mixes a zero right-hand side, a point source
+    and Gaussian ones, so they converge after different iteration counts."""
+    from paper_1202_2462_amd.mgdd import F64
+    dims, block, agg, N, op = small_problem(seed=6)
+    say("batched fgmres precision", precision, dims)
+    lat = lattice(op, block)
+    lat.build_P(agg, lat.pack(latgen.gaussian_fields(dims, N, 79), F64))
+    g = latgen.gaussian_fields(dims, 2, 8)
+    pt = latgen.point_sources(dims, 9)[4:5]
+    b = np.concatenate([g[:1], np.zeros_like(g[:1]), pt, 1e-3 * g[1:]], 0)
+    zb, sb = lat.solve(lat.pack(b, F64), precision=precision, restart=8, tol=1e-10, maxit=400)
+    got = lat.unpack(zb)
+    for r in range(b.shape[0]):
+        z1, s1 = lat.solve(lat.pack(b[r:r + 1], F64), precision=precision, restart=8, tol=1e-10, maxit=400)
+        one = lat.unpack(z1)[0]
+        say("rhs", r, "batched iters", sb[r].iters, "restarts", sb[r].restarts, "single", s1[0].iters)
+        assert sb[r].converged and s1[0].converged
+        assert sb[r].iters == s1[0].iters and sb[r].restarts == s1[0].restarts
+        nb = np.linalg.norm(b[r])
+        if nb == 0:
+            assert np.all(got[r] == 0)
+            continue
+        assert np.linalg.norm(b[r] - op.apply(got[r])) <= 1e-10 * nb
+        assert np.abs(got[r] - one).max() <= 1e-12 * np.abs(one).max()
+
+
+def test_batched_coarse_solve_and_preconditioner_equal_single():
+    from paper_1202_2462_amd.mgdd import F32, F64
+    dims, block, agg, N, op = small_problem(seed=7)
+    say("batched coarse solve / preconditioner", dims)
+    lat = lattice(op, block)
+    lat.build_P(agg, lat.pack(latgen.gaussian_fields(dims, N, 80), F64))
+    for prec in (F64, F32):
+        cb = lat.coarse_field(prec, 3)
+        cb.normal_()
+        xb = lat.coarse_solve(cb, 12)
+        for r in range(3):
+            x1 = lat.coarse_solve(cb[r:r + 1].clone(), 12)
+            assert (xb[r] - x1[0]).abs().max().item() <= 1e-12 * x1.abs().max().item()
+        r64 = lat.pack(latgen.gaussian_fields(dims, 3, 11), F64)
+        zb = lat.precondition(r64, prec=prec)
+        for r in range(3):
+            z1 = lat.precondition(r64[r:r + 1].clone(), prec=prec)
+            assert (zb[r] - z1[0]).abs().max().item() <= 1e-12 * z1.abs().max().item()
+
+
 @pytest.mark.parametrize("solver", [1, 2])
 def test_gcr_and_even_odd_gcr(solver):
     from paper_1202_2462_amd.mgdd import F64

@@ -411,6 +411,81 @@ __global__ __launch_bounds__(256) void coarse_apply_kernel(int Vc, int N, const 
         y[((size_t)r * Vc + a) * n2 + i] = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
 }
 
+// D_c applied to many right-hand sides on the matrix cores. Per coarse site
+// a the product is Y = sum_dir B_dir X_nbr(dir), a (2N x 2N) by (2N x R)
+// complex matrix product for R right-hand sides, done as real 16x16x4 MFMA
+// tiles: Re Y += Re B Re X - Im B Im X, Im Y += Re B Im X + Im B Re X.
+// A wave owns output rows 16t .. 16t+15 of one coarse site for one tile of
+// 16 right-hand sides; its A operand (rows of B_dir, column-major blocks)
+// streams from HBM, its B operand (4 consecutive entries of 16 neighbour
+// vectors) comes through the caches, which the row tiles of a site share.
+// Rows and columns past 2N and right-hand sides past nrhs enter as zeros and
+// are not written.
+template <typename T> struct MfmaTypes;
+// Operands of both: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.
+// Result register v of lane l holds D[row][l % 16] with row = 4 (l / 16) + v
+// (FP32) or row = 4 v + l / 16 (FP64).
+template <> struct MfmaTypes<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int v, int kq) { return 4 * kq + v; }
+};
+template <> struct MfmaTypes<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int v, int kq) { return 4 * v + kq; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void coarse_apply_mfma_kernel(int Vc, int N, int nrhs, int ntiles,
+                                                               const int *__restrict__ cnbr,
+                                                               const C<T> *__restrict__ Dc,
+                                                               const C<T> *__restrict__ x, C<T> *__restrict__ y) {
+    using M = MfmaTypes<T>;
+    // one wave per (coarse site, row tile, rhs tile); the row tiles of one
+    // site are consecutive waves on one XCD, so that they share its L2
+    const int w = xcd_block(gridDim.x);
+    const int t = w % ntiles, a = w / ntiles, r0 = blockIdx.y * 16;
+    const int n2 = 2 * N;
+    const int lane = threadIdx.x;
+    const int row = t * 16 + (lane & 15), kq = lane >> 4, rl = lane & 15;
+    const bool rhs_ok = r0 + rl < nrhs;
+    // four independent accumulator chains (Re and Im, two each), so that
+    // consecutive MFMAs do not wait for each other's results
+    typename M::v4 re0 = {0, 0, 0, 0}, im0 = {0, 0, 0, 0}, re1 = {0, 0, 0, 0}, im1 = {0, 0, 0, 0};
+    const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
+    const int nq = (n2 + 3) >> 2;   // k-steps of 4 columns per direction (n2 <= 64)
+    for (int dd = 0; dd < 9; dd++) {
+        const C<T> *Bd = B + (size_t)dd * n2 * n2;
+        const C<T> *xd = x + ((size_t)(r0 + rl) * Vc + cnbr[a * 9 + dd]) * n2;
+        // all operands of this direction first, so that their loads overlap
+        C<T> av[16], bv[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int j = 4 * q + kq;
+            const bool kin = q < nq && j < n2;
+            av[q] = (kin && row < n2) ? Bd[(size_t)j * n2 + row] : mk<T>(0, 0);
+            bv[q] = (kin && rhs_ok) ? xd[j] : mk<T>(0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            if (q < nq) {
+                re0 = M::mma(av[q].x, bv[q].x, re0);
+                im0 = M::mma(av[q].x, bv[q].y, im0);
+                re1 = M::mma(-av[q].y, bv[q].y, re1);
+                im1 = M::mma(av[q].y, bv[q].x, im1);
+            }
+        }
+    }
+    if (!rhs_ok) return;
+    const typename M::v4 re = re0 + re1, im = im0 + im1;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int i = t * 16 + M::row(v, kq);
+        if (i < n2) y[((size_t)(r0 + rl) * Vc + a) * n2 + i] = mk<T>(re[v], im[v]);
+    }
+}
+
 template <typename T>
 __global__ void dc_to_f32(int Vc, int n2, const double2 *__restrict__ src, C<T> *__restrict__ dst) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -421,6 +496,9 @@ __global__ void dc_to_f32(int Vc, int n2, const double2 *__restrict__ src, C<T> 
 }  // namespace
 
 // ---------------------------------------------------------------- host side
+
+// from this many right-hand sides on, D_c is applied on the matrix cores
+static int MFMA_MIN_RHS = 4;
 
 int transfer_setup(Ctx *c, const int *agg, int N) {
     Level1 &L1 = c->c;
@@ -600,6 +678,17 @@ int launch_coarse_build(Ctx *c) {
 
 int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     const Level1 &L1 = c->c;
+    if (nrhs >= MFMA_MIN_RHS) {
+        const int ntiles = (2 * L1.N + 15) / 16;
+        dim3 grid(L1.Vc * ntiles, (nrhs + 15) / 16);
+        if (prec == MGDD_F64)
+            coarse_apply_mfma_kernel<double><<<grid, 64, 0, c->stream>>>(
+                L1.Vc, L1.N, nrhs, ntiles, L1.cnbr, (const double2 *)L1.Dc64, (const double2 *)in, (double2 *)out);
+        else
+            coarse_apply_mfma_kernel<float><<<grid, 64, 0, c->stream>>>(
+                L1.Vc, L1.N, nrhs, ntiles, L1.cnbr, (const float2 *)L1.Dc32, (const float2 *)in, (float2 *)out);
+        return hip_check(c, hipGetLastError(), "coarse apply kernel (MFMA)");
+    }
     dim3 grid(L1.Vc, nrhs);
     if (prec == MGDD_F64)
         coarse_apply_kernel<double><<<grid, 256, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,

@@ -78,6 +78,26 @@ def test_coarse_operator_parity(dims, block, agg, N):
         assert rel(got, want) < tol, (prec, rel(got, want))
 
 
+@pytest.mark.parametrize("agg,N", [((4, 4, 4, 4), 20), ((4, 4, 4, 4), 32), ((2, 2, 2, 2), 5), ((4, 4, 4, 2), 8)])
+def test_coarse_operator_many_rhs_matrix_cores(agg, N):
+    """From 4 right-hand sides on, D_c runs on the matrix cores in tiles of
+    16 right-hand sides and 16 rows: ragged row tiles (2N = 40, 10), a
+    column count that is not a multiple of 4 (2N = 10), full 64-row blocks,
+    and a second, ragged tile of right-hand sides (17)."""
+    from paper_1202_2462_amd.mgdd import F32, F64
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    say("coarse operator, many rhs", agg, N)
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    Vc = lat.Vc
+    for nrhs in (4, 12, 17):
+        x = latgen.gaussian_vector(nrhs * Vc * 2 * N, 12 + nrhs).reshape(nrhs, Vc, 2, N)
+        want = np.stack([tl.coarse_apply(x[i]) for i in range(nrhs)])
+        for prec, tol in ((F64, TOL64), (F32, TOL32)):
+            got = to_np_coarse(lat.coarse_apply(to_dev_coarse(lat, x, prec)))
+            err = max(rel(got[i], want[i]) for i in range(nrhs))
+            assert err < tol, (nrhs, prec, err)
+
+
 @pytest.mark.parametrize("dims,block,agg,N", CASES[:2])
 def test_coarse_gmres_parity(dims, block, agg, N):
     from paper_1202_2462_amd.mgdd import F32, F64

@@ -29,7 +29,16 @@ def leftmost(dims, U, csw, tol=1e-6, k=6, ncv=40):
     op = Operator(dims, U, 0.0, csw)
     n = int(np.prod(dims)) * 12
     shape = (int(np.prod(dims)), 4, 3)
-    L = sla.LinearOperator((n, n), matvec=lambda v: op.apply(v.reshape(shape)).ravel(), dtype=np.complex128)
+    count = [0]
+    t0 = time.time()
+
+    def mv(v):
+        count[0] += 1
+        if count[0] % 200 == 0:
+            print(f"  {count[0]} applications of D, {time.time() - t0:.0f} s", flush=True)
+        return op.apply(v.reshape(shape)).ravel()
+
+    L = sla.LinearOperator((n, n), matvec=mv, dtype=np.complex128)
     v0 = latgen.gaussian_vector(n, 12345)
     vals, vecs = sla.eigs(L, k=k, which="SR", tol=tol, v0=v0, ncv=max(ncv, 3 * k), maxiter=5000)
     i = int(np.argmin(vals.real))

@@ -301,7 +301,7 @@ def main():
     bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
     result["dirac"] = bench.dirac_rates()
     if d_n:
-        result["dirac"]["f64_in_solves"] = {"launches": d_n, "us_per_launch": d_ms * 1e3 / d_n,
+        result["dirac"]["f64_in_timed_steps"] = {"launches": d_n, "us_per_launch": d_ms * 1e3 / d_n,
                                             "gbs": 1536 * d_units / (d_ms * 1e-3) / 1e9}
     # roofline of the dominant kernel of the step, the FP32 Schwarz colour
     # kernel, from its launches in the timed steps (HIP events around each

@@ -1,0 +1,302 @@
+// Arnoldi process on the coarse operator D_c for the fixed-step coarse GMRES
+// (Section 4), in three kernels per step for nb right-hand sides at once:
+//
+//   apply:  v_j = w_j / ||w_j||  (the norm from the previous step's partial
+//           sums), y = D_c v_j, and partial sums of <v_i, y> per coarse site;
+//   orth:   h1 = <V, y> (summing the partials), y <- y - V h1, and partial
+//           sums of <v_i, y>;
+//   reorth: h2 = <V, y>, y <- y - V h2, and partial sums of ||y||^2.
+//
+// This is classical Gram-Schmidt with one re-orthogonalisation, the same
+// arithmetic as the general solver path, with the normalisation and the dot
+// products folded into the kernels that produce their operands. The coarse
+// vectors are small (2N complex per coarse site), so the step count of
+// launches, not bandwidth, decides the time. Every sum runs in a fixed order,
+// and every workgroup that needs a coefficient adds the same partials in the
+// same order, so results are deterministic.
+#include "blas.h"
+#include "transfer.h"
+
+namespace mgdd {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int KMAX = 16;   // basis vectors per pass: at most 15 coarse GMRES steps
+
+struct VecList {
+    const void *p[KMAX];
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// out[q] = sum_{g < np} part[q * np + g] for q < nq, one wave per q (lanes
+// take g = lane, lane + 64, ... in order, then a butterfly); the result is
+// left in red[q] (LDS). Called by every thread of the workgroup.
+__device__ inline void sum_partials(const double2 *__restrict__ part, int nq, int np, double2 *red) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int q = wv; q < nq; q += nw) {
+        double a = 0, b = 0;
+        for (int g = lane; g < np; g += 64) {
+            double2 v = part[(size_t)q * np + g];
+            a += v.x;
+            b += v.y;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) red[q] = make_double2(a, b);
+    }
+    __syncthreads();
+}
+
+// apply step. Grid (Vc, nb), 256 threads: wave q adds the directions q, q+4,
+// q+8 of row i = lane of y(a) (as the coarse stencil kernel), wave 0 then
+// forms y(a) and the dot products of the basis vectors at site a with it.
+template <typename T>
+__global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
+                                                            const C<T> *__restrict__ Dc, const C<T> *__restrict__ w,
+                                                            const double2 *__restrict__ npart, int nnp, VecList V,
+                                                            int j, C<T> *__restrict__ vj, C<T> *__restrict__ y,
+                                                            double2 *__restrict__ part1, double2 *__restrict__ nr) {
+    const int a = blockIdx.x, sg = blockIdx.y, nb = gridDim.y;
+    const int n2 = 2 * N;
+    const size_t so = (size_t)sg * Vc * n2;
+    __shared__ double2 red[1];
+    __shared__ C<T> xs[9][64];
+    __shared__ C<T> part[4][64];
+    sum_partials(npart + (size_t)sg * nnp, 1, nnp, red);
+    const double nn = red[0].x;
+    const T sc = (T)(nn > 0 ? 1.0 / sqrt(nn) : 0.0);
+    if (a == 0 && threadIdx.x == 0) nr[sg] = make_double2(nn, 0);
+    for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
+        const int dd = e / n2, jj = e % n2;
+        C<T> v = w[so + (size_t)cnbr[a * 9 + dd] * n2 + jj];
+        xs[dd][jj] = mk<T>(v.x * sc, v.y * sc);
+    }
+    __syncthreads();
+    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
+    C<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+    if (i < n2) {
+        const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
+        for (int dd = q; dd < 9; dd += 4) {
+            const C<T> *Bd = B + (size_t)dd * n2 * n2 + i;
+            int jj = 0;
+            for (; jj + 1 < n2; jj += 2) {
+                cfma(acc0, Bd[(size_t)jj * n2], xs[dd][jj]);
+                cfma(acc1, Bd[(size_t)(jj + 1) * n2], xs[dd][jj + 1]);
+            }
+            if (jj < n2) cfma(acc0, Bd[(size_t)jj * n2], xs[dd][jj]);
+        }
+    }
+    part[q][i] = cadd(acc0, acc1);
+    __syncthreads();
+    if (q != 0) return;
+    C<T> yv = mk<T>(0, 0), vv = mk<T>(0, 0);
+    if (i < n2) {
+        yv = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
+        vv = xs[0][i];   // v_j at this site (direction 0 is the site itself)
+        y[so + (size_t)a * n2 + i] = yv;
+        vj[so + (size_t)a * n2 + i] = vv;
+    }
+    const double2 yd = make_double2((double)yv.x, (double)yv.y);
+    for (int k = 0; k <= j; k++) {
+        C<T> xv = vv;
+        if (k < j && i < n2) xv = ((const C<T> *)V.p[k])[so + (size_t)a * n2 + i];
+        double2 d = make_double2(0, 0);
+        cfmac(d, make_double2((double)xv.x, (double)xv.y), yd);
+        const double re = wave_sum(d.x), im = wave_sum(d.y);
+        if (i == 0) part1[((size_t)k * nb + sg) * Vc + a] = make_double2(re, im);
+    }
+}
+
+// orth / reorth step: y <- y - sum_k coef_k v_k over k < nk, coef summed from
+// pin (npin partials per coefficient); then partial sums of <v_k, y> (or of
+// ||y||^2 when last) per workgroup into pout; workgroup 0 stores the
+// coefficients in hout[k * nb + segment]. Grid (G, nb).
+template <typename T>
+__global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, int nk, const double2 *__restrict__ pin,
+                                                           int npin, C<T> *__restrict__ y, double2 *__restrict__ pout,
+                                                           int last, double2 *__restrict__ hout) {
+    const int sg = blockIdx.y, nb = gridDim.y, G = gridDim.x, g = blockIdx.x;
+    const size_t so = (size_t)sg * n;
+    __shared__ double2 coef[KMAX];
+    __shared__ double red[TPB / 64][2 * KMAX];
+    // pin is laid out [k][segment][partial]
+    {
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int k = wv; k < nk; k += TPB / 64) {
+            double a = 0, b = 0;
+            const double2 *pk = pin + ((size_t)k * nb + sg) * npin;
+            for (int q = lane; q < npin; q += 64) {
+                a += pk[q].x;
+                b += pk[q].y;
+            }
+            a = wave_sum(a);
+            b = wave_sum(b);
+            if (lane == 0) coef[k] = make_double2(a, b);
+        }
+    }
+    __syncthreads();
+    if (g == 0 && (int)threadIdx.x < nk) hout[(size_t)threadIdx.x * nb + sg] = coef[threadIdx.x];
+    const int nout = last ? 1 : nk;
+    double2 acc[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; k++) acc[k] = make_double2(0, 0);
+    for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
+        C<T> yv = y[so + e];
+        double2 r = make_double2((double)yv.x, (double)yv.y);
+#pragma unroll
+        for (int k = 0; k < KMAX; k++) {
+            if (k < nk) {
+                C<T> v = ((const C<T> *)V.p[k])[so + e];
+                cfma(r, cneg(coef[k]), make_double2((double)v.x, (double)v.y));
+            }
+        }
+        const C<T> rt = mk<T>((T)r.x, (T)r.y);
+        y[so + e] = rt;
+        const double2 rd = make_double2((double)rt.x, (double)rt.y);
+        if (last) {
+            acc[0].x += rd.x * rd.x + rd.y * rd.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < KMAX; k++) {
+                if (k < nk) {   // second read of v_k (a cache hit)
+                    C<T> v = ((const C<T> *)V.p[k])[so + e];
+                    cfmac(acc[k], make_double2((double)v.x, (double)v.y), rd);
+                }
+            }
+        }
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < KMAX; k++) {
+        if (k < nout) {
+            double a = wave_sum(acc[k].x), b = wave_sum(acc[k].y);
+            if (lane == 0) { red[wv][2 * k] = a; red[wv][2 * k + 1] = b; }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nout) {
+        const int k = threadIdx.x;
+        double a = 0, b = 0;
+        for (int q = 0; q < TPB / 64; q++) { a += red[q][2 * k]; b += red[q][2 * k + 1]; }
+        pout[((size_t)k * nb + sg) * G + g] = make_double2(a, b);
+    }
+}
+
+// partial sums of ||x||^2 per workgroup: pout[segment * G + g]
+template <typename T>
+__global__ __launch_bounds__(TPB) void norm_partials_kernel(size_t n, const C<T> *__restrict__ x,
+                                                            double2 *__restrict__ pout) {
+    const int sg = blockIdx.y, G = gridDim.x, g = blockIdx.x;
+    __shared__ double red[TPB / 64];
+    double acc = 0;
+    for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
+        C<T> v = x[(size_t)sg * n + e];
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0;
+        for (int q = 0; q < TPB / 64; q++) a += red[q];
+        pout[(size_t)sg * G + g] = make_double2(a, 0);
+    }
+}
+
+// out[q] = sum_g part[q * np + g]
+__global__ __launch_bounds__(64) void sum_kernel(int np, const double2 *__restrict__ part, double2 *__restrict__ out) {
+    const int q = blockIdx.x, lane = threadIdx.x;
+    double a = 0, b = 0;
+    for (int g = lane; g < np; g += 64) {
+        double2 v = part[(size_t)q * np + g];
+        a += v.x;
+        b += v.y;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) out[q] = make_double2(a, b);
+}
+
+inline int orth_grid(size_t n) {
+    size_t g = (n + 4 * TPB - 1) / (4 * TPB);
+    return (int)(g < 1 ? 1 : g > 256 ? 256 : g);
+}
+
+}  // namespace
+
+size_t coarse_arnoldi_scratch(const Ctx *c, int m, int nb) {
+    const size_t n = (size_t)c->c.Vc * 2 * c->c.N;
+    const size_t G = orth_grid(n);
+    return ((size_t)(m + 1) * nb * c->c.Vc + 3 * (size_t)(m + 1) * nb * G + 2 * (size_t)(m + 1) * nb) * 16 + 4096;
+}
+
+// m Arnoldi steps on D_c from b for nb segments. V: m + 1 basis vectors
+// (written); work0, work1: two coarse vectors (nb segments each); scratch:
+// coarse_arnoldi_scratch bytes. Outputs: H1, H2 (column j at j (m + 1) nb,
+// entry [i][segment]) and NR (NR[j nb + segment] = squared norm of the
+// j-th unnormalised vector, j = 0 .. m).
+int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *const *V, void *work0, void *work1,
+                          void *scratch, double2 *H1, double2 *H2, double2 *NR) {
+    const Level1 &L1 = c->c;
+    const int Vc = L1.Vc, N = L1.N;
+    const size_t n = (size_t)Vc * 2 * N;
+    const int G = orth_grid(n);
+    if (m + 1 > KMAX) return fail(c, MGDD_EINVAL, "too many coarse GMRES steps for the fused Arnoldi kernels");
+    double2 *part1 = (double2 *)scratch;                              // [k][s][Vc]
+    double2 *part1s = part1 + (size_t)(m + 1) * nb * Vc;             // [k][s] (summed, large Vc)
+    double2 *part2 = part1s + (size_t)(m + 1) * nb;                   // [k][s][G]
+    double2 *part3 = part2 + (size_t)(m + 1) * nb * G;                // [s][G]
+    const bool presum = Vc > 1024;
+    dim3 gorth(G, nb);
+#define NORMP(T) norm_partials_kernel<T><<<gorth, TPB, 0, c->stream>>>(n, (const C<T> *)b, part3)
+    if (p == MGDD_F64) NORMP(double); else NORMP(float);
+#undef NORMP
+    int rc = hip_check(c, hipGetLastError(), "arnoldi");
+    void *work[2] = {work0, work1};
+    const void *w = b;
+    for (int j = 0; j < m && !rc; j++) {
+        VecList vl{};
+        for (int k = 0; k <= j; k++) vl.p[k] = V[k];
+        void *y = work[j & 1];
+        dim3 gapp(Vc, nb);
+#define APPLY(T)                                                                                                  \
+    arnoldi_apply_kernel<T><<<gapp, TPB, 0, c->stream>>>(Vc, N, L1.cnbr, (const C<T> *)(p == MGDD_F64 ? L1.Dc64 : L1.Dc32), \
+                                                         (const C<T> *)w, part3, G, vl, j, (C<T> *)V[j], (C<T> *)y,  \
+                                                         part1, NR + (size_t)j * nb)
+        if (p == MGDD_F64) APPLY(double); else APPLY(float);
+#undef APPLY
+        const double2 *pin = part1;
+        int npin = Vc;
+        if (presum) {
+            sum_kernel<<<(j + 1) * nb, 64, 0, c->stream>>>(Vc, part1, part1s);
+            pin = part1s;
+            npin = 1;
+        }
+        double2 *h1 = H1 + (size_t)j * (m + 1) * nb, *h2 = H2 + (size_t)j * (m + 1) * nb;
+#define ORTH(T, PIN, NPIN, POUT, LAST, HOUT) \
+    arnoldi_orth_kernel<T><<<gorth, TPB, 0, c->stream>>>(n, vl, j + 1, PIN, NPIN, (C<T> *)y, POUT, LAST, HOUT)
+        if (p == MGDD_F64) {
+            ORTH(double, pin, npin, part2, 0, h1);
+            ORTH(double, part2, G, part3, 1, h2);
+        } else {
+            ORTH(float, pin, npin, part2, 0, h1);
+            ORTH(float, part2, G, part3, 1, h2);
+        }
+#undef ORTH
+        rc = hip_check(c, hipGetLastError(), "arnoldi");
+        w = y;
+    }
+    if (!rc) {
+        sum_kernel<<<nb, 64, 0, c->stream>>>(G, part3, NR + (size_t)m * nb);
+        rc = hip_check(c, hipGetLastError(), "arnoldi");
+    }
+    return rc;
+}
+
+}  // namespace mgdd

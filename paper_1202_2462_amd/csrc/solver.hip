@@ -129,18 +129,21 @@ static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2
     return rc;
 }
 
-// modified Gram-Schmidt of nv vectors in index order (global orthonormalisation)
+// Gram-Schmidt orthonormalisation of nv vectors in index order (global
+// orthonormalisation): vector k is orthogonalised against vectors 0..k-1 by
+// two classical passes (one multi-dot and one linear combination each, the
+// same span and, in exact arithmetic, the same result as modified
+// Gram-Schmidt), then normalised. scal: device space for 2 nv + 1 values.
 static int mgs_device(Ctx *c, int p, size_t n, void *const *X, int nv, double2 *scal) {
     for (int k = 0; k < nv; k++) {
-        for (int j = 0; j < k; j++) {
-            const void *xj = X[j];
-            int rc = blas_multidot(c, p, p, n, &xj, 1, X[k], scal);
-            if (!rc) rc = blas_lincomb(c, p, p, n, &xj, 1, scal, -1.0, 1.0, X[k]);
-            if (rc) return rc;
+        int rc = MGDD_OK;
+        if (k > 0) {
+            rc = cgs2(c, p, n, X, k, X[k], scal, scal + nv, scal + 2 * nv);
+        } else {
+            const void *x0 = X[0];
+            rc = blas_multidot(c, p, p, n, &x0, 1, X[0], scal + 2 * nv);
         }
-        const void *xk = X[k];
-        int rc = blas_multidot(c, p, p, n, &xk, 1, X[k], scal);
-        if (!rc) rc = blas_normalize(c, p, p, n, X[k], scal, X[k]);
+        if (!rc) rc = blas_normalize(c, p, p, n, X[k], scal + 2 * nv, X[k]);
         if (rc) return rc;
     }
     return MGDD_OK;
@@ -150,7 +153,8 @@ static int mgs_device(Ctx *c, int p, size_t n, void *const *X, int nv, double2 *
 
 size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb) {
     size_t n = (size_t)c->c.Vc * 2 * c->c.N * nb;
-    return (size_t)(m + 2) * (n * csize(p) + 256) + (4 * (size_t)(m + 2) * (m + 2) + 2 * (size_t)(m + 2)) * nb * 16 + 4096;
+    return (size_t)(m + 3) * (n * csize(p) + 256) + (4 * (size_t)(m + 2) * (m + 2) + 2 * (size_t)(m + 2)) * nb * 16 +
+           coarse_arnoldi_scratch(c, m, nb) + 8192;
 }
 
 // x_s = GMRES_m(D_c, b_s) from x = 0, no restart, for nb right-hand sides at
@@ -168,14 +172,23 @@ int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A)
     double2 *nr = (double2 *)A.take((size_t)(m + 2) * nb * 16);
     double2 *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
     if (!coef) return fail(c, MGDD_ENOMEM, "coarse GMRES workspace");
-    const void *bp = b;
-    int rc = blas_multidot(c, p, p, n, &bp, 1, b, nr, nb);
-    if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0], nb);
-    for (int j = 0; j < m && !rc; j++) {
-        rc = launch_coarse_apply(c, p, nb, V[j], w);
-        if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1) * nb, h2 + (size_t)j * (m + 1) * nb,
-                           nr + (size_t)(j + 1) * nb, nb);
-        if (!rc) rc = blas_normalize(c, p, p, n, w, nr + (size_t)(j + 1) * nb, V[j + 1], nb);
+    int rc = MGDD_OK;
+    if (m <= ARNOLDI_FUSED_MAX_STEPS) {
+        // three fused kernels per Arnoldi step
+        void *w2 = A.take(n * nb * cs);
+        void *scr = A.take(coarse_arnoldi_scratch(c, m, nb));
+        if (!scr) return fail(c, MGDD_ENOMEM, "coarse GMRES workspace");
+        rc = launch_coarse_arnoldi(c, p, m, nb, b, V.data(), w, w2, scr, h1, h2, nr);
+    } else {
+        const void *bp = b;
+        rc = blas_multidot(c, p, p, n, &bp, 1, b, nr, nb);
+        if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0], nb);
+        for (int j = 0; j < m && !rc; j++) {
+            rc = launch_coarse_apply(c, p, nb, V[j], w);
+            if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1) * nb,
+                               h2 + (size_t)j * (m + 1) * nb, nr + (size_t)(j + 1) * nb, nb);
+            if (!rc) rc = blas_normalize(c, p, p, n, w, nr + (size_t)(j + 1) * nb, V[j + 1], nb);
+        }
     }
     if (rc) return rc;
     cd *hb = host_buf(c, 2 * hs + (size_t)(m + 1) * nb + (size_t)m * nb);

@@ -21,4 +21,10 @@ int launch_prolong(Ctx *c, int prec, int nrhs, const void *coarse, void *fine);
 int launch_coarse_build(Ctx *c);
 int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out);
 
+// Fused Arnoldi process on D_c for the coarse GMRES (arnoldi.hip); m <= 15.
+constexpr int ARNOLDI_FUSED_MAX_STEPS = 15;
+size_t coarse_arnoldi_scratch(const Ctx *c, int m, int nb);
+int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *const *V, void *work0, void *work1,
+                          void *scratch, double2 *H1, double2 *H2, double2 *NR);
+
 }  // namespace mgdd

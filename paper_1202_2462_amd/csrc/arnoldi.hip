@@ -15,6 +15,7 @@
 // and every workgroup that needs a coefficient adds the same partials in the
 // same order, so results are deterministic.
 #include "blas.h"
+#include "coarse.h"
 #include "transfer.h"
 
 namespace mgdd {
@@ -22,10 +23,11 @@ namespace mgdd {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int KMAX = 16;   // basis vectors per pass: at most 15 coarse GMRES steps
+constexpr int KMAX = 16;   // basis vectors of the coarse Arnoldi: at most 15 coarse GMRES steps
+constexpr int VMAX = 16;   // basis vectors of one fused Gram-Schmidt pass
 
 struct VecList {
-    const void *p[KMAX];
+    const void *p[VMAX];
 };
 
 __device__ inline double wave_sum(double v) {
@@ -53,9 +55,9 @@ __device__ inline void sum_partials(const double2 *__restrict__ part, int nq, in
     __syncthreads();
 }
 
-// apply step. Grid (Vc, nb), 256 threads: wave q adds the directions q, q+4,
-// q+8 of row i = lane of y(a) (as the coarse stencil kernel), wave 0 then
-// forms y(a) and the dot products of the basis vectors at site a with it.
+// apply step. Grid (Vc, nb), 256 threads share the 9 2N products of y(a)
+// (dc_row_partial); wave 0 then forms y(a), row i in lane i, and the dot
+// products of the basis vectors at site a with it.
 template <typename T>
 __global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
                                                             const C<T> *__restrict__ Dc, const C<T> *__restrict__ w,
@@ -66,8 +68,8 @@ __global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const
     const int n2 = 2 * N;
     const size_t so = (size_t)sg * Vc * n2;
     __shared__ double2 red[1];
-    __shared__ C<T> xs[9][64];
-    __shared__ C<T> part[4][64];
+    __shared__ C<T> xs[9 * 64];
+    __shared__ C<T> part[TPB];
     sum_partials(npart + (size_t)sg * nnp, 1, nnp, red);
     const double nn = red[0].x;
     const T sc = (T)(nn > 0 ? 1.0 / sqrt(nn) : 0.0);
@@ -75,30 +77,17 @@ __global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const
     for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
         const int dd = e / n2, jj = e % n2;
         C<T> v = w[so + (size_t)cnbr[a * 9 + dd] * n2 + jj];
-        xs[dd][jj] = mk<T>(v.x * sc, v.y * sc);
+        xs[e] = mk<T>(v.x * sc, v.y * sc);
     }
     __syncthreads();
-    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
-    C<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
-    if (i < n2) {
-        const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
-        for (int dd = q; dd < 9; dd += 4) {
-            const C<T> *Bd = B + (size_t)dd * n2 * n2 + i;
-            int jj = 0;
-            for (; jj + 1 < n2; jj += 2) {
-                cfma(acc0, Bd[(size_t)jj * n2], xs[dd][jj]);
-                cfma(acc1, Bd[(size_t)(jj + 1) * n2], xs[dd][jj + 1]);
-            }
-            if (jj < n2) cfma(acc0, Bd[(size_t)jj * n2], xs[dd][jj]);
-        }
-    }
-    part[q][i] = cadd(acc0, acc1);
+    dc_row_partial<T>(Dc + (size_t)a * 9 * n2 * n2, xs, n2, part);
     __syncthreads();
-    if (q != 0) return;
+    if (threadIdx.x >= 64) return;
+    const int i = threadIdx.x, nparts = TPB / n2;
     C<T> yv = mk<T>(0, 0), vv = mk<T>(0, 0);
     if (i < n2) {
-        yv = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
-        vv = xs[0][i];   // v_j at this site (direction 0 is the site itself)
+        for (int q = 0; q < nparts; q++) yv = cadd(yv, part[q * n2 + i]);
+        vv = xs[i];   // v_j at this site (direction 0 is the site itself)
         y[so + (size_t)a * n2 + i] = yv;
         vj[so + (size_t)a * n2 + i] = vv;
     }
@@ -117,40 +106,55 @@ __global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const
 // pin (npin partials per coefficient); then partial sums of <v_k, y> (or of
 // ||y||^2 when last) per workgroup into pout; workgroup 0 stores the
 // coefficients in hout[k * nb + segment]. Grid (G, nb).
-template <typename T>
+template <typename T, int NV>
 __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, int nk, const double2 *__restrict__ pin,
                                                            int npin, C<T> *__restrict__ y, double2 *__restrict__ pout,
                                                            int last, double2 *__restrict__ hout) {
     const int sg = blockIdx.y, nb = gridDim.y, G = gridDim.x, g = blockIdx.x;
     const size_t so = (size_t)sg * n;
-    __shared__ double2 coef[KMAX];
-    __shared__ double red[TPB / 64][2 * KMAX];
-    // pin is laid out [k][segment][partial]
+    __shared__ double2 coef[NV];
+    __shared__ double red[TPB / 64][2 * NV];
+    // pin is laid out [k][segment][partial]. 16 threads per coefficient:
+    // thread u adds the partials u, u + 16, ... (two independent loads at a
+    // time), then a butterfly over the group.
+    constexpr int GS = 16;
     {
-        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int k = wv; k < nk; k += TPB / 64) {
-            double a = 0, b = 0;
+        const int k = threadIdx.x / GS, u = threadIdx.x % GS;
+        double a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+        if (k < nk) {
             const double2 *pk = pin + ((size_t)k * nb + sg) * npin;
-            for (int q = lane; q < npin; q += 64) {
-                a += pk[q].x;
-                b += pk[q].y;
+            int q = u;
+            for (; q + GS < npin; q += 2 * GS) {
+                const double2 v0 = pk[q], v1 = pk[q + GS];
+                a0 += v0.x;
+                b0 += v0.y;
+                a1 += v1.x;
+                b1 += v1.y;
             }
-            a = wave_sum(a);
-            b = wave_sum(b);
-            if (lane == 0) coef[k] = make_double2(a, b);
+            if (q < npin) {
+                a0 += pk[q].x;
+                b0 += pk[q].y;
+            }
         }
+        double a = a0 + a1, b = b0 + b1;
+#pragma unroll
+        for (int m = GS / 2; m >= 1; m >>= 1) {
+            a += __shfl_xor(a, m, 64);
+            b += __shfl_xor(b, m, 64);
+        }
+        if (k < nk && u == 0) coef[k] = make_double2(a, b);
     }
     __syncthreads();
-    if (g == 0 && (int)threadIdx.x < nk) hout[(size_t)threadIdx.x * nb + sg] = coef[threadIdx.x];
+    if (hout && g == 0 && (int)threadIdx.x < nk) hout[(size_t)threadIdx.x * nb + sg] = coef[threadIdx.x];
     const int nout = last ? 1 : nk;
-    double2 acc[KMAX];
+    double2 acc[NV];
 #pragma unroll
-    for (int k = 0; k < KMAX; k++) acc[k] = make_double2(0, 0);
+    for (int k = 0; k < NV; k++) acc[k] = make_double2(0, 0);
     for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
         C<T> yv = y[so + e];
         double2 r = make_double2((double)yv.x, (double)yv.y);
 #pragma unroll
-        for (int k = 0; k < KMAX; k++) {
+        for (int k = 0; k < NV; k++) {
             if (k < nk) {
                 C<T> v = ((const C<T> *)V.p[k])[so + e];
                 cfma(r, cneg(coef[k]), make_double2((double)v.x, (double)v.y));
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
             acc[0].x += rd.x * rd.x + rd.y * rd.y;
         } else {
 #pragma unroll
-            for (int k = 0; k < KMAX; k++) {
+            for (int k = 0; k < NV; k++) {
                 if (k < nk) {   // second read of v_k (a cache hit)
                     C<T> v = ((const C<T> *)V.p[k])[so + e];
                     cfmac(acc[k], make_double2((double)v.x, (double)v.y), rd);
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
     }
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < KMAX; k++) {
+    for (int k = 0; k < NV; k++) {
         if (k < nout) {
             double a = wave_sum(acc[k].x), b = wave_sum(acc[k].y);
             if (lane == 0) { red[wv][2 * k] = a; red[wv][2 * k + 1] = b; }
@@ -181,6 +185,44 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
     }
     __syncthreads();
     if ((int)threadIdx.x < nout) {
+        const int k = threadIdx.x;
+        double a = 0, b = 0;
+        for (int q = 0; q < TPB / 64; q++) { a += red[q][2 * k]; b += red[q][2 * k + 1]; }
+        pout[((size_t)k * nb + sg) * G + g] = make_double2(a, b);
+    }
+}
+
+// partial sums of <v_k, w> per workgroup: pout[(k * nb + segment) * G + g]
+template <typename T, int NV>
+__global__ __launch_bounds__(TPB) void dot_partials_kernel(size_t n, VecList V, int nk, const C<T> *__restrict__ w,
+                                                           double2 *__restrict__ pout) {
+    const int sg = blockIdx.y, nb = gridDim.y, G = gridDim.x, g = blockIdx.x;
+    const size_t so = (size_t)sg * n;
+    __shared__ double red[TPB / 64][2 * NV];
+    double2 acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) acc[k] = make_double2(0, 0);
+    for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
+        const C<T> wv = w[so + e];
+        const double2 wd = make_double2((double)wv.x, (double)wv.y);
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            if (k < nk) {
+                C<T> v = ((const C<T> *)V.p[k])[so + e];
+                cfmac(acc[k], make_double2((double)v.x, (double)v.y), wd);
+            }
+        }
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        if (k < nk) {
+            double a = wave_sum(acc[k].x), b = wave_sum(acc[k].y);
+            if (lane == 0) { red[wv][2 * k] = a; red[wv][2 * k + 1] = b; }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nk) {
         const int k = threadIdx.x;
         double a = 0, b = 0;
         for (int q = 0; q < TPB / 64; q++) { a += red[q][2 * k]; b += red[q][2 * k + 1]; }
@@ -223,9 +265,11 @@ __global__ __launch_bounds__(64) void sum_kernel(int np, const double2 *__restri
     if (lane == 0) out[q] = make_double2(a, b);
 }
 
+// one element per thread up to 1024 workgroups: these passes are short and
+// latency-bound, so more workgroups with fewer elements each finish sooner
 inline int orth_grid(size_t n) {
-    size_t g = (n + 4 * TPB - 1) / (4 * TPB);
-    return (int)(g < 1 ? 1 : g > 256 ? 256 : g);
+    size_t g = (n + TPB - 1) / TPB;
+    return (int)(g < 1 ? 1 : g > 1024 ? 1024 : g);
 }
 
 }  // namespace
@@ -280,7 +324,7 @@ int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *con
         }
         double2 *h1 = H1 + (size_t)j * (m + 1) * nb, *h2 = H2 + (size_t)j * (m + 1) * nb;
 #define ORTH(T, PIN, NPIN, POUT, LAST, HOUT) \
-    arnoldi_orth_kernel<T><<<gorth, TPB, 0, c->stream>>>(n, vl, j + 1, PIN, NPIN, (C<T> *)y, POUT, LAST, HOUT)
+    arnoldi_orth_kernel<T, KMAX><<<gorth, TPB, 0, c->stream>>>(n, vl, j + 1, PIN, NPIN, (C<T> *)y, POUT, LAST, HOUT)
         if (p == MGDD_F64) {
             ORTH(double, pin, npin, part2, 0, h1);
             ORTH(double, part2, G, part3, 1, h2);
@@ -297,6 +341,43 @@ int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *con
         rc = hip_check(c, hipGetLastError(), "arnoldi");
     }
     return rc;
+}
+
+size_t fused_cgs2_red_doubles(size_t n, int k, int nb) {
+    return 2 * (2 * (size_t)k + 1) * nb * (size_t)orth_grid(n) + 16;
+}
+
+// Classical Gram-Schmidt with one re-orthogonalisation of w against the k
+// vectors V (nb segments of length n each) in three passes over memory:
+// dot partials; subtract the first projection (coefficients summed first)
+// with the dot partials of the second; subtract the second with the partials
+// of the squared norm. Outputs: h1[i][s], h2[i][s], nrm[s] (device).
+int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, double2 *h1, double2 *h2,
+               double2 *nrm) {
+    if (k < 1 || k > VMAX) return fail(c, MGDD_EINVAL, "fused Gram-Schmidt: bad vector count");
+    const int G = orth_grid(n);
+    double2 *part = (double2 *)ensure_red(c, fused_cgs2_red_doubles(n, k, nb));
+    if (!part) return MGDD_ENOMEM;
+    double2 *part2 = part + (size_t)k * nb * G;
+    VecList vl{};
+    for (int i = 0; i < k; i++) vl.p[i] = V[i];
+    dim3 grid(G, nb);
+#define CGS(T, NV)                                                                                                 \
+    do {                                                                                                           \
+        dot_partials_kernel<T, NV><<<grid, TPB, 0, c->stream>>>(n, vl, k, (const C<T> *)w, part);                  \
+        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part, h1);                                                     \
+        arnoldi_orth_kernel<T, NV><<<grid, TPB, 0, c->stream>>>(n, vl, k, h1, 1, (C<T> *)w, part2, 0, nullptr);  \
+        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part2, h2);                                                    \
+        arnoldi_orth_kernel<T, NV><<<grid, TPB, 0, c->stream>>>(n, vl, k, h2, 1, (C<T> *)w, part, 1, nullptr);   \
+        sum_kernel<<<nb, 64, 0, c->stream>>>(G, part, nrm);                                                        \
+    } while (0)
+    if (p == MGDD_F64) {
+        if (k <= 4) CGS(double, 4); else if (k <= 8) CGS(double, 8); else CGS(double, 16);
+    } else {
+        if (k <= 4) CGS(float, 4); else if (k <= 8) CGS(float, 8); else CGS(float, 16);
+    }
+#undef CGS
+    return hip_check(c, hipGetLastError(), "fused Gram-Schmidt");
 }
 
 }  // namespace mgdd

@@ -120,6 +120,9 @@ static void hessenberg_lsq(int k, const std::vector<cd> &Hcol, int ldh, double b
 // of w after.
 static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm,
                 int nb = 1) {
+    // short vectors (the coarse level): three fused passes, launch count
+    // matters more than bandwidth there
+    if (k <= FUSED_CGS2_MAX && n <= (size_t)1 << 18) return fused_cgs2(c, p, n, nb, V, k, w, h1, h2, nrm);
     int rc = blas_multidot(c, p, p, n, V, k, w, h1, nb);
     if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h1, -1.0, 1.0, w, nb);
     if (!rc) rc = blas_multidot(c, p, p, n, V, k, w, h2, nb);

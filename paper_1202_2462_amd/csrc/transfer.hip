@@ -6,6 +6,7 @@
 // as well.
 #include "stencil.h"
 #include "transfer.h"
+#include "coarse.h"
 
 namespace mgdd {
 
@@ -372,10 +373,10 @@ __global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N
 
 // ---------------------------------------------------------------- coarse stencil y = D_c x
 //
-// One workgroup of 256 threads per (coarse site, right-hand side): wave q
-// handles the directions q, q+4, q+8 and lane i < 2N forms row i of their
-// products; the four partial rows are added in wave order through LDS. Blocks
-// are stored column-major, B[a][dir][col][row], so the lanes of a wave read
+// One workgroup of 256 threads per (coarse site, right-hand side): the 9 2N
+// products of each row are split over floor(256 / 2N) thread sets
+// (dc_row_partial), whose partial rows are then added in set order. Blocks
+// are stored column-major, B[a][dir][col][row], so consecutive threads read
 // consecutive rows of one column.
 template <typename T>
 __global__ __launch_bounds__(256) void coarse_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
@@ -383,32 +384,19 @@ __global__ __launch_bounds__(256) void coarse_apply_kernel(int Vc, int N, const 
                                                            C<T> *__restrict__ y) {
     const int a = blockIdx.x, r = blockIdx.y;
     const int n2 = 2 * N;
-    const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
-    __shared__ C<T> xs[9][64];
-    __shared__ C<T> part[4][64];
+    __shared__ C<T> xs[9 * 64];
+    __shared__ C<T> part[256];
     const C<T> *xr = x + (size_t)r * Vc * n2;
-    for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
-        int dd = e / n2, j = e % n2;
-        xs[dd][j] = xr[(size_t)cnbr[a * 9 + dd] * n2 + j];
-    }
+    for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) xs[e] = xr[(size_t)cnbr[a * 9 + e / n2] * n2 + e % n2];
     __syncthreads();
-    C<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+    dc_row_partial<T>(Dc + (size_t)a * 9 * n2 * n2, xs, n2, part);
+    __syncthreads();
+    const int i = threadIdx.x, nparts = blockDim.x / n2;
     if (i < n2) {
-        const C<T> *B = Dc + (size_t)a * 9 * n2 * n2;
-        for (int dd = q; dd < 9; dd += 4) {
-            const C<T> *Bd = B + (size_t)dd * n2 * n2 + i;
-            int j = 0;
-            for (; j + 1 < n2; j += 2) {
-                cfma(acc0, Bd[(size_t)j * n2], xs[dd][j]);
-                cfma(acc1, Bd[(size_t)(j + 1) * n2], xs[dd][j + 1]);
-            }
-            if (j < n2) cfma(acc0, Bd[(size_t)j * n2], xs[dd][j]);
-        }
+        C<T> acc = mk<T>(0, 0);
+        for (int q = 0; q < nparts; q++) acc = cadd(acc, part[q * n2 + i]);
+        y[((size_t)r * Vc + a) * n2 + i] = acc;
     }
-    part[q][i] = cadd(acc0, acc1);
-    __syncthreads();
-    if (q == 0 && i < n2)
-        y[((size_t)r * Vc + a) * n2 + i] = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
 }
 
 // D_c applied to many right-hand sides on the matrix cores. Per coarse site

@@ -24,6 +24,10 @@ int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *c
                int nseg = 1);
 // y_s = x_s / sqrt(re nrm2[s]) (y_s = 0 when that is 0); x and y may alias
 int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y, int nseg = 1);
+// FP64 vector sets (at most 64 each, length n): out[i * ny + j] = <x_i, y_j>
+int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const *ys, int ny, double2 *out);
+// FP64: y_k = sum_i M[i * ny + k] x_i for k < ny (M on the device); y may be x (ny == nx)
+int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys);
 // coef[0] = 1/sqrt(re v[0])
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef);
 

@@ -139,6 +139,110 @@ __global__ void rsqrt_kernel(const double2 *v, double2 *coef) {
     coef[0] = make_double2(n > 0 ? 1.0 / n : 0.0, 0.0);
 }
 
+// ---- tall-skinny products of vector sets (bootstrap setup, FP64)
+//
+// gram: part[wg][i][j] = sum over the workgroup's elements of conj(x_i) y_j.
+// Elements are processed in tiles of GT; the tiles of x and y go through LDS
+// and thread t owns the 4x4 block (i0 .. i0+3, j0 .. j0+3) of the output.
+constexpr int GMAX = 64;   // vectors per set
+constexpr int GT = 32;     // elements per tile
+
+struct PtrList64 {
+    const void *p[GMAX];
+};
+
+__global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int nx, PtrList64 ys, int ny,
+                                                   double2 *__restrict__ part) {
+    __shared__ double2 xt[GMAX][GT], yt[GMAX][GT];
+    const int tx = (nx + 3) / 4, ty = (ny + 3) / 4;
+    const int t = threadIdx.x, bi = t / ty, bj = t % ty;
+    const bool owner = t < tx * ty;
+    double2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = make_double2(0, 0);
+    const size_t ntile = (n + GT - 1) / GT;
+    for (size_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const size_t e0 = tile * GT;
+        for (int q = t; q < (nx + ny) * GT; q += blockDim.x) {
+            const int v = q / GT, e = q % GT;
+            double2 val = make_double2(0, 0);
+            if (e0 + e < n) val = v < nx ? ((const double2 *)xs.p[v])[e0 + e] : ((const double2 *)ys.p[v - nx])[e0 + e];
+            if (v < nx) xt[v][e] = val; else yt[v - nx][e] = val;
+        }
+        __syncthreads();
+        if (owner) {
+            for (int e = 0; e < GT; e++) {
+                double2 xv[4], yv[4];
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    xv[a] = xt[(4 * bi + a) & (GMAX - 1)][e];
+                    yv[a] = yt[(4 * bj + a) & (GMAX - 1)][e];
+                }
+#pragma unroll
+                for (int a = 0; a < 4; a++)
+#pragma unroll
+                    for (int b = 0; b < 4; b++) cfmac(acc[a][b], xv[a], yv[b]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!owner) return;
+    double2 *pw = part + (size_t)blockIdx.x * nx * ny;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int i = 4 * bi + a, j = 4 * bj + b;
+            if (i < nx && j < ny) pw[(size_t)i * ny + j] = acc[a][b];
+        }
+}
+
+// out[q] = sum_wg part[wg][q] in workgroup order, q < nq
+__global__ __launch_bounds__(256) void gram_finish_kernel(int nwg, int nq, const double2 *__restrict__ part,
+                                                          double2 *__restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    double a = 0, b = 0;
+    for (int w = 0; w < nwg; w++) {
+        const double2 v = part[(size_t)w * nq + q];
+        a += v.x;
+        b += v.y;
+    }
+    out[q] = make_double2(a, b);
+}
+
+// y_k = sum_{i < nx} M[i * ny + k] x_i for k < ny, over tiles of GT elements:
+// the tile of every x_i is read into LDS before any output of the tile is
+// written, so y may be x itself (ny == nx, in place).
+__global__ __launch_bounds__(256) void transform_kernel(size_t n, PtrList64 xs, int nx, const double2 *__restrict__ M,
+                                                        int ny, PtrList64 ys) {
+    extern __shared__ double2 tsm[];
+    double2 *Ms = tsm;                                  // [nx * ny]
+    double2 (*xt)[GT] = (double2 (*)[GT])(tsm + nx * ny);   // [nx][GT]
+    const int t = threadIdx.x;
+    for (int q = t; q < nx * ny; q += blockDim.x) Ms[q] = M[q];
+    const size_t ntile = (n + GT - 1) / GT;
+    const int e = t % GT, k0 = t / GT, kstep = blockDim.x / GT;
+    for (size_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const size_t e0 = tile * GT;
+        __syncthreads();
+        for (int q = t; q < nx * GT; q += blockDim.x) {
+            const int v = q / GT, ee = q % GT;
+            xt[v][ee] = e0 + ee < n ? ((const double2 *)xs.p[v])[e0 + ee] : make_double2(0, 0);
+        }
+        __syncthreads();
+        if (e0 + e < n) {
+            for (int k = k0; k < ny; k += kstep) {
+                double2 acc = make_double2(0, 0);
+                for (int i = 0; i < nx; i++) cfma(acc, Ms[i * ny + k], xt[i][e]);
+                ((double2 *)ys.p[k])[e0 + e] = acc;
+            }
+        }
+    }
+}
+
 int lin_grid(size_t n) {
     size_t g = (n + TPB - 1) / TPB;
     if (g > 8192) g = 8192;
@@ -220,6 +324,33 @@ int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *c
 
 int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double2 *nrm2, void *y, int nseg) {
     return scale_launch(c, px, py, n, x, nrm2, make_double2(1, 0), 1, y, nseg);
+}
+
+int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const *ys, int ny, double2 *out) {
+    if (nx < 1 || ny < 1 || nx > GMAX || ny > GMAX) return fail(c, MGDD_EINVAL, "gram: bad vector count");
+    const size_t ntile = (n + GT - 1) / GT;
+    const int nwg = (int)(ntile < 512 ? ntile : 512);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * nwg * nx * ny + 16);
+    if (!part) return MGDD_ENOMEM;
+    PtrList64 px{}, py{};
+    for (int i = 0; i < nx; i++) px.p[i] = xs[i];
+    for (int j = 0; j < ny; j++) py.p[j] = ys[j];
+    gram_kernel<<<nwg, 256, 0, c->stream>>>(n, px, nx, py, ny, part);
+    const int nq = nx * ny;
+    gram_finish_kernel<<<(nq + 255) / 256, 256, 0, c->stream>>>(nwg, nq, part, out);
+    return hip_check(c, hipGetLastError(), "gram");
+}
+
+int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys) {
+    if (nx < 1 || ny < 1 || nx > GMAX || ny > GMAX) return fail(c, MGDD_EINVAL, "transform: bad vector count");
+    const size_t ntile = (n + GT - 1) / GT;
+    const int nwg = (int)(ntile < 4096 ? ntile : 4096);
+    PtrList64 px{}, py{};
+    for (int i = 0; i < nx; i++) px.p[i] = xs[i];
+    for (int j = 0; j < ny; j++) py.p[j] = ys[j];
+    const size_t lds = ((size_t)nx * ny + (size_t)nx * GT) * sizeof(double2);
+    transform_kernel<<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+    return hip_check(c, hipGetLastError(), "transform");
 }
 
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef) {

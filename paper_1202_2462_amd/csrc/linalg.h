@@ -26,6 +26,40 @@ inline void givens(cd a, cd b, double &c, cd &s, cd &rho) {
     rho = (a / aa) * r;
 }
 
+// Cholesky factor of a Hermitian positive definite G (n x n, row-major):
+// G = R^H R with R upper triangular and a positive real diagonal; false when
+// a pivot is not positive (then R is incomplete).
+inline bool cholesky_upper(int n, const Mat &G, Mat &R) {
+    R.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; i++) {
+        double d = G[(size_t)i * n + i].real();
+        for (int k = 0; k < i; k++) d -= std::norm(R[(size_t)k * n + i]);
+        if (!(d > 0.0)) return false;
+        const double rii = std::sqrt(d);
+        R[(size_t)i * n + i] = rii;
+        for (int j = i + 1; j < n; j++) {
+            cd sum = G[(size_t)i * n + j];
+            for (int k = 0; k < i; k++) sum -= std::conj(R[(size_t)k * n + i]) * R[(size_t)k * n + j];
+            R[(size_t)i * n + j] = sum / rii;
+        }
+    }
+    return true;
+}
+
+// Inverse of an upper triangular R (n x n, row-major), by back substitution.
+inline Mat upper_inverse(int n, const Mat &R) {
+    Mat X((size_t)n * n, 0.0);
+    for (int j = 0; j < n; j++) {
+        X[(size_t)j * n + j] = 1.0 / R[(size_t)j * n + j];
+        for (int i = j - 1; i >= 0; i--) {
+            cd sum = 0.0;
+            for (int k = i + 1; k <= j; k++) sum += R[(size_t)i * n + k] * X[(size_t)k * n + j];
+            X[(size_t)i * n + j] = -sum / R[(size_t)i * n + i];
+        }
+    }
+    return X;
+}
+
 // Solves A x = b (n x n, row-major) by LU with partial pivoting; false if singular.
 inline bool lu_solve(int n, Mat A, std::vector<cd> &b) {
     for (int k = 0; k < n; k++) {

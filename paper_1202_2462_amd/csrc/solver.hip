@@ -132,21 +132,46 @@ static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2
     return rc;
 }
 
-// Gram-Schmidt orthonormalisation of nv vectors in index order (global
-// orthonormalisation): vector k is orthogonalised against vectors 0..k-1 by
-// two classical passes (one multi-dot and one linear combination each, the
-// same span and, in exact arithmetic, the same result as modified
-// Gram-Schmidt), then normalised. scal: device space for 2 nv + 1 values.
-static int mgs_device(Ctx *c, int p, size_t n, void *const *X, int nv, double2 *scal) {
+// Orthonormalisation of nv FP64 vectors in index order (global
+// orthonormalisation): the Q of X = Q R with R upper triangular and a
+// positive real diagonal, the result of Gram-Schmidt in index order. Computed
+// as Cholesky QR applied twice: G = X^H X (one pass over the vectors),
+// G = R^H R on the host, X <- X R^{-1} (one pass, in place); the second
+// application removes the loss of orthogonality of the first. When a
+// Cholesky factorisation fails (X nearly rank deficient), the vectors are
+// orthonormalised one by one with two classical Gram-Schmidt passes instead.
+// gbuf, mbuf: device space for nv^2 values each; scal: 2 nv + 1 values.
+static int orthonormalise(Ctx *c, size_t n, void *const *X, int nv, double2 *gbuf, double2 *mbuf, double2 *scal) {
+    if (nv <= 64) {
+        bool ok = true;
+        for (int pass = 0; pass < 2 && ok; pass++) {
+            std::vector<cd> G((size_t)nv * nv);
+            int rc = blas_gram(c, n, (const void *const *)X, nv, (const void *const *)X, nv, gbuf);
+            if (!rc) rc = read_dev(c, gbuf, (size_t)nv * nv, G.data());
+            if (rc) return rc;
+            la::Mat R;
+            ok = la::cholesky_upper(nv, G, R);
+            if (!ok) break;
+            la::Mat Ri = la::upper_inverse(nv, R);
+            cd *hb = host_buf(c, (size_t)nv * nv);
+            if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+            for (size_t q = 0; q < (size_t)nv * nv; q++) hb[q] = Ri[q];   // M[i][k] = R^{-1}[i][k]
+            rc = write_dev(c, hb, (size_t)nv * nv, mbuf);
+            if (!rc) rc = blas_transform(c, n, (const void *const *)X, nv, mbuf, nv, X);
+            if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");   // hb is reused
+            if (rc) return rc;
+        }
+        if (ok) return MGDD_OK;
+    }
     for (int k = 0; k < nv; k++) {
         int rc = MGDD_OK;
         if (k > 0) {
-            rc = cgs2(c, p, n, X, k, X[k], scal, scal + nv, scal + 2 * nv);
+            rc = cgs2(c, MGDD_F64, n, X, k, X[k], scal, scal + nv, scal + 2 * nv);
         } else {
             const void *x0 = X[0];
-            rc = blas_multidot(c, p, p, n, &x0, 1, X[0], scal + 2 * nv);
+            rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &x0, 1, X[0], scal + 2 * nv);
         }
-        if (!rc) rc = blas_normalize(c, p, p, n, X[k], scal + 2 * nv, X[k]);
+        if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, n, X[k], scal + 2 * nv, X[k]);
         if (rc) return rc;
     }
     return MGDD_OK;
@@ -666,7 +691,8 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     void *vs = p == MGDD_F32 ? A.take((size_t)N * n * 8) : vt;
     void *zero = A.take((size_t)N * n * csize(p));
     double2 *scal = (double2 *)A.take(4096);
-    if (!scal) return fail(c, MGDD_ENOMEM, "setup workspace");
+    double2 *gdev = (double2 *)A.take((size_t)4 * N * N * 16 + 256), *ydev = (double2 *)A.take((size_t)4 * N * N * 16 + 256);
+    if (!ydev) return fail(c, MGDD_ENOMEM, "setup workspace");
     for (int i = 0; i < N; i++) Vt[i] = (char *)vt + (size_t)i * n * 16;
     rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
     if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, (size_t)N * n * csize(p), c->stream), "memset");
@@ -675,7 +701,7 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
         if (p == MGDD_F32) rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)N * n, vt, vs);
         if (!rc) rc = launch_sap(c, p, N, 1, sp->mr_iters, 0.0, 0.0, zero, vs);
         if (!rc && p == MGDD_F32) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)N * n, vs, vt);
-        if (!rc) rc = mgs_device(c, MGDD_F64, n, Vt.data(), N, scal);
+        if (!rc) rc = orthonormalise(c, n, Vt.data(), N, gdev, ydev, scal);
     }
     if (!rc) rc = launch_build_P(c, vt);
     if (!rc) rc = launch_coarse_build(c);
@@ -686,8 +712,7 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     void *tmp32 = p == MGDD_F32 ? A.take(n * 8) : nullptr;
     std::vector<void *> phi(N);
     for (int i = 0; i < N; i++) phi[i] = A.take(nc * 16);
-    double2 *gdev = (double2 *)A.take((size_t)4 * N * N * 16 + 256), *ydev = (double2 *)A.take((size_t)4 * N * N * 16 + 256);
-    if (!ydev || !dwbuf || !phi[N - 1]) return fail(c, MGDD_ENOMEM, "setup workspace");
+    if (!dwbuf || !phi[N - 1]) return fail(c, MGDD_ENOMEM, "setup workspace");
     for (int i = 0; i < 2 * N; i++) {
         W[i] = (char *)wbuf + (size_t)i * n * 16;
         DW[i] = (char *)dwbuf + (size_t)i * n * 16;
@@ -750,24 +775,22 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
         const int nw = nk + N;
         for (int j = 0; j < N && !rc; j++)
             rc = hip_check(c, hipMemcpyAsync(W[nk + j], Vt[j], n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
-        if (!rc) rc = mgs_device(c, MGDD_F64, n, W.data(), nw, scal);
+        if (!rc) rc = orthonormalise(c, n, W.data(), nw, gdev, ydev, scal);
         if (!rc) rc = launch_dirac(c, MGDD_F64, nw, wbuf, dwbuf);
-        for (int j = 0; j < nw && !rc; j++) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, DW.data(), nw, DW[j], gdev + (size_t)j * nw);
-        std::vector<cd> G((size_t)nw * nw);
-        if (!rc) rc = read_dev(c, gdev, (size_t)nw * nw, G.data());
-        if (rc) return rc;
-        // column j of the device result holds <DW_i, DW_j>: G[i][j]
+        // G[i][j] = <DW_i, DW_j>
         la::Mat Gm((size_t)nw * nw);
-        for (int i = 0; i < nw; i++)
-            for (int j = 0; j < nw; j++) Gm[(size_t)i * nw + j] = G[(size_t)j * nw + i];
+        if (!rc) rc = blas_gram(c, n, (const void *const *)DW.data(), nw, (const void *const *)DW.data(), nw, gdev);
+        if (!rc) rc = read_dev(c, gdev, (size_t)nw * nw, Gm.data());
+        if (rc) return rc;
         std::vector<double> sig;
         la::Mat Z;
         la::eigh(nw, Gm, sig, Z);
+        // V_i = sum_j W_j Z[j][i] for the N smallest eigenpairs (columns of Z)
         hb = host_buf(c, (size_t)nw * N + 8);
-        for (int i = 0; i < N; i++)
-            for (int j = 0; j < nw; j++) hb[(size_t)i * nw + j] = Z[(size_t)j * nw + i];
+        for (int j = 0; j < nw; j++)
+            for (int i = 0; i < N; i++) hb[(size_t)j * N + i] = Z[(size_t)j * nw + i];
         rc = write_dev(c, hb, (size_t)nw * N, ydev);
-        for (int i = 0; i < N && !rc; i++) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, W.data(), nw, ydev + (size_t)i * nw, 1.0, 0.0, Vt[i]);
+        if (!rc) rc = blas_transform(c, n, (const void *const *)W.data(), nw, ydev, N, Vt.data());
         if (!rc) rc = launch_build_P(c, vt);
         if (!rc) rc = launch_coarse_build(c);
         if (rc) return rc;

@@ -1,7 +1,8 @@
 // Host check of the library's small dense linear algebra (run by
 // tests/test_linalg.py): Givens rotations, LU solves, the Jacobi Hermitian
-// eigensolver and the Hessenberg-QR general eigensolver, checked by their
-// residuals, orthonormality and known spectra.
+// eigensolver, the Hessenberg-QR general eigensolver, the Cholesky factor
+// and the triangular inverse, checked by their residuals, orthonormality and
+// known spectra.
 #include <cstdio>
 #include <random>
 
@@ -109,6 +110,40 @@ int main() {
             for (int j = 0; j < n; j++) best = std::min(best, std::abs(lam[j] - A[i * n + i]));
             if (best > 1e-12) { printf("triangular spectrum\n"); bad++; }
         }
+    }
+    // Cholesky and triangular inverse: G = B^H B + 1, R^H R = G, R upper with
+    // a positive diagonal, R R^{-1} = 1; an indefinite matrix is rejected
+    for (int n : {1, 3, 20, 40}) {
+        Mat B = rnd(n, 31 + n), G((size_t)n * n, 0.0), R;
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                for (int k = 0; k < n; k++) G[i * n + j] += std::conj(B[k * n + i]) * B[k * n + j];
+                if (i == j) G[i * n + j] += 1.0;
+            }
+        if (!cholesky_upper(n, G, R)) { printf("cholesky rejected a definite matrix n=%d\n", n); bad++; continue; }
+        double gn = nrm(G), err = 0, ierr = 0;
+        for (int i = 0; i < n; i++) {
+            if (R[i * n + i].imag() != 0.0 || R[i * n + i].real() <= 0.0) bad++;
+            for (int j = 0; j < i; j++)
+                if (R[i * n + j] != 0.0) bad++;
+            for (int j = 0; j < n; j++) {
+                cd sum = -G[i * n + j];
+                for (int k = 0; k < n; k++) sum += std::conj(R[k * n + i]) * R[k * n + j];
+                err += std::norm(sum);
+            }
+        }
+        Mat Ri = upper_inverse(n, R);
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                cd sum = i == j ? -1.0 : 0.0;
+                for (int k = 0; k < n; k++) sum += R[i * n + k] * Ri[k * n + j];
+                ierr += std::norm(sum);
+            }
+        if (std::sqrt(err) > 1e-12 * gn || std::sqrt(ierr) > 1e-10) { printf("cholesky n=%d %g %g\n", n, err, ierr); bad++; }
+    }
+    {
+        Mat G = {cd(1, 0), cd(2, 0), cd(2, 0), cd(1, 0)}, R;   // eigenvalues 3 and -1
+        if (cholesky_upper(2, G, R)) { printf("cholesky accepted an indefinite matrix\n"); bad++; }
     }
     printf(bad ? "LINALG FAILED %d\n" : "LINALG OK\n", bad);
     return bad ? 1 : 0;

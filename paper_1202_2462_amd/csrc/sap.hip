@@ -210,6 +210,60 @@ __device__ inline void hop_rt(C<T> *acc, const Proj &p, const C<T> *u, const C<T
     }
 }
 
+// Per-lane constants of the spin projection along the lane's direction, for
+// the hops inside the block (rho in LDS). With beta in {+-1, +-i},
+// beta v = (sx * v'.x, sy * v'.y) where v' = v with real and imaginary parts
+// exchanged when beta is imaginary (directions x and z): that exchange is
+// done by the LDS addresses (the two halves of a complex are read as two
+// floats), and the spin permutation pi (x, y) too, so that a projected
+// component costs two FMAs.
+struct ProjLds {
+    int ox, oy;          // float offsets of the parts read as (x, y): (1, 0) when exchanged
+    int src[2];          // LDS component block of l_pi(s): 6 + 3 pi(s)
+    float sx[2], sy[2];  // signs of beta_s
+    float cx[2], cy[2];  // signs of conj(beta_pi(t)) for the lower spins t
+    bool swp, rot;
+};
+
+__device__ inline ProjLds proj_lds_of(int mu, const Proj &p) {
+    ProjLds q;
+    q.rot = !(mu & 1);
+    q.swp = p.swap;
+    q.ox = q.rot ? 1 : 0;
+    q.oy = 1 - q.ox;
+    const float2 bs[2] = {p.b0, p.b1};
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        q.src[s] = 6 + 3 * (q.swp ? 1 - s : s);
+        q.sx[s] = q.rot ? -bs[s].y : bs[s].x;
+        q.sy[s] = q.rot ? bs[s].y : bs[s].x;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        const float2 bp = q.swp ? bs[1 - t] : bs[t];   // beta_pi(t), conjugated below
+        q.cx[t] = q.rot ? bp.y : bp.x;
+        q.cy[t] = q.rot ? -bp.y : bp.x;
+    }
+    return q;
+}
+
+// h = (1 -+ gamma_mu) psi projected to its upper half (FWD: 1 - gamma):
+// h_s = u_s -+ beta_s l_pi(s), psi read from the LDS field rho (component
+// stride RS) at site i
+template <bool FWD>
+__device__ inline void project_lds(const float *rf, int RS, int i, const ProjLds &q, float2 *h) {
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float2 u = ((const float2 *)rf)[(3 * s + a) * RS + i];
+            const int li = ((q.src[s] + a) * RS + i) * 2;
+            const float lx = rf[li + q.ox], ly = rf[li + q.oy];
+            h[3 * s + a] = FWD ? make_float2(u.x - q.sx[s] * lx, u.y - q.sy[s] * ly)
+                               : make_float2(u.x + q.sx[s] * lx, u.y + q.sy[s] * ly);
+        }
+}
+
 // sum of a 12-component partial over the 4 lanes of a site, returned for
 // spin m only (3 components) in out
 template <typename T> __device__ inline void reduce_scatter4(const C<T> *acc, int m, C<T> *out) {
@@ -286,9 +340,13 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
                                                     int mr, T sre, T sim) {
     extern __shared__ unsigned char smem[];
     const int Vb = g.Vb;
-    C<T> *rho_lds = (C<T> *)smem;                        // [12][Vb]
-    C<T> *lnk_lds = rho_lds + 12 * Vb;                   // [4 * 9][Vb]
-    T *red = (T *)(lnk_lds + 36 * Vb);                   // [3 * waves]
+    // component strides padded by 4 complex numbers, so that the four lanes
+    // of a site (different components or directions, same site) fall in
+    // different LDS banks
+    const int RS = Vb + 4, MS = 9 * Vb + 4;
+    C<T> *rho_lds = (C<T> *)smem;                        // [12][RS]
+    C<T> *lnk_lds = rho_lds + 12 * RS;                   // [4][MS]: direction m, entry k at m MS + k Vb
+    T *red = (T *)(lnk_lds + 4 * MS);                    // [3 * waves]
     const size_t V = g.V;
     const int pos = (colour ? g.ncol0 : 0) + xcd_block(gridDim.x);
     const int m = threadIdx.x & 3, l = threadIdx.x >> 2;
@@ -336,7 +394,7 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
 
     // stage the forward link of direction m of this site
 #pragma unroll
-    for (int k = 0; k < 9; k++) lnk_lds[(m * 9 + k) * Vb + l] = Uall.ld_lane(k, d, uoff);
+    for (int k = 0; k < 9; k++) lnk_lds[m * MS + k * Vb + l] = Uall.ld_lane(k, d, uoff);
     __syncthreads();
 
     // r = b - (D - shift) z, spin m
@@ -347,12 +405,12 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
         for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
         load_spinor<T>(zf, nf, psi);
 #pragma unroll
-        for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + l];
+        for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + l];
         hop_rt<T, true>(acc, pr, u, psi);
         load_spinor<T>(zf, nbk, psi);
         if (lnb >= 0) {
 #pragma unroll
-            for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + lnb];
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + lnb];
         } else {
 #pragma unroll
             for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, nbk, uoff);
@@ -370,34 +428,52 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
             C<T> dz = csub(csub(az[c], cscale(hs[c], (T)0.5)), cmul(shift, zs[c]));
             rho[c] = csub(bs[c], dz);
             e[c] = mk<T>(0, 0);
-            rho_lds[(3 * m + c) * Vb + l] = rho[c];
+            rho_lds[(3 * m + c) * RS + l] = rho[c];
         }
     }
     __syncthreads();
 
+    const float *rf = (const float *)rho_lds;
     for (int it = 0; it < mr; it++) {
         const unsigned salt = opaque_zero();
-        C<T> acc[12], psi[12], u[9];
+        // the projection constants are recomputed from the lane's direction
+        // in every step (a few instructions) rather than held in registers
+        // across the loop
+        const int mq = m + (int)salt;
+        const ProjLds pq = proj_lds_of(mq, proj_of(mq));
+        // the two hops along the lane's direction: w_f = U h_f, w_b = U^H h_b
+        // (upper halves); the lower halves are -B^H w_f + B^H w_b = B^H (w_b - w_f)
+        C<T> acc[12], h[6], u[9], wf[6], wb[6];
 #pragma unroll
-        for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
+        for (int k = 0; k < 6; k++) wf[k] = wb[k] = mk<T>(0, 0);
         if (lnf >= 0) {
+            project_lds<true>(rf, RS, lnf, pq, h);
 #pragma unroll
-            for (int k = 0; k < 12; k++) psi[k] = rho_lds[k * Vb + lnf];
-#pragma unroll
-            for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + l];
-            hop_rt<T, true>(acc, pr, u, psi);
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + l];
+            su3_mv<T, false>(u, h, wf);
+            su3_mv<T, false>(u, h + 3, wf + 3);
         }
         if (lnb >= 0) {
+            project_lds<false>(rf, RS, lnb, pq, h);
 #pragma unroll
-            for (int k = 0; k < 12; k++) psi[k] = rho_lds[k * Vb + lnb];
-#pragma unroll
-            for (int k = 0; k < 9; k++) u[k] = lnk_lds[(m * 9 + k) * Vb + lnb];
-            hop_rt<T, false>(acc, pr, u, psi);
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + lnb];
+            su3_mv<T, true>(u, h, wb);
+            su3_mv<T, true>(u, h + 3, wb + 3);
         }
+#pragma unroll
+        for (int k = 0; k < 6; k++) acc[k] = cadd(wf[k], wb[k]);
+#pragma unroll
+        for (int t = 0; t < 2; t++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const C<T> d0 = csub(wb[a], wf[a]), d1 = csub(wb[3 + a], wf[3 + a]);
+                const C<T> src = pq.swp ? (t ? d0 : d1) : (t ? d1 : d0);
+                acc[6 + 3 * t + a] = mk<T>(pq.cx[t] * (pq.rot ? src.y : src.x), pq.cy[t] * (pq.rot ? src.x : src.y));
+            }
         C<T> hs[3], xc[6], ax[3];
         reduce_scatter4<T>(acc, m, hs);
 #pragma unroll
-        for (int c = 0; c < 6; c++) xc[c] = rho_lds[(6 * ch + c) * Vb + l];
+        for (int c = 0; c < 6; c++) xc[c] = rho_lds[(6 * ch + c) * RS + l];
         clover_rows<T>(Aall, aoff, d, m, xc, ax, salt);
         Red3<T> part{0, 0, 0};
 #pragma unroll
@@ -417,7 +493,7 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
         }
         if (it + 1 < mr) {
 #pragma unroll
-            for (int c = 0; c < 3; c++) rho_lds[(3 * m + c) * Vb + l] = rho[c];
+            for (int c = 0; c < 3; c++) rho_lds[(3 * m + c) * RS + l] = rho[c];
             __syncthreads();
         }
     }
@@ -433,7 +509,7 @@ int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, doub
         return fail(c, MGDD_ESHAPE, "the Schwarz kernel needs 64 <= block volume <= 256");
     size_t lds = (prec == MGDD_F64 ? 16 : 8) * 12 * (size_t)g.Vb + (prec == MGDD_F64 ? 8 : 4) * 3 * (g.Vb / 64);
     // four lanes per site with the block's links staged in LDS (FP32)
-    const size_t lds4 = 8 * (12 + 36) * (size_t)g.Vb + 4 * 3 * (4 * g.Vb / 64);
+    const size_t lds4 = 8 * (12 * ((size_t)g.Vb + 4) + 4 * (9 * (size_t)g.Vb + 4)) + 4 * 3 * (4 * g.Vb / 64);
     for (int s = 0; s < nsweeps; s++)
         for (int col = 0; col < 2; col++) {
             int nblocks = col ? g.nblocks - g.ncol0 : g.ncol0;

@@ -166,6 +166,16 @@ class Bench:
             out[name] = dict(applies_per_s=1.0 / t, us_per_apply=t * 1e6, gbs=bps * self.V / t / 1e9)
         return out
 
+    def copy_rate(self):
+        """Device-to-device copy of 1 GiB (read + write), the stream-copy
+        ceiling the stencil rates can be read against."""
+        torch = self.torch
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        t = self.time_calls(lambda: y.copy_(x), 10)
+        del x, y
+        return 2 * (1 << 30) / t / 1e9
+
     def sap_launch_time(self):
         """Average duration of one colour step of the FP32 Schwarz kernel
         (mgdd_sap with one sweep launches one kernel per colour)."""
@@ -300,6 +310,7 @@ def main():
 
     bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
     result["dirac"] = bench.dirac_rates()
+    result["stream_copy_gbs"] = bench.copy_rate()
     if d_n:
         result["dirac"]["f64_in_timed_steps"] = {"launches": d_n, "us_per_launch": d_ms * 1e3 / d_n,
                                             "gbs": 1536 * d_units / (d_ms * 1e-3) / 1e9}

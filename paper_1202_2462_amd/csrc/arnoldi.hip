@@ -22,7 +22,8 @@ namespace mgdd {
 
 namespace {
 
-constexpr int TPB = 256;
+constexpr int TPB = 512;   // threads of the orthogonalisation and dot-product kernels (8 waves)
+constexpr int APB = 1024;  // threads of the apply kernel: the 9 2N products of a site over many threads
 constexpr int KMAX = 16;   // basis vectors of the coarse Arnoldi: at most 15 coarse GMRES steps
 constexpr int VMAX = 16;   // basis vectors of one fused Gram-Schmidt pass
 
@@ -55,11 +56,11 @@ __device__ inline void sum_partials(const double2 *__restrict__ part, int nq, in
     __syncthreads();
 }
 
-// apply step. Grid (Vc, nb), 256 threads share the 9 2N products of y(a)
+// apply step. Grid (Vc, nb), 1024 threads share the 9 2N products of y(a)
 // (dc_row_partial); wave 0 then forms y(a), row i in lane i, and the dot
 // products of the basis vectors at site a with it.
 template <typename T>
-__global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
+__global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
                                                             const C<T> *__restrict__ Dc, const C<T> *__restrict__ w,
                                                             const double2 *__restrict__ npart, int nnp, VecList V,
                                                             int j, C<T> *__restrict__ vj, C<T> *__restrict__ y,
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const
     const size_t so = (size_t)sg * Vc * n2;
     __shared__ double2 red[1];
     __shared__ C<T> xs[9 * 64];
-    __shared__ C<T> part[TPB];
+    __shared__ C<T> part[APB];
     sum_partials(npart + (size_t)sg * nnp, 1, nnp, red);
     const double nn = red[0].x;
     const T sc = (T)(nn > 0 ? 1.0 / sqrt(nn) : 0.0);
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(TPB) void arnoldi_apply_kernel(int Vc, int N, const
     dc_row_partial<T>(Dc + (size_t)a * 9 * n2 * n2, xs, n2, part);
     __syncthreads();
     if (threadIdx.x >= 64) return;
-    const int i = threadIdx.x, nparts = TPB / n2;
+    const int i = threadIdx.x, nparts = APB / n2;
     C<T> yv = mk<T>(0, 0), vv = mk<T>(0, 0);
     if (i < n2) {
         for (int q = 0; q < nparts; q++) yv = cadd(yv, part[q * n2 + i]);
@@ -114,34 +115,28 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
     const size_t so = (size_t)sg * n;
     __shared__ double2 coef[NV];
     __shared__ double red[TPB / 64][2 * NV];
-    // pin is laid out [k][segment][partial]. 16 threads per coefficient:
-    // thread u adds the partials u, u + 16, ... (two independent loads at a
-    // time), then a butterfly over the group.
-    constexpr int GS = 16;
-    {
-        const int k = threadIdx.x / GS, u = threadIdx.x % GS;
+    // pin is laid out [k][segment][partial]. One wave per coefficient (wave
+    // w takes k = w and w + 8): lane u adds the partials u, u + 64, ...
+    // (four independent loads at a time), then a butterfly.
+    for (int k = threadIdx.x >> 6; k < NV; k += TPB / 64) {
+        const int u = threadIdx.x & 63;
         double a0 = 0, b0 = 0, a1 = 0, b1 = 0;
         if (k < nk) {
             const double2 *pk = pin + ((size_t)k * nb + sg) * npin;
             int q = u;
-            for (; q + GS < npin; q += 2 * GS) {
-                const double2 v0 = pk[q], v1 = pk[q + GS];
-                a0 += v0.x;
-                b0 += v0.y;
-                a1 += v1.x;
-                b1 += v1.y;
+            for (; q + 192 < npin; q += 256) {
+                const double2 v0 = pk[q], v1 = pk[q + 64], v2 = pk[q + 128], v3 = pk[q + 192];
+                a0 += v0.x + v2.x;
+                b0 += v0.y + v2.y;
+                a1 += v1.x + v3.x;
+                b1 += v1.y + v3.y;
             }
-            if (q < npin) {
+            for (; q < npin; q += 64) {
                 a0 += pk[q].x;
                 b0 += pk[q].y;
             }
         }
-        double a = a0 + a1, b = b0 + b1;
-#pragma unroll
-        for (int m = GS / 2; m >= 1; m >>= 1) {
-            a += __shfl_xor(a, m, 64);
-            b += __shfl_xor(b, m, 64);
-        }
+        const double a = wave_sum(a0 + a1), b = wave_sum(b0 + b1);
         if (k < nk && u == 0) coef[k] = make_double2(a, b);
     }
     __syncthreads();
@@ -310,7 +305,7 @@ int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *con
         void *y = work[j & 1];
         dim3 gapp(Vc, nb);
 #define APPLY(T)                                                                                                  \
-    arnoldi_apply_kernel<T><<<gapp, TPB, 0, c->stream>>>(Vc, N, L1.cnbr, (const C<T> *)(p == MGDD_F64 ? L1.Dc64 : L1.Dc32), \
+    arnoldi_apply_kernel<T><<<gapp, APB, 0, c->stream>>>(Vc, N, L1.cnbr, (const C<T> *)(p == MGDD_F64 ? L1.Dc64 : L1.Dc32), \
                                                          (const C<T> *)w, part3, G, vl, j, (C<T> *)V[j], (C<T> *)y,  \
                                                          part1, NR + (size_t)j * nb)
         if (p == MGDD_F64) APPLY(double); else APPLY(float);

@@ -373,19 +373,19 @@ __global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N
 
 // ---------------------------------------------------------------- coarse stencil y = D_c x
 //
-// One workgroup of 256 threads per (coarse site, right-hand side): the 9 2N
-// products of each row are split over floor(256 / 2N) thread sets
+// One workgroup of 1024 threads per (coarse site, right-hand side): the 9 2N
+// products of each row are split over floor(1024 / 2N) thread sets
 // (dc_row_partial), whose partial rows are then added in set order. Blocks
 // are stored column-major, B[a][dir][col][row], so consecutive threads read
 // consecutive rows of one column.
 template <typename T>
-__global__ __launch_bounds__(256) void coarse_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
-                                                           const C<T> *__restrict__ Dc, const C<T> *__restrict__ x,
-                                                           C<T> *__restrict__ y) {
+__global__ __launch_bounds__(1024) void coarse_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
+                                                            const C<T> *__restrict__ Dc, const C<T> *__restrict__ x,
+                                                            C<T> *__restrict__ y) {
     const int a = blockIdx.x, r = blockIdx.y;
     const int n2 = 2 * N;
     __shared__ C<T> xs[9 * 64];
-    __shared__ C<T> part[256];
+    __shared__ C<T> part[1024];
     const C<T> *xr = x + (size_t)r * Vc * n2;
     for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) xs[e] = xr[(size_t)cnbr[a * 9 + e / n2] * n2 + e % n2];
     __syncthreads();
@@ -679,10 +679,10 @@ int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     }
     dim3 grid(L1.Vc, nrhs);
     if (prec == MGDD_F64)
-        coarse_apply_kernel<double><<<grid, 256, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,
+        coarse_apply_kernel<double><<<grid, 1024, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,
                                                                 (const double2 *)in, (double2 *)out);
     else
-        coarse_apply_kernel<float><<<grid, 256, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const float2 *)L1.Dc32,
+        coarse_apply_kernel<float><<<grid, 1024, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const float2 *)L1.Dc32,
                                                                (const float2 *)in, (float2 *)out);
     return hip_check(c, hipGetLastError(), "coarse apply kernel");
 }

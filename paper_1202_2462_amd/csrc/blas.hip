@@ -142,8 +142,12 @@ __global__ void rsqrt_kernel(const double2 *v, double2 *coef) {
 // ---- tall-skinny products of vector sets (bootstrap setup, FP64)
 //
 // gram: part[wg][i][j] = sum over the workgroup's elements of conj(x_i) y_j.
-// Elements are processed in tiles of GT; the tiles of x and y go through LDS
-// and thread t owns the 4x4 block (i0 .. i0+3, j0 .. j0+3) of the output.
+// Elements are processed in tiles of GT; the tiles of x and y go through LDS.
+// The output is cut into 4x4 blocks (only those with bi <= bj when y is x:
+// the rest is the conjugate transpose); thread t owns block t % nblk for the
+// elements e = t / nblk, t / nblk + ngroups, ... of each tile, so that up to
+// 256 threads work also when there are few blocks; the ngroups partial
+// blocks are added in group order at the end.
 constexpr int GMAX = 64;   // vectors per set
 constexpr int GT = 32;     // elements per tile
 
@@ -151,12 +155,26 @@ struct PtrList64 {
     const void *p[GMAX];
 };
 
-__global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int nx, PtrList64 ys, int ny,
+__global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int nx, PtrList64 ys, int ny, int sym,
                                                    double2 *__restrict__ part) {
-    __shared__ double2 xt[GMAX][GT], yt[GMAX][GT];
+    __shared__ double2 sm[2 * GMAX * GT];   // x and y tiles; reused for the group reduction
+    double2 (*xt)[GT] = (double2 (*)[GT])sm;
+    double2 (*yt)[GT] = (double2 (*)[GT])(sm + GMAX * GT);
     const int tx = (nx + 3) / 4, ty = (ny + 3) / 4;
-    const int t = threadIdx.x, bi = t / ty, bj = t % ty;
-    const bool owner = t < tx * ty;
+    const int nblk = sym ? tx * (tx + 1) / 2 : tx * ty;
+    int ngroups = 1;
+    while (ngroups < 8 && 2 * ngroups * nblk <= (int)blockDim.x) ngroups *= 2;
+    const int t = threadIdx.x, blk = t % nblk, grp = t / nblk;
+    const bool owner = t < nblk * ngroups;
+    int bi = 0, bj = 0;
+    if (sym) {   // blk -> (bi, bj), bi <= bj, row by row
+        int r = blk;
+        while (r >= tx - bi) { r -= tx - bi; bi++; }
+        bj = bi + r;
+    } else {
+        bi = blk / ty;
+        bj = blk % ty;
+    }
     double2 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -173,7 +191,7 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
         }
         __syncthreads();
         if (owner) {
-            for (int e = 0; e < GT; e++) {
+            for (int e = grp; e < GT; e += ngroups) {
                 double2 xv[4], yv[4];
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
@@ -188,7 +206,32 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
         }
         __syncthreads();
     }
-    if (!owner) return;
+    // add the groups' partial blocks in group order (through LDS)
+    if (ngroups > 1) {
+        double2 *red = sm;   // [256][16]
+        if (owner) {
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++) red[t * 16 + 4 * a + b] = acc[a][b];
+        }
+        __syncthreads();
+        if (t < nblk) {
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    double2 v = red[t * 16 + 4 * a + b];
+                    for (int gq = 1; gq < ngroups; gq++) {
+                        const double2 w = red[(gq * nblk + t) * 16 + 4 * a + b];
+                        v.x += w.x;
+                        v.y += w.y;
+                    }
+                    acc[a][b] = v;
+                }
+        }
+    }
+    if (t >= nblk) return;
     double2 *pw = part + (size_t)blockIdx.x * nx * ny;
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -199,18 +242,23 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
         }
 }
 
-// out[q] = sum_wg part[wg][q] in workgroup order, q < nq
-__global__ __launch_bounds__(256) void gram_finish_kernel(int nwg, int nq, const double2 *__restrict__ part,
-                                                          double2 *__restrict__ out) {
+// out[q] = sum_wg part[wg][q] in workgroup order, q = i ny + j < nq; with sym
+// only the blocks with bi <= bj were formed, the others are the conjugates
+// of their transposes
+__global__ __launch_bounds__(256) void gram_finish_kernel(int nwg, int nx, int ny, int sym,
+                                                          const double2 *__restrict__ part, double2 *__restrict__ out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
+    if (q >= nx * ny) return;
+    const int i = q / ny, j = q % ny;
+    const bool mirror = sym && (i / 4) > (j / 4);
+    const int src = mirror ? j * ny + i : q;
     double a = 0, b = 0;
     for (int w = 0; w < nwg; w++) {
-        const double2 v = part[(size_t)w * nq + q];
+        const double2 v = part[(size_t)w * nx * ny + src];
         a += v.x;
         b += v.y;
     }
-    out[q] = make_double2(a, b);
+    out[q] = make_double2(a, mirror ? -b : b);
 }
 
 // y_k = sum_{i < nx} M[i * ny + k] x_i for k < ny, over tiles of GT elements:
@@ -335,9 +383,11 @@ int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const
     PtrList64 px{}, py{};
     for (int i = 0; i < nx; i++) px.p[i] = xs[i];
     for (int j = 0; j < ny; j++) py.p[j] = ys[j];
-    gram_kernel<<<nwg, 256, 0, c->stream>>>(n, px, nx, py, ny, part);
+    int sym = nx == ny;
+    for (int i = 0; i < nx && sym; i++) sym = xs[i] == ys[i];
+    gram_kernel<<<nwg, 256, 0, c->stream>>>(n, px, nx, py, ny, sym, part);
     const int nq = nx * ny;
-    gram_finish_kernel<<<(nq + 255) / 256, 256, 0, c->stream>>>(nwg, nq, part, out);
+    gram_finish_kernel<<<(nq + 255) / 256, 256, 0, c->stream>>>(nwg, nx, ny, sym, part, out);
     return hip_check(c, hipGetLastError(), "gram");
 }
 

@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N
                                                        const double2 *__restrict__ Up, const double2 *__restrict__ Ap,
                                                        const double2 *__restrict__ P, double2 *__restrict__ Dc,
                                                        int nwg) {
-    extern __shared__ double dred[];  // [waves][N][9][4]
+    extern __shared__ double dred[];  // reduction space (see below)
     const int n2 = 2 * N;
     const int w = xcd_block(nwg);
     const int a = w / n2, j = w % n2, chi = j / N, kk = j % N;
@@ -327,7 +327,15 @@ __global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N
 #pragma unroll
         for (int c = 0; c < 12; c++) wt[0][c] = csub(ap[c], cscale(self[c], 0.5));
     }
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // projections onto the N test-vector columns of aggregate a: for each k
+    // every thread writes its 36 partial products (9 terms x re/im x two row
+    // chiralities) to LDS, then S threads per product add the partials in a
+    // fixed order (a tree through LDS costs fewer instructions than 36
+    // cross-lane reductions per wave)
+    const int nthr = blockDim.x, S = nthr / 36 > 0 ? nthr / 36 : 1;
+    double *red = dred;                         // [36][nthr]
+    double *p2 = red + 36 * nthr;               // [36][S]
+    double *res = p2 + 36 * S;                  // [N][36]
     for (int k = 0; k < N; k++) {
         double2 pk[12];
         if (active) {
@@ -348,26 +356,29 @@ __global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N
                 p[c < 6 ? 1 : 3] += im;
             }
 #pragma unroll
-            for (int q = 0; q < 4; q++) p[q] = wsum(p[q]);
-            if (lane == 0) {
-                double *o = dred + (((size_t)wv * N + k) * 9 + t) * 4;
-                o[0] = p[0]; o[1] = p[1]; o[2] = p[2]; o[3] = p[3];
-            }
+            for (int q = 0; q < 4; q++) red[(t * 4 + q) * nthr + threadIdx.x] = p[q];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < 36 * S) {
+            const int q = threadIdx.x / S, sidx = threadIdx.x % S;
+            double acc = 0;
+            for (int i = sidx; i < nthr; i += S) acc += red[q * nthr + i];
+            p2[q * S + sidx] = acc;
+        }
+        __syncthreads();
+        if (threadIdx.x < 36) {
+            double acc = 0;
+            for (int sidx = 0; sidx < S; sidx++) acc += p2[threadIdx.x * S + sidx];
+            res[k * 36 + threadIdx.x] = acc;
         }
     }
     __syncthreads();
-    const int nw = blockDim.x >> 6;
     const size_t blk = (size_t)n2 * n2;
     for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
         int t = e / n2, i = e % n2;
         int rchi = i / N, k = i % N;
-        double re = 0, im = 0;
-        for (int q = 0; q < nw; q++) {
-            const double *o = dred + (((size_t)q * N + k) * 9 + t) * 4;
-            re += o[2 * rchi];
-            im += o[2 * rchi + 1];
-        }
-        Dc[((size_t)a * 9 + t) * blk + (size_t)j * n2 + i] = make_double2(re, im);
+        const double *o = res + (size_t)k * 36 + t * 4;
+        Dc[((size_t)a * 9 + t) * blk + (size_t)j * n2 + i] = make_double2(o[2 * rchi], o[2 * rchi + 1]);
     }
 }
 
@@ -628,7 +639,8 @@ int launch_coarse_build(Ctx *c) {
         for (int m = 0; m < 4; m++) ag.a[m] = L1.agg[m];
         int threads = ((L1.Va + 63) / 64) * 64;
         int nwg = L1.Vc * n2;
-        size_t lds = (size_t)(threads / 64) * N * 9 * 4 * sizeof(double);
+        const int S = threads / 36 > 0 ? threads / 36 : 1;
+        size_t lds = ((size_t)36 * threads + 36 * S + (size_t)36 * N) * sizeof(double);
         dc_build_kernel<<<nwg, threads, lds, c->stream>>>(g, ag, N, L1.Va, L1.agg_sites, (const double2 *)c->U64,
                                                            (const double2 *)c->A64, (const double2 *)L1.P64,
                                                            (double2 *)L1.Dc64, nwg);

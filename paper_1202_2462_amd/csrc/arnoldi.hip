@@ -57,8 +57,8 @@ __device__ inline void sum_partials(const double2 *__restrict__ part, int nq, in
 }
 
 // apply step. Grid (Vc, nb), 1024 threads share the 9 2N products of y(a)
-// (dc_row_partial); wave 0 then forms y(a), row i in lane i, and the dot
-// products of the basis vectors at site a with it.
+// (dc_row_partial); wave 0 then forms y(a), row i in lane i, and wave k
+// the dot product of basis vector k at site a with it.
 template <typename T>
 __global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
                                                             const C<T> *__restrict__ Dc, const C<T> *__restrict__ w,
@@ -83,21 +83,27 @@ __global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const
     __syncthreads();
     dc_row_partial<T>(Dc + (size_t)a * 9 * n2 * n2, xs, n2, part);
     __syncthreads();
-    if (threadIdx.x >= 64) return;
-    const int i = threadIdx.x, nparts = APB / n2;
-    C<T> yv = mk<T>(0, 0), vv = mk<T>(0, 0);
-    if (i < n2) {
-        for (int q = 0; q < nparts; q++) yv = cadd(yv, part[q * n2 + i]);
-        vv = xs[i];   // v_j at this site (direction 0 is the site itself)
-        y[so + (size_t)a * n2 + i] = yv;
-        vj[so + (size_t)a * n2 + i] = vv;
+    // wave 0 forms y(a) (row i in lane i) and stores it with v_j(a)
+    __shared__ C<T> ys[64];
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x, nparts = APB / n2;
+        C<T> yv = mk<T>(0, 0);
+        if (i < n2) {
+            for (int q = 0; q < nparts; q++) yv = cadd(yv, part[q * n2 + i]);
+            y[so + (size_t)a * n2 + i] = yv;
+            vj[so + (size_t)a * n2 + i] = xs[i];   // v_j at this site (direction 0 is the site itself)
+        }
+        ys[i] = yv;
     }
-    const double2 yd = make_double2((double)yv.x, (double)yv.y);
-    for (int k = 0; k <= j; k++) {
-        C<T> xv = vv;
-        if (k < j && i < n2) xv = ((const C<T> *)V.p[k])[so + (size_t)a * n2 + i];
+    __syncthreads();
+    // dot products <v_k(a), y(a)>, k <= j: wave k (a second round for k >= 16)
+    const int i = threadIdx.x & 63;
+    for (int k = threadIdx.x >> 6; k <= j; k += APB / 64) {
+        C<T> xv = mk<T>(0, 0);
+        if (i < n2) xv = k < j ? ((const C<T> *)V.p[k])[so + (size_t)a * n2 + i] : xs[i];
+        const C<T> yv = ys[i];
         double2 d = make_double2(0, 0);
-        cfmac(d, make_double2((double)xv.x, (double)xv.y), yd);
+        cfmac(d, make_double2((double)xv.x, (double)xv.y), make_double2((double)yv.x, (double)yv.y));
         const double re = wave_sum(d.x), im = wave_sum(d.y);
         if (i == 0) part1[((size_t)k * nb + sg) * Vc + a] = make_double2(re, im);
     }

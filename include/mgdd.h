@@ -92,7 +92,8 @@ int mgdd_destroy(mgdd_ctx *ctx);
 const char *mgdd_last_error(const mgdd_ctx *ctx);
 
 /* Bytes of a device field: level 0 = fine lattice, level 1 = coarse lattice
- * of the current P (0 if there is none). */
+ * of the current P, level 2 = level-3 lattice of the current P2 (0 if there
+ * is none). */
 size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level);
 
 /* Sets the gauge field and mass of D = D(U) + m (Section 1): U is the
@@ -234,6 +235,36 @@ typedef struct {
  * MGDD_ENOTREADY (no gauge field; no P for FGMRES_MG). */
 int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const void *b, void *z,
                mgdd_solve_stats *stats);
+
+/* ------------------------------------------------------------------ third level
+ * Section 3: the two-level construction applied to the coarse equation
+ * D_c x = r_c (the paper's recursive extension). Level-2 aggregates are
+ * blocks of coarse sites (agg2, dividing the coarse lattice); each is split
+ * by the coarse chirality (the first / last N dof of a coarse site) into two
+ * pieces of vol(agg2) * N dof. Level-3 vectors: [rhs][level-3 site
+ * (lexicographic)][chirality][N2] complex, MGDD_F64 or MGDD_F32
+ * (mgdd_field_bytes with level 2). Building P2 or D_c again (mgdd_build_P,
+ * mgdd_setup_bootstrap) invalidates the third level. */
+
+/* P2 from ntv2 coarse FP64 test vectors (ntv2 coarse fields, device
+ * memory, copied): every (aggregate, chirality) piece orthonormalised in
+ * column order (the unique thin QR with a positive diagonal of R), then
+ * D_cc = P2^H D_c P2 as a 9-point stencil with 2*ntv2 x 2*ntv2 blocks, built
+ * by the local formula (a hop of D_c inside an aggregate goes to the self
+ * block, one crossing its face in direction d to block d). Errors:
+ * MGDD_ENOTREADY (no P), MGDD_ESHAPE (agg2 does not divide the coarse
+ * lattice), MGDD_EINVAL (ntv2 not in 1..32), MGDD_ERANK (rank-deficient
+ * piece). Synchronous. */
+int mgdd_build_P2(mgdd_ctx *ctx, const int agg2[4], int ntv2, const void *test_vectors2);
+
+/* coarse2 = P2^H coarse; nrhs coarse fields to nrhs level-3 fields. */
+int mgdd_restrict2(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *coarse2);
+
+/* coarse = P2 coarse2. */
+int mgdd_prolong2(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse2, void *coarse);
+
+/* out = D_cc in on nrhs level-3 fields (in and out must not alias). */
+int mgdd_coarse2_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out);
 
 /* ------------------------------------------------------------------ kernel timing
  * Instrumentation, not part of the method. While timing is enabled the

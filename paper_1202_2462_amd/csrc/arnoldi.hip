@@ -275,10 +275,10 @@ inline int orth_grid(size_t n) {
 
 }  // namespace
 
-size_t coarse_arnoldi_scratch(const Ctx *c, int m, int nb) {
-    const size_t n = (size_t)c->c.Vc * 2 * c->c.N;
+size_t coarse_arnoldi_scratch(const StencilOp &op, int m, int nb) {
+    const size_t n = (size_t)op.V * 2 * op.N;
     const size_t G = orth_grid(n);
-    return ((size_t)(m + 1) * nb * c->c.Vc + 3 * (size_t)(m + 1) * nb * G + 2 * (size_t)(m + 1) * nb) * 16 + 4096;
+    return ((size_t)(m + 1) * nb * op.V + 3 * (size_t)(m + 1) * nb * G + 2 * (size_t)(m + 1) * nb) * 16 + 4096;
 }
 
 // m Arnoldi steps on D_c from b for nb segments. V: m + 1 basis vectors
@@ -286,10 +286,9 @@ size_t coarse_arnoldi_scratch(const Ctx *c, int m, int nb) {
 // coarse_arnoldi_scratch bytes. Outputs: H1, H2 (column j at j (m + 1) nb,
 // entry [i][segment]) and NR (NR[j nb + segment] = squared norm of the
 // j-th unnormalised vector, j = 0 .. m).
-int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *const *V, void *work0, void *work1,
-                          void *scratch, double2 *H1, double2 *H2, double2 *NR) {
-    const Level1 &L1 = c->c;
-    const int Vc = L1.Vc, N = L1.N;
+int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *const *V,
+                          void *work0, void *work1, void *scratch, double2 *H1, double2 *H2, double2 *NR) {
+    const int Vc = op.V, N = op.N;
     const size_t n = (size_t)Vc * 2 * N;
     const int G = orth_grid(n);
     if (m + 1 > KMAX) return fail(c, MGDD_EINVAL, "too many coarse GMRES steps for the fused Arnoldi kernels");
@@ -311,7 +310,7 @@ int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *con
         void *y = work[j & 1];
         dim3 gapp(Vc, nb);
 #define APPLY(T)                                                                                                  \
-    arnoldi_apply_kernel<T><<<gapp, APB, 0, c->stream>>>(Vc, N, L1.cnbr, (const C<T> *)(p == MGDD_F64 ? L1.Dc64 : L1.Dc32), \
+    arnoldi_apply_kernel<T><<<gapp, APB, 0, c->stream>>>(Vc, N, op.nbr, (const C<T> *)(p == MGDD_F64 ? op.D64 : op.D32), \
                                                          (const C<T> *)w, part3, G, vl, j, (C<T> *)V[j], (C<T> *)y,  \
                                                          part1, NR + (size_t)j * nb)
         if (p == MGDD_F64) APPLY(double); else APPLY(float);

@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "level2.h"
 #include "mgdd_internal.h"
 #include "solver.h"
 #include "transfer.h"
@@ -229,6 +230,7 @@ size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level) {
     if (!ctx || !valid_prec(prec) || nrhs < 0) return 0;
     if (level == 0) return csize(prec) * fine_elems(&ctx->c, nrhs);
     if (level == 1 && ctx->c.c.ready) return csize(prec) * (size_t)nrhs * ctx->c.c.Vc * 2 * ctx->c.c.N;
+    if (level == 2 && ctx->c.c2.ready) return csize(prec) * (size_t)nrhs * ctx->c.c2.Vcc * 2 * ctx->c.c2.N2;
     return 0;
 }
 
@@ -338,6 +340,7 @@ int mgdd_build_P(mgdd_ctx *ctx, const int agg[4], int ntv, const void *test_vect
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     c->c.ready = false;
+    c->c2.ready = false;
     int rc = transfer_setup(c, agg, ntv);
     if (!rc) rc = launch_build_P(c, test_vectors);
     if (!rc) rc = launch_coarse_build(c);
@@ -384,6 +387,57 @@ int mgdd_coarse_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *o
     GUARD_END
 }
 
+static int need_level2(mgdd_ctx *ctx) {
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    if (!ctx->c.c2.ready) return fail(&ctx->c, MGDD_ENOTREADY, "no third level (call mgdd_build_P2 or mgdd_setup_level2)");
+    return MGDD_OK;
+}
+
+int mgdd_build_P2(mgdd_ctx *ctx, const int agg2[4], int ntv2, const void *test_vectors2) {
+    if (!ctx || !agg2 || !test_vectors2) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    c->c2.ready = false;
+    rc = level2_setup(c, agg2, ntv2);
+    if (!rc) rc = launch_build_P2(c, test_vectors2);
+    if (!rc) rc = launch_dcc_build(c);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (rc) c->c2.ready = false;
+    return rc;
+    GUARD_END
+}
+
+int mgdd_restrict2(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *coarse2) {
+    if (!ctx || !coarse || !coarse2 || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    int rc = need_level2(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_restrict2(&ctx->c, prec, nrhs, coarse, coarse2);
+    GUARD_END
+}
+
+int mgdd_prolong2(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse2, void *coarse) {
+    if (!ctx || !coarse || !coarse2 || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    int rc = need_level2(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_prolong2(&ctx->c, prec, nrhs, coarse2, coarse);
+    GUARD_END
+}
+
+int mgdd_coarse2_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out) {
+    if (!ctx || !in || !out || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (in == out) return fail(&ctx->c, MGDD_EINVAL, "in and out alias");
+    int rc = need_level2(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_stencil_apply(&ctx->c, level2_op(&ctx->c), prec, nrhs, in, out);
+    GUARD_END
+}
+
 int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x) {
     if (!ctx || !b || !x || !valid_prec(prec) || nrhs <= 0 || iters < 1 || iters > 1000) return MGDD_EINVAL;
     if (b == x) return fail(&ctx->c, MGDD_EINVAL, "b and x alias");
@@ -425,6 +479,7 @@ int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const v
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     c->c.ready = false;
+    c->c2.ready = false;
     int rc = bootstrap(c, sp, random_vectors, arnoldi_start);
     if (!rc) c->c.ready = true;
     return rc;

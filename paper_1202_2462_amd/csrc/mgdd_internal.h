@@ -72,6 +72,28 @@ struct Level1 {  // coarse level of the current P
     void *tv64 = nullptr;                   // the N test vectors P was built from
 };
 
+// Third level: aggregates of coarse sites, P2 from N2 coarse test vectors,
+// D_cc = P2^H D_c P2 on the level-3 lattice, and the blocks of the level-2
+// Schwarz smoother on the coarse lattice.
+struct Level2 {
+    bool ready = false;                     // P2 and D_cc built
+    int agg[4] = {0, 0, 0, 0}, Lcc[4] = {0, 0, 0, 0};
+    int Vcc = 0, Va2 = 0, N2 = 0, N1 = 0;
+    void *P2_64 = nullptr, *P2_32 = nullptr;    // [N2][Vc][2 N1] complex (coarse vectors)
+    void *Dcc64 = nullptr, *Dcc32 = nullptr;    // [Vcc][9][2N2 (col)][2N2 (row)] complex
+    int *cnbr2 = nullptr;                   // [Vcc][9]
+    int *agg2_sites = nullptr;              // [Vcc][Va2] coarse sites of each level-3 site
+    int *site_agg2 = nullptr;               // [Vc] level-3 site of each coarse site
+    int *geo = nullptr;                     // coarse extents Lc[4], then the aggregate shape [4]
+    void *tv2_64 = nullptr;                 // the N2 test vectors P2 was built from
+    // Schwarz blocks of the level-2 smoother
+    int blk[4] = {0, 0, 0, 0};
+    int nblk = 0, ncol0 = 0, Vb2 = 0;
+    int *blk_sites = nullptr;               // [nblk][Vb2], colour-0 blocks first
+    int *blk_lnbr = nullptr;                // [nblk][Vb2][9] local index of the neighbour in the block, or -1
+    int *blk_nbr = nullptr;                 // [nblk][Vb2][9] coarse site of the neighbour
+};
+
 // Optional timing of kernel families with HIP events on the context's stream:
 // each launch is bracketed by an event pair from a fixed pool; durations are
 // added up when the pool is full or when the caller reads them.
@@ -103,6 +125,7 @@ struct Ctx {
     void *A64 = nullptr, *A32 = nullptr;    // [36][V] complex pairs (packed Hermitian 6x6 x 2 chiralities)
     void *Ainv64 = nullptr;                 // [36][V] the same for the inverse of A (even-odd)
     Level1 c;
+    Level2 c2;
     // workspace
     std::vector<void *> owned;
     void *stage = nullptr;                  // canonical staging buffer

@@ -179,17 +179,23 @@ static int orthonormalise(Ctx *c, size_t n, void *const *X, int nv, double2 *gbu
 
 // ---------------------------------------------------------------- coarse GMRES
 
-size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb) {
-    size_t n = (size_t)c->c.Vc * 2 * c->c.N * nb;
+size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb) { return stencil_gmres_bytes(level1_op(c), p, m, nb); }
+
+size_t stencil_gmres_bytes(const StencilOp &op, int p, int m, int nb) {
+    size_t n = (size_t)op.V * 2 * op.N * nb;
     return (size_t)(m + 3) * (n * csize(p) + 256) + (4 * (size_t)(m + 2) * (m + 2) + 2 * (size_t)(m + 2)) * nb * 16 +
-           coarse_arnoldi_scratch(c, m, nb) + 8192;
+           coarse_arnoldi_scratch(op, m, nb) + 8192;
 }
 
-// x_s = GMRES_m(D_c, b_s) from x = 0, no restart, for nb right-hand sides at
+int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A) {
+    return stencil_gmres(c, level1_op(c), p, m, nb, b, x, A);
+}
+
+// x_s = GMRES_m(op, b_s) from x = 0, no restart, for nb right-hand sides at
 // once (one Krylov basis and one Hessenberg matrix each, shared launches);
 // one host synchronisation.
-int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A) {
-    const size_t n = (size_t)c->c.Vc * 2 * c->c.N, cs = csize(p);
+int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *x, Arena &A) {
+    const size_t n = (size_t)op.V * 2 * op.N, cs = csize(p);
     const size_t mark = A.off;
     std::vector<void *> V(m + 1);
     for (int i = 0; i <= m; i++) V[i] = A.take(n * nb * cs);
@@ -204,15 +210,15 @@ int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A)
     if (m <= ARNOLDI_FUSED_MAX_STEPS) {
         // three fused kernels per Arnoldi step
         void *w2 = A.take(n * nb * cs);
-        void *scr = A.take(coarse_arnoldi_scratch(c, m, nb));
+        void *scr = A.take(coarse_arnoldi_scratch(op, m, nb));
         if (!scr) return fail(c, MGDD_ENOMEM, "coarse GMRES workspace");
-        rc = launch_coarse_arnoldi(c, p, m, nb, b, V.data(), w, w2, scr, h1, h2, nr);
+        rc = launch_coarse_arnoldi(c, op, p, m, nb, b, V.data(), w, w2, scr, h1, h2, nr);
     } else {
         const void *bp = b;
         rc = blas_multidot(c, p, p, n, &bp, 1, b, nr, nb);
         if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0], nb);
         for (int j = 0; j < m && !rc; j++) {
-            rc = launch_coarse_apply(c, p, nb, V[j], w);
+            rc = launch_stencil_apply(c, op, p, nb, V[j], w);
             if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1) * nb,
                                h2 + (size_t)j * (m + 1) * nb, nr + (size_t)(j + 1) * nb, nb);
             if (!rc) rc = blas_normalize(c, p, p, n, w, nr + (size_t)(j + 1) * nb, V[j + 1], nb);

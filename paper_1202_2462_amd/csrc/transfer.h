@@ -10,6 +10,34 @@ struct AggGeom {
     int a[4];
 };
 
+// A 9-point stencil operator with 2N x 2N complex blocks per site (D_c on the
+// coarse lattice, D_cc on the level-3 lattice): sites, N, neighbour table
+// [V][9] (self first), blocks [V][9][col][row] in FP64 and FP32.
+struct StencilOp {
+    int V = 0, N = 0;
+    const int *nbr = nullptr;
+    const void *D64 = nullptr, *D32 = nullptr;
+};
+inline StencilOp level1_op(const Ctx *c) {
+    StencilOp o;
+    o.V = c->c.Vc;
+    o.N = c->c.N;
+    o.nbr = c->c.cnbr;
+    o.D64 = c->c.Dc64;
+    o.D32 = c->c.Dc32;
+    return o;
+}
+inline StencilOp level2_op(const Ctx *c) {
+    StencilOp o;
+    o.V = c->c2.Vcc;
+    o.N = c->c2.N2;
+    o.nbr = c->c2.cnbr2;
+    o.D64 = c->c2.Dcc64;
+    o.D32 = c->c2.Dcc32;
+    return o;
+}
+int launch_stencil_apply(Ctx *c, const StencilOp &op, int prec, int nrhs, const void *in, void *out);
+
 // tables and buffers of the coarse level for aggregates agg and N test vectors
 int transfer_setup(Ctx *c, const int *agg, int N);
 // P from N FP64 fine fields (device layout); FP32 copy made too. MGDD_ERANK if rank deficient.
@@ -23,12 +51,12 @@ int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out);
 
 // Fused Arnoldi process on D_c for the coarse GMRES (arnoldi.hip); m <= 15.
 constexpr int ARNOLDI_FUSED_MAX_STEPS = 15;
-size_t coarse_arnoldi_scratch(const Ctx *c, int m, int nb);
+size_t coarse_arnoldi_scratch(const StencilOp &op, int m, int nb);
 // w <- w - V V^H w twice (nb segments of n), three passes; k <= 16 vectors.
 constexpr int FUSED_CGS2_MAX = 16;
 int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, double2 *h1, double2 *h2,
                double2 *nrm);
-int launch_coarse_arnoldi(Ctx *c, int p, int m, int nb, const void *b, void *const *V, void *work0, void *work1,
-                          void *scratch, double2 *H1, double2 *H2, double2 *NR);
+int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *const *V,
+                          void *work0, void *work1, void *scratch, double2 *H1, double2 *H2, double2 *NR);
 
 }  // namespace mgdd

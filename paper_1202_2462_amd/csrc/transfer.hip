@@ -7,6 +7,7 @@
 #include "stencil.h"
 #include "transfer.h"
 #include "coarse.h"
+#include "level2.h"
 
 namespace mgdd {
 
@@ -513,7 +514,8 @@ int transfer_setup(Ctx *c, const int *agg, int N) {
     bool same = L1.agg_sites && L1.N == N && L1.Vc == Vc;
     for (int m = 0; m < 4 && same; m++) same = L1.agg[m] == agg[m];
     if (same) return MGDD_OK;
-    // free the previous level
+    // free the previous level (and the third level built on it)
+    level2_free(c);
     void *old[] = {L1.P64, L1.P32, L1.Dc64, L1.Dc32, L1.cnbr, L1.agg_sites, L1.site_agg, L1.tv64};
     (void)hipStreamSynchronize(c->stream);
     for (void *p : old) dfree(c, p);
@@ -676,27 +678,30 @@ int launch_coarse_build(Ctx *c) {
     return hip_check(c, hipGetLastError(), "D_c convert");
 }
 
-int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out) {
-    const Level1 &L1 = c->c;
+int launch_stencil_apply(Ctx *c, const StencilOp &op, int prec, int nrhs, const void *in, void *out) {
     if (nrhs >= MFMA_MIN_RHS) {
-        const int ntiles = (2 * L1.N + 15) / 16;
-        dim3 grid(L1.Vc * ntiles, (nrhs + 15) / 16);
+        const int ntiles = (2 * op.N + 15) / 16;
+        dim3 grid(op.V * ntiles, (nrhs + 15) / 16);
         if (prec == MGDD_F64)
             coarse_apply_mfma_kernel<double><<<grid, 64, 0, c->stream>>>(
-                L1.Vc, L1.N, nrhs, ntiles, L1.cnbr, (const double2 *)L1.Dc64, (const double2 *)in, (double2 *)out);
+                op.V, op.N, nrhs, ntiles, op.nbr, (const double2 *)op.D64, (const double2 *)in, (double2 *)out);
         else
             coarse_apply_mfma_kernel<float><<<grid, 64, 0, c->stream>>>(
-                L1.Vc, L1.N, nrhs, ntiles, L1.cnbr, (const float2 *)L1.Dc32, (const float2 *)in, (float2 *)out);
+                op.V, op.N, nrhs, ntiles, op.nbr, (const float2 *)op.D32, (const float2 *)in, (float2 *)out);
         return hip_check(c, hipGetLastError(), "coarse apply kernel (MFMA)");
     }
-    dim3 grid(L1.Vc, nrhs);
+    dim3 grid(op.V, nrhs);
     if (prec == MGDD_F64)
-        coarse_apply_kernel<double><<<grid, 1024, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const double2 *)L1.Dc64,
-                                                                (const double2 *)in, (double2 *)out);
+        coarse_apply_kernel<double><<<grid, 1024, 0, c->stream>>>(op.V, op.N, op.nbr, (const double2 *)op.D64,
+                                                                 (const double2 *)in, (double2 *)out);
     else
-        coarse_apply_kernel<float><<<grid, 1024, 0, c->stream>>>(L1.Vc, L1.N, L1.cnbr, (const float2 *)L1.Dc32,
-                                                               (const float2 *)in, (float2 *)out);
+        coarse_apply_kernel<float><<<grid, 1024, 0, c->stream>>>(op.V, op.N, op.nbr, (const float2 *)op.D32,
+                                                                (const float2 *)in, (float2 *)out);
     return hip_check(c, hipGetLastError(), "coarse apply kernel");
+}
+
+int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out) {
+    return launch_stencil_apply(c, level1_op(c), prec, nrhs, in, out);
 }
 
 }  // namespace mgdd

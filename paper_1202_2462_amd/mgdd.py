@@ -96,6 +96,10 @@ _sig("mgdd_precondition", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.
      _vp, _vp)
 _sig("mgdd_setup_bootstrap", ctypes.c_int, _vp, ctypes.POINTER(SetupParams), _vp, _vp)
 _sig("mgdd_solve", ctypes.c_int, _vp, ctypes.POINTER(SolveParams), ctypes.c_int, _vp, _vp, ctypes.POINTER(SolveStats))
+_sig("mgdd_build_P2", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp)
+_sig("mgdd_restrict2", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_prolong2", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_coarse2_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_timing_enable", ctypes.c_int, _vp, ctypes.c_int)
 _sig("mgdd_timing_read", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong))
@@ -228,6 +232,22 @@ def mgdd_solve(ctx, params: SolveParams, nrhs, b, z, allow_noconv=False):
     return [stats[i] for i in range(nrhs)]
 
 
+def mgdd_build_P2(ctx, agg2, ntv2, test_vectors2):
+    return _check(ctx, _lib.mgdd_build_P2(ctx, _i4(*agg2), ntv2, _ptr(test_vectors2)))
+
+
+def mgdd_restrict2(ctx, prec, nrhs, coarse, coarse2):
+    return _check(ctx, _lib.mgdd_restrict2(ctx, prec, nrhs, _ptr(coarse), _ptr(coarse2)))
+
+
+def mgdd_prolong2(ctx, prec, nrhs, coarse2, coarse):
+    return _check(ctx, _lib.mgdd_prolong2(ctx, prec, nrhs, _ptr(coarse2), _ptr(coarse)))
+
+
+def mgdd_coarse2_apply(ctx, prec, nrhs, x, y):
+    return _check(ctx, _lib.mgdd_coarse2_apply(ctx, prec, nrhs, _ptr(x), _ptr(y)))
+
+
 def mgdd_timing_enable(ctx, on=True):
     return _check(ctx, _lib.mgdd_timing_enable(ctx, 1 if on else 0))
 
@@ -309,6 +329,35 @@ class Lattice:
         self.N = test_vectors.shape[0]
         self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
         self.Vc = int(np.prod(self.cdims))
+
+    # third level -------------------------------------------------------
+    def build_P2(self, agg2, test_vectors2):
+        """test_vectors2: (N2, Vc, 2, N, 2) float64 device tensor of coarse fields."""
+        mgdd_build_P2(self.ctx, agg2, test_vectors2.shape[0], test_vectors2)
+        self.agg2 = tuple(agg2)
+        self.N2 = test_vectors2.shape[0]
+        self.ccdims = tuple(d // a for d, a in zip(self.cdims, self.agg2))
+        self.Vcc = int(np.prod(self.ccdims))
+
+    def coarse2_field(self, prec=F64, nrhs=1):
+        t = self.torch
+        dt = t.float64 if prec == F64 else t.float32
+        return t.zeros((nrhs, self.Vcc, 2, self.N2, 2), dtype=dt, device="cuda")
+
+    def restrict2(self, c, cc=None):
+        cc = self.coarse2_field(self.prec_of(c), c.shape[0]) if cc is None else cc
+        mgdd_restrict2(self.ctx, self.prec_of(c), c.shape[0], c, cc)
+        return cc
+
+    def prolong2(self, cc, c=None):
+        c = self.coarse_field(self.prec_of(cc), cc.shape[0]) if c is None else c
+        mgdd_prolong2(self.ctx, self.prec_of(cc), cc.shape[0], cc, c)
+        return c
+
+    def coarse2_apply(self, x, y=None):
+        y = self.torch.empty_like(x) if y is None else y
+        mgdd_coarse2_apply(self.ctx, self.prec_of(x), x.shape[0], x, y)
+        return y
 
     def coarse_field(self, prec=F64, nrhs=1):
         t = self.torch

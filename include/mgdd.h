@@ -209,6 +209,12 @@ typedef struct {
     int coarse_iters;  /* GMRES steps on D_c per preconditioner application */
     int nu;            /* Schwarz sweeps per preconditioner application */
     int mr_iters;      /* MR steps per block solve */
+    int levels;        /* 3: three-level preconditioner (needs mgdd_setup_level2 or
+                          mgdd_build_P2); 0 or 2: two levels */
+    int k2;            /* three levels: flexible GMRES steps on D_c per coarse solve */
+    int nu2;           /* three levels: level-2 Schwarz sweeps per application of
+                          the level-2 preconditioner */
+    int mr2;           /* three levels: MR steps per level-2 block solve */
 } mgdd_solve_params;
 
 typedef struct {
@@ -222,7 +228,9 @@ typedef struct {
 /* Solves D z = b (eq. (1.1)) for nrhs FP64 device fields b; z (FP64 device
  * fields) holds the initial guess on entry and the solution on exit.
  * FGMRES_MG: flexible GMRES(restart) right-preconditioned by the two-level
- * method (Section 4). GCR: plain GCR(restart) on D. GCR_EO: GCR(restart) on
+ * method (Section 4), or with levels = 3 by the three-level method
+ * (mgdd_precondition3); coarse_iters is then the GMRES step count on the
+ * coarsest operator D_cc. GCR: plain GCR(restart) on D. GCR_EO: GCR(restart) on
  * the even-odd Schur complement, convergence judged on the full system.
  * With FGMRES_MG the nrhs right-hand sides are solved together: one Krylov
  * basis, Hessenberg matrix, restart and stopping test each, with D, the
@@ -232,7 +240,8 @@ typedef struct {
  * into smaller batches. GCR and GCR_EO solve them one after the other.
  * stats: array of nrhs entries (may be NULL). Synchronous. Errors:
  * MGDD_ENOCONV (maxit reached; z and stats written), MGDD_ENAN,
- * MGDD_ENOTREADY (no gauge field; no P for FGMRES_MG). */
+ * MGDD_ENOTREADY (no gauge field; no P for FGMRES_MG; no third level or no
+ * level-2 Schwarz blocks for levels = 3). */
 int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const void *b, void *z,
                mgdd_solve_stats *stats);
 
@@ -265,6 +274,51 @@ int mgdd_prolong2(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse2, void *
 
 /* out = D_cc in on nrhs level-3 fields (in and out must not alias). */
 int mgdd_coarse2_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out);
+
+/* nsweeps sweeps of the red-black Schwarz method (Algorithm 2.1) on the
+ * coarse equation D_c z = b, the smoother of the second level: the coarse
+ * lattice is split into blocks of block2 coarse sites (dividing it, with an
+ * even number of blocks or one block per direction, at most 1024 / (2N)
+ * sites per block); blocks whose block coordinates have an even sum (colour
+ * 0) are updated first, then colour 1, each by MR(mr_iters) on the block
+ * operator (D_c restricted to the block: hops leaving it dropped) started
+ * from a zero correction. b, z: nrhs coarse fields of precision prec, z holds
+ * the initial guess on entry and the result on exit (z and b must not
+ * alias). Errors: MGDD_ENOTREADY (no P), MGDD_ESHAPE (block2 invalid).
+ * Synchronous. */
+int mgdd_coarse_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block2[4], int nsweeps, int mr_iters, const void *b,
+                    void *z);
+
+/* Three-level preconditioner (Section 3 applied recursively): as
+ * mgdd_precondition, with the coarse equation D_c x_c = P^H r solved by k2
+ * steps of flexible GMRES from x_c = 0 (no restart), right-preconditioned by
+ * the two-level method on D_c: M2(v) = nu2 level-2 Schwarz sweeps (mr2 MR
+ * steps per block, the blocks of the last mgdd_setup_level2 or
+ * mgdd_coarse_sap call) on D_c y = v from y0 = P2 GMRES_coarse_iters(D_cc,
+ * P2^H v). Errors: MGDD_ENOTREADY (no third level; no level-2 blocks while
+ * nu2 > 0), MGDD_EINVAL (k2 not in 1..64). Synchronous. */
+int mgdd_precondition3(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, int k2, int nu2, int mr2,
+                       int coarse_iters, const void *r, void *z);
+
+typedef struct {
+    int agg2[4];       /* level-2 aggregate in coarse sites (divides the coarse lattice) */
+    int ntv2;          /* N2: test vectors of the second level, 1..32 */
+    int block2[4];     /* level-2 Schwarz block in coarse sites (as mgdd_coarse_sap) */
+    int nu2;           /* smoothing rounds of the test vectors */
+    int mr_iters;      /* MR steps per level-2 block solve */
+} mgdd_level2_params;
+
+/* Setup of the third level (the recursive part of the bootstrap setup,
+ * Section 3): the test vectors of the second level are the fine test vectors
+ * P was built from, taken to the coarse grid with P^H (the first min(N,
+ * ntv2)), then ntv2 - N of the caller's random coarse vectors when ntv2 > N,
+ * orthonormalised in index order; nu2 rounds of one level-2 Schwarz sweep on
+ * D_c y = 0 started from each vector, each round followed by the
+ * orthonormalisation; then P2 and D_cc as in mgdd_build_P2. FP64 throughout.
+ * random2: ntv2 - N FP64 coarse fields in device memory (may be NULL when
+ * ntv2 <= N). Errors: those of mgdd_build_P2 and mgdd_coarse_sap,
+ * MGDD_EINVAL (random2 missing). Synchronous. */
+int mgdd_setup_level2(mgdd_ctx *ctx, const mgdd_level2_params *params, const void *random2);
 
 /* ------------------------------------------------------------------ kernel timing
  * Instrumentation, not part of the method. While timing is enabled the

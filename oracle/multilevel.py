@@ -18,10 +18,10 @@ The pieces, each the level-1 construction restated on D_c:
   formula (a hop of D_c between coarse sites of the same aggregate goes to
   the self block, one that crosses the aggregate face in direction d to
   block d);
-* `level2_test_vectors`: the fine test vectors restricted with P^H (the
-  setup "restricts smoothed test vectors with P^H to the next coarser
-  grid"), completed with random coarse vectors when more are asked for,
-  smoothed by level-2 SAP sweeps and kept orthonormal;
+* `level2_test_vectors`: the smoothed fine test vectors taken to the coarse
+  grid with P^H (the recursive step of the bootstrap setup, Section 3),
+  completed with random coarse vectors when more are asked for, smoothed
+  by level-2 SAP sweeps and kept orthonormal;
 * `ThreeLevel`: the preconditioner with the coarse equation solved by a
   fixed number of flexible GMRES steps preconditioned by the two-level
   method of the second level.

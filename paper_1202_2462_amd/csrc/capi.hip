@@ -438,6 +438,67 @@ int mgdd_coarse2_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *
     GUARD_END
 }
 
+static int need_level3_solver(mgdd_ctx *ctx, int k2, int nu2, int mr2) {
+    if (k2 < 1 || k2 > 64 || nu2 < 0 || mr2 < 0) return fail(&ctx->c, MGDD_EINVAL, "bad level-2 solver parameters");
+    int rc = need_level2(ctx);
+    if (rc) return rc;
+    if (nu2 > 0 && !ctx->c.c2.blk_sites)
+        return fail(&ctx->c, MGDD_ENOTREADY, "no level-2 Schwarz blocks (call mgdd_setup_level2 or mgdd_coarse_sap)");
+    return MGDD_OK;
+}
+
+int mgdd_precondition3(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, int k2, int nu2, int mr2,
+                       int coarse_iters, const void *r, void *z) {
+    if (!ctx || !r || !z || !valid_prec(prec) || nrhs <= 0 || nu < 0 || mr_iters < 0 || coarse_iters < 1)
+        return MGDD_EINVAL;
+    int rc = need_level3_solver(ctx, k2, nu2, mr2);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    MgOpts o;
+    o.nu = nu;
+    o.mr = mr_iters;
+    o.cit = coarse_iters;
+    o.levels = 3;
+    o.k2 = k2;
+    o.nu2 = nu2;
+    o.mr2 = mr2;
+    Arena A;
+    rc = arena_open(c, precond_bytes(c, prec, o, nrhs), A);
+    if (!rc) rc = mg_precond(c, prec, nrhs, r, z, o, A);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc && A.need) rc = fail(c, MGDD_ENOMEM, "preconditioner workspace estimate too small");
+    return rc;
+    GUARD_END
+}
+
+int mgdd_setup_level2(mgdd_ctx *ctx, const mgdd_level2_params *params, const void *random2) {
+    if (!ctx || !params || params->nu2 < 0 || params->mr_iters < 0) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    rc = level2_bootstrap(&ctx->c, params, random2);
+    if (rc) ctx->c.c2.ready = false;
+    return rc;
+    GUARD_END
+}
+
+int mgdd_coarse_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block2[4], int nsweeps, int mr_iters, const void *b,
+                    void *z) {
+    if (!ctx || !block2 || !b || !z || !valid_prec(prec) || nrhs <= 0 || nsweeps < 0 || mr_iters < 0)
+        return MGDD_EINVAL;
+    if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    rc = level2_sap_setup(c, block2);
+    if (!rc) rc = launch_sap2(c, prec, nrhs, nsweeps, mr_iters, b, z);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    return rc;
+    GUARD_END
+}
+
 int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x) {
     if (!ctx || !b || !x || !valid_prec(prec) || nrhs <= 0 || iters < 1 || iters > 1000) return MGDD_EINVAL;
     if (b == x) return fail(&ctx->c, MGDD_EINVAL, "b and x alias");
@@ -462,8 +523,12 @@ int mgdd_precondition(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, i
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     Arena A;
-    rc = arena_open(c, precond_bytes(c, prec, coarse_iters, nrhs), A);
-    if (!rc) rc = mg_precond(c, prec, nrhs, r, z, nu, mr_iters, coarse_iters, A);
+    MgOpts o;
+    o.nu = nu;
+    o.mr = mr_iters;
+    o.cit = coarse_iters;
+    rc = arena_open(c, precond_bytes(c, prec, o, nrhs), A);
+    if (!rc) rc = mg_precond(c, prec, nrhs, r, z, o, A);
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     return rc;
     GUARD_END
@@ -499,6 +564,12 @@ int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const v
         int rc = need_coarse(ctx);
         if (rc) return rc;
         if (sp->coarse_iters < 1 || sp->nu < 0 || sp->mr_iters < 0) return fail(&ctx->c, MGDD_EINVAL, "bad solve parameters");
+        if (sp->levels == 3) {
+            rc = need_level3_solver(ctx, sp->k2, sp->nu2, sp->mr2);
+            if (rc) return rc;
+        } else if (sp->levels != 0 && sp->levels != 2) {
+            return fail(&ctx->c, MGDD_EINVAL, "levels must be 2 or 3");
+        }
     }
     GUARD_BEGIN
     Ctx *c = &ctx->c;

@@ -182,6 +182,77 @@ __global__ __launch_bounds__(1024) void dcc_build_kernel(int Vc, int N1, int N2,
     }
 }
 
+// Colour step of the level-2 Schwarz smoother (Algorithm 2.1 on D_c): one
+// workgroup per block of coarse sites (blocks of one colour, blockIdx.y the
+// right-hand side), one thread per (site l of the block, row i of its 2 N1).
+// r = b - D_c z on the block (all nine terms), then MR(mr) on the block
+// operator (terms whose neighbour lies in the block; lnbr < 0 otherwise)
+// from e = 0 with rho in LDS, and z += e.
+template <typename T>
+__global__ __launch_bounds__(1024) void sap2_kernel(int Vc, int N1, int Vb2, int blk0, const int *__restrict__ bsites,
+                                                    const int *__restrict__ lnbr, const int *__restrict__ gnbr,
+                                                    const C<T> *__restrict__ Dc, const C<T> *__restrict__ b,
+                                                    C<T> *__restrict__ z, int mr) {
+    extern __shared__ unsigned char smem2[];
+    const int n1 = 2 * N1;
+    C<T> *rho = (C<T> *)smem2;                 // [Vb2][n1]
+    double *red = (double *)(rho + Vb2 * n1);  // [3 * waves]
+    const int blk = blk0 + blockIdx.x, r = blockIdx.y;
+    const int t = threadIdx.x, l = t / n1, i = t % n1;
+    const bool act = l < Vb2;
+    const size_t vs = (size_t)Vc * n1;
+    const C<T> *br = b + (size_t)r * vs;
+    C<T> *zr = z + (size_t)r * vs;
+    int a = 0;
+    if (act) a = bsites[(size_t)blk * Vb2 + l];
+    // residual
+    C<T> rv = mk<T>(0, 0);
+    if (act) {
+        C<T> acc = mk<T>(0, 0);
+        for (int d = 0; d < 9; d++) {
+            const int ap = gnbr[((size_t)blk * Vb2 + l) * 9 + d];
+            const C<T> *B = Dc + ((size_t)a * 9 + d) * n1 * n1 + i;
+            const C<T> *zv = zr + (size_t)ap * n1;
+            for (int j = 0; j < n1; j++) cfma(acc, B[(size_t)j * n1], zv[j]);
+        }
+        rv = csub(br[(size_t)a * n1 + i], acc);
+        rho[l * n1 + i] = rv;
+    }
+    C<T> e = mk<T>(0, 0);
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+    for (int it = 0; it < mr; it++) {
+        C<T> q = mk<T>(0, 0);
+        if (act) {
+            for (int d = 0; d < 9; d++) {
+                const int ln = lnbr[((size_t)blk * Vb2 + l) * 9 + d];
+                if (ln < 0) continue;
+                const C<T> *B = Dc + ((size_t)a * 9 + d) * n1 * n1 + i;
+                const C<T> *rr = rho + ln * n1;
+                for (int j = 0; j < n1; j++) cfma(q, B[(size_t)j * n1], rr[j]);
+            }
+        }
+        double p0 = (double)q.x * q.x + (double)q.y * q.y;
+        double p1 = (double)q.x * rv.x + (double)q.y * rv.y;   // conj(q) rho
+        double p2 = (double)q.x * rv.y - (double)q.y * rv.x;
+        p0 = wave_sum_d(p0);
+        p1 = wave_sum_d(p1);
+        p2 = wave_sum_d(p2);
+        if (lane == 0) { red[3 * wv] = p0; red[3 * wv + 1] = p1; red[3 * wv + 2] = p2; }
+        __syncthreads();
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int k = 0; k < nw; k++) { s0 += red[3 * k]; s1 += red[3 * k + 1]; s2 += red[3 * k + 2]; }
+        if (s0 == 0.0) break;
+        const C<T> alpha = mk<T>((T)(s1 / s0), (T)(s2 / s0));
+        cfma(e, alpha, rv);
+        rv = csub(rv, cmul(alpha, q));
+        __syncthreads();   // every thread has read rho and red
+        if (act) rho[l * n1 + i] = rv;
+        __syncthreads();
+    }
+    if (act) zr[(size_t)a * n1 + i] = cadd(zr[(size_t)a * n1 + i], e);
+}
+
 template <typename T>
 __global__ void to_f32_kernel(size_t n, const double2 *__restrict__ src, C<T> *__restrict__ dst) {
     size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,13 +267,24 @@ int upload(Ctx *c, int **dst, const std::vector<int> &v) {
 
 }  // namespace
 
-void level2_free(Ctx *c) {
+void level2_free(Ctx *c, bool keep_blocks) {
     Level2 &L2 = c->c2;
-    void *old[] = {L2.P2_64, L2.P2_32, L2.Dcc64, L2.Dcc32, L2.cnbr2, L2.agg2_sites, L2.site_agg2, L2.geo,
-                   L2.tv2_64, L2.blk_sites, L2.blk_lnbr, L2.blk_nbr};
+    void *old[] = {L2.P2_64, L2.P2_32, L2.Dcc64, L2.Dcc32, L2.cnbr2, L2.agg2_sites, L2.site_agg2, L2.geo, L2.tv2_64};
     (void)hipStreamSynchronize(c->stream);
     for (void *p : old) dfree(c, p);
-    L2 = Level2();
+    Level2 fresh;
+    if (keep_blocks) {   // the Schwarz block tables depend on the coarse lattice only
+        fresh.blk_sites = L2.blk_sites;
+        fresh.blk_lnbr = L2.blk_lnbr;
+        fresh.blk_nbr = L2.blk_nbr;
+        for (int m = 0; m < 4; m++) fresh.blk[m] = L2.blk[m];
+        fresh.nblk = L2.nblk;
+        fresh.ncol0 = L2.ncol0;
+        fresh.Vb2 = L2.Vb2;
+    } else {
+        for (void *p : {(void *)L2.blk_sites, (void *)L2.blk_lnbr, (void *)L2.blk_nbr}) dfree(c, p);
+    }
+    L2 = fresh;
 }
 
 // tables of the level-3 lattice for aggregates agg2 of coarse sites and N2 test vectors
@@ -221,7 +303,7 @@ int level2_setup(Ctx *c, const int *agg2, int N2) {
     bool same = L2.agg2_sites && L2.N2 == N2 && L2.N1 == L1.N && L2.Vcc == Vcc;
     for (int m = 0; m < 4 && same; m++) same = L2.agg[m] == agg2[m];
     if (same) return MGDD_OK;
-    level2_free(c);
+    level2_free(c, true);
     const int Vc = L1.Vc;
     std::vector<int> sites((size_t)Vcc * Va2), site_agg(Vc), cnbr((size_t)Vcc * 9), lc(L1.Lc, L1.Lc + 4),
         ag(agg2, agg2 + 4);
@@ -313,6 +395,104 @@ int launch_dcc_build(Ctx *c) {
     rc = hip_check(c, hipGetLastError(), "convert");
     if (!rc) L2.ready = true;
     return rc;
+}
+
+// blocks of the level-2 Schwarz smoother on the coarse lattice
+int level2_sap_setup(Ctx *c, const int *block2) {
+    const Level1 &L1 = c->c;
+    Level2 &L2 = c->c2;
+    if (!L1.ready) return fail(c, MGDD_ENOTREADY, "no coarse level (build P first)");
+    bool same = L2.blk_sites != nullptr;
+    for (int m = 0; m < 4 && same; m++) same = L2.blk[m] == block2[m];
+    if (same) return MGDD_OK;
+    int nb[4], Vb2 = 1;
+    for (int m = 0; m < 4; m++) {
+        if (block2[m] <= 0 || L1.Lc[m] % block2[m])
+            return fail(c, MGDD_ESHAPE, "level-2 Schwarz blocks must divide the coarse lattice");
+        nb[m] = L1.Lc[m] / block2[m];
+        if (nb[m] > 1 && nb[m] % 2) return fail(c, MGDD_ESHAPE, "level-2 Schwarz block counts must be even or 1");
+        Vb2 *= block2[m];
+    }
+    if (Vb2 * 2 * L1.N > 1024) return fail(c, MGDD_ESHAPE, "level-2 Schwarz block too large (sites x 2N > 1024)");
+    const int nblk = nb[0] * nb[1] * nb[2] * nb[3];
+    // block order: colour 0 first, lexicographic within a colour
+    std::vector<int> order, pos(nblk);
+    for (int col = 0; col < 2; col++)
+        for (int q = 0; q < nblk; q++) {
+            int t = q, s = 0;
+            for (int m = 0; m < 4; m++) { s += t % nb[m]; t /= nb[m]; }
+            if (s % 2 == col) order.push_back(q);
+        }
+    int ncol0 = 0;
+    for (int q = 0; q < nblk; q++) {
+        int t = order[q], s = 0;
+        for (int m = 0; m < 4; m++) { s += t % nb[m]; t /= nb[m]; }
+        if (s % 2 == 0) ncol0++;
+        pos[order[q]] = q;
+    }
+    std::vector<int> bsites((size_t)nblk * Vb2), lnbr((size_t)nblk * Vb2 * 9), gnbr((size_t)nblk * Vb2 * 9);
+    std::vector<int> blk_of(L1.Vc), loc_of(L1.Vc), fill(nblk, 0);
+    const int *Lc = L1.Lc;
+    for (int a = 0; a < L1.Vc; a++) {
+        int t = a, x[4];
+        for (int m = 0; m < 4; m++) { x[m] = t % Lc[m]; t /= Lc[m]; }
+        int bx[4];
+        for (int m = 0; m < 4; m++) bx[m] = x[m] / block2[m];
+        const int q = pos[bx[0] + nb[0] * (bx[1] + nb[1] * (bx[2] + nb[2] * bx[3]))];
+        const int l = fill[q]++;
+        bsites[(size_t)q * Vb2 + l] = a;
+        blk_of[a] = q;
+        loc_of[a] = l;
+    }
+    std::vector<int> cn((size_t)L1.Vc * 9);
+    int rc = hip_check(c, hipMemcpy(cn.data(), L1.cnbr, cn.size() * sizeof(int), hipMemcpyDeviceToHost), "copy");
+    if (rc) return rc;
+    for (int q = 0; q < nblk; q++)
+        for (int l = 0; l < Vb2; l++) {
+            const int a = bsites[(size_t)q * Vb2 + l];
+            for (int d = 0; d < 9; d++) {
+                const int ap = cn[(size_t)a * 9 + d];
+                gnbr[((size_t)q * Vb2 + l) * 9 + d] = ap;
+                lnbr[((size_t)q * Vb2 + l) * 9 + d] = blk_of[ap] == q ? loc_of[ap] : -1;
+            }
+        }
+    for (void *p : {(void *)L2.blk_sites, (void *)L2.blk_lnbr, (void *)L2.blk_nbr}) dfree(c, p);
+    L2.blk_sites = L2.blk_lnbr = L2.blk_nbr = nullptr;
+    rc = upload(c, &L2.blk_sites, bsites);
+    if (!rc) rc = upload(c, &L2.blk_lnbr, lnbr);
+    if (!rc) rc = upload(c, &L2.blk_nbr, gnbr);
+    if (rc) return rc;
+    for (int m = 0; m < 4; m++) L2.blk[m] = block2[m];
+    L2.nblk = nblk;
+    L2.ncol0 = ncol0;
+    L2.Vb2 = Vb2;
+    return MGDD_OK;
+}
+
+int launch_sap2(Ctx *c, int prec, int nrhs, int nsweeps, int mr, const void *b, void *z) {
+    const Level1 &L1 = c->c;
+    const Level2 &L2 = c->c2;
+    const int n1 = 2 * L1.N, threads = ((L2.Vb2 * n1 + 63) / 64) * 64;
+    const size_t lds = (size_t)L2.Vb2 * n1 * csize(prec) + 3 * 8 * (threads / 64);
+    for (int s = 0; s < nsweeps; s++)
+        for (int col = 0; col < 2; col++) {
+            const int nbl = col ? L2.nblk - L2.ncol0 : L2.ncol0;
+            if (nbl == 0) continue;
+            dim3 grid(nbl, nrhs);
+            const int blk0 = col ? L2.ncol0 : 0;
+            if (prec == MGDD_F64)
+                sap2_kernel<double><<<grid, threads, lds, c->stream>>>(L1.Vc, L1.N, L2.Vb2, blk0, L2.blk_sites,
+                                                                       L2.blk_lnbr, L2.blk_nbr,
+                                                                       (const double2 *)L1.Dc64, (const double2 *)b,
+                                                                       (double2 *)z, mr);
+            else
+                sap2_kernel<float><<<grid, threads, lds, c->stream>>>(L1.Vc, L1.N, L2.Vb2, blk0, L2.blk_sites,
+                                                                      L2.blk_lnbr, L2.blk_nbr, (const float2 *)L1.Dc32,
+                                                                      (const float2 *)b, (float2 *)z, mr);
+            int rc = hip_check(c, hipGetLastError(), "level-2 Schwarz kernel");
+            if (rc) return rc;
+        }
+    return MGDD_OK;
 }
 
 int launch_restrict2(Ctx *c, int prec, int nrhs, const void *in, void *out) {

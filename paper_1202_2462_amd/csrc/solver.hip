@@ -9,6 +9,7 @@
 
 #include "blas.h"
 #include "eo.h"
+#include "level2.h"
 #include "linalg.h"
 #include "solver.h"
 #include "transfer.h"
@@ -177,6 +178,50 @@ static int orthonormalise(Ctx *c, size_t n, void *const *X, int nv, double2 *gbu
     return MGDD_OK;
 }
 
+// The end of a GMRES cycle of m steps for nb right-hand sides: the
+// Hessenberg matrices (h1 + h2 above the diagonal, sqrt(nr) below; column j
+// at j (m + 1) nb, entry [i][segment]) are read back, the small least
+// squares problems min ||beta e_1 - H y|| solved on the host (a column whose
+// subdiagonal is 0 ends the basis), and x = sum_i y_i basis_i. nr[s] is the
+// squared norm of the start vector. One host synchronisation.
+static int hessenberg_combine(Ctx *c, int p, int m, int nb, size_t n, const double2 *h1, const double2 *h2,
+                              const double2 *nr, double2 *coef, void *const *basis, void *x) {
+    const size_t hs = (size_t)(m + 1) * (m + 1) * nb;
+    cd *hb = host_buf(c, 2 * hs + (size_t)(m + 1) * nb + (size_t)m * nb);
+    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+    int rc = hip_check(c, hipMemcpyAsync(hb, h1, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(hb + hs, h2, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = read_dev(c, nr, (size_t)(m + 1) * nb, hb + 2 * hs);
+    if (rc) return rc;
+    const cd *H1 = hb, *H2 = hb + hs, *NR = hb + 2 * hs;
+    cd *yb = hb + 2 * hs + (size_t)(m + 1) * nb;   // [i][s]
+    for (size_t q = 0; q < (size_t)m * nb; q++) yb[q] = 0.0;
+    std::vector<cd> Hc((size_t)m * (m + 1)), y;
+    for (int sg = 0; sg < nb; sg++) {
+        const double beta = std::sqrt(NR[sg].real());
+        if (!std::isfinite(beta)) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
+        if (beta == 0.0) continue;   // x_s = 0
+        std::fill(Hc.begin(), Hc.end(), cd(0.0));
+        int k = m;
+        for (int j = 0; j < m; j++) {
+            const size_t cj = (size_t)j * (m + 1) * nb;
+            for (int i = 0; i <= j; i++)
+                Hc[(size_t)j * (m + 1) + i] = H1[cj + (size_t)i * nb + sg] + H2[cj + (size_t)i * nb + sg];
+            double hn = std::sqrt(std::max(NR[(size_t)(j + 1) * nb + sg].real(), 0.0));
+            Hc[(size_t)j * (m + 1) + j + 1] = hn;
+            if (hn == 0.0) { k = j + 1; break; }
+        }
+        hessenberg_lsq(k, Hc, m + 1, beta, y);
+        for (int i = 0; i < k; i++) {
+            if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
+            yb[(size_t)i * nb + sg] = y[i];
+        }
+    }
+    rc = write_dev(c, yb, (size_t)m * nb, coef);
+    if (!rc) rc = blas_lincomb(c, p, p, n, basis, m, coef, 1.0, 0.0, x, nb);
+    return rc;
+}
+
 // ---------------------------------------------------------------- coarse GMRES
 
 size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb) { return stencil_gmres_bytes(level1_op(c), p, m, nb); }
@@ -225,52 +270,79 @@ int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void 
         }
     }
     if (rc) return rc;
-    cd *hb = host_buf(c, 2 * hs + (size_t)(m + 1) * nb + (size_t)m * nb);
-    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
-    rc = hip_check(c, hipMemcpyAsync(hb, h1, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
-    if (!rc) rc = hip_check(c, hipMemcpyAsync(hb + hs, h2, hs * 16, hipMemcpyDeviceToHost, c->stream), "read");
-    if (!rc) rc = read_dev(c, nr, (size_t)(m + 1) * nb, hb + 2 * hs);
-    if (rc) return rc;
-    const cd *H1 = hb, *H2 = hb + hs, *NR = hb + 2 * hs;
-    cd *yb = hb + 2 * hs + (size_t)(m + 1) * nb;   // [i][s]
-    for (size_t q = 0; q < (size_t)m * nb; q++) yb[q] = 0.0;
-    std::vector<cd> Hc((size_t)m * (m + 1)), y;
-    for (int sg = 0; sg < nb; sg++) {
-        const double beta = std::sqrt(NR[sg].real());
-        if (!std::isfinite(beta)) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
-        if (beta == 0.0) continue;   // x_s = 0
-        std::fill(Hc.begin(), Hc.end(), cd(0.0));
-        int k = m;
-        for (int j = 0; j < m; j++) {
-            const size_t cj = (size_t)j * (m + 1) * nb;
-            for (int i = 0; i <= j; i++)
-                Hc[(size_t)j * (m + 1) + i] = H1[cj + (size_t)i * nb + sg] + H2[cj + (size_t)i * nb + sg];
-            double hn = std::sqrt(std::max(NR[(size_t)(j + 1) * nb + sg].real(), 0.0));
-            Hc[(size_t)j * (m + 1) + j + 1] = hn;
-            if (hn == 0.0) { k = j + 1; break; }
-        }
-        hessenberg_lsq(k, Hc, m + 1, beta, y);
-        for (int i = 0; i < k; i++) {
-            if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
-            yb[(size_t)i * nb + sg] = y[i];
-        }
-    }
-    rc = write_dev(c, yb, (size_t)m * nb, coef);
-    if (!rc) rc = blas_lincomb(c, p, p, n, V.data(), m, coef, 1.0, 0.0, x, nb);
+    rc = hessenberg_combine(c, p, m, nb, n, h1, h2, nr, coef, V.data(), x);
     A.off = mark;
     return rc;
 }
 
-// ---------------------------------------------------------------- two-level preconditioner
+// ---------------------------------------------------------------- multilevel preconditioner
 
-size_t precond_bytes(const Ctx *c, int p, int cit, int nb) {
-    size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
-    return n * 8 + 2 * nc * csize(p) + coarse_gmres_bytes(c, p, cit, nb) + 4096;
+MgOpts mg_opts(const mgdd_solve_params *sp) {
+    MgOpts o;
+    o.nu = sp->nu;
+    o.mr = sp->mr_iters;
+    o.cit = sp->coarse_iters;
+    o.levels = sp->levels == 3 ? 3 : 2;
+    o.k2 = sp->k2;
+    o.nu2 = sp->nu2;
+    o.mr2 = sp->mr2;
+    return o;
 }
 
-// z = SAP^nu(D, r, z0 = P GMRES_cit(D_c, P^H r)) for nb right-hand sides at
-// once; r in FP64, z in precision p.
-int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, int nu, int mr, int cit, Arena &A) {
+static size_t level2_fgmres_bytes(const Ctx *c, int p, const MgOpts &o, int nb) {
+    const size_t nc = (size_t)c->c.Vc * 2 * c->c.N * nb, ncc = (size_t)c->c2.Vcc * 2 * c->c2.N2 * nb;
+    const size_t cs = csize(p), k = o.k2;
+    return (2 * k + 2) * (nc * cs + 256) + 2 * (ncc * cs + 256) + 2 * (k + 1) * (k + 1) * nb * 16 +
+           2 * (k + 2) * nb * 16 + 1024 + stencil_gmres_bytes(level2_op(c), p, o.cit, nb) + 8192;
+}
+
+// x_s = k2 steps of flexible GMRES on D_c x = b_s from x = 0 (no restart),
+// right-preconditioned by M2(v) = SAP2^nu2(D_c, v, z0 = P2 GMRES_cit(D_cc,
+// P2^H v)), for nb right-hand sides at once (one basis and Hessenberg matrix
+// each, shared launches).
+static int level2_fgmres(Ctx *c, int p, const MgOpts &o, int nb, const void *b, void *x, Arena &A) {
+    const StencilOp op1 = level1_op(c), op2 = level2_op(c);
+    const size_t n = (size_t)op1.V * 2 * op1.N, ncc = (size_t)op2.V * 2 * op2.N, cs = csize(p);
+    const int m = o.k2;
+    const size_t mark = A.off;
+    std::vector<void *> V(m + 1), Z(m);
+    for (int i = 0; i <= m; i++) V[i] = A.take(n * nb * cs);
+    for (int i = 0; i < m; i++) Z[i] = A.take(n * nb * cs);
+    void *w = A.take(n * nb * cs);
+    void *cb = A.take(ncc * nb * cs), *cx = A.take(ncc * nb * cs);
+    const size_t hs = (size_t)(m + 1) * (m + 1) * nb;
+    double2 *h1 = (double2 *)A.take(hs * 16), *h2 = (double2 *)A.take(hs * 16);
+    double2 *nr = (double2 *)A.take((size_t)(m + 2) * nb * 16);
+    double2 *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
+    if (!coef) return fail(c, MGDD_ENOMEM, "level-2 FGMRES workspace");
+    const void *bp = b;
+    int rc = blas_multidot(c, p, p, n, &bp, 1, b, nr, nb);
+    if (!rc) rc = blas_normalize(c, p, p, n, b, nr, V[0], nb);
+    for (int j = 0; j < m && !rc; j++) {
+        rc = launch_restrict2(c, p, nb, V[j], cb);
+        if (!rc) rc = stencil_gmres(c, op2, p, o.cit, nb, cb, cx, A);
+        if (!rc) rc = launch_prolong2(c, p, nb, cx, Z[j]);
+        if (!rc && o.nu2 > 0) rc = launch_sap2(c, p, nb, o.nu2, o.mr2, V[j], Z[j]);
+        if (!rc) rc = launch_stencil_apply(c, op1, p, nb, Z[j], w);
+        if (!rc) rc = cgs2(c, p, n, V.data(), j + 1, w, h1 + (size_t)j * (m + 1) * nb, h2 + (size_t)j * (m + 1) * nb,
+                           nr + (size_t)(j + 1) * nb, nb);
+        if (!rc) rc = blas_normalize(c, p, p, n, w, nr + (size_t)(j + 1) * nb, V[j + 1], nb);
+    }
+    if (!rc) rc = hessenberg_combine(c, p, m, nb, n, h1, h2, nr, coef, Z.data(), x);
+    A.off = mark;
+    return rc;
+}
+
+size_t precond_bytes(const Ctx *c, int p, const MgOpts &o, int nb) {
+    size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
+    const size_t inner = o.levels == 3 ? level2_fgmres_bytes(c, p, o, nb) : coarse_gmres_bytes(c, p, o.cit, nb);
+    return n * 8 + 2 * nc * csize(p) + inner + 4096;
+}
+
+// z = SAP^nu(D, r, z0 = P x_c) for nb right-hand sides at once, x_c the
+// coarse solve of P^H r: GMRES_cit on D_c (two levels) or the level-2
+// flexible GMRES (three levels); r in FP64, z in precision p.
+int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o, Arena &A) {
     const size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
     const size_t mark = A.off;
     const void *rp = r64;
@@ -284,9 +356,9 @@ int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, int nu, int mr, 
     void *cb = A.take(nc * csize(p)), *cx = A.take(nc * csize(p));
     if (!cx) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
     if (!rc) rc = launch_restrict(c, p, nb, rp, cb);
-    if (!rc) rc = coarse_gmres(c, p, cit, nb, cb, cx, A);
+    if (!rc) rc = o.levels == 3 ? level2_fgmres(c, p, o, nb, cb, cx, A) : coarse_gmres(c, p, o.cit, nb, cb, cx, A);
     if (!rc) rc = launch_prolong(c, p, nb, cx, z);
-    if (!rc && nu > 0) rc = launch_sap(c, p, nb, nu, mr, 0.0, 0.0, rp, z);
+    if (!rc && o.nu > 0) rc = launch_sap(c, p, nb, o.nu, o.mr, 0.0, 0.0, rp, z);
     A.off = mark;
     return rc;
 }
@@ -391,7 +463,7 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
         }
         int kmax = 0;
         for (int j = 0; j < m; j++) {
-            rc = mg_precond(c, p, nb, V[j], Z[j], sp->nu, sp->mr_iters, sp->coarse_iters, A);
+            rc = mg_precond(c, p, nb, V[j], Z[j], mg_opts(sp), A);
             if (!rc && p == MGDD_F32) {
                 rc = launch_convert(c, MGDD_F32, MGDD_F64, nn, Z[j], z64);
                 if (!rc) rc = launch_dirac(c, MGDD_F64, nb, z64, w);
@@ -610,7 +682,7 @@ size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb) {
     if (sp->solver == MGDD_SOLVER_FGMRES_MG) {
         int p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
         return (size_t)(m + 4) * (n * nb * 16 + 256) + (size_t)m * (n * nb * csize(p) + 256) +
-               (3 * (size_t)m + 8) * nb * 16 + precond_bytes(c, p, sp->coarse_iters, nb) + 65536;
+               (3 * (size_t)m + 8) * nb * 16 + precond_bytes(c, p, mg_opts(sp), nb) + 65536;
     }
     return (size_t)(2 * m + 10) * (n * 16 + 256) + 65536;
 }
@@ -804,6 +876,51 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     }
     rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     if (A.need) return fail(c, MGDD_ENOMEM, "setup workspace estimate too small");
+    return rc;
+}
+
+
+// ---------------------------------------------------------------- third level setup
+
+// Test vectors of the second level and the third level built from them:
+// the fine test vectors taken to the coarse grid with P^H (the first
+// min(N, N2)), completed by the caller's random coarse vectors, orthonormalised
+// in index order; nu2 rounds of one level-2 Schwarz sweep on D_c v = 0 from
+// each vector, each followed by the orthonormalisation; then P2 and D_cc.
+// FP64 throughout.
+int level2_bootstrap(Ctx *c, const mgdd_level2_params *lp, const void *random2) {
+    const Level1 &L1 = c->c;
+    c->c2.ready = false;
+    int rc = level2_sap_setup(c, lp->block2);
+    if (!rc) rc = level2_setup(c, lp->agg2, lp->ntv2);
+    if (rc) return rc;
+    const int N2 = lp->ntv2, nres = std::min(N2, L1.N);
+    if (N2 > nres && !random2) return fail(c, MGDD_EINVAL, "random coarse vectors needed (ntv2 > N)");
+    const size_t nc = (size_t)L1.Vc * 2 * L1.N;
+    Arena A;
+    rc = arena_open(c, 2 * ((size_t)N2 * nc * 16 + 256) + 2 * (size_t)N2 * N2 * 16 + (2 * (size_t)N2 + 1) * 16 + 4096, A);
+    if (rc) return rc;
+    char *X0 = (char *)A.take((size_t)N2 * nc * 16);
+    void *zero = A.take(nc * 16 * N2);
+    double2 *gbuf = (double2 *)A.take((size_t)N2 * N2 * 16), *mbuf = (double2 *)A.take((size_t)N2 * N2 * 16);
+    double2 *scal = (double2 *)A.take((2 * (size_t)N2 + 1) * 16);
+    if (!scal) return fail(c, MGDD_ENOMEM, "level-2 setup workspace");
+    std::vector<void *> X(N2);
+    for (int k = 0; k < N2; k++) X[k] = X0 + (size_t)k * nc * 16;
+    rc = launch_restrict(c, MGDD_F64, nres, L1.tv64, X0);
+    if (!rc && N2 > nres)
+        rc = hip_check(c, hipMemcpyAsync(X[nres], random2, (size_t)(N2 - nres) * nc * 16, hipMemcpyDeviceToDevice,
+                                         c->stream), "copy");
+    if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, nc * 16 * N2, c->stream), "memset");
+    if (!rc) rc = orthonormalise(c, nc, X.data(), N2, gbuf, mbuf, scal);
+    for (int r = 0; r < lp->nu2 && !rc; r++) {
+        rc = launch_sap2(c, MGDD_F64, N2, 1, lp->mr_iters, zero, X0);
+        if (!rc) rc = orthonormalise(c, nc, X.data(), N2, gbuf, mbuf, scal);
+    }
+    if (!rc) rc = launch_build_P2(c, X0);
+    if (!rc) rc = launch_dcc_build(c);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc && A.need) rc = fail(c, MGDD_ENOMEM, "level-2 setup workspace estimate too small");
     return rc;
 }
 

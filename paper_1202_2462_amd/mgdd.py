@@ -72,7 +72,13 @@ class SetupParams(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
                 ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("coarse_iters", ctypes.c_int),
-                ("nu", ctypes.c_int), ("mr_iters", ctypes.c_int)]
+                ("nu", ctypes.c_int), ("mr_iters", ctypes.c_int), ("levels", ctypes.c_int), ("k2", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("mr2", ctypes.c_int)]
+
+
+class Level2Params(ctypes.Structure):
+    _fields_ = [("agg2", ctypes.c_int * 4), ("ntv2", ctypes.c_int), ("block2", ctypes.c_int * 4),
+                ("nu2", ctypes.c_int), ("mr_iters", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -100,6 +106,11 @@ _sig("mgdd_build_P2", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.c_
 _sig("mgdd_restrict2", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_prolong2", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_coarse2_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_precondition3", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_setup_level2", ctypes.c_int, _vp, ctypes.POINTER(Level2Params), _vp)
+_sig("mgdd_coarse_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+     _vp, _vp)
 _sig("mgdd_timing_enable", ctypes.c_int, _vp, ctypes.c_int)
 _sig("mgdd_timing_read", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong))
@@ -219,6 +230,15 @@ def mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, r, z):
     return _check(ctx, _lib.mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, _ptr(r), _ptr(z)))
 
 
+def mgdd_precondition3(ctx, prec, nrhs, nu, mr_iters, k2, nu2, mr2, coarse_iters, r, z):
+    return _check(ctx, _lib.mgdd_precondition3(ctx, prec, nrhs, nu, mr_iters, k2, nu2, mr2, coarse_iters, _ptr(r),
+                                               _ptr(z)))
+
+
+def mgdd_setup_level2(ctx, params: Level2Params, random2):
+    return _check(ctx, _lib.mgdd_setup_level2(ctx, ctypes.byref(params), None if random2 is None else _ptr(random2)))
+
+
 def mgdd_setup_bootstrap(ctx, params: SetupParams, random_vectors, arnoldi_start):
     return _check(ctx, _lib.mgdd_setup_bootstrap(ctx, ctypes.byref(params), _ptr(random_vectors), _ptr(arnoldi_start)))
 
@@ -246,6 +266,10 @@ def mgdd_prolong2(ctx, prec, nrhs, coarse2, coarse):
 
 def mgdd_coarse2_apply(ctx, prec, nrhs, x, y):
     return _check(ctx, _lib.mgdd_coarse2_apply(ctx, prec, nrhs, _ptr(x), _ptr(y)))
+
+
+def mgdd_coarse_sap(ctx, prec, nrhs, block2, nsweeps, mr_iters, b, z):
+    return _check(ctx, _lib.mgdd_coarse_sap(ctx, prec, nrhs, _i4(*block2), nsweeps, mr_iters, _ptr(b), _ptr(z)))
 
 
 def mgdd_timing_enable(ctx, on=True):
@@ -354,6 +378,11 @@ class Lattice:
         mgdd_prolong2(self.ctx, self.prec_of(cc), cc.shape[0], cc, c)
         return c
 
+    def coarse_sap(self, block2, b, z, nsweeps=1, mr_iters=4):
+        """nsweeps red-black Schwarz sweeps on D_c z = b (z updated in place)."""
+        mgdd_coarse_sap(self.ctx, self.prec_of(b), b.shape[0], block2, nsweeps, mr_iters, b, z)
+        return z
+
     def coarse2_apply(self, x, y=None):
         y = self.torch.empty_like(x) if y is None else y
         mgdd_coarse2_apply(self.ctx, self.prec_of(x), x.shape[0], x, y)
@@ -389,6 +418,20 @@ class Lattice:
         mgdd_precondition(self.ctx, prec, r.shape[0], nu, mr_iters, coarse_iters, r, z)
         return z
 
+    def precondition3(self, r, prec=F64, nu=1, mr_iters=4, k2=8, nu2=1, mr2=4, coarse_iters=12):
+        z = self.field(prec, r.shape[0])
+        mgdd_precondition3(self.ctx, prec, r.shape[0], nu, mr_iters, k2, nu2, mr2, coarse_iters, r, z)
+        return z
+
+    def setup_level2(self, agg2, ntv2, block2, random2=None, nu2=2, mr_iters=4):
+        """random2: (ntv2 - N, Vc, 2, N, 2) float64 device tensor (needed when ntv2 > N)."""
+        lp = Level2Params((ctypes.c_int * 4)(*agg2), ntv2, (ctypes.c_int * 4)(*block2), nu2, mr_iters)
+        mgdd_setup_level2(self.ctx, lp, random2)
+        self.agg2 = tuple(agg2)
+        self.N2 = ntv2
+        self.ccdims = tuple(d // a for d, a in zip(self.cdims, self.agg2))
+        self.Vcc = int(np.prod(self.ccdims))
+
     def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64):
         N = random_vectors.shape[0]
         sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, arnoldi_m, n_part2, prec)
@@ -404,8 +447,8 @@ class Lattice:
         return out
 
     def solve(self, b, z=None, solver=SOLVER_FGMRES_MG, precision=PLAIN_F64, restart=20, tol=1e-10, maxit=1000,
-              coarse_iters=12, nu=1, mr_iters=4, allow_noconv=False):
+              coarse_iters=12, nu=1, mr_iters=4, allow_noconv=False, levels=2, k2=8, nu2=1, mr2=4):
         z = self.torch.zeros_like(b) if z is None else z
-        sp = SolveParams(solver, precision, restart, tol, maxit, coarse_iters, nu, mr_iters)
+        sp = SolveParams(solver, precision, restart, tol, maxit, coarse_iters, nu, mr_iters, levels, k2, nu2, mr2)
         stats = mgdd_solve(self.ctx, sp, b.shape[0], b, z, allow_noconv=allow_noconv)
         return z, stats

@@ -34,3 +34,17 @@ def lattice(op, block):
     lat = Lattice(op.dims, block)
     lat.set_gauge(op.U, op.m0, op.csw)
     return lat
+
+
+def dev_to_np(t):
+    """Complex numpy array of a device tensor with a trailing (re, im) axis."""
+    a = t.detach().cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def np_to_dev(c, prec):
+    """Device tensor (trailing (re, im) axis) of a complex array, in FP64 or FP32."""
+    import torch
+    from paper_1202_2462_amd.mgdd import F64
+    return torch.tensor(np.stack([np.real(c), np.imag(c)], -1), dtype=torch.float64 if prec == F64 else torch.float32,
+                        device="cuda")

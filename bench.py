@@ -38,6 +38,13 @@ WORKLOAD = "c1"
 # (FP32): bytes = z in 96 + b 96 + links 288 + clover 288 + z out 96;
 # flops = (1 + k) operator applications of 1896 + k MR updates of 336
 SAP_BYTES_PER_SITE = 864
+# the three-level variant timed beside the two-level method: aggregates of
+# 2^4 coarse sites, 28 level-2 test vectors (the 20 restricted fine ones and
+# 8 random), two smoothing rounds of level-2 Schwarz sweeps on 2^4 blocks in
+# the setup; in the solve 8 flexible GMRES steps on D_c per coarse solve,
+# each preconditioned by one level-2 Schwarz sweep (4 MR steps) after 12
+# GMRES steps on D_cc
+LEVEL3 = dict(agg2=(2, 2, 2, 2), ntv2=28, block2=(2, 2, 2, 2), setup_nu2=2, k2=8, nu2=1, mr2=4, cit=12)
 
 
 def sap_flops_per_site(k):
@@ -113,12 +120,16 @@ class Bench:
         st = latgen.gaussian_vector(self.Vc * 2 * self.N, 1000 * k + latgen.TAG_ARNOLDI)
         self.start_host = st
         self.start = torch.tensor(np.stack([st.real, st.imag], -1), dtype=torch.float64, device="cuda")
+        n2 = max(LEVEL3["ntv2"] - self.N, 1)
+        r2 = latgen.gaussian_vector(n2 * self.Vc * 2 * self.N, 1000 * k + latgen.TAG_TV2)
+        self.rnd2 = torch.tensor(np.stack([r2.real, r2.imag], -1), dtype=torch.float64,
+                                 device="cuda").reshape(n2, self.Vc, 2, self.N, 2)
         self.b_host = latgen.gaussian_fields(self.dims, 1, 1000 * k + latgen.TAG_RHS)
         self.b = self.lat.pack(self.b_host, F64)
         torch.cuda.synchronize()
 
     # one pass of the hot path
-    def step(self, setup_prec=None, solve_prec=None, split=None):
+    def step(self, setup_prec=None, solve_prec=None, split=None, levels=2):
         mg = self.mgdd
         w = self.w
         setup_prec = mg.F32 if setup_prec is None else setup_prec
@@ -126,9 +137,15 @@ class Bench:
         t0 = time.perf_counter()
         self.lat.set_gauge(self.U_dev, self.m0, self.csw)
         self.lat.setup(self.agg, self.rnd, self.start, nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], prec=setup_prec)
+        l3 = {}
+        if levels == 3:
+            q = LEVEL3
+            self.lat.setup_level2(q["agg2"], q["ntv2"], q["block2"], random2=self.rnd2, nu2=q["setup_nu2"],
+                                  mr_iters=q["mr2"])
+            l3 = dict(levels=3, k2=q["k2"], nu2=q["nu2"], mr2=q["mr2"])
         t1 = time.perf_counter()
         z, stats = self.lat.solve(self.b, precision=solve_prec, restart=w["restart"], tol=w["tol"], maxit=2000,
-                                  coarse_iters=12, nu=1, mr_iters=w["mr"])
+                                  coarse_iters=LEVEL3["cit"] if levels == 3 else 12, nu=1, mr_iters=w["mr"], **l3)
         t2 = time.perf_counter()
         if split is not None:
             split.update(setup_s=t1 - t0, solve_s=t2 - t1, iters=stats[0].iters, restarts=stats[0].restarts,
@@ -297,6 +314,11 @@ def main():
         s64 = {}
         bench.step(setup_prec=mg.F64, solve_prec=mg.PLAIN_F64, split=s64)
         result["time_to_solution"]["mg_fp64"] = s64
+        log("three-level, mixed precision")
+        s3 = {}
+        bench.step(levels=3, split=s3)
+        s3["params"] = LEVEL3
+        result["time_to_solution"]["mg3_mixed"] = s3
         log("plain FP64 GCR")
         result["time_to_solution"]["gcr_fp64"], _ = bench.gcr(False)
         log("even-odd FP64 GCR")

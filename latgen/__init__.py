@@ -26,7 +26,7 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
 # seed tags: seed = 1000*config + tag
-TAG_GAUGE, TAG_EPS, TAG_RHS, TAG_TV, TAG_POINT, TAG_ARNOLDI = 1, 2, 3, 4, 5, 6
+TAG_GAUGE, TAG_EPS, TAG_RHS, TAG_TV, TAG_POINT, TAG_ARNOLDI, TAG_TV2 = 1, 2, 3, 4, 5, 6, 7
 
 
 def _mix64(z: np.ndarray) -> np.ndarray:

@@ -343,6 +343,107 @@ int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, con
     return rc;
 }
 
+// Least-squares step of a GMRES cycle of m <= LSQ_MAX_STEPS steps on the
+// device, one workgroup (one wave) per right-hand side s. The (m+1) x m
+// Hessenberg matrix (column j: h1 + h2 in rows 0..j, sqrt(nr[j+1]) in row
+// j+1) is cut at the first zero subdiagonal entry (k columns) and reduced
+// to upper triangular form by Givens rotations: lane 0 forms rotation j from
+// column j and applies it to g = beta e_1, the lanes owning the later
+// columns apply it to theirs. y then solves the triangular system (lane 0,
+// back substitution), coef[i][s] = y_i for i < k and 0 for the rest; all 0
+// when beta = sqrt(nr[0]) is 0. A non-finite beta or y sets *status (if
+// given) to 1.
+__device__ inline double2 zmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__global__ __launch_bounds__(64) void hessenberg_lsq_kernel(int m, int nb, const double2 *__restrict__ h1,
+                                                            const double2 *__restrict__ h2,
+                                                            const double2 *__restrict__ nr, double2 *__restrict__ coef,
+                                                            int *__restrict__ status) {
+    __shared__ double2 R[LSQ_MAX_STEPS][LSQ_MAX_STEPS + 2];   // [column][row]
+    __shared__ double2 g[LSQ_MAX_STEPS + 1], y[LSQ_MAX_STEPS];
+    __shared__ double rot_c;
+    __shared__ double2 rot_s;
+    const int s = blockIdx.x, l = threadIdx.x;
+    const double beta = sqrt(nr[s].x);
+    if (!(beta > 0.0) || !isfinite(beta)) {   // zero start vector: x = 0
+        if (l < m) coef[(size_t)l * nb + s] = make_double2(0, 0);
+        if (l == 0 && status && !isfinite(beta)) *status = 1;
+        return;
+    }
+    int k = m;
+    for (int j = 0; j < m; j++) {
+        const double v = nr[(size_t)(j + 1) * nb + s].x;
+        if (l == 0 && status && isnan(v)) *status = 1;
+        if (!(v > 0.0)) { k = j + 1; break; }
+    }
+    if (l < k) {
+        const size_t cj = (size_t)l * (m + 1) * nb;
+        for (int i = 0; i <= l; i++) {
+            const double2 a = h1[cj + (size_t)i * nb + s], b = h2[cj + (size_t)i * nb + s];
+            R[l][i] = make_double2(a.x + b.x, a.y + b.y);
+        }
+        R[l][l + 1] = make_double2(sqrt(fmax(nr[(size_t)(l + 1) * nb + s].x, 0.0)), 0.0);
+    }
+    if (l <= k) g[l] = make_double2(l == 0 ? beta : 0.0, 0.0);
+    __syncthreads();
+    for (int j = 0; j < k; j++) {
+        if (l == 0) {
+            const double2 a = R[j][j], b = R[j][j + 1];
+            const double aa = hypot(a.x, a.y), bb = hypot(b.x, b.y);
+            double cr;
+            double2 sr, rho;
+            if (bb == 0.0) {
+                cr = 1.0; sr = make_double2(0, 0); rho = a;
+            } else if (aa == 0.0) {
+                cr = 0.0; sr = make_double2(1, 0); rho = b;
+            } else {
+                const double r = hypot(aa, bb);
+                const double2 ph = make_double2(a.x / aa, a.y / aa);
+                cr = aa / r;
+                const double2 t = zmul(ph, zconj(b));
+                sr = make_double2(t.x / r, t.y / r);
+                rho = make_double2(ph.x * r, ph.y * r);
+            }
+            R[j][j] = rho;
+            R[j][j + 1] = make_double2(0, 0);
+            const double2 gj = g[j];
+            g[j] = make_double2(cr * gj.x, cr * gj.y);
+            const double2 t = zmul(zconj(sr), gj);
+            g[j + 1] = make_double2(-t.x, -t.y);
+            rot_c = cr;
+            rot_s = sr;
+        }
+        __syncthreads();
+        if (l > j && l < k) {
+            const double cr = rot_c;
+            const double2 sr = rot_s, a = R[l][j], b = R[l][j + 1];
+            const double2 u = zmul(sr, b), v = zmul(zconj(sr), a);
+            R[l][j] = make_double2(cr * a.x + u.x, cr * a.y + u.y);
+            R[l][j + 1] = make_double2(cr * b.x - v.x, cr * b.y - v.y);
+        }
+        __syncthreads();
+    }
+    if (l == 0) {
+        bool ok = true;
+        for (int i = k - 1; i >= 0; i--) {
+            double2 t = g[i];
+            for (int q = i + 1; q < k; q++) {
+                const double2 u = zmul(R[q][i], y[q]);
+                t = make_double2(t.x - u.x, t.y - u.y);
+            }
+            const double2 d = R[i][i];
+            const double dn = d.x * d.x + d.y * d.y;
+            const double2 yi = make_double2((t.x * d.x + t.y * d.y) / dn, (t.y * d.x - t.x * d.y) / dn);
+            y[i] = yi;
+            ok = ok && isfinite(yi.x) && isfinite(yi.y);
+        }
+        if (!ok && status) *status = 1;
+    }
+    __syncthreads();
+    if (l < m) coef[(size_t)l * nb + s] = l < k ? y[l] : make_double2(0, 0);
+}
+
 size_t fused_cgs2_red_doubles(size_t n, int k, int nb) {
     return 2 * (2 * (size_t)k + 1) * nb * (size_t)orth_grid(n) + 16;
 }
@@ -378,6 +479,13 @@ int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, 
     }
 #undef CGS
     return hip_check(c, hipGetLastError(), "fused Gram-Schmidt");
+}
+
+int launch_hessenberg_lsq(Ctx *c, int m, int nb, const double2 *h1, const double2 *h2, const double2 *nr, double2 *coef,
+                          int *status) {
+    if (m < 1 || m > LSQ_MAX_STEPS) return fail(c, MGDD_EINVAL, "device least squares: bad step count");
+    hessenberg_lsq_kernel<<<nb, 64, 0, c->stream>>>(m, nb, h1, h2, nr, coef, status);
+    return hip_check(c, hipGetLastError(), "least squares");
 }
 
 }  // namespace mgdd

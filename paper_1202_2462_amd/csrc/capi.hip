@@ -507,9 +507,15 @@ int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     Arena A;
-    rc = arena_open(c, coarse_gmres_bytes(c, prec, iters, nrhs), A);
-    if (!rc) rc = coarse_gmres(c, prec, iters, nrhs, b, x, A);
+    rc = arena_open(c, coarse_gmres_bytes(c, prec, iters, nrhs) + 256, A);
+    int *status = rc ? nullptr : (int *)A.take(sizeof(int));
+    if (!rc && !status) rc = fail(c, MGDD_ENOMEM, "coarse solve workspace");
+    if (!rc) rc = hip_check(c, hipMemsetAsync(status, 0, sizeof(int), c->stream), "memset");
+    if (!rc) rc = coarse_gmres(c, prec, iters, nrhs, b, x, A, status);
+    int hstatus = 0;
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, c->stream), "read");
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc && hstatus) rc = fail(c, MGDD_ENAN, "NaN in the coarse solve");
     return rc;
     GUARD_END
 }

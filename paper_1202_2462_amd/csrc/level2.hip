@@ -188,6 +188,21 @@ __global__ __launch_bounds__(1024) void dcc_build_kernel(int Vc, int N1, int N2,
 // r = b - D_c z on the block (all nine terms), then MR(mr) on the block
 // operator (terms whose neighbour lies in the block; lnbr < 0 otherwise)
 // from e = 0 with rho in LDS, and z += e.
+// sum_j B[j n1] x[j] over j < n1 (one row of a column-major 2N x 2N block
+// times x) in two interleaved FMA chains, so that loads overlap
+template <typename T>
+__device__ inline C<T> row_dot(const C<T> *__restrict__ B, const C<T> *x, int n1) {
+    C<T> a0 = mk<T>(0, 0), a1 = mk<T>(0, 0);
+    int j = 0;
+#pragma unroll 4
+    for (; j + 1 < n1; j += 2) {
+        cfma(a0, B[(size_t)j * n1], x[j]);
+        cfma(a1, B[(size_t)(j + 1) * n1], x[j + 1]);
+    }
+    if (j < n1) cfma(a0, B[(size_t)j * n1], x[j]);
+    return cadd(a0, a1);
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void sap2_kernel(int Vc, int N1, int Vb2, int blk0, const int *__restrict__ bsites,
                                                     const int *__restrict__ lnbr, const int *__restrict__ gnbr,
@@ -212,8 +227,7 @@ __global__ __launch_bounds__(1024) void sap2_kernel(int Vc, int N1, int Vb2, int
         for (int d = 0; d < 9; d++) {
             const int ap = gnbr[((size_t)blk * Vb2 + l) * 9 + d];
             const C<T> *B = Dc + ((size_t)a * 9 + d) * n1 * n1 + i;
-            const C<T> *zv = zr + (size_t)ap * n1;
-            for (int j = 0; j < n1; j++) cfma(acc, B[(size_t)j * n1], zv[j]);
+            acc = cadd(acc, row_dot<T>(B, zr + (size_t)ap * n1, n1));
         }
         rv = csub(br[(size_t)a * n1 + i], acc);
         rho[l * n1 + i] = rv;
@@ -228,8 +242,7 @@ __global__ __launch_bounds__(1024) void sap2_kernel(int Vc, int N1, int Vb2, int
                 const int ln = lnbr[((size_t)blk * Vb2 + l) * 9 + d];
                 if (ln < 0) continue;
                 const C<T> *B = Dc + ((size_t)a * 9 + d) * n1 * n1 + i;
-                const C<T> *rr = rho + ln * n1;
-                for (int j = 0; j < n1; j++) cfma(q, B[(size_t)j * n1], rr[j]);
+                q = cadd(q, row_dot<T>(B, rho + ln * n1, n1));
             }
         }
         double p0 = (double)q.x * q.x + (double)q.y * q.y;

@@ -34,9 +34,10 @@ MgOpts mg_opts(const mgdd_solve_params *sp);
 size_t coarse_gmres_bytes(const Ctx *c, int p, int m, int nb);
 size_t precond_bytes(const Ctx *c, int p, const MgOpts &o, int nb);
 size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb);
-int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A);
+int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A, int *status = nullptr);
 size_t stencil_gmres_bytes(const StencilOp &op, int p, int m, int nb);
-int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *x, Arena &A);
+int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *x, Arena &A,
+                  int *status = nullptr);
 int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o, Arena &A);
 int solve_batch(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st);
 int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64);

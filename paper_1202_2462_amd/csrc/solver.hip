@@ -232,14 +232,17 @@ size_t stencil_gmres_bytes(const StencilOp &op, int p, int m, int nb) {
            coarse_arnoldi_scratch(op, m, nb) + 8192;
 }
 
-int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A) {
-    return stencil_gmres(c, level1_op(c), p, m, nb, b, x, A);
+int coarse_gmres(Ctx *c, int p, int m, int nb, const void *b, void *x, Arena &A, int *status) {
+    return stencil_gmres(c, level1_op(c), p, m, nb, b, x, A, status);
 }
 
 // x_s = GMRES_m(op, b_s) from x = 0, no restart, for nb right-hand sides at
-// once (one Krylov basis and one Hessenberg matrix each, shared launches);
-// one host synchronisation.
-int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *x, Arena &A) {
+// once (one Krylov basis and one Hessenberg matrix each, shared launches).
+// Up to LSQ_MAX_STEPS steps the least-squares step runs on the device and
+// the whole cycle is asynchronous (a non-finite result sets *status when
+// given); longer cycles solve it on the host (one synchronisation, MGDD_ENAN
+// on a non-finite result).
+int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *x, Arena &A, int *status) {
     const size_t n = (size_t)op.V * 2 * op.N, cs = csize(p);
     const size_t mark = A.off;
     std::vector<void *> V(m + 1);
@@ -270,7 +273,12 @@ int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void 
         }
     }
     if (rc) return rc;
-    rc = hessenberg_combine(c, p, m, nb, n, h1, h2, nr, coef, V.data(), x);
+    if (m <= LSQ_MAX_STEPS) {   // no host round trip
+        rc = launch_hessenberg_lsq(c, m, nb, h1, h2, nr, coef, status);
+        if (!rc) rc = blas_lincomb(c, p, p, n, V.data(), m, coef, 1.0, 0.0, x, nb);
+    } else {
+        rc = hessenberg_combine(c, p, m, nb, n, h1, h2, nr, coef, V.data(), x);
+    }
     A.off = mark;
     return rc;
 }
@@ -328,7 +336,12 @@ static int level2_fgmres(Ctx *c, int p, const MgOpts &o, int nb, const void *b, 
                            nr + (size_t)(j + 1) * nb, nb);
         if (!rc) rc = blas_normalize(c, p, p, n, w, nr + (size_t)(j + 1) * nb, V[j + 1], nb);
     }
-    if (!rc) rc = hessenberg_combine(c, p, m, nb, n, h1, h2, nr, coef, Z.data(), x);
+    if (!rc && m <= LSQ_MAX_STEPS) {
+        rc = launch_hessenberg_lsq(c, m, nb, h1, h2, nr, coef, nullptr);
+        if (!rc) rc = blas_lincomb(c, p, p, n, Z.data(), m, coef, 1.0, 0.0, x, nb);
+    } else if (!rc) {
+        rc = hessenberg_combine(c, p, m, nb, n, h1, h2, nr, coef, Z.data(), x);
+    }
     A.off = mark;
     return rc;
 }

@@ -58,5 +58,12 @@ int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, 
                double2 *nrm);
 int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *const *V,
                           void *work0, void *work1, void *scratch, double2 *H1, double2 *H2, double2 *NR);
+// Least squares of a GMRES cycle on the device (arnoldi.hip): coef[i][s] = y_i
+// of min ||beta e_1 - H y|| from the Gram-Schmidt outputs h1, h2, nr of m
+// steps (the layout of launch_coarse_arnoldi); *status (may be null) set to
+// 1 on a non-finite result. m <= LSQ_MAX_STEPS.
+constexpr int LSQ_MAX_STEPS = 32;
+int launch_hessenberg_lsq(Ctx *c, int m, int nb, const double2 *h1, const double2 *h2, const double2 *nr, double2 *coef,
+                          int *status);
 
 }  // namespace mgdd

@@ -105,13 +105,29 @@ def test_coarse_gmres_parity(dims, block, agg, N):
     op, lat, tl, tv = setup(dims, block, agg, N)
     Vc = lat.Vc
     b = latgen.gaussian_vector(2 * Vc * 2 * N, 9).reshape(2, Vc, 2, N)
-    want = np.stack([solvers.gmres_fixed(tl.coarse_apply, b[i], 12) for i in range(2)])
-    for prec, tol in ((F64, 1e-10), (F32, 1e-4)):
-        got = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, b, prec), 12))
-        assert rel(got, want) < tol, (prec, rel(got, want))
-    # zero right-hand side gives zero
-    z = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, 0 * b, F64), 12))
-    assert np.all(z == 0)
+    # 12 steps: fused Arnoldi kernels, least squares on the device; 20: general
+    # Gram-Schmidt path, device least squares; 40: least squares on the host
+    for m, t64, t32 in ((12, 1e-10, 1e-4), (20, 1e-9, 1e-3), (40, 1e-9, 1e-3)):
+        want = np.stack([solvers.gmres_fixed(tl.coarse_apply, b[i], m) for i in range(2)])
+        for prec, tol in ((F64, t64), (F32, t32)):
+            got = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, b, prec), m))
+            assert rel(got, want) < tol, (m, prec, rel(got, want))
+        # zero right-hand side gives zero
+        z = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, 0 * b, F64), m))
+        assert np.all(z == 0)
+
+
+def test_coarse_gmres_nan_reported():
+    from paper_1202_2462_amd.mgdd import ENAN, F64, MgddError
+    dims, block, agg, N = CASES[0]
+    say("coarse gmres NaN")
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    b = latgen.gaussian_vector(lat.Vc * 2 * N, 9).reshape(1, lat.Vc, 2, N)
+    b[0, 3, 1, 2] = np.nan
+    for m in (12, 40):
+        with pytest.raises(MgddError) as e:
+            lat.coarse_solve(to_dev_coarse(lat, b, F64), m)
+        assert e.value.code == ENAN, m
 
 
 @pytest.mark.parametrize("dims,block,agg,N", CASES[:2])

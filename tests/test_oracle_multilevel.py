@@ -134,3 +134,69 @@ def test_three_level_fgmres_reaches_dense_solution():
     z, st = fgmres(op.apply, three.precond, b, 20, 1e-10, 200)
     assert st.converged
     assert np.linalg.norm(b - op.apply(z)) <= 1e-10 * np.linalg.norm(b)
+
+
+def qr_positive(cols):
+    """Q of the thin QR of the matrix with the given columns, diagonal of R made positive."""
+    A = np.stack([np.asarray(c).ravel() for c in cols], axis=1)
+    Q, R = np.linalg.qr(A)
+    ph = np.diag(R) / np.abs(np.diag(R))
+    return Q * ph[None, :]
+
+
+def test_level2_test_vectors_are_qr_of_smoothed_vectors(level2):
+    """nu2 = 0: the Q factor (positive diagonal of R) of the restricted vectors
+    completed by the random ones; each smoothing round: one level-2 SAP sweep
+    with b = 0 from every vector, then the Q factor again (numpy QR instead of
+    Gram-Schmidt)"""
+    op, tl = level2
+    cd, block2 = tl.cdims, (2, 2, 2, 2)
+    shape = tl.Dc.shape[:1] + (2, tl.N)
+    restricted = [coarse_random(shape, 70 + i) for i in range(tl.N)]
+    rnd = [coarse_random(shape, 80 + i) for i in range(3)]
+    N2 = tl.N + 2
+    v0 = ml.level2_test_vectors(cd, tl.Dc, block2, restricted, N2, 0, 4, rnd)
+    Q0 = qr_positive(restricted + rnd[:2])
+    assert rel(np.stack([v.ravel() for v in v0], 1), Q0) < 1e-12
+    v2 = ml.level2_test_vectors(cd, tl.Dc, block2, restricted, N2, 2, 4, rnd)
+    Q = Q0
+    for _ in range(2):
+        sm = [ml.coarse_sap(cd, tl.Dc, block2, np.zeros(shape), Q[:, k].reshape(shape), 1, 4) for k in range(N2)]
+        Q = qr_positive(sm)
+    got = np.stack([v.ravel() for v in v2], 1)
+    assert rel(got, Q) < 1e-10
+    assert np.abs(got.conj().T @ got - np.eye(N2)).max() < 1e-12
+    # fewer level-2 vectors than fine ones: only the first restricted vectors are used
+    v3 = ml.level2_test_vectors(cd, tl.Dc, block2, restricted, 2, 0, 4, rnd)
+    assert rel(np.stack([v.ravel() for v in v3], 1), qr_positive(restricted[:2])) < 1e-12
+
+
+def test_level2_correction_is_galerkin(level2):
+    """with the coarsest equation solved exactly (GMRES at the full dimension
+    of D_cc) and no level-2 smoothing, M2 is the coarse-grid correction of
+    D_c: P2^H (r - D_c M2 r) = 0"""
+    op, tl = level2
+    cd, agg2, N2 = tl.cdims, (2, 2, 2, 2), 3
+    shape = tl.Dc.shape[:1] + (2, tl.N)
+    tv2 = [coarse_random(shape, 90 + i) for i in range(N2)]
+    ncc = int(np.prod([L // g for L, g in zip(cd, agg2)])) * 2 * N2
+    three = ml.ThreeLevel(tl, agg2, (2, 2, 2, 2), tv2, nu2=0, cit=ncc)
+    r = coarse_random(shape, 95)
+    e = three.M2(r)
+    res = ml.restrict2(cd, agg2, three.P2, r - ml.apply_Dc(cd, tl.Dc, e))
+    assert np.abs(res).max() < 1e-9 * np.abs(ml.restrict2(cd, agg2, three.P2, r)).max()
+    assert rel(e, np.zeros_like(e)) > 0.1
+
+
+def test_level2_coarse_solve_exact_with_exact_smoother(level2):
+    """one block covering the coarse lattice with converged MR makes M2 = D_c^{-1},
+    so one flexible GMRES step solves the coarse equation"""
+    op, tl = level2
+    cd = tl.cdims
+    shape = tl.Dc.shape[:1] + (2, tl.N)
+    tv2 = [coarse_random(shape, 100 + i) for i in range(3)]
+    three = ml.ThreeLevel(tl, (2, 2, 2, 2), cd, tv2, k2=1, nu2=1, mr2=60, cit=4)
+    b = coarse_random(shape, 105)
+    Dd = dense(lambda c: ml.apply_Dc(cd, tl.Dc, c), shape)
+    want = np.linalg.solve(Dd, b.ravel()).reshape(shape)
+    assert rel(three.coarse_solve(b), want) < 1e-7

@@ -100,6 +100,24 @@ def sap(dims, U, A, block, b, z0, nsweeps: int, mr_iters: int, shift: complex = 
     return z
 
 
+BLOCK_MR, BLOCK_GMRES = 0, 1
+
+
+def schwarz(dims, U, A, block, b, z0, nsweeps: int, k: int, block_solver: int = BLOCK_MR, additive: bool = False,
+            shift: complex = 0.0) -> np.ndarray:
+    """nsweeps Schwarz sweeps on (D - shift) z = b from z0: red-black
+    multiplicative (Algorithm 2.1) or additive, block systems by k MR or GMRES
+    steps."""
+    U, A, b = _c(U), _c(A), _c(b)
+    z = _c(z0).copy()
+    rc = lib().or_schwarz(_i4(dims), _p(U), _p(A), _i4(block), int(nsweeps), int(k), int(block_solver),
+                          int(bool(additive)), ctypes.c_double(complex(shift).real),
+                          ctypes.c_double(complex(shift).imag), _p(b), _p(z))
+    if rc:
+        raise ValueError(f"or_schwarz: status {rc}")
+    return z
+
+
 def block_apply(dims, U, A, block, blk: int, psi, shift: complex = 0.0) -> np.ndarray:
     """I^T (D - shift) I psi on block blk; zero elsewhere."""
     U, A, psi = _c(U), _c(A), _c(psi)

@@ -349,21 +349,152 @@ int or_sap_check(const int *L, const int *B) {
     return OR_OK;
 }
 
-/* nsweeps applications of Red-Black Schwarz (Section 2, Algorithm 2.1) to
- * (D - shift) z = b. Each block system I^T (D - shift) I e = I^T r is
- * approximated by mr_iters steps of minimal residual from e = 0. */
-int or_sap(const int *L, const double *Ud, const double *Ad, const int *B, int nsweeps, int mr_iters,
-           double shift_re, double shift_im, const double *bd, double *zd) {
+/* sum over the sites of a block of conj(x) y */
+static cplx block_dot(const int *sites, int Vb, const cplx *x, const cplx *y) {
+    cplx acc = 0;
+    for (int n = 0; n < Vb; n++)
+        for (int i = 0; i < 12; i++) {
+            size_t k = (size_t)sites[n] * 12 + i;
+            acc += conj(x[k]) * y[k];
+        }
+    return acc;
+}
+
+/* e = approximate solution of the block system I^T (D - shift) I e = I^T r by
+ * mr_iters steps of minimal residual from e = 0 (stop if q^H q = 0). rho, q:
+ * work fields (only the block's sites are touched). */
+static void block_mr(const int *L, const cplx *U, const cplx *A, cplx shift, const int *B, int bb, const int *sites,
+                     int Vb, int mr_iters, const cplx *r, cplx *e, cplx *rho, cplx *q) {
+    for (int n = 0; n < Vb; n++)
+        for (int i = 0; i < 12; i++) {
+            size_t k = (size_t)sites[n] * 12 + i;
+            rho[k] = r[k];
+            e[k] = 0;
+        }
+    for (int it = 0; it < mr_iters; it++) {
+        for (int n = 0; n < Vb; n++) dirac_site(L, U, A, shift, rho, sites[n], B, bb, q + (size_t)sites[n] * 12);
+        double qq = 0;
+        cplx qr = 0;
+        for (int n = 0; n < Vb; n++)
+            for (int i = 0; i < 12; i++) {
+                size_t k = (size_t)sites[n] * 12 + i;
+                qq += creal(conj(q[k]) * q[k]);
+                qr += conj(q[k]) * rho[k];
+            }
+        if (qq == 0.0) break;
+        cplx alpha = qr / qq;
+        for (int n = 0; n < Vb; n++)
+            for (int i = 0; i < 12; i++) {
+                size_t k = (size_t)sites[n] * 12 + i;
+                e[k] += alpha * rho[k];
+                rho[k] -= alpha * q[k];
+            }
+    }
+}
+
+/* e = approximate solution of the same block system by k steps of GMRES from
+ * e = 0 (the block solver of the paper's experiments, Section 4): Arnoldi with
+ * modified Gram-Schmidt on I^T (D - shift) I started from r / ||r||, stopped
+ * early when h_{j+1,j} = 0; y minimises ||beta e_1 - H y|| (Givens rotations
+ * applied to the columns as they are formed, then back substitution), and
+ * e = sum_i y_i v_i. Vk: k + 1 work fields, w: one more (block sites only). */
+static void block_gmres(const int *L, const cplx *U, const cplx *A, cplx shift, const int *B, int bb,
+                        const int *sites, int Vb, int k, const cplx *r, cplx *e, cplx **Vk, cplx *w) {
+    for (int n = 0; n < Vb; n++)
+        for (int i = 0; i < 12; i++) e[(size_t)sites[n] * 12 + i] = 0;
+    double beta = sqrt(creal(block_dot(sites, Vb, r, r)));
+    if (beta == 0.0 || k < 1) return;
+    cplx *H = calloc((size_t)(k + 1) * k, sizeof(cplx));   /* column j at H + j (k + 1) */
+    double *cs = calloc(k, sizeof(double));
+    cplx *sn = calloc(k, sizeof(cplx)), *g = calloc(k + 1, sizeof(cplx)), *y = calloc(k, sizeof(cplx));
+    for (int n = 0; n < Vb; n++)
+        for (int i = 0; i < 12; i++) {
+            size_t q = (size_t)sites[n] * 12 + i;
+            Vk[0][q] = r[q] / beta;
+        }
+    int kk = k;
+    for (int j = 0; j < k; j++) {
+        cplx *h = H + (size_t)j * (k + 1);
+        for (int n = 0; n < Vb; n++) dirac_site(L, U, A, shift, Vk[j], sites[n], B, bb, w + (size_t)sites[n] * 12);
+        for (int i = 0; i <= j; i++) {
+            h[i] = block_dot(sites, Vb, Vk[i], w);
+            for (int n = 0; n < Vb; n++)
+                for (int c = 0; c < 12; c++) {
+                    size_t q = (size_t)sites[n] * 12 + c;
+                    w[q] -= h[i] * Vk[i][q];
+                }
+        }
+        double hn = sqrt(creal(block_dot(sites, Vb, w, w)));
+        h[j + 1] = hn;
+        if (hn == 0.0) {
+            kk = j + 1;
+            break;
+        }
+        for (int n = 0; n < Vb; n++)
+            for (int c = 0; c < 12; c++) {
+                size_t q = (size_t)sites[n] * 12 + c;
+                Vk[j + 1][q] = w[q] / hn;
+            }
+    }
+    g[0] = beta;
+    for (int j = 0; j < kk; j++) {
+        cplx *h = H + (size_t)j * (k + 1);
+        for (int i = 0; i < j; i++) {   /* earlier rotations on column j */
+            cplx a = h[i], b = h[i + 1];
+            h[i] = cs[i] * a + sn[i] * b;
+            h[i + 1] = -conj(sn[i]) * a + cs[i] * b;
+        }
+        cplx a = h[j], b = h[j + 1];
+        double aa = cabs(a), bb2 = cabs(b);
+        if (bb2 == 0.0) {
+            cs[j] = 1.0; sn[j] = 0.0;
+        } else if (aa == 0.0) {
+            cs[j] = 0.0; sn[j] = 1.0; h[j] = b;
+        } else {
+            double rr = sqrt(aa * aa + bb2 * bb2);
+            cs[j] = aa / rr;
+            sn[j] = (a / aa) * conj(b) / rr;
+            h[j] = (a / aa) * rr;
+        }
+        h[j + 1] = 0.0;
+        cplx gj = g[j];
+        g[j] = cs[j] * gj;
+        g[j + 1] = -conj(sn[j]) * gj;
+    }
+    for (int i = kk - 1; i >= 0; i--) {
+        cplx t = g[i];
+        for (int l = i + 1; l < kk; l++) t -= H[(size_t)l * (k + 1) + i] * y[l];
+        y[i] = t / H[(size_t)i * (k + 1) + i];
+    }
+    for (int i = 0; i < kk; i++)
+        for (int n = 0; n < Vb; n++)
+            for (int c = 0; c < 12; c++) {
+                size_t q = (size_t)sites[n] * 12 + c;
+                e[q] += y[i] * Vk[i][q];
+            }
+    free(H); free(cs); free(sn); free(g); free(y);
+}
+
+/* nsweeps applications of a Schwarz method (Section 2) to (D - shift) z = b.
+ * additive = 0: red-black multiplicative Schwarz, Algorithm 2.1 (colour 0
+ * first; the residual is recomputed before each colour). additive = 1:
+ * additive Schwarz (the first error propagator of eq. (2.1)): one residual
+ * r = b - (D - shift) z per sweep, every block system solved for it, then z
+ * += sum of the block corrections. Block solver: solver = 0 MR(k), 1 GMRES(k),
+ * both from e = 0 on I^T (D - shift) I. */
+int or_schwarz(const int *L, const double *Ud, const double *Ad, const int *B, int nsweeps, int k, int solver,
+               int additive, double shift_re, double shift_im, const double *bd, double *zd) {
     build_gamma();
     if (or_sap_check(L, B)) return OR_ESHAPE;
     const cplx *U = (const cplx *)Ud, *A = (const cplx *)Ad, *b = (const cplx *)bd;
     cplx *z = (cplx *)zd;
     cplx shift = shift_re + I * shift_im;
     int V = vol(L), Vb = B[0] * B[1] * B[2] * B[3], nblk = V / Vb;
-    cplx *r = calloc((size_t)V * 12, sizeof(cplx));
-    cplx *rho = calloc((size_t)V * 12, sizeof(cplx));
-    cplx *q = calloc((size_t)V * 12, sizeof(cplx));
-    cplx *e = calloc((size_t)V * 12, sizeof(cplx));
+    const size_t V12 = (size_t)V * 12;
+    cplx *r = calloc(V12, sizeof(cplx)), *e = calloc(V12, sizeof(cplx));
+    int nwork = solver == 1 ? k + 2 : 2;
+    cplx **work = malloc(sizeof(cplx *) * nwork);
+    for (int i = 0; i < nwork; i++) work[i] = calloc(V12, sizeof(cplx));
     int *colour = malloc(sizeof(int) * nblk);
     for (int bb = 0; bb < nblk; bb++) {
         int bc[4], t = bb, csum = 0;
@@ -371,61 +502,52 @@ int or_sap(const int *L, const double *Ud, const double *Ad, const int *B, int n
         for (int mu = 0; mu < 4; mu++) { bc[mu] = t % nb[mu]; t /= nb[mu]; csum += bc[mu]; }
         colour[bb] = csum & 1;
     }
+    const int nsteps = additive ? 1 : 2;
     for (int sweep = 0; sweep < nsweeps; sweep++) {
-        for (int c = 0; c < 2; c++) {
-            /* r <- b - (D - shift) z on the sites of colour-c blocks */
+        for (int c = 0; c < nsteps; c++) {
+            /* r <- b - (D - shift) z on the sites of the blocks treated in this step */
 #pragma omp parallel for schedule(static)
             for (int s = 0; s < V; s++) {
                 int col;
                 block_of(L, B, s, &col);
-                if (col != c) continue;
+                if (!additive && col != c) continue;
                 cplx Dz[12];
                 dirac_site(L, U, A, shift, z, s, NULL, -1, Dz);
                 for (int i = 0; i < 12; i++) r[(size_t)s * 12 + i] = b[(size_t)s * 12 + i] - Dz[i];
             }
-            /* z <- z + B_i r on every block of colour c */
+            /* e <- B_i r on every block of this step (blocks touch disjoint sites) */
 #pragma omp parallel for schedule(static)
             for (int bb = 0; bb < nblk; bb++) {
-                if (colour[bb] != c) continue;
+                if (!additive && colour[bb] != c) continue;
                 int *sites = malloc(sizeof(int) * Vb);
                 block_sites(L, B, bb, sites);
-                for (int n = 0; n < Vb; n++)
-                    for (int i = 0; i < 12; i++) {
-                        size_t k = (size_t)sites[n] * 12 + i;
-                        rho[k] = r[k];
-                        e[k] = 0;
-                    }
-                for (int it = 0; it < mr_iters; it++) {
-                    for (int n = 0; n < Vb; n++)
-                        dirac_site(L, U, A, shift, rho, sites[n], B, bb, q + (size_t)sites[n] * 12);
-                    double qq = 0;
-                    cplx qr = 0;
-                    for (int n = 0; n < Vb; n++)
-                        for (int i = 0; i < 12; i++) {
-                            size_t k = (size_t)sites[n] * 12 + i;
-                            qq += creal(conj(q[k]) * q[k]);
-                            qr += conj(q[k]) * rho[k];
-                        }
-                    if (qq == 0.0) break;
-                    cplx alpha = qr / qq;
-                    for (int n = 0; n < Vb; n++)
-                        for (int i = 0; i < 12; i++) {
-                            size_t k = (size_t)sites[n] * 12 + i;
-                            e[k] += alpha * rho[k];
-                            rho[k] -= alpha * q[k];
-                        }
-                }
-                for (int n = 0; n < Vb; n++)
-                    for (int i = 0; i < 12; i++) {
-                        size_t k = (size_t)sites[n] * 12 + i;
-                        z[k] += e[k];
-                    }
+                if (solver == 1)
+                    block_gmres(L, U, A, shift, B, bb, sites, Vb, k, r, e, work, work[k + 1]);
+                else
+                    block_mr(L, U, A, shift, B, bb, sites, Vb, k, r, e, work[0], work[1]);
                 free(sites);
+            }
+            /* z <- z + e on the same sites */
+#pragma omp parallel for schedule(static)
+            for (int s = 0; s < V; s++) {
+                int col;
+                block_of(L, B, s, &col);
+                if (!additive && col != c) continue;
+                for (int i = 0; i < 12; i++) z[(size_t)s * 12 + i] += e[(size_t)s * 12 + i];
             }
         }
     }
-    free(r); free(rho); free(q); free(e); free(colour);
+    for (int i = 0; i < nwork; i++) free(work[i]);
+    free(work); free(r); free(e); free(colour);
     return OR_OK;
+}
+
+/* nsweeps applications of Red-Black Schwarz (Section 2, Algorithm 2.1) to
+ * (D - shift) z = b. Each block system I^T (D - shift) I e = I^T r is
+ * approximated by mr_iters steps of minimal residual from e = 0. */
+int or_sap(const int *L, const double *Ud, const double *Ad, const int *B, int nsweeps, int mr_iters,
+           double shift_re, double shift_im, const double *bd, double *zd) {
+    return or_schwarz(L, Ud, Ad, B, nsweeps, mr_iters, 0, 0, shift_re, shift_im, bd, zd);
 }
 
 /* block matrix I^T (D - shift) I applied to a field given on the whole lattice

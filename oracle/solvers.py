@@ -9,8 +9,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (block_apply, build_P, clover, coarse_apply, coarse_build, coarse_dims, dirac, prolong, restrict,
-               sap)
+from . import (BLOCK_MR, block_apply, build_P, clover, coarse_apply, coarse_build, coarse_dims, dirac, gamma, prolong,
+               restrict, sap, schwarz)
 
 
 def dot(a, b) -> complex:
@@ -173,6 +173,45 @@ def gcr(applyD, b, m, tol, maxit, z0=None, precond=None, check=None):
             return z, st
 
 
+def cgn(applyD, applyDdag, b, tol, maxit, x0=None):
+    """CG on the normal equations D^H D x = D^H b (CGNR: the residual
+    r = b - D x is updated alongside and judges convergence, the comparator of
+    the paper's Section 4). When the updated residual reaches tol ||b|| the
+    true residual is recomputed; if it is still too large, CG starts again
+    from the current iterate (counted as a restart)."""
+    st = Stats()
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128, copy=True)
+    bn = norm(b)
+    if bn == 0.0:
+        st.converged, st.relres = True, 0.0
+        return np.zeros_like(b), st
+    while True:
+        r = b - applyD(x)
+        rn = norm(r)
+        st.relres = rn / bn
+        if rn <= tol * bn:
+            st.converged = True
+            return x, st
+        if st.iters >= maxit:
+            return x, st
+        s = applyDdag(r)
+        p = s.copy()
+        ss = dot(s, s).real
+        while st.iters < maxit:
+            w = applyD(p)
+            alpha = ss / dot(w, w).real
+            x = x + alpha * p
+            r = r - alpha * w
+            st.iters += 1
+            if norm(r) <= tol * bn:
+                break
+            s = applyDdag(r)
+            ss_new = dot(s, s).real
+            p = s + (ss_new / ss) * p
+            ss = ss_new
+        st.restarts += 1
+
+
 # --------------------------------------------------------------------- operator bundle
 
 def parity(dims) -> np.ndarray:
@@ -206,6 +245,15 @@ class Operator:
 
     def sap(self, block, b, z0, nsweeps, mr_iters, shift=0.0):
         return sap(self.dims, self.U, self.A, block, b, z0, nsweeps, mr_iters, shift)
+
+    def schwarz(self, block, b, z0, nsweeps, k, block_solver=BLOCK_MR, additive=False, shift=0.0):
+        return schwarz(self.dims, self.U, self.A, block, b, z0, nsweeps, k, block_solver, additive, shift)
+
+    def apply_dag(self, psi):
+        """D^H psi = gamma_5 D gamma_5 psi (D is gamma_5-Hermitian)."""
+        g5 = np.diag(gamma()[1]).real
+        x = np.asarray(psi, dtype=np.complex128) * g5[None, :, None]
+        return self.apply(x) * g5[None, :, None]
 
     def block_apply(self, block, blk, psi, shift=0.0):
         return block_apply(self.dims, self.U, self.A, block, blk, psi, shift)

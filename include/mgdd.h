@@ -126,6 +126,28 @@ int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *ou
 int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, double shift_re, double shift_im,
              const void *b, void *z);
 
+/* Schwarz variants of Section 2 and of the paper's experiments (Section 4:
+ * 3 GMRES steps per block system). block_solver: MGDD_BLOCK_MR (k steps of
+ * minimal residual, as mgdd_sap) or MGDD_BLOCK_GMRES (k = 1..3 steps of GMRES
+ * from e = 0 on I^T (D - shift) I: Arnoldi, then the small least-squares
+ * problem, per block). additive = 0: red-black multiplicative sweeps
+ * (Algorithm 2.1); additive = 1: additive Schwarz (the first propagator of
+ * eq. (2.1)): per sweep one residual r = b - D z, every block system solved
+ * for it, z += the sum of the corrections (needs shift = 0). b, z: nrhs
+ * fields of precision prec, z in/out, not aliased. Uses the context's
+ * workspace (additive). Errors: MGDD_EINVAL (bad parameters), MGDD_ESHAPE
+ * (block volume outside 64..256), MGDD_ENOTREADY (no gauge field).
+ * Asynchronous. */
+enum { MGDD_BLOCK_MR = 0, MGDD_BLOCK_GMRES = 1 };
+typedef struct {
+    int nsweeps;
+    int block_iters;       /* k */
+    int block_solver;      /* MGDD_BLOCK_MR or MGDD_BLOCK_GMRES */
+    int additive;          /* 0 red-black multiplicative, 1 additive */
+    double shift_re, shift_im;
+} mgdd_schwarz_params;
+int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const mgdd_schwarz_params *params, const void *b, void *z);
+
 /* ------------------------------------------------------------------ coarse level (Section 3) */
 
 /* Builds the aggregation interpolation P from ntv test vectors (Section 3,
@@ -194,7 +216,7 @@ typedef struct {
 int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const void *random_vectors,
                          const void *arnoldi_start);
 
-enum { MGDD_SOLVER_FGMRES_MG = 0, MGDD_SOLVER_GCR = 1, MGDD_SOLVER_GCR_EO = 2 };
+enum { MGDD_SOLVER_FGMRES_MG = 0, MGDD_SOLVER_GCR = 1, MGDD_SOLVER_GCR_EO = 2, MGDD_SOLVER_CGN = 3 };
 enum { MGDD_PLAIN_F64 = 0, MGDD_MIXED = 1 };
 
 typedef struct {
@@ -215,6 +237,9 @@ typedef struct {
     int nu2;           /* three levels: level-2 Schwarz sweeps per application of
                           the level-2 preconditioner */
     int mr2;           /* three levels: MR steps per level-2 block solve */
+    int block_solver;  /* smoother's block solves: MGDD_BLOCK_MR (mr_iters MR steps) or
+                          MGDD_BLOCK_GMRES (mr_iters = 1..3 GMRES steps) */
+    int additive;      /* smoother: 0 red-black multiplicative, 1 additive Schwarz */
 } mgdd_solve_params;
 
 typedef struct {
@@ -231,13 +256,17 @@ typedef struct {
  * method (Section 4), or with levels = 3 by the three-level method
  * (mgdd_precondition3); coarse_iters is then the GMRES step count on the
  * coarsest operator D_cc. GCR: plain GCR(restart) on D. GCR_EO: GCR(restart) on
- * the even-odd Schur complement, convergence judged on the full system.
+ * the even-odd Schur complement, convergence judged on the full system. CGN:
+ * conjugate gradients on D^H D z = D^H b (the paper's comparator, Section 4)
+ * with the residual b - D z updated alongside; when it reaches the tolerance
+ * the true residual is recomputed, and CG starts again from the iterate if
+ * it is still too large (counted in restarts); restart is unused.
  * With FGMRES_MG the nrhs right-hand sides are solved together: one Krylov
  * basis, Hessenberg matrix, restart and stopping test each, with D, the
  * preconditioner and the Gram-Schmidt steps applied to all of them in shared
  * launches (a right-hand side that has converged stops changing). If the
  * workspace for all of them does not fit in device memory they are split
- * into smaller batches. GCR and GCR_EO solve them one after the other.
+ * into smaller batches. GCR, GCR_EO and CGN solve them one after the other.
  * stats: array of nrhs entries (may be NULL). Synchronous. Errors:
  * MGDD_ENOCONV (maxit reached; z and stats written), MGDD_ENAN,
  * MGDD_ENOTREADY (no gauge field; no P for FGMRES_MG; no third level or no

@@ -265,9 +265,11 @@ class TwoLevel:
     """P from test vectors, D_c = P^H D P, and the two-level preconditioner:
     coarse-grid correction with a fixed-step GMRES on D_c, then nu SAP sweeps."""
 
-    def __init__(self, op: Operator, agg, test_vectors, block, mr_iters=4, nu=1, coarse_iters=12):
+    def __init__(self, op: Operator, agg, test_vectors, block, mr_iters=4, nu=1, coarse_iters=12,
+                 block_solver=BLOCK_MR, additive=False):
         self.op, self.agg, self.block = op, tuple(agg), tuple(block)
         self.mr_iters, self.nu, self.coarse_iters = mr_iters, nu, coarse_iters
+        self.block_solver, self.additive = block_solver, additive
         self.set_test_vectors(test_vectors)
 
     def set_test_vectors(self, tv):
@@ -292,8 +294,12 @@ class TwoLevel:
         return gmres_fixed(self.coarse_apply, c, self.coarse_iters)
 
     def precond(self, r):
+        """coarse-grid correction, then nu Schwarz sweeps from it (red-black
+        with MR blocks unless another variant was chosen)"""
         z0 = self.prolong(self.coarse_solve(self.restrict(r)))
-        return self.op.sap(self.block, r, z0, self.nu, self.mr_iters)
+        if self.block_solver == BLOCK_MR and not self.additive:
+            return self.op.sap(self.block, r, z0, self.nu, self.mr_iters)
+        return self.op.schwarz(self.block, r, z0, self.nu, self.mr_iters, self.block_solver, self.additive)
 
 
 # --------------------------------------------------------------------- even-odd Schur complement

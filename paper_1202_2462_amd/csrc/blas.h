@@ -28,6 +28,8 @@ int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double
 int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const *ys, int ny, double2 *out);
 // FP64: y_k = sum_i M[i * ny + k] x_i for k < ny (M on the device); y may be x (ny == nx)
 int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys);
+// y = gamma_5 x for nrhs fine fields of V sites (x and y may alias)
+int blas_gamma5(Ctx *c, int p, size_t V, int nrhs, const void *x, void *y);
 // coef[0] = 1/sqrt(re v[0])
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef);
 

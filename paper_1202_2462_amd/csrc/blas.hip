@@ -403,6 +403,23 @@ int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double
     return hip_check(c, hipGetLastError(), "transform");
 }
 
+// y = gamma_5 x on fields [rhs][12][V]: in the chiral basis gamma_5 =
+// diag(1, 1, -1, -1) in spin, so components 6..11 (spins 2, 3) change sign
+template <typename T> __global__ void gamma5_kernel(size_t V, size_t n, const C<T> *__restrict__ x, C<T> *y) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const C<T> v = x[e];
+    y[e] = ((e / V) % 12) >= 6 ? mk<T>(-v.x, -v.y) : v;
+}
+
+int blas_gamma5(Ctx *c, int p, size_t V, int nrhs, const void *x, void *y) {
+    const size_t n = 12 * V * (size_t)nrhs;
+    const unsigned nwg = (unsigned)((n + 255) / 256);
+    if (p == MGDD_F64) gamma5_kernel<double><<<nwg, 256, 0, c->stream>>>(V, n, (const double2 *)x, (double2 *)y);
+    else gamma5_kernel<float><<<nwg, 256, 0, c->stream>>>(V, n, (const float2 *)x, (float2 *)y);
+    return hip_check(c, hipGetLastError(), "gamma5");
+}
+
 int blas_rsqrt(Ctx *c, const double2 *v, double2 *coef) {
     rsqrt_kernel<<<1, 1, 0, c->stream>>>(v, coef);
     return hip_check(c, hipGetLastError(), "rsqrt");

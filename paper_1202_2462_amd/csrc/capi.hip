@@ -328,6 +328,33 @@ int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, doubl
     GUARD_END
 }
 
+int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const mgdd_schwarz_params *params, const void *b, void *z) {
+    if (!ctx || !params || !b || !z || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    const mgdd_schwarz_params *q = params;
+    if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
+    if (q->nsweeps < 0 || q->block_iters < 0 || (q->block_solver != MGDD_BLOCK_MR && q->block_solver != MGDD_BLOCK_GMRES))
+        return fail(&ctx->c, MGDD_EINVAL, "bad Schwarz parameters");
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    SchwarzOpts o;
+    o.nsweeps = q->nsweeps;
+    o.k = q->block_iters;
+    o.gmres = q->block_solver == MGDD_BLOCK_GMRES;
+    o.additive = q->additive != 0;
+    Arena A;
+    void *work = nullptr;
+    const size_t wb = schwarz_work_bytes(c, prec, nrhs, o);
+    int rc = MGDD_OK;
+    if (wb) {
+        rc = arena_open(c, wb, A);
+        if (!rc && !(work = A.take(wb))) rc = fail(c, MGDD_ENOMEM, "Schwarz workspace");
+    }
+    if (!rc) rc = launch_schwarz(c, prec, nrhs, o, q->shift_re, q->shift_im, b, z, work);
+    return rc;
+    GUARD_END
+}
+
 static int need_coarse(mgdd_ctx *ctx) {
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     if (!ctx->c.c.ready) return fail(&ctx->c, MGDD_ENOTREADY, "no interpolation P (call mgdd_build_P or mgdd_setup_bootstrap)");
@@ -562,7 +589,8 @@ int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const v
     if (!ctx || !params || !b || !z || nrhs <= 0) return MGDD_EINVAL;
     const mgdd_solve_params *sp = params;
     if (sp->restart < 1 || sp->restart > 256 || sp->maxit < 0 || !(sp->tol > 0) ||
-        (sp->solver != MGDD_SOLVER_FGMRES_MG && sp->solver != MGDD_SOLVER_GCR && sp->solver != MGDD_SOLVER_GCR_EO) ||
+        (sp->solver != MGDD_SOLVER_FGMRES_MG && sp->solver != MGDD_SOLVER_GCR && sp->solver != MGDD_SOLVER_GCR_EO &&
+         sp->solver != MGDD_SOLVER_CGN) ||
         (sp->precision != MGDD_PLAIN_F64 && sp->precision != MGDD_MIXED))
         return fail(&ctx->c, MGDD_EINVAL, "bad solve parameters");
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
@@ -570,6 +598,9 @@ int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const v
         int rc = need_coarse(ctx);
         if (rc) return rc;
         if (sp->coarse_iters < 1 || sp->nu < 0 || sp->mr_iters < 0) return fail(&ctx->c, MGDD_EINVAL, "bad solve parameters");
+        if ((sp->block_solver != MGDD_BLOCK_MR && sp->block_solver != MGDD_BLOCK_GMRES) ||
+            (sp->block_solver == MGDD_BLOCK_GMRES && (sp->mr_iters < 1 || sp->mr_iters > SCHWARZ_GMRES_MAX)))
+            return fail(&ctx->c, MGDD_EINVAL, "bad smoother block solver (GMRES takes 1 to 3 steps)");
         if (sp->levels == 3) {
             rc = need_level3_solver(ctx, sp->k2, sp->nu2, sp->mr2);
             if (rc) return rc;

@@ -166,7 +166,8 @@ int launch_convert(Ctx *c, int from, int to, size_t n, const void *src, void *ds
 // dirac.hip
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out);
 
-// sap.hip
+// sap.hip: nsweeps red-black sweeps with MR(mr) block solves; one colour step
 int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, double sim, const void *b, void *z);
+int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, double sim, const void *b, void *z);
 
 }  // namespace mgdd

@@ -503,34 +503,37 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
 
 }  // namespace
 
-int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, double sim, const void *b, void *z) {
+int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, double sim, const void *b, void *z) {
     const Geom &g = c->g;
     if (g.Vb < 64 || g.Vb > 256)
         return fail(c, MGDD_ESHAPE, "the Schwarz kernel needs 64 <= block volume <= 256");
+    const int nblocks = col ? g.nblocks - g.ncol0 : g.ncol0;
+    if (nblocks == 0) return MGDD_OK;
     size_t lds = (prec == MGDD_F64 ? 16 : 8) * 12 * (size_t)g.Vb + (prec == MGDD_F64 ? 8 : 4) * 3 * (g.Vb / 64);
     // four lanes per site with the block's links staged in LDS (FP32)
     const size_t lds4 = 8 * (12 * ((size_t)g.Vb + 4) + 4 * (9 * (size_t)g.Vb + 4)) + 4 * 3 * (4 * g.Vb / 64);
+    dim3 grid(nblocks, nrhs);
+    const int slot = kt_begin(c);
+    if (prec == MGDD_F64) {
+        sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64, (const double2 *)c->A64,
+                                                                  (const double2 *)b, (double2 *)z, col, mr, sre, sim);
+    } else if (lds4 <= c->lds_max) {
+        sap4_kernel<float><<<grid, 4 * g.Vb, lds4, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,
+                                                                (const float2 *)b, (float2 *)z, col, mr, (float)sre,
+                                                                (float)sim);
+    } else {
+        sap_colour_kernel<float><<<grid, g.Vb, lds, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,
+                                                                 (const float2 *)b, (float2 *)z, col, mr, (float)sre,
+                                                                 (float)sim);
+    }
+    kt_end(c, slot, KF_SAP, prec, (double)nblocks * g.Vb * nrhs);
+    return hip_check(c, hipGetLastError(), "sap kernel");
+}
+
+int launch_sap(Ctx *c, int prec, int nrhs, int nsweeps, int mr, double sre, double sim, const void *b, void *z) {
     for (int s = 0; s < nsweeps; s++)
         for (int col = 0; col < 2; col++) {
-            int nblocks = col ? g.nblocks - g.ncol0 : g.ncol0;
-            if (nblocks == 0) continue;
-            dim3 grid(nblocks, nrhs);
-            const int slot = kt_begin(c);
-            if (prec == MGDD_F64) {
-                sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64,
-                                                                          (const double2 *)c->A64, (const double2 *)b,
-                                                                          (double2 *)z, col, mr, sre, sim);
-            } else if (lds4 <= c->lds_max) {
-                sap4_kernel<float><<<grid, 4 * g.Vb, lds4, c->stream>>>(g, (const float2 *)c->U32,
-                                                                        (const float2 *)c->A32, (const float2 *)b,
-                                                                        (float2 *)z, col, mr, (float)sre, (float)sim);
-            } else {
-                sap_colour_kernel<float><<<grid, g.Vb, lds, c->stream>>>(g, (const float2 *)c->U32,
-                                                                         (const float2 *)c->A32, (const float2 *)b,
-                                                                         (float2 *)z, col, mr, (float)sre, (float)sim);
-            }
-            kt_end(c, slot, KF_SAP, prec, (double)nblocks * g.Vb * nrhs);
-            int rc = hip_check(c, hipGetLastError(), "sap kernel");
+            int rc = launch_sap_colour(c, prec, nrhs, col, mr, sre, sim, b, z);
             if (rc) return rc;
         }
     return MGDD_OK;

@@ -4,6 +4,7 @@
 #include <complex>
 
 #include "mgdd_internal.h"
+#include "schwarz.h"
 #include "transfer.h"
 
 namespace mgdd {
@@ -27,6 +28,8 @@ struct MgOpts {
     int nu = 1, mr = 4, cit = 12;
     int levels = 2;
     int k2 = 0, nu2 = 0, mr2 = 0;
+    int gmres_blocks = 0;   // smoother block solves: 0 MR(mr), 1 GMRES(mr)
+    int additive = 0;       // smoother: 0 red-black multiplicative, 1 additive
 };
 MgOpts mg_opts(const mgdd_solve_params *sp);
 

@@ -294,7 +294,18 @@ MgOpts mg_opts(const mgdd_solve_params *sp) {
     o.k2 = sp->k2;
     o.nu2 = sp->nu2;
     o.mr2 = sp->mr2;
+    o.gmres_blocks = sp->block_solver == MGDD_BLOCK_GMRES;
+    o.additive = sp->additive != 0;
     return o;
+}
+
+static SchwarzOpts smoother_opts(const MgOpts &o) {
+    SchwarzOpts so;
+    so.nsweeps = o.nu;
+    so.k = o.mr;
+    so.gmres = o.gmres_blocks;
+    so.additive = o.additive;
+    return so;
 }
 
 static size_t level2_fgmres_bytes(const Ctx *c, int p, const MgOpts &o, int nb) {
@@ -349,7 +360,7 @@ static int level2_fgmres(Ctx *c, int p, const MgOpts &o, int nb, const void *b, 
 size_t precond_bytes(const Ctx *c, int p, const MgOpts &o, int nb) {
     size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
     const size_t inner = o.levels == 3 ? level2_fgmres_bytes(c, p, o, nb) : coarse_gmres_bytes(c, p, o.cit, nb);
-    return n * 8 + 2 * nc * csize(p) + inner + 4096;
+    return n * 8 + 2 * nc * csize(p) + inner + schwarz_work_bytes(c, p, nb, smoother_opts(o)) + 4096;
 }
 
 // z = SAP^nu(D, r, z0 = P x_c) for nb right-hand sides at once, x_c the
@@ -371,7 +382,13 @@ int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o,
     if (!rc) rc = launch_restrict(c, p, nb, rp, cb);
     if (!rc) rc = o.levels == 3 ? level2_fgmres(c, p, o, nb, cb, cx, A) : coarse_gmres(c, p, o.cit, nb, cb, cx, A);
     if (!rc) rc = launch_prolong(c, p, nb, cx, z);
-    if (!rc && o.nu > 0) rc = launch_sap(c, p, nb, o.nu, o.mr, 0.0, 0.0, rp, z);
+    if (!rc && o.nu > 0) {
+        const SchwarzOpts so = smoother_opts(o);
+        void *work = nullptr;
+        if (so.additive && !(work = A.take(schwarz_work_bytes(c, p, nb, so))))
+            return fail(c, MGDD_ENOMEM, "preconditioner workspace");
+        rc = launch_schwarz(c, p, nb, so, 0.0, 0.0, rp, z, work);
+    }
     A.off = mark;
     return rc;
 }
@@ -687,6 +704,92 @@ static int gcr_solve(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z
     }
 }
 
+// ---------------------------------------------------------------- CGN (the paper's comparator)
+
+// CG on D^H D z = D^H b with the residual r = b - D z updated alongside
+// (CGNR); D^H = gamma_5 D gamma_5. When the updated residual reaches tol ||b||
+// (or maxit is reached) the true residual is recomputed; CG starts again from
+// the iterate while it is too large. Two host reads per iteration.
+static int cgn_solve(Ctx *c, const mgdd_solve_params *sp, const void *b, void *z, mgdd_solve_stats *st, Arena &A) {
+    const size_t V = c->g.V, n = 12 * V;
+    double2 *sc = (double2 *)A.take(64), *one = (double2 *)A.take(16);
+    void *r = A.take(n * 16), *s = A.take(n * 16), *p = A.take(n * 16), *w = A.take(n * 16);
+    if (!w) return fail(c, MGDD_ENOMEM, "CGN workspace");
+    cd *hb = host_buf(c, 8);
+    if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
+    hb[0] = 1.0;
+    int rc = write_dev(c, hb, 1, one);
+    const void *bp = b;
+    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &bp, 1, b, sc);
+    if (!rc) rc = read_dev(c, sc, 1, hb + 4);
+    if (rc) return rc;
+    const double bn = std::sqrt(hb[4].real());
+    if (!std::isfinite(bn)) return fail(c, MGDD_ENAN, "right-hand side holds NaN or Inf");
+    st->iters = st->restarts = 0;
+    st->converged = 0;
+    if (bn == 0.0) {
+        st->converged = 1;
+        st->relres = 0;
+        return blas_lincomb(c, MGDD_F64, MGDD_F64, n, nullptr, 0, nullptr, 0.0, 0.0, z);
+    }
+    const double thr = sp->tol * bn;
+    auto dag = [&](const void *x, void *y) {   // y = gamma_5 D gamma_5 x (w as temporary)
+        int e = blas_gamma5(c, MGDD_F64, V, 1, x, w);
+        if (!e) e = launch_dirac(c, MGDD_F64, 1, w, y);
+        if (!e) e = blas_gamma5(c, MGDD_F64, V, 1, y, y);
+        return e;
+    };
+    auto norm2 = [&](const void *x, double2 *out) {
+        const void *xp = x;
+        return blas_multidot(c, MGDD_F64, MGDD_F64, n, &xp, 1, x, out);
+    };
+    for (;;) {
+        // true residual
+        rc = launch_dirac(c, MGDD_F64, 1, z, w);
+        if (!rc) rc = hip_check(c, hipMemcpyAsync(r, b, n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+        const void *wp = w;
+        if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &wp, 1, one, -1.0, 1.0, r);
+        if (!rc) rc = norm2(r, sc);
+        if (!rc) rc = read_dev(c, sc, 1, hb + 4);
+        if (rc) return rc;
+        const double rn = std::sqrt(hb[4].real());
+        if (!std::isfinite(rn)) return fail(c, MGDD_ENAN, "NaN in the CGN residual");
+        st->relres = rn / bn;
+        if (rn <= thr) { st->converged = 1; return MGDD_OK; }
+        if (st->iters >= sp->maxit) return MGDD_OK;
+        rc = dag(r, s);
+        if (!rc) rc = hip_check(c, hipMemcpyAsync(p, s, n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+        if (!rc) rc = norm2(s, sc);
+        if (!rc) rc = read_dev(c, sc, 1, hb + 4);
+        if (rc) return rc;
+        double ss = hb[4].real();
+        while (st->iters < sp->maxit) {
+            rc = launch_dirac(c, MGDD_F64, 1, p, w);
+            if (!rc) rc = norm2(w, sc);
+            if (!rc) rc = read_dev(c, sc, 1, hb + 4);
+            if (rc) return rc;
+            const double alpha = ss / hb[4].real();
+            if (!std::isfinite(alpha)) return fail(c, MGDD_ENAN, "NaN in CGN");
+            const void *pp = p, *wq = w;
+            rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &pp, 1, one, alpha, 1.0, z);
+            if (!rc) rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &wq, 1, one, -alpha, 1.0, r);
+            st->iters++;
+            if (!rc) rc = dag(r, s);
+            if (!rc) rc = norm2(r, sc);
+            if (!rc) rc = norm2(s, sc + 1);
+            if (!rc) rc = read_dev(c, sc, 2, hb + 4);
+            if (rc) return rc;
+            if (std::sqrt(hb[4].real()) <= thr) break;
+            const double ss_new = hb[5].real();
+            const void *sq = s;
+            rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, &sq, 1, one, 1.0, ss_new / ss, p);   // p = s + beta p
+            if (rc) return rc;
+            ss = ss_new;
+        }
+        st->restarts++;
+    }
+}
+
 // ---------------------------------------------------------------- solve entry
 
 size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb) {
@@ -713,7 +816,10 @@ int solve_batch(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void
         const size_t fb = (size_t)12 * c->g.V * 16;
         for (int r = 0; r < nb && !rc; r++) {
             A.off = 0;
-            rc = gcr_solve(c, sp, (const char *)b + r * fb, (char *)z + r * fb, &st[r], A);
+            if (sp->solver == MGDD_SOLVER_CGN)
+                rc = cgn_solve(c, sp, (const char *)b + r * fb, (char *)z + r * fb, &st[r], A);
+            else
+                rc = gcr_solve(c, sp, (const char *)b + r * fb, (char *)z + r * fb, &st[r], A);
         }
     }
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");

@@ -73,7 +73,13 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("precision", ctypes.c_int), ("restart", ctypes.c_int),
                 ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("coarse_iters", ctypes.c_int),
                 ("nu", ctypes.c_int), ("mr_iters", ctypes.c_int), ("levels", ctypes.c_int), ("k2", ctypes.c_int),
-                ("nu2", ctypes.c_int), ("mr2", ctypes.c_int)]
+                ("nu2", ctypes.c_int), ("mr2", ctypes.c_int), ("block_solver", ctypes.c_int),
+                ("additive", ctypes.c_int)]
+
+
+class SchwarzParams(ctypes.Structure):
+    _fields_ = [("nsweeps", ctypes.c_int), ("block_iters", ctypes.c_int), ("block_solver", ctypes.c_int),
+                ("additive", ctypes.c_int), ("shift_re", ctypes.c_double), ("shift_im", ctypes.c_double)]
 
 
 class Level2Params(ctypes.Structure):
@@ -89,9 +95,11 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO = 0, 1, 2
+SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO, SOLVER_CGN = 0, 1, 2, 3
+BLOCK_MR, BLOCK_GMRES = 0, 1
 PLAIN_F64, MIXED = 0, 1
 
+_sig("mgdd_schwarz", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SchwarzParams), _vp, _vp)
 _sig("mgdd_build_P", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp)
 _sig("mgdd_get_test_vectors", ctypes.c_int, _vp, _vp)
 _sig("mgdd_restrict", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
@@ -230,6 +238,10 @@ def mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, r, z):
     return _check(ctx, _lib.mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, _ptr(r), _ptr(z)))
 
 
+def mgdd_schwarz(ctx, prec, nrhs, params: SchwarzParams, b, z):
+    return _check(ctx, _lib.mgdd_schwarz(ctx, prec, nrhs, ctypes.byref(params), _ptr(b), _ptr(z)))
+
+
 def mgdd_precondition3(ctx, prec, nrhs, nu, mr_iters, k2, nu2, mr2, coarse_iters, r, z):
     return _check(ctx, _lib.mgdd_precondition3(ctx, prec, nrhs, nu, mr_iters, k2, nu2, mr2, coarse_iters, _ptr(r),
                                                _ptr(z)))
@@ -345,6 +357,13 @@ class Lattice:
         mgdd_sap(self.ctx, self.prec_of(b), b.shape[0], nsweeps, mr_iters, shift, b, z)
         return z
 
+    def schwarz(self, b, z, nsweeps=1, k=3, block_solver=BLOCK_GMRES, additive=False, shift=0.0):
+        """Schwarz sweeps on (D - shift) z = b (z updated in place): red-black or
+        additive, MR(k) or GMRES(k) block solves."""
+        q = SchwarzParams(nsweeps, k, block_solver, 1 if additive else 0, complex(shift).real, complex(shift).imag)
+        mgdd_schwarz(self.ctx, self.prec_of(b), b.shape[0], q, b, z)
+        return z
+
     # coarse level -------------------------------------------------------
     def build_P(self, agg, test_vectors):
         """test_vectors: (N, 12, V, 2) float64 device tensor."""
@@ -447,8 +466,10 @@ class Lattice:
         return out
 
     def solve(self, b, z=None, solver=SOLVER_FGMRES_MG, precision=PLAIN_F64, restart=20, tol=1e-10, maxit=1000,
-              coarse_iters=12, nu=1, mr_iters=4, allow_noconv=False, levels=2, k2=8, nu2=1, mr2=4):
+              coarse_iters=12, nu=1, mr_iters=4, allow_noconv=False, levels=2, k2=8, nu2=1, mr2=4,
+              block_solver=BLOCK_MR, additive=False):
         z = self.torch.zeros_like(b) if z is None else z
-        sp = SolveParams(solver, precision, restart, tol, maxit, coarse_iters, nu, mr_iters, levels, k2, nu2, mr2)
+        sp = SolveParams(solver, precision, restart, tol, maxit, coarse_iters, nu, mr_iters, levels, k2, nu2, mr2,
+                         block_solver, 1 if additive else 0)
         stats = mgdd_solve(self.ctx, sp, b.shape[0], b, z, allow_noconv=allow_noconv)
         return z, stats

@@ -7,9 +7,10 @@ P and D_c, harmonic Ritz vectors, second setup part) and the mixed-precision
 FGMRES solve of one Gaussian right-hand side to ||b - D z|| <= 1e-10 ||b||.
 `value` is solves per second (setup included). Beside it the same JSON line
 carries the Wilson-clover apply rates (Dirac applies/s and HBM GB/s), the
-time-to-1e-10 of the plain FP64 two-level solve and of plain FP64 GCR (also
-even-odd), the roofline of the dominant kernel, and the oracle on the host
-cores as a CPU baseline.
+time-to-1e-10 of the plain FP64 two-level solve, of the three-level variant,
+of the paper's own protocol (GMRES(3) block solves, FGMRES(25)), of plain
+FP64 CGN (the paper's comparator) and GCR (also even-odd), the roofline of
+the dominant kernel, and the oracle on the host cores as a CPU baseline.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        python bench.py --kernel-only step|sap|dirac|copy   (short runs for hardware counters:
@@ -129,7 +130,7 @@ class Bench:
         torch.cuda.synchronize()
 
     # one pass of the hot path
-    def step(self, setup_prec=None, solve_prec=None, split=None, levels=2):
+    def step(self, setup_prec=None, solve_prec=None, split=None, levels=2, paper_protocol=False):
         mg = self.mgdd
         w = self.w
         setup_prec = mg.F32 if setup_prec is None else setup_prec
@@ -144,13 +145,25 @@ class Bench:
                                   mr_iters=q["mr2"])
             l3 = dict(levels=3, k2=q["k2"], nu2=q["nu2"], mr2=q["mr2"])
         t1 = time.perf_counter()
-        z, stats = self.lat.solve(self.b, precision=solve_prec, restart=w["restart"], tol=w["tol"], maxit=2000,
-                                  coarse_iters=LEVEL3["cit"] if levels == 3 else 12, nu=1, mr_iters=w["mr"], **l3)
+        if paper_protocol:   # GMRES(3) block solves, FGMRES(25)
+            z, stats = self.lat.solve(self.b, precision=solve_prec, restart=25, tol=w["tol"], maxit=2000,
+                                      coarse_iters=12, nu=1, mr_iters=3, block_solver=mg.BLOCK_GMRES)
+        else:
+            z, stats = self.lat.solve(self.b, precision=solve_prec, restart=w["restart"], tol=w["tol"], maxit=2000,
+                                      coarse_iters=LEVEL3["cit"] if levels == 3 else 12, nu=1, mr_iters=w["mr"],
+                                      **l3)
         t2 = time.perf_counter()
         if split is not None:
             split.update(setup_s=t1 - t0, solve_s=t2 - t1, iters=stats[0].iters, restarts=stats[0].restarts,
                          relres=stats[0].relres)
         return z, stats[0]
+
+    def cgn(self):
+        mg = self.mgdd
+        t0 = time.perf_counter()
+        z, stats = self.lat.solve(self.b, solver=mg.SOLVER_CGN, tol=self.w["tol"], maxit=200000)
+        return dict(seconds=time.perf_counter() - t0, iters=stats[0].iters, restarts=stats[0].restarts,
+                    relres=stats[0].relres, converged=bool(stats[0].converged)), z
 
     def gcr(self, even_odd):
         mg = self.mgdd
@@ -319,6 +332,12 @@ def main():
         bench.step(levels=3, split=s3)
         s3["params"] = LEVEL3
         result["time_to_solution"]["mg3_mixed"] = s3
+        log("paper protocol (GMRES(3) blocks, FGMRES(25)), mixed precision")
+        sp = {}
+        bench.step(paper_protocol=True, split=sp)
+        result["time_to_solution"]["mg_paper_protocol"] = sp
+        log("plain FP64 CGN")
+        result["time_to_solution"]["cgn_fp64"], _ = bench.cgn()
         log("plain FP64 GCR")
         result["time_to_solution"]["gcr_fp64"], _ = bench.gcr(False)
         log("even-odd FP64 GCR")
@@ -327,6 +346,8 @@ def main():
         mgt = tts["mg_mixed"]["setup_s"] + tts["mg_mixed"]["solve_s"]
         result["speedup_vs_gcr_fp64"] = {"solve_only": tts["gcr_fp64"]["seconds"] / tts["mg_mixed"]["solve_s"],
                                          "with_setup": tts["gcr_fp64"]["seconds"] / mgt}
+        result["speedup_vs_cgn_fp64"] = {"solve_only": tts["cgn_fp64"]["seconds"] / tts["mg_mixed"]["solve_s"],
+                                         "with_setup": tts["cgn_fp64"]["seconds"] / mgt}
 
     bench.lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
     result["dirac"] = bench.dirac_rates()

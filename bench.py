@@ -190,7 +190,8 @@ class Bench:
     def dirac_rates(self):
         mg = self.mgdd
         out = {}
-        for prec, name, bps in ((mg.F64, "f64", 1536), (mg.F32, "f32", 768)):
+        # bytes per site: spinor in + out, 4 links, clover (FP16: half spinors, FP32 links and clover)
+        for prec, name, bps in ((mg.F64, "f64", 1536), (mg.F32, "f32", 768), (mg.F16, "f16", 672)):
             x = self.lat.field(prec, 1)
             x.normal_()
             y = self.lat.field(prec, 1)

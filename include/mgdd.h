@@ -48,7 +48,11 @@
  *    block the sites of even parity first. mgdd_pack / mgdd_unpack convert
  *    between canonical and device layout. Sizes: mgdd_field_bytes().
  *    coarse field: [rhs][a][chi][k] of complex p (the canonical order).
- *  Precision codes: MGDD_F64 (complex double), MGDD_F32 (complex float).
+ *  Precision codes: MGDD_F64 (complex double), MGDD_F32 (complex float),
+ *    MGDD_F16 (complex stored as two IEEE binary16 values, 4 bytes; a storage
+ *    format of fine fields only: accepted by mgdd_field_bytes (level 0),
+ *    mgdd_pack, mgdd_unpack, mgdd_dirac_apply and mgdd_timing_read, whose
+ *    arithmetic is FP32; values are rounded to nearest even when stored).
  */
 #ifndef MGDD_H
 #define MGDD_H
@@ -72,7 +76,7 @@ enum {
     MGDD_ENOMEM = -9      /* device allocation failed */
 };
 
-enum { MGDD_F64 = 0, MGDD_F32 = 1 };
+enum { MGDD_F64 = 0, MGDD_F32 = 1, MGDD_F16 = 2 };
 
 typedef struct mgdd_ctx mgdd_ctx;
 
@@ -115,7 +119,8 @@ int mgdd_pack(mgdd_ctx *ctx, int prec, int nrhs, const double *src, int src_on_d
 int mgdd_unpack(mgdd_ctx *ctx, int prec, int nrhs, const void *src, double *dst, int dst_on_device);
 
 /* out = D in for nrhs fields (Section 1, eq. (1.1)); in and out are device
- * fields of precision prec. Asynchronous. */
+ * fields of precision prec (MGDD_F16: half-precision spinors, FP32 links,
+ * clover term and arithmetic, the result rounded to half). Asynchronous. */
 int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out);
 
 /* nsweeps sweeps of Red-Black Schwarz (Section 2, Algorithm 2.1) on

@@ -99,7 +99,7 @@ int kt_flush(Ctx *c) {
     for (int i = 0; i < k.used && !rc; i++) {
         float ms = 0;
         rc = hip_check(c, hipEventElapsedTime(&ms, k.ev[2 * i], k.ev[2 * i + 1]), "timing");
-        const int f = k.fam[i] >> 1, p = k.fam[i] & 1;
+        const int f = k.fam[i] / 3, p = k.fam[i] % 3;
         k.ms[f][p] += ms;
         k.usum[f][p] += k.units[i];
         k.launches[f][p]++;
@@ -125,7 +125,7 @@ void kt_end(Ctx *c, int slot, int family, int prec, double units) {
     if (slot < 0) return;
     KTimer &k = c->kt;
     (void)hipEventRecord(k.ev[2 * slot + 1], c->stream);
-    k.fam[slot] = family * 2 + (prec == MGDD_F32 ? 1 : 0);
+    k.fam[slot] = family * 3 + prec;
     k.units[slot] = units;
 }
 
@@ -158,6 +158,8 @@ static int setup_geometry(Ctx *c, const int *dims, const int *block) {
 }
 
 static bool valid_prec(int p) { return p == MGDD_F64 || p == MGDD_F32; }
+// fine fields for storage, layout conversion and the Wilson-clover apply may also be FP16
+static bool valid_fine_prec(int p) { return valid_prec(p) || p == MGDD_F16; }
 
 // true when the last error was a failed device allocation (then a smaller
 // batch may fit); clears the HIP error state
@@ -227,8 +229,9 @@ int mgdd_destroy(mgdd_ctx *ctx) {
 const char *mgdd_last_error(const mgdd_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
 
 size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level) {
-    if (!ctx || !valid_prec(prec) || nrhs < 0) return 0;
+    if (!ctx || !valid_fine_prec(prec) || nrhs < 0) return 0;
     if (level == 0) return csize(prec) * fine_elems(&ctx->c, nrhs);
+    if (!valid_prec(prec)) return 0;
     if (level == 1 && ctx->c.c.ready) return csize(prec) * (size_t)nrhs * ctx->c.c.Vc * 2 * ctx->c.c.N;
     if (level == 2 && ctx->c.c2.ready) return csize(prec) * (size_t)nrhs * ctx->c.c2.Vcc * 2 * ctx->c.c2.N2;
     return 0;
@@ -269,7 +272,7 @@ int mgdd_set_gauge(mgdd_ctx *ctx, const double *U, int src_on_device, double m0,
 }
 
 int mgdd_pack(mgdd_ctx *ctx, int prec, int nrhs, const double *src, int src_on_device, void *dst) {
-    if (!ctx || !src || !dst || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (!ctx || !src || !dst || !valid_fine_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     size_t bytes = (size_t)nrhs * 12 * c->g.V * 16;
@@ -289,7 +292,7 @@ int mgdd_pack(mgdd_ctx *ctx, int prec, int nrhs, const double *src, int src_on_d
 }
 
 int mgdd_unpack(mgdd_ctx *ctx, int prec, int nrhs, const void *src, double *dst, int dst_on_device) {
-    if (!ctx || !src || !dst || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (!ctx || !src || !dst || !valid_fine_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     size_t bytes = (size_t)nrhs * 12 * c->g.V * 16;
@@ -310,7 +313,7 @@ int mgdd_unpack(mgdd_ctx *ctx, int prec, int nrhs, const void *src, double *dst,
 }
 
 int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out) {
-    if (!ctx || !in || !out || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (!ctx || !in || !out || !valid_fine_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     if (in == out) return fail(&ctx->c, MGDD_EINVAL, "in and out alias");
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     GUARD_BEGIN
@@ -663,12 +666,12 @@ int mgdd_timing_enable(mgdd_ctx *ctx, int on) {
 
 int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *total_ms, double *site_updates,
                      long long *launches) {
-    if (!ctx || kernel < 0 || kernel >= KF_COUNT || !valid_prec(prec)) return MGDD_EINVAL;
+    if (!ctx || kernel < 0 || kernel >= KF_COUNT || !valid_fine_prec(prec)) return MGDD_EINVAL;
     GUARD_BEGIN
     Ctx *c = &ctx->c;
     int rc = kt_flush(c);
     if (rc) return rc;
-    const int p = prec == MGDD_F32 ? 1 : 0;
+    const int p = prec;
     if (total_ms) *total_ms = c->kt.ms[kernel][p];
     if (site_updates) *site_updates = c->kt.usum[kernel][p];
     if (launches) *launches = c->kt.launches[kernel][p];

@@ -13,9 +13,14 @@ constexpr int TPB = 256;
 // right-hand side; the right-hand sides of one range of sites are consecutive
 // workgroups on one XCD, so the links and the clover term of those sites come
 // from HBM once and from L2 for the other right-hand sides.
-template <typename T>
+// S: storage type of the spinors (T, or _Float16 with T = float: half
+// storage, FP32 arithmetic, links and clover term in FP32)
+template <typename T, typename S = T> struct SpinorView { using type = FieldView<T>; };
+template <> struct SpinorView<float, _Float16> { using type = HalfFieldView; };
+
+template <typename T, typename S = T>
 __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restrict__ Up, const C<T> *__restrict__ Ap,
-                                                    const C<T> *__restrict__ in, C<T> *__restrict__ out, int nrhs,
+                                                    const C<S> *__restrict__ in, C<S> *__restrict__ out, int nrhs,
                                                     int nwg) {
     const int w = xcd_block(nwg);
     const int r = w % nrhs;
@@ -27,7 +32,8 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
     const size_t V = g.V;
     LinkViews<T> U(Up, V);
     CloverViews<T> A(Ap, V);
-    FieldView<T> f(in + (size_t)r * 12 * V, V, 12), o(out + (size_t)r * 12 * V, V, 12);
+    using FV = typename SpinorView<T, S>::type;
+    FV f(in + (size_t)r * 12 * V, V, 12), o(out + (size_t)r * 12 * V, V, 12);
     C<T> acc[12], psi[12], res[12];
     hop_sum<T>(U, f, d, nbr, acc);
     load_spinor<T>(f, d, psi);
@@ -45,9 +51,13 @@ int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     if (prec == MGDD_F64)
         dirac_kernel<double><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
                                                          (const double2 *)in, (double2 *)out, nrhs, nwg);
-    else
+    else if (prec == MGDD_F32)
         dirac_kernel<float><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32, (const float2 *)c->A32,
                                                         (const float2 *)in, (float2 *)out, nrhs, nwg);
+    else
+        dirac_kernel<float, _Float16><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32,
+                                                                  (const float2 *)c->A32, (const half_cx *)in,
+                                                                  (half_cx *)out, nrhs, nwg);
     kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs);
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }

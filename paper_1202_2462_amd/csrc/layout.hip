@@ -18,7 +18,12 @@ __global__ void pack_kernel(Geom g, int nrhs, const double2 *__restrict__ canon,
     int s = lex_of(g, d);
     const double2 *src = canon + ((size_t)rhs * g.V + s) * 12;
     C<T> *o = dst + (size_t)rhs * 12 * g.V + d;
-    for (int k = 0; k < 12; k++) o[(size_t)k * g.V] = mk<T>((T)src[k].x, (T)src[k].y);
+    for (int k = 0; k < 12; k++) {   // one rounding from FP64 to the storage precision
+        C<T> v;
+        v.x = (T)src[k].x;
+        v.y = (T)src[k].y;
+        o[(size_t)k * g.V] = v;
+    }
 }
 
 template <typename T>
@@ -231,8 +236,10 @@ int launch_pack(Ctx *c, int prec, int nrhs, const double2 *canon, void *dst) {
     size_t n = (size_t)nrhs * c->g.V;
     if (prec == MGDD_F64)
         pack_kernel<double><<<nblk(n), TPB, 0, c->stream>>>(c->g, nrhs, canon, (double2 *)dst);
-    else
+    else if (prec == MGDD_F32)
         pack_kernel<float><<<nblk(n), TPB, 0, c->stream>>>(c->g, nrhs, canon, (float2 *)dst);
+    else
+        pack_kernel<_Float16><<<nblk(n), TPB, 0, c->stream>>>(c->g, nrhs, canon, (half_cx *)dst);
     return hip_check(c, hipGetLastError(), "pack kernel");
 }
 
@@ -240,8 +247,10 @@ int launch_unpack(Ctx *c, int prec, int nrhs, const void *src, double2 *canon) {
     size_t n = (size_t)nrhs * c->g.V;
     if (prec == MGDD_F64)
         unpack_kernel<double><<<nblk(n), TPB, 0, c->stream>>>(c->g, nrhs, (const double2 *)src, canon);
-    else
+    else if (prec == MGDD_F32)
         unpack_kernel<float><<<nblk(n), TPB, 0, c->stream>>>(c->g, nrhs, (const float2 *)src, canon);
+    else
+        unpack_kernel<_Float16><<<nblk(n), TPB, 0, c->stream>>>(c->g, nrhs, (const half_cx *)src, canon);
     return hip_check(c, hipGetLastError(), "unpack kernel");
 }
 

@@ -14,9 +14,15 @@ namespace mgdd {
 
 // ------------------------------------------------------------------ complex arithmetic
 
+// complex number stored in half precision (storage only: arithmetic is FP32)
+struct alignas(4) half_cx {
+    _Float16 x, y;
+};
+
 template <typename T> struct cx;
 template <> struct cx<double> { using t = double2; };
 template <> struct cx<float> { using t = float2; };
+template <> struct cx<_Float16> { using t = half_cx; };
 template <typename T> using C = typename cx<T>::t;
 
 template <typename T> __host__ __device__ inline C<T> mk(T r, T i) { C<T> z; z.x = r; z.y = i; return z; }
@@ -101,12 +107,12 @@ enum KernelFamily { KF_DIRAC = 0, KF_SAP = 1, KF_COUNT = 2 };
 struct KTimer {
     bool on = false;
     std::vector<hipEvent_t> ev;      // 2 per slot
-    std::vector<int> fam;            // family * 2 + precision, per used slot
+    std::vector<int> fam;            // family * 3 + precision code, per used slot
     std::vector<double> units;       // site-rhs updates, per used slot
     int used = 0;
-    double ms[KF_COUNT][2] = {};
-    double usum[KF_COUNT][2] = {};
-    long long launches[KF_COUNT][2] = {};
+    double ms[KF_COUNT][3] = {};
+    double usum[KF_COUNT][3] = {};
+    long long launches[KF_COUNT][3] = {};
 };
 
 struct Ctx {
@@ -152,7 +158,7 @@ double *ensure_red(Ctx *c, size_t ndoubles);
 int kt_begin(Ctx *c);
 void kt_end(Ctx *c, int slot, int family, int prec, double units);
 int kt_flush(Ctx *c);
-inline size_t csize(int prec) { return prec == MGDD_F64 ? 16 : 8; }
+inline size_t csize(int prec) { return prec == MGDD_F64 ? 16 : prec == MGDD_F32 ? 8 : 4; }
 inline size_t fine_elems(const Ctx *c, int nrhs) { return (size_t)nrhs * 12 * c->g.V; }
 
 // ------------------------------------------------------------------ launchers (one per kernel family)

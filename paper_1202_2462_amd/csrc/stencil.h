@@ -65,12 +65,36 @@ template <typename T> struct FieldView {
     }
 };
 
-template <typename T> __device__ inline void load_spinor(const FieldView<T> &f, int d, C<T> *s) {
+// A set of `ncomp` complex components of V sites stored in half precision
+// ([comp][V], 4 bytes per complex), read and written as FP32 complex numbers
+// (round to nearest even on the way out).
+struct HalfFieldView {
+    rsrc_t r;
+    unsigned cs;
+    __device__ HalfFieldView(const void *base, size_t V, int ncomp) {
+        r = make_rsrc(base, (size_t)ncomp * V * 4);
+        cs = (unsigned)(V * 4);
+    }
+    __device__ float2 ld(int comp, int site, unsigned salt = 0) const {
+        const half_cx h =
+            __builtin_bit_cast(half_cx, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)site * 4u, comp * cs + salt, 0));
+        return make_float2((float)h.x, (float)h.y);
+    }
+    __device__ void st(int comp, int site, float2 v) const {
+        half_cx h;
+        h.x = (_Float16)v.x;
+        h.y = (_Float16)v.y;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, (unsigned)site * 4u, comp * cs, 0);
+    }
+};
+
+// FV: FieldView<T>, or HalfFieldView with T = float
+template <typename T, typename FV> __device__ inline void load_spinor(const FV &f, int d, C<T> *s) {
 #pragma unroll
     for (int k = 0; k < 12; k++) s[k] = f.ld(k, d);
 }
 
-template <typename T> __device__ inline void store_spinor(const FieldView<T> &f, int d, const C<T> *s) {
+template <typename T, typename FV> __device__ inline void store_spinor(const FV &f, int d, const C<T> *s) {
 #pragma unroll
     for (int k = 0; k < 12; k++) f.st(k, d, s[k]);
 }
@@ -200,8 +224,8 @@ __device__ inline void clover_mv(const CloverViews<T> &A, int d, const C<T> *in,
     herm6_mv<T>(p, in + 6, out + 6);
 }
 
-template <typename T, int MU, bool FWD>
-__device__ inline void hop_from(const LinkViews<T> &U, const FieldView<T> &f, int d, int dn, C<T> *acc) {
+template <typename T, int MU, bool FWD, typename FV>
+__device__ inline void hop_from(const LinkViews<T> &U, const FV &f, int d, int dn, C<T> *acc) {
     C<T> psi[12], u[9];
     load_spinor<T>(f, dn, psi);
     load_link<T, MU>(U, FWD ? d : dn, u);
@@ -212,8 +236,8 @@ __device__ inline void hop_from(const LinkViews<T> &U, const FieldView<T> &f, in
 
 // sum over the 8 hops of the Wilson term, without the factor -1/2:
 // H psi(x) = sum_mu (1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^H psi(x-mu)
-template <typename T>
-__device__ inline void hop_sum(const LinkViews<T> &U, const FieldView<T> &f, int d, const int *nbr, C<T> *acc) {
+template <typename T, typename FV>
+__device__ inline void hop_sum(const LinkViews<T> &U, const FV &f, int d, const int *nbr, C<T> *acc) {
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
     hop_from<T, 0, true>(U, f, d, nbr[0], acc);

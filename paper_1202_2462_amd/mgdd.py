@@ -28,7 +28,7 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ESHAPE, ERANK, ENOTREADY, ENOCONV, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-F64, F32 = 0, 1
+F64, F32, F16 = 0, 1, 2
 KERNEL_DIRAC, KERNEL_SAP = 0, 1
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ERANK", -4: "ENOTREADY", -5: "ENOCONV", -6: "EBREAKDOWN",
           -7: "ENAN", -8: "EHIP", -9: "ENOMEM"}
@@ -322,7 +322,7 @@ class Lattice:
 
     def field(self, prec=F64, nrhs=1):
         t = self.torch
-        dt = t.float64 if prec == F64 else t.float32
+        dt = {F64: t.float64, F32: t.float32, F16: t.float16}[prec]
         return t.zeros((nrhs, 12, self.V, 2), dtype=dt, device="cuda")
 
     def set_gauge(self, U, m0, csw):
@@ -337,7 +337,7 @@ class Lattice:
         return f
 
     def unpack(self, f, prec=None) -> np.ndarray:
-        prec = (F64 if f.dtype == self.torch.float64 else F32) if prec is None else prec
+        prec = self.prec_of(f) if prec is None else prec
         nrhs = f.shape[0]
         out = np.zeros((nrhs, self.V, 4, 3), dtype=np.complex128)
         mgdd_unpack(self.ctx, prec, nrhs, f, out)
@@ -346,7 +346,7 @@ class Lattice:
     @staticmethod
     def prec_of(f):
         import torch
-        return F64 if f.dtype == torch.float64 else F32
+        return {torch.float64: F64, torch.float32: F32, torch.float16: F16}[f.dtype]
 
     def dirac(self, x, y=None):
         y = self.torch.empty_like(x) if y is None else y

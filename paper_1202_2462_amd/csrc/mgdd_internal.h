@@ -35,13 +35,19 @@ template <typename V> __host__ __device__ inline V cmul(V a, V b) {
 template <typename V> __host__ __device__ inline V cmulc(V a, V b) {
     V z; z.x = a.x * b.x + a.y * b.y; z.y = a.x * b.y - a.y * b.x; return z;
 }
-// acc += a * b
+// acc += a * b, as four fused multiply-adds into the accumulator
 template <typename V> __host__ __device__ inline void cfma(V &acc, V a, V b) {
-    acc.x += a.x * b.x - a.y * b.y; acc.y += a.x * b.y + a.y * b.x;
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
 }
 // acc += conj(a) * b
 template <typename V> __host__ __device__ inline void cfmac(V &acc, V a, V b) {
-    acc.x += a.x * b.x + a.y * b.y; acc.y += a.x * b.y - a.y * b.x;
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
 }
 template <typename V, typename S> __host__ __device__ inline V cscale(V a, S s) { V z; z.x = a.x * s; z.y = a.y * s; return z; }
 // i * a

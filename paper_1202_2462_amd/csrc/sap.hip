@@ -14,16 +14,32 @@ namespace {
 
 template <typename T> struct Red3 { T a, b, c; };
 
+// v from lane (lane ^ X) of the same quad, X = 1 or 2: a DPP quad permutation
+// ([1,0,3,2] or [2,3,0,1]) for FP32, a cross-lane shuffle for FP64
+template <int X> __device__ inline float quad_xor(float v) {
+    constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+}
+template <int X> __device__ inline double quad_xor(double v) { return __shfl_xor(v, X, 64); }
+
 // deterministic block-wide sum of three values: an XOR butterfly inside each
 // 64-lane wave (every lane ends with the same bits), then the per-wave sums
 // added in wave order by every thread.
-template <typename T> __device__ inline Red3<T> block_sum3(Red3<T> v, T *red) {
+// TRAIL = false leaves out the closing barrier: for callers that pass a
+// barrier of their own before red is written again
+template <typename T, bool TRAIL = true> __device__ inline Red3<T> block_sum3(Red3<T> v, T *red) {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
+    for (int m = 32; m >= 4; m >>= 1) {
         v.a += __shfl_xor(v.a, m, 64);
         v.b += __shfl_xor(v.b, m, 64);
         v.c += __shfl_xor(v.c, m, 64);
     }
+    v.a += quad_xor<2>(v.a);
+    v.b += quad_xor<2>(v.b);
+    v.c += quad_xor<2>(v.c);
+    v.a += quad_xor<1>(v.a);
+    v.b += quad_xor<1>(v.b);
+    v.c += quad_xor<1>(v.c);
     int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[3 * w] = v.a;
@@ -37,7 +53,7 @@ template <typename T> __device__ inline Red3<T> block_sum3(Red3<T> v, T *red) {
         s.b += red[3 * i + 1];
         s.c += red[3 * i + 2];
     }
-    __syncthreads();
+    if (TRAIL) __syncthreads();
     return s;
 }
 
@@ -275,7 +291,7 @@ template <typename T> __device__ inline void reduce_scatter4(const C<T> *acc, in
         for (int c = 0; c < 3; c++) {
             C<T> mine = hi ? acc[(2 + k) * 3 + c] : acc[k * 3 + c];
             C<T> send = hi ? acc[k * 3 + c] : acc[(2 + k) * 3 + c];
-            C<T> recv = mk<T>(__shfl_xor(send.x, 2, 64), __shfl_xor(send.y, 2, 64));
+            C<T> recv = mk<T>(quad_xor<2>(send.x), quad_xor<2>(send.y));
             kept[k][c] = cadd(mine, recv);
         }
     const bool odd = m & 1;
@@ -283,7 +299,7 @@ template <typename T> __device__ inline void reduce_scatter4(const C<T> *acc, in
     for (int c = 0; c < 3; c++) {
         C<T> mine = odd ? kept[1][c] : kept[0][c];
         C<T> send = odd ? kept[0][c] : kept[1][c];
-        C<T> recv = mk<T>(__shfl_xor(send.x, 1, 64), __shfl_xor(send.y, 1, 64));
+        C<T> recv = mk<T>(quad_xor<1>(send.x), quad_xor<1>(send.y));
         out[c] = cadd(mine, recv);
     }
 }
@@ -334,12 +350,14 @@ __device__ inline void clover_rows(const FieldView<T> &A, unsigned aoff, int d, 
 // With links + rho resident a workgroup takes about 100 KB of LDS, so one
 // block runs per CU and the clover term re-read at every MR step stays in
 // the XCD's L2.
-template <typename T>
+template <typename T, int VB>
 __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restrict__ Up, const C<T> *__restrict__ Ap,
                                                     const C<T> *__restrict__ b, C<T> *__restrict__ z, int colour,
                                                     int mr, T sre, T sim) {
     extern __shared__ unsigned char smem[];
-    const int Vb = g.Vb;
+    // the block volume as a compile-time constant: every LDS offset of a
+    // component or link entry becomes an immediate of the LDS instruction
+    constexpr int Vb = VB;
     // component strides padded by 4 complex numbers, so that the four lanes
     // of a site (different components or directions, same site) fall in
     // different LDS banks
@@ -392,29 +410,24 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
     }
     const int ch = m >> 1;  // chirality of spin m
 
-    // stage the forward link of direction m of this site
-#pragma unroll
-    for (int k = 0; k < 9; k++) lnk_lds[m * MS + k * Vb + l] = Uall.ld_lane(k, d, uoff);
-    __syncthreads();
-
-    // r = b - (D - shift) z, spin m
+    // r = b - (D - shift) z, spin m. Every operand comes from global memory
+    // (the backward hop's link too), so that no barrier separates the loads;
+    // the site's forward link is staged in LDS for the MR steps on the way,
+    // and the one barrier after the residual covers it and rho.
     C<T> rho[3], e[3], q[3];
     {
         C<T> acc[12], psi[12], u[9];
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
+#pragma unroll
+        for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, d, uoff);
         load_spinor<T>(zf, nf, psi);
-#pragma unroll
-        for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + l];
         hop_rt<T, true>(acc, pr, u, psi);
+#pragma unroll
+        for (int k = 0; k < 9; k++) lnk_lds[m * MS + k * Vb + l] = u[k];
         load_spinor<T>(zf, nbk, psi);
-        if (lnb >= 0) {
 #pragma unroll
-            for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + lnb];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, nbk, uoff);
-        }
+        for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, nbk, uoff);
         hop_rt<T, false>(acc, pr, u, psi);
         C<T> hs[3], zc[6], az[3], zs[3], bs[3];
         reduce_scatter4<T>(acc, m, hs);
@@ -434,13 +447,9 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
     __syncthreads();
 
     const float *rf = (const float *)rho_lds;
+    const ProjLds pq = proj_lds_of(m, pr);
     for (int it = 0; it < mr; it++) {
         const unsigned salt = opaque_zero();
-        // the projection constants are recomputed from the lane's direction
-        // in every step (a few instructions) rather than held in registers
-        // across the loop
-        const int mq = m + (int)salt;
-        const ProjLds pq = proj_lds_of(mq, proj_of(mq));
         // the two hops along the lane's direction: w_f = U h_f, w_b = U^H h_b
         // (upper halves); the lower halves are -B^H w_f + B^H w_b = B^H (w_b - w_f)
         C<T> acc[12], h[6], u[9], wf[6], wb[6];
@@ -483,9 +492,12 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
             part.b += q[c].x * rho[c].x + q[c].y * rho[c].y;   // conj(q) rho
             part.c += q[c].x * rho[c].y - q[c].y * rho[c].x;
         }
-        Red3<T> s = block_sum3<T>(part, red);
+        // the barrier after the rho update below (or the end of the loop) comes
+        // before any thread writes red again
+        Red3<T> s = block_sum3<T, false>(part, red);
         if (s.a == (T)0) break;
-        C<T> alpha = mk<T>(s.b / s.a, s.c / s.a);
+        const T inv = (T)1 / s.a;
+        C<T> alpha = mk<T>(s.b * inv, s.c * inv);
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             cfma(e[c], alpha, rho[c]);
@@ -505,8 +517,8 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
 
 int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, double sim, const void *b, void *z) {
     const Geom &g = c->g;
-    if (g.Vb < 64 || g.Vb > 256)
-        return fail(c, MGDD_ESHAPE, "the Schwarz kernel needs 64 <= block volume <= 256");
+    if (g.Vb < 64 || g.Vb > 256 || (g.Vb & (g.Vb - 1)))
+        return fail(c, MGDD_ESHAPE, "the Schwarz kernel needs a block volume of 64, 128 or 256");
     const int nblocks = col ? g.nblocks - g.ncol0 : g.ncol0;
     if (nblocks == 0) return MGDD_OK;
     size_t lds = (prec == MGDD_F64 ? 16 : 8) * 12 * (size_t)g.Vb + (prec == MGDD_F64 ? 8 : 4) * 3 * (g.Vb / 64);
@@ -518,9 +530,14 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
         sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64, (const double2 *)c->A64,
                                                                   (const double2 *)b, (double2 *)z, col, mr, sre, sim);
     } else if (lds4 <= c->lds_max) {
-        sap4_kernel<float><<<grid, 4 * g.Vb, lds4, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,
-                                                                (const float2 *)b, (float2 *)z, col, mr, (float)sre,
-                                                                (float)sim);
+#define SAP4(VB)                                                                                               \
+    sap4_kernel<float, VB><<<grid, 4 * VB, lds4, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,  \
+                                                              (const float2 *)b, (float2 *)z, col, mr, (float)sre, \
+                                                              (float)sim)
+        if (g.Vb == 256) SAP4(256);
+        else if (g.Vb == 128) SAP4(128);
+        else SAP4(64);   // the only other power of two in range
+#undef SAP4
     } else {
         sap_colour_kernel<float><<<grid, g.Vb, lds, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,
                                                                  (const float2 *)b, (float2 *)z, col, mr, (float)sre,

@@ -410,25 +410,31 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
     }
     const int ch = m >> 1;  // chirality of spin m
 
-    // r = b - (D - shift) z, spin m. Every operand comes from global memory
-    // (the backward hop's link too), so that no barrier separates the loads;
-    // the site's forward link is staged in LDS for the MR steps on the way,
-    // and the one barrier after the residual covers it and rho.
+    // r = b - (D - shift) z, spin m. The site's forward link is loaded and
+    // staged in LDS, and both neighbour spinors are requested before the
+    // barrier that publishes the links; the backward hop then takes its link
+    // from LDS when the neighbour is in the block (each link leaves memory once).
     C<T> rho[3], e[3], q[3];
     {
-        C<T> acc[12], psi[12], u[9];
+        C<T> acc[12], psi[12], psb[12], u[9];
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
 #pragma unroll
         for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, d, uoff);
         load_spinor<T>(zf, nf, psi);
-        hop_rt<T, true>(acc, pr, u, psi);
+        load_spinor<T>(zf, nbk, psb);
 #pragma unroll
         for (int k = 0; k < 9; k++) lnk_lds[m * MS + k * Vb + l] = u[k];
-        load_spinor<T>(zf, nbk, psi);
+        __syncthreads();
+        hop_rt<T, true>(acc, pr, u, psi);
+        if (lnb >= 0) {
 #pragma unroll
-        for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, nbk, uoff);
-        hop_rt<T, false>(acc, pr, u, psi);
+            for (int k = 0; k < 9; k++) u[k] = lnk_lds[m * MS + k * Vb + lnb];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = Uall.ld_lane(k, nbk, uoff);
+        }
+        hop_rt<T, false>(acc, pr, u, psb);
         C<T> hs[3], zc[6], az[3], zs[3], bs[3];
         reduce_scatter4<T>(acc, m, hs);
 #pragma unroll

@@ -206,3 +206,17 @@ def workload_gauge(name: str, dims=None) -> np.ndarray:
     dims = tuple(dims or w["dims"])
     eps = w["eps"] if w["eps"] is not None else eps_from_seed(1000 * k + TAG_EPS)
     return gauge_field(dims, eps, 1000 * k + TAG_GAUGE, ape_steps=w["ape"])
+
+
+def network_weights(widths, seed):
+    """Seeded complex weights of a gauge-covariant network with the given
+    channel widths (layer l: [widths[l+1], widths[l], 9]): Gaussian entries of
+    scale 0.1 / sqrt(fan-in), plus 1 / fan-in on the identity hop, so that the
+    initial network is close to a multiple of the identity."""
+    rng = np.random.default_rng(seed)
+    Ws = []
+    for cin, cout in zip(widths[:-1], widths[1:]):
+        W = (rng.standard_normal((cout, cin, 9)) + 1j * rng.standard_normal((cout, cin, 9))) * (0.1 / np.sqrt(cin))
+        W[:, :, 0] += 1.0 / cin
+        Ws.append(W)
+    return Ws

@@ -354,6 +354,58 @@ typedef struct {
  * MGDD_EINVAL (random2 missing). Synchronous. */
 int mgdd_setup_level2(mgdd_ctx *ctx, const mgdd_level2_params *params, const void *random2);
 
+/* ------------------------------------------------------------------ learned setup
+ * Not from the paper: a gauge-covariant network that maps random vectors to
+ * test vectors, in place of most iterations of the bootstrap setup (whose
+ * test-vector iterations are described in Section 3). Layer l maps
+ * widths[l] spinor channels to widths[l+1]:
+ *   y[c] = sum_{c', h} W_l[c][c'][h] T_h x[c'],   h = 0..8,
+ * with complex scalar weights, T_0 = 1, T_{1+2mu} x(s) = U_mu(s) x(s + mu),
+ * T_{2+2mu} x(s) = U_mu(s - mu)^H x(s - mu) (colour hops of the Wilson
+ * stencil, antiperiodic in time, every spin alike), so the network commutes
+ * with gauge transformations. widths[0] = widths[nlayers] = 1; widths in
+ * {1, 2, 4, 8, 16}, neighbouring widths equal, 2x apart, or one of them 1.
+ * Weights: device array of complex FP64, layer by layer, [c][c'][h] within
+ * a layer (mgdd_net_weight_count entries). Samples: nsamples fine fields of
+ * one channel each, MGDD_F32, device layout. */
+typedef struct {
+    int nlayers;      /* 1..8 */
+    int widths[9];
+} mgdd_net_shape;
+
+/* number of complex weights (0 for an invalid shape) */
+size_t mgdd_net_weight_count(const mgdd_net_shape *shape);
+
+/* out = net(in) for nsamples fields (in and out must not alias).
+ * Synchronous. Errors: MGDD_EINVAL (shape), MGDD_ENOTREADY (no gauge field). */
+int mgdd_net_apply(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights, int nsamples, const void *in,
+                   void *out);
+
+/* Training loss and gradient against the context's current interpolation P
+ * (built from bootstrap test vectors of the same gauge field): loss = mean
+ * over the samples of ||(1 - P P^H) f||^2 / ||f||^2, f = net(in_s), the
+ * part of the output outside the bootstrap's coarse space; grad (device,
+ * complex FP64, weight layout, written) = dloss / dconj(W), by
+ * back-propagation through the layers (FP32 activations, FP64 weight
+ * gradients). Synchronous. Errors: MGDD_ENOTREADY (no P), MGDD_ENAN (zero or
+ * non-finite output). */
+int mgdd_net_grad(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights, int nsamples, const void *in,
+                  double *loss, void *grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected for step
+ * >= 1) on the real and imaginary parts of every weight; m and v: device
+ * state of the weights' layout, zero before step 1. Asynchronous. */
+int mgdd_net_adam(mgdd_ctx *ctx, const mgdd_net_shape *shape, void *weights, const void *grad, void *m, void *v,
+                  int step, double lr);
+
+/* Setup with the network: the random vectors (params->ntv FP64 fine
+ * fields) are mapped by the network, then the bootstrap setup continues
+ * from the outputs as from its random vectors (params->nu part-1 rounds,
+ * params->n_part2 second parts; with both 0 only P and D_c are built).
+ * arnoldi_start may be NULL when n_part2 = 0. Synchronous. */
+int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights,
+                       const mgdd_setup_params *params, const void *random_vectors, const void *arnoldi_start);
+
 /* ------------------------------------------------------------------ kernel timing
  * Instrumentation, not part of the method. While timing is enabled the
  * library brackets every launch of the Wilson-clover kernel

@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "learn.h"
 #include "level2.h"
 #include "mgdd_internal.h"
 #include "solver.h"
@@ -582,6 +583,93 @@ int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const v
     c->c.ready = false;
     c->c2.ready = false;
     int rc = bootstrap(c, sp, random_vectors, arnoldi_start);
+    if (!rc) c->c.ready = true;
+    return rc;
+    GUARD_END
+}
+
+// ---------------------------------------------------------------- learned setup
+
+static int net_shape(mgdd_ctx *ctx, const mgdd_net_shape *s, NetShape &sh) {
+    if (!s) return MGDD_EINVAL;
+    if (s->nlayers < 1 || s->nlayers > NET_MAX_LAYERS) return fail(&ctx->c, MGDD_EINVAL, "network: 1 to 8 layers");
+    sh.nlayers = s->nlayers;
+    for (int l = 0; l <= s->nlayers; l++) sh.widths[l] = s->widths[l];
+    return check_net_shape(&ctx->c, sh);
+}
+
+size_t mgdd_net_weight_count(const mgdd_net_shape *shape) {
+    if (!shape || shape->nlayers < 1 || shape->nlayers > NET_MAX_LAYERS) return 0;
+    NetShape sh;
+    sh.nlayers = shape->nlayers;
+    for (int l = 0; l <= shape->nlayers; l++) sh.widths[l] = shape->widths[l];
+    return net_shape_valid(sh) ? sh.nweights() : 0;
+}
+
+int mgdd_net_apply(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights, int nsamples, const void *in,
+                   void *out) {
+    if (!ctx || !shape || !weights || !in || !out || nsamples <= 0) return MGDD_EINVAL;
+    if (in == out) return fail(&ctx->c, MGDD_EINVAL, "in and out alias");
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    NetShape sh;
+    int rc = net_shape(ctx, shape, sh);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    Arena A;
+    rc = arena_open(c, net_forward_bytes(c, sh, nsamples), A);
+    if (!rc) rc = net_forward(c, sh, (const double2 *)weights, nsamples, in, out, A);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    return rc;
+    GUARD_END
+}
+
+int mgdd_net_grad(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights, int nsamples, const void *in,
+                  double *loss, void *grad) {
+    if (!ctx || !shape || !weights || !in || !loss || !grad || nsamples <= 0) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    NetShape sh;
+    rc = net_shape(ctx, shape, sh);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    Arena A;
+    rc = arena_open(c, net_grad_bytes(c, sh, nsamples), A);
+    if (!rc) rc = net_grad(c, sh, (const double2 *)weights, nsamples, in, loss, (double2 *)grad, A);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    return rc;
+    GUARD_END
+}
+
+int mgdd_net_adam(mgdd_ctx *ctx, const mgdd_net_shape *shape, void *weights, const void *grad, void *m, void *v,
+                  int step, double lr) {
+    if (!ctx || !shape || !weights || !grad || !m || !v || step < 1 || !(lr > 0)) return MGDD_EINVAL;
+    NetShape sh;
+    int rc = net_shape(ctx, shape, sh);
+    if (rc) return rc;
+    GUARD_BEGIN
+    return launch_net_adam(&ctx->c, sh.nweights(), (double2 *)weights, (const double2 *)grad, (double2 *)m,
+                           (double2 *)v, step, lr, 0.9, 0.999, 1e-8);
+    GUARD_END
+}
+
+int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights,
+                       const mgdd_setup_params *params, const void *random_vectors, const void *arnoldi_start) {
+    if (!ctx || !shape || !weights || !params || !random_vectors) return MGDD_EINVAL;
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    const mgdd_setup_params *sp = params;
+    if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0)
+        return fail(&ctx->c, MGDD_EINVAL, "bad setup parameters");
+    if (sp->n_part2 > 0 && !arnoldi_start) return fail(&ctx->c, MGDD_EINVAL, "the second setup part needs a start vector");
+    NetShape sh;
+    int rc = net_shape(ctx, shape, sh);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    c->c.ready = false;
+    c->c2.ready = false;
+    rc = setup_learned(c, sh, (const double2 *)weights, sp, random_vectors, arnoldi_start);
     if (!rc) c->c.ready = true;
     return rc;
     GUARD_END

@@ -45,5 +45,8 @@ int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o,
 int solve_batch(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st);
 int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64);
 int level2_bootstrap(Ctx *c, const mgdd_level2_params *lp, const void *random2);
+struct NetShape;
+int setup_learned(Ctx *c, const NetShape &sh, const double2 *W64, const mgdd_setup_params *sp, const void *rv64,
+                  const void *start64);
 
 }  // namespace mgdd

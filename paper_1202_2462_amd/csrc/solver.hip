@@ -9,6 +9,7 @@
 
 #include "blas.h"
 #include "eo.h"
+#include "learn.h"
 #include "level2.h"
 #include "linalg.h"
 #include "solver.h"
@@ -1040,6 +1041,32 @@ int level2_bootstrap(Ctx *c, const mgdd_level2_params *lp, const void *random2) 
     if (!rc) rc = launch_dcc_build(c);
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     if (!rc && A.need) rc = fail(c, MGDD_ENOMEM, "level-2 setup workspace estimate too small");
+    return rc;
+}
+
+// ---------------------------------------------------------------- learned setup
+
+// The network maps the caller's random vectors to test vectors; the bootstrap
+// setup then continues from them (sp->nu part-1 rounds, sp->n_part2 second
+// parts), so that with nu = n_part2 = 0 only P and D_c are built from the
+// network's vectors.
+int setup_learned(Ctx *c, const NetShape &sh, const double2 *W64, const mgdd_setup_params *sp, const void *rv64,
+                  const void *start64) {
+    const int N = sp->ntv;
+    const size_t n = (size_t)12 * c->g.V;
+    void *tv = dalloc(c, (size_t)N * n * 16);
+    if (!tv) return MGDD_ENOMEM;
+    Arena A;
+    int rc = arena_open(c, net_forward_bytes(c, sh, N) + 2 * ((size_t)N * n * 8 + 256) + 4096, A);
+    void *in32 = rc ? nullptr : A.take((size_t)N * n * 8), *out32 = rc ? nullptr : A.take((size_t)N * n * 8);
+    if (!rc && !out32) rc = fail(c, MGDD_ENOMEM, "learned setup workspace");
+    if (!rc) rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)N * n, rv64, in32);
+    if (!rc) rc = net_forward(c, sh, W64, N, in32, out32, A);
+    if (!rc) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)N * n, out32, tv);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc) rc = bootstrap(c, sp, tv, start64);
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, tv);
     return rc;
 }
 

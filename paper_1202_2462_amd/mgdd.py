@@ -87,6 +87,15 @@ class Level2Params(ctypes.Structure):
                 ("nu2", ctypes.c_int), ("mr_iters", ctypes.c_int)]
 
 
+class NetShape(ctypes.Structure):
+    _fields_ = [("nlayers", ctypes.c_int), ("widths", ctypes.c_int * 9)]
+
+
+def net_shape(widths):
+    w = list(widths) + [0] * (9 - len(widths))
+    return NetShape(len(widths) - 1, (ctypes.c_int * 9)(*w))
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("relres", ctypes.c_double), ("seconds", ctypes.c_double)]
@@ -99,6 +108,12 @@ SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO, SOLVER_CGN = 0, 1, 2, 3
 BLOCK_MR, BLOCK_GMRES = 0, 1
 PLAIN_F64, MIXED = 0, 1
 
+_sig("mgdd_net_weight_count", ctypes.c_size_t, ctypes.POINTER(NetShape))
+_sig("mgdd_net_apply", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c_int, _vp, _vp)
+_sig("mgdd_net_grad", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
+     _vp)
+_sig("mgdd_net_adam", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double)
+_sig("mgdd_setup_learned", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.POINTER(SetupParams), _vp, _vp)
 _sig("mgdd_schwarz", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SchwarzParams), _vp, _vp)
 _sig("mgdd_build_P", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp)
 _sig("mgdd_get_test_vectors", ctypes.c_int, _vp, _vp)
@@ -236,6 +251,36 @@ def mgdd_coarse_solve(ctx, prec, nrhs, iters, b, x):
 
 def mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, r, z):
     return _check(ctx, _lib.mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, _ptr(r), _ptr(z)))
+
+
+def mgdd_net_weight_count(widths):
+    sh = net_shape(widths)
+    return _lib.mgdd_net_weight_count(ctypes.byref(sh))
+
+
+def mgdd_net_apply(ctx, widths, weights, nsamples, x, y):
+    sh = net_shape(widths)
+    return _check(ctx, _lib.mgdd_net_apply(ctx, ctypes.byref(sh), _ptr(weights), nsamples, _ptr(x), _ptr(y)))
+
+
+def mgdd_net_grad(ctx, widths, weights, nsamples, x, grad):
+    sh = net_shape(widths)
+    loss = ctypes.c_double()
+    _check(ctx, _lib.mgdd_net_grad(ctx, ctypes.byref(sh), _ptr(weights), nsamples, _ptr(x), ctypes.byref(loss),
+                                   _ptr(grad)))
+    return loss.value
+
+
+def mgdd_net_adam(ctx, widths, weights, grad, m, v, step, lr):
+    sh = net_shape(widths)
+    return _check(ctx, _lib.mgdd_net_adam(ctx, ctypes.byref(sh), _ptr(weights), _ptr(grad), _ptr(m), _ptr(v), step, lr))
+
+
+def mgdd_setup_learned(ctx, widths, weights, params, random_vectors, arnoldi_start):
+    sh = net_shape(widths)
+    return _check(ctx, _lib.mgdd_setup_learned(ctx, ctypes.byref(sh), _ptr(weights), ctypes.byref(params),
+                                               _ptr(random_vectors),
+                                               None if arnoldi_start is None else _ptr(arnoldi_start)))
 
 
 def mgdd_schwarz(ctx, prec, nrhs, params: SchwarzParams, b, z):
@@ -450,6 +495,45 @@ class Lattice:
         self.N2 = ntv2
         self.ccdims = tuple(d // a for d, a in zip(self.cdims, self.agg2))
         self.Vcc = int(np.prod(self.ccdims))
+
+    # learned setup ----------------------------------------------------
+    def weights_to_dev(self, Ws):
+        """list of complex arrays [c_out, c_in, 9] -> device FP64 weights"""
+        flat = np.concatenate([np.asarray(W, dtype=np.complex128).ravel() for W in Ws])
+        return self.torch.tensor(np.stack([flat.real, flat.imag], -1), dtype=self.torch.float64, device="cuda")
+
+    @staticmethod
+    def weights_from_dev(t, widths):
+        a = t.detach().cpu().numpy()
+        flat = a[:, 0] + 1j * a[:, 1]
+        out, o = [], 0
+        for cin, cout in zip(widths[:-1], widths[1:]):
+            out.append(flat[o:o + cout * cin * 9].reshape(cout, cin, 9))
+            o += cout * cin * 9
+        return out
+
+    def net_apply(self, widths, weights, x):
+        y = self.torch.empty_like(x)
+        mgdd_net_apply(self.ctx, widths, weights, x.shape[0], x, y)
+        return y
+
+    def net_grad(self, widths, weights, x):
+        grad = self.torch.empty_like(weights)
+        loss = mgdd_net_grad(self.ctx, widths, weights, x.shape[0], x, grad)
+        return loss, grad
+
+    def net_adam(self, widths, weights, grad, m, v, step, lr):
+        mgdd_net_adam(self.ctx, widths, weights, grad, m, v, step, lr)
+
+    def setup_learned(self, widths, weights, agg, random_vectors, arnoldi_start=None, nu=0, iota=3, mr_iters=4,
+                      n_part2=0, prec=F32):
+        N = random_vectors.shape[0]
+        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, 0, n_part2, prec)
+        mgdd_setup_learned(self.ctx, widths, weights, sp, random_vectors, arnoldi_start)
+        self.agg = tuple(agg)
+        self.N = N
+        self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
+        self.Vc = int(np.prod(self.cdims))
 
     def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64):
         N = random_vectors.shape[0]

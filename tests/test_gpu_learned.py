@@ -1,0 +1,141 @@
+"""GPU parity of the learned setup's network (through the C ABI) against the
+oracle: the forward map, the training loss and its gradient against the
+bootstrap's interpolation, one Adam step, the setup built from the
+network's vectors, a short training run that lowers the loss, and the
+error paths."""
+import numpy as np
+import pytest
+
+import latgen
+from gpu_common import lattice, problem, rel, say
+from oracle import learned as nl
+from oracle.solvers import TwoLevel
+
+pytestmark = pytest.mark.gpu
+
+DIMS, BLOCK, AGG, N = (8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 4, 4), 6
+
+
+@pytest.mark.parametrize("widths", [[1, 4, 4, 1], [1, 16, 16, 16, 1], [1, 2, 4, 8, 16, 8, 1]])
+def test_forward_parity(widths):
+    from paper_1202_2462_amd.mgdd import F32
+    say("network forward", widths)
+    op = problem(DIMS, seed=21, m0=0.1)
+    lat = lattice(op, BLOCK)
+    Ws = latgen.network_weights(widths, 22)
+    x = latgen.gaussian_fields(DIMS, 2, 23)
+    want = np.stack([nl.forward(DIMS, op.U, Ws, x[s])[-1][0] for s in range(2)])
+    got = lat.unpack(lat.net_apply(widths, lat.weights_to_dev(Ws), lat.pack(x, F32)))
+    for s in range(2):
+        assert rel(got[s], want[s]) < 2e-5, (s, rel(got[s], want[s]))
+
+
+def two_level(op, lat, seed=24):
+    from paper_1202_2462_amd.mgdd import F64
+    tv = latgen.gaussian_fields(DIMS, N, seed)
+    zero = np.zeros_like(tv[0])
+    tv = np.stack([op.sap(BLOCK, zero, v, 2, 4) for v in tv])
+    lat.build_P(AGG, lat.pack(tv, F64))
+    return TwoLevel(op, AGG, tv, BLOCK)
+
+
+def test_loss_and_gradient_parity():
+    from paper_1202_2462_amd.mgdd import F32
+    widths = [1, 8, 8, 1]
+    say("network loss and gradient", widths)
+    op = problem(DIMS, seed=25, m0=0.1)
+    lat = lattice(op, BLOCK)
+    tl = two_level(op, lat)
+    project = lambda v: tl.prolong(tl.restrict(v))
+    Ws = latgen.network_weights(widths, 26)
+    x = latgen.gaussian_fields(DIMS, 2, 27)
+    ref = [nl.loss_and_grad(DIMS, op.U, Ws, x[s], project) for s in range(2)]
+    want_L = np.mean([r[0] for r in ref])
+    want_g = [0.5 * (ref[0][1][l] + ref[1][1][l]) for l in range(len(Ws))]
+    L, g = lat.net_grad(widths, lat.weights_to_dev(Ws), lat.pack(x, F32))
+    got_g = lat.weights_from_dev(g, widths)
+    say("loss gpu", L, "oracle", want_L)
+    assert abs(L - want_L) < 1e-5 * want_L
+    for l in range(len(Ws)):
+        assert rel(got_g[l], want_g[l]) < 1e-4, (l, rel(got_g[l], want_g[l]))
+
+
+def test_adam_step():
+    import torch
+    widths = [1, 2, 1]
+    op = problem(DIMS, seed=28)
+    lat = lattice(op, BLOCK)
+    Ws = latgen.network_weights(widths, 29)
+    w = lat.weights_to_dev(Ws)
+    w0 = w.clone()
+    g = torch.randn_like(w)
+    m, v = torch.zeros_like(w), torch.zeros_like(w)
+    for step in (1, 2):
+        lat.net_adam(widths, w, g, m, v, step, 1e-2)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy()
+    mm, vv, ww = np.zeros_like(gg), np.zeros_like(gg), w0.cpu().numpy()
+    for step in (1, 2):   # the update rule, written out
+        mm = 0.9 * mm + 0.1 * gg
+        vv = 0.999 * vv + 0.001 * gg * gg
+        ww = ww - 1e-2 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
+    assert np.abs(w.cpu().numpy() - ww).max() < 1e-12
+
+
+def test_learned_setup_builds_P_from_network_vectors_and_solves():
+    from paper_1202_2462_amd.mgdd import F64, MIXED
+    widths = [1, 4, 4, 1]
+    say("learned setup")
+    op = problem(DIMS, seed=30, m0=0.1)
+    lat = lattice(op, BLOCK)
+    Ws = latgen.network_weights(widths, 31)
+    rnd = latgen.gaussian_fields(DIMS, N, 32)
+    lat.setup_learned(widths, lat.weights_to_dev(Ws), AGG, lat.pack(rnd, F64), nu=0, n_part2=0)
+    tv = np.stack([nl.forward(DIMS, op.U, Ws, v)[-1][0] for v in rnd])
+    tl = TwoLevel(op, AGG, tv, BLOCK)
+    f = latgen.gaussian_fields(DIMS, 1, 33)
+    got = lat.unpack(lat.prolong(lat.restrict(lat.pack(f, F64))))[0]
+    want = tl.prolong(tl.restrict(f[0]))
+    assert rel(got, want) < 1e-4
+    b = latgen.gaussian_fields(DIMS, 1, 34)
+    z, st = lat.solve(lat.pack(b, F64), precision=MIXED, tol=1e-10, maxit=500)
+    assert st[0].converged
+    assert np.linalg.norm(b[0] - op.apply(lat.unpack(z)[0])) <= 1.5e-10 * np.linalg.norm(b[0])
+
+
+def test_short_training_lowers_the_loss():
+    import torch
+    from paper_1202_2462_amd.mgdd import F32
+    widths = [1, 4, 4, 1]
+    say("short training")
+    op = problem(DIMS, seed=35, m0=0.1)
+    lat = lattice(op, BLOCK)
+    two_level(op, lat, seed=36)
+    w = lat.weights_to_dev(latgen.network_weights(widths, 37))
+    m, v = torch.zeros_like(w), torch.zeros_like(w)
+    x = lat.pack(latgen.gaussian_fields(DIMS, 2, 38), F32)
+    losses = []
+    for step in range(1, 41):
+        L, g = lat.net_grad(widths, w, x)
+        losses.append(L)
+        lat.net_adam(widths, w, g, m, v, step, 2e-2)
+    say("loss", losses[0], "->", losses[-1])
+    # the loss falls (a linear network of three layers is a low-degree filter:
+    # it moves slowly from the value of random vectors, 1 - dim range(P) / n)
+    assert losses[-1] < losses[0] - 0.01
+    assert np.mean(losses[-5:]) < np.mean(losses[:5])
+
+
+def test_network_errors():
+    from paper_1202_2462_amd.mgdd import EINVAL, ENOTREADY, F32, MgddError
+    op = problem(DIMS, seed=39)
+    lat = lattice(op, BLOCK)
+    x = lat.pack(latgen.gaussian_fields(DIMS, 1, 40), F32)
+    w = lat.weights_to_dev(latgen.network_weights([1, 4, 1], 41))
+    with pytest.raises(MgddError) as e:
+        lat.net_grad([1, 4, 1], w, x)          # no interpolation yet
+    assert e.value.code == ENOTREADY
+    for widths in ([1, 3, 1], [2, 4, 1], [1, 16, 4, 1]):
+        with pytest.raises(MgddError) as e:
+            lat.net_apply(widths, w, x)
+        assert e.value.code == EINVAL, widths

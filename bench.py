@@ -8,7 +8,9 @@ FGMRES solve of one Gaussian right-hand side to ||b - D z|| <= 1e-10 ||b||.
 `value` is solves per second (setup included). Beside it the same JSON line
 carries the Wilson-clover apply rates (Dirac applies/s and HBM GB/s), the
 time-to-1e-10 of the plain FP64 two-level solve, of the three-level variant,
-of the paper's own protocol (GMRES(3) block solves, FGMRES(25)), of plain
+of the paper's own protocol (GMRES(3) block solves, FGMRES(25)), of the
+setup with the shipped learned network in place of most bootstrap
+iterations, of plain
 FP64 CGN (the paper's comparator) and GCR (also even-odd), the roofline of
 the dominant kernel, and the oracle on the host cores as a CPU baseline.
 
@@ -157,6 +159,31 @@ class Bench:
             split.update(setup_s=t1 - t0, solve_s=t2 - t1, iters=stats[0].iters, restarts=stats[0].restarts,
                          relres=stats[0].relres)
         return z, stats[0]
+
+    def learned_step(self, split):
+        """gauge ingest + learned setup (the shipped network on the random
+        vectors, one round of Schwarz sweeps, the second setup part) + the
+        mixed-precision solve; None without the shipped weights"""
+        path = os.path.join(ROOT, "paper_1202_2462_amd", "learned_weights_16x16x16x32.npz")
+        if not os.path.exists(path):
+            return None
+        d = np.load(path)
+        widths = [int(t) for t in d["widths"]]
+        W = self.lat.weights_to_dev([d[f"W{l}"] for l in range(len(widths) - 1)])
+        mg, w = self.mgdd, self.w
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.lat.set_gauge(self.U_dev, self.m0, self.csw)
+        self.lat.setup_learned(widths, W, self.agg, self.rnd, self.start, nu=1, iota=w["iota"], mr_iters=w["mr"],
+                               n_part2=1, prec=mg.F32)
+        self.torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        z, stats = self.lat.solve(self.b, precision=mg.MIXED, restart=w["restart"], tol=w["tol"], maxit=2000,
+                                  coarse_iters=12, nu=1, mr_iters=w["mr"])
+        t2 = time.perf_counter()
+        split.update(setup_s=t1 - t0, solve_s=t2 - t1, iters=stats[0].iters, restarts=stats[0].restarts,
+                     relres=stats[0].relres, converged=bool(stats[0].converged), widths=widths)
+        return split
 
     def cgn(self):
         mg = self.mgdd
@@ -337,6 +364,10 @@ def main():
         sp = {}
         bench.step(paper_protocol=True, split=sp)
         result["time_to_solution"]["mg_paper_protocol"] = sp
+        log("learned setup")
+        sl = bench.learned_step({})
+        if sl is not None:
+            result["time_to_solution"]["mg_learned"] = sl
         log("plain FP64 CGN")
         result["time_to_solution"]["cgn_fp64"], _ = bench.cgn()
         log("plain FP64 GCR")

@@ -406,6 +406,12 @@ int mgdd_net_adam(mgdd_ctx *ctx, const mgdd_net_shape *shape, void *weights, con
 int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights,
                        const mgdd_setup_params *params, const void *random_vectors, const void *arnoldi_start);
 
+/* Frees the context's solver / setup workspace and staging buffer (they grow
+ * on demand and are otherwise kept until mgdd_destroy), for programs that
+ * hold many contexts; the next call that needs them allocates them again.
+ * Synchronises the context's stream. */
+int mgdd_release_workspace(mgdd_ctx *ctx);
+
 /* ------------------------------------------------------------------ kernel timing
  * Instrumentation, not part of the method. While timing is enabled the
  * library brackets every launch of the Wilson-clover kernel

@@ -227,6 +227,19 @@ int mgdd_destroy(mgdd_ctx *ctx) {
     return MGDD_OK;
 }
 
+int mgdd_release_workspace(mgdd_ctx *ctx) {
+    if (!ctx) return MGDD_EINVAL;
+    Ctx *c = &ctx->c;
+    (void)hipStreamSynchronize(c->stream);
+    for (void **p : {&c->ws, &c->stage}) {
+        if (*p) dfree(c, *p);
+        *p = nullptr;
+    }
+    c->ws_bytes = 0;
+    c->stage_bytes = 0;
+    return MGDD_OK;
+}
+
 const char *mgdd_last_error(const mgdd_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
 
 size_t mgdd_field_bytes(const mgdd_ctx *ctx, int prec, int nrhs, int level) {

@@ -177,6 +177,7 @@ def main():
     train_f = [Field(U, s, a.m0) for U, s in zip(Us[:a.train], tseeds)]
     for f in train_f:
         f.bootstrap()
+        f.lat.release_workspace()   # keep only P, D_c and the links of each training field
     log("bootstrap setups of the training fields done")
     t1 = time.time()
     W, hist = train(train_f, widths, a.steps, a.lr, a.samples, log=log)

@@ -108,6 +108,7 @@ SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO, SOLVER_CGN = 0, 1, 2, 3
 BLOCK_MR, BLOCK_GMRES = 0, 1
 PLAIN_F64, MIXED = 0, 1
 
+_sig("mgdd_release_workspace", ctypes.c_int, _vp)
 _sig("mgdd_net_weight_count", ctypes.c_size_t, ctypes.POINTER(NetShape))
 _sig("mgdd_net_apply", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c_int, _vp, _vp)
 _sig("mgdd_net_grad", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
@@ -495,6 +496,9 @@ class Lattice:
         self.N2 = ntv2
         self.ccdims = tuple(d // a for d, a in zip(self.cdims, self.agg2))
         self.Vcc = int(np.prod(self.ccdims))
+
+    def release_workspace(self):
+        _check(self.ctx, _lib.mgdd_release_workspace(self.ctx))
 
     # learned setup ----------------------------------------------------
     def weights_to_dev(self, Ws):

@@ -139,3 +139,31 @@ def test_network_errors():
         with pytest.raises(MgddError) as e:
             lat.net_apply(widths, w, x)
         assert e.value.code == EINVAL, widths
+
+
+def test_shipped_weights_beat_random_vectors():
+    """the network trained on 16^3x32 fields (shipped weights) is local and
+    gauge covariant, so it applies to any lattice: on an 8^4 problem its
+    vectors with one Schwarz round give fewer outer iterations than random
+    vectors with the same round"""
+    import os
+    from paper_1202_2462_amd.mgdd import F64, MIXED
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1202_2462_amd",
+                        "learned_weights_16x16x16x32.npz")
+    d = np.load(path)
+    widths = [int(t) for t in d["widths"]]
+    Ws = [d[f"W{l}"] for l in range(len(widths) - 1)]
+    op = problem(DIMS, seed=42, m0=0.02, eps=0.5)
+    lat = lattice(op, BLOCK)
+    rnd = lat.pack(latgen.gaussian_fields(DIMS, 8, 43), F64)
+    b = lat.pack(latgen.gaussian_fields(DIMS, 1, 44), F64)
+    its = {}
+    lat.setup_learned(widths, lat.weights_to_dev(Ws), AGG, rnd, nu=1, n_part2=0)
+    its["learned"] = lat.solve(b, precision=MIXED, tol=1e-10, maxit=2000)[1][0]
+    import torch
+    start = torch.zeros((lat.Vc, 2, 8, 2), dtype=torch.float64, device="cuda")
+    lat.setup(AGG, rnd, start, nu=1, n_part2=0)
+    its["random"] = lat.solve(b, precision=MIXED, tol=1e-10, maxit=2000)[1][0]
+    say({k: v.iters for k, v in its.items()})
+    assert its["learned"].converged and its["random"].converged
+    assert its["learned"].iters < its["random"].iters

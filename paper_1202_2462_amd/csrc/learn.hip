@@ -22,10 +22,12 @@ namespace {
 
 constexpr int TPB = 256;   // 64 sites x 4 spins
 
-template <int CIN, int COUT>
+// S samples per thread (blockIdx.y covers samples S at a time): each link
+// leaves memory once for the S samples of a site
+template <int CIN, int COUT, int S>
 __global__ __launch_bounds__(TPB) void net_layer_kernel(Geom g, const float2 *__restrict__ Up,
                                                         const float2 *__restrict__ W, const float2 *__restrict__ x,
-                                                        float2 *__restrict__ y) {
+                                                        float2 *__restrict__ y, int ns) {
     const int t = blockIdx.x * TPB + threadIdx.x;
     const int i = t >> 2, s = t & 3;
     if (i >= g.V) return;
@@ -33,50 +35,65 @@ __global__ __launch_bounds__(TPB) void net_layer_kernel(Geom g, const float2 *__
     int nbr[8];
     site_neighbours(g, d, nbr);
     const size_t V = g.V;
-    const int smp = blockIdx.y;
+    const int smp0 = blockIdx.y * S;
     LinkViews<float> U(Up, V);
-    float2 acc[COUT][3];
+    float2 acc[S][COUT][3];
 #pragma unroll
-    for (int c = 0; c < COUT; c++)
+    for (int q = 0; q < S; q++)
 #pragma unroll
-        for (int a = 0; a < 3; a++) acc[c][a] = make_float2(0.f, 0.f);
+        for (int c = 0; c < COUT; c++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) acc[q][c][a] = make_float2(0.f, 0.f);
+    // hop outermost: the link of a hop is loaded once and applied to every
+    // input channel of every sample
+#pragma unroll
+    for (int h = 0; h < 9; h++) {
+        const int mu = h > 0 ? (h - 1) >> 1 : 0;
+        const bool back = h > 0 && ((h - 1) & 1);
+        const int dn = h > 0 ? nbr[h - 1] : d;
+        float2 u[9];
+        if (h > 0) {
+            const FieldView<float> &uf = mu == 0 ? U.u0 : mu == 1 ? U.u1 : mu == 2 ? U.u2 : U.u3;
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = uf.ld(k, back ? dn : d);
+        }
 #pragma unroll 1
-    for (int cp = 0; cp < CIN; cp++) {
-        const FieldView<float> xf(x + ((size_t)smp * CIN + cp) * 12 * V, V, 12);
+        for (int cp = 0; cp < CIN; cp++) {
 #pragma unroll
-        for (int h = 0; h < 9; h++) {
-            float2 w[3];
-            if (h == 0) {
-#pragma unroll
-                for (int a = 0; a < 3; a++) w[a] = xf.ld_lane(a, d, 3u * s * xf.cs);
-            } else {
-                const int mu = (h - 1) >> 1;
-                const bool back = (h - 1) & 1;
-                const int dn = nbr[h - 1];
-                float2 v[3], u[9];
+            for (int q = 0; q < S; q++) {
+                if (S > 1 && smp0 + q >= ns) break;   // the same for the whole workgroup
+                const FieldView<float> xf(x + ((size_t)(smp0 + q) * CIN + cp) * 12 * V, V, 12);
+                float2 v[3], w[3];
 #pragma unroll
                 for (int a = 0; a < 3; a++) v[a] = xf.ld_lane(a, dn, 3u * s * xf.cs);
-                const FieldView<float> &uf = mu == 0 ? U.u0 : mu == 1 ? U.u1 : mu == 2 ? U.u2 : U.u3;
+                if (h == 0) {
 #pragma unroll
-                for (int k = 0; k < 9; k++) u[k] = uf.ld(k, back ? dn : d);
-                if (back) su3_mv<float, true>(u, v, w);
-                else su3_mv<float, false>(u, v, w);
+                    for (int a = 0; a < 3; a++) w[a] = v[a];
+                } else if (back) {
+                    su3_mv<float, true>(u, v, w);
+                } else {
+                    su3_mv<float, false>(u, v, w);
+                }
+#pragma unroll
+                for (int c = 0; c < COUT; c++) {
+                    const float2 wt = W[((size_t)c * CIN + cp) * 9 + h];
+#pragma unroll
+                    for (int a = 0; a < 3; a++) cfma(acc[q][c][a], wt, w[a]);
+                }
             }
-#pragma unroll
-            for (int c = 0; c < COUT; c++) {
-                const float2 wt = W[((size_t)c * CIN + cp) * 9 + h];
-#pragma unroll
-                for (int a = 0; a < 3; a++) cfma(acc[c][a], wt, w[a]);
-            }
-            // one hop's loads at a time (hoisting all nine would exhaust the registers)
-            __builtin_amdgcn_sched_barrier(0);
         }
+        // one hop's link in registers at a time
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int c = 0; c < COUT; c++) {
-        const FieldView<float> yf(y + ((size_t)smp * COUT + c) * 12 * V, V, 12);
+    for (int q = 0; q < S; q++) {
+        if (S > 1 && smp0 + q >= ns) break;
 #pragma unroll
-        for (int a = 0; a < 3; a++) yf.st_lane(a, d, 3u * s * yf.cs, acc[c][a]);
+        for (int c = 0; c < COUT; c++) {
+            const FieldView<float> yf(y + ((size_t)(smp0 + q) * COUT + c) * 12 * V, V, 12);
+#pragma unroll
+            for (int a = 0; a < 3; a++) yf.st_lane(a, d, 3u * s * yf.cs, acc[q][c][a]);
+        }
     }
 }
 
@@ -158,9 +175,11 @@ __global__ void adam_kernel(size_t n, double2 *__restrict__ W, const double2 *__
 
 template <int CIN, int COUT>
 void layer_launch(Ctx *c, const float2 *W, int ns, const void *x, void *y) {
+    // samples per thread: as many as keep the accumulators near 48 complex numbers
+    constexpr int S = COUT <= 4 ? 4 : COUT <= 8 ? 2 : 1;
     const unsigned nwg = (unsigned)((4 * (size_t)c->g.V + TPB - 1) / TPB);
-    net_layer_kernel<CIN, COUT><<<dim3(nwg, ns), TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32, W,
-                                                                      (const float2 *)x, (float2 *)y);
+    net_layer_kernel<CIN, COUT, S><<<dim3(nwg, (ns + S - 1) / S), TPB, 0, c->stream>>>(
+        c->g, (const float2 *)c->U32, W, (const float2 *)x, (float2 *)y, ns);
 }
 
 }  // namespace
@@ -231,7 +250,19 @@ int check_net_shape(Ctx *c, const NetShape &sh) {
 
 static size_t field32(const Ctx *c) { return (size_t)12 * c->g.V * 8; }
 
+static int max_width(const NetShape &sh) {
+    int w = 1;
+    for (int l = 0; l <= sh.nlayers; l++) w = sh.widths[l] > w ? sh.widths[l] : w;
+    return w;
+}
+
+// inference: two activation buffers of the widest layer, used in turn
 size_t net_forward_bytes(const Ctx *c, const NetShape &sh, int ns) {
+    return sh.nweights() * 8 + 2 * ((size_t)ns * max_width(sh) * field32(c) + 256) + 4096;
+}
+
+// training: every layer's activations are kept for the backward pass
+static size_t net_acts_bytes(const Ctx *c, const NetShape &sh, int ns) {
     size_t b = sh.nweights() * 8 + 4096;
     for (int l = 1; l <= sh.nlayers; l++) b += (size_t)ns * sh.widths[l] * field32(c) + 256;
     return b;
@@ -241,7 +272,7 @@ size_t net_grad_bytes(const Ctx *c, const NetShape &sh, int ns) {
     int wmax = 1;
     for (int l = 0; l <= sh.nlayers; l++) wmax = sh.widths[l] > wmax ? sh.widths[l] : wmax;
     const size_t nc = (size_t)c->c.Vc * 2 * c->c.N;
-    return net_forward_bytes(c, sh, ns) + sh.nweights() * 8 + (size_t)NET_MAX_WIDTH * NET_MAX_WIDTH * 9 * 8 +
+    return net_acts_bytes(c, sh, ns) + sh.nweights() * 8 + (size_t)NET_MAX_WIDTH * NET_MAX_WIDTH * 9 * 8 +
            2 * (size_t)ns * wmax * field32(c) +                      // gradients of two neighbouring layers (FP32)
            2 * (size_t)ns * wmax * field32(c) * 2 +                  // FP64 gradient and hopped activations
            2 * (size_t)ns * field32(c) + (size_t)ns * nc * 8 +      // P P^H f, (1 - P P^H) f, P^H f
@@ -267,12 +298,16 @@ static int forward_acts(Ctx *c, const NetShape &sh, const double2 *W64, int ns, 
 
 int net_forward(Ctx *c, const NetShape &sh, const double2 *W64, int ns, const void *in32, void *out32, Arena &A) {
     const size_t mark = A.off;
-    std::vector<const void *> xs;
-    float2 *W32 = nullptr;
-    int rc = forward_acts(c, sh, W64, ns, in32, A, xs, W32);
-    if (!rc)
-        rc = hip_check(c, hipMemcpyAsync(out32, xs[sh.nlayers], (size_t)ns * field32(c), hipMemcpyDeviceToDevice,
-                                         c->stream), "copy");
+    float2 *W32 = (float2 *)A.take(sh.nweights() * 8);
+    void *buf[2] = {A.take((size_t)ns * max_width(sh) * field32(c)), A.take((size_t)ns * max_width(sh) * field32(c))};
+    if (!buf[1]) return fail(c, MGDD_ENOMEM, "network workspace");
+    int rc = launch_net_weights32(c, sh.nweights(), W64, W32);
+    const void *x = in32;
+    for (int l = 0; l < sh.nlayers && !rc; l++) {
+        void *y = l + 1 == sh.nlayers ? out32 : buf[l & 1];
+        rc = launch_net_layer(c, sh.widths[l], sh.widths[l + 1], W32 + sh.offset(l), ns, x, y);
+        x = y;
+    }
     A.off = mark;
     return rc;
 }

@@ -14,6 +14,7 @@ than `fallback_margin`) is solved with the bootstrap.
 
 usage: python -m paper_1202_2462_amd.learned [--train 8] [--eval 2] [--steps 300]
            [--widths 1,16,16,16,1] [--out weights.npz]
+       python -m paper_1202_2462_amd.learned --weights weights.npz --eval 4   (evaluation only)
 """
 from __future__ import annotations
 
@@ -160,9 +161,14 @@ def main():
     ap.add_argument("--m0", type=float, default=None)
     ap.add_argument("--eval-tiled", type=int, default=0,
                     help="also evaluate on this many held-out fields repeated twice in every direction")
+    ap.add_argument("--weights", default=None, help="evaluate these weights (.npz) instead of training")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     widths = [int(t) for t in a.widths.split(",")]
+    if a.weights:
+        d = np.load(a.weights)
+        widths = [int(t) for t in d["widths"]]
+        a.train = 0
     if a.m0 is None:
         import os
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -174,18 +180,23 @@ def main():
     eseeds = [EVAL_SEED0 + i for i in range(a.eval)]
     Us = gauge_fields(tseeds + eseeds)
     log(f"{len(Us)} gauge fields in {time.time() - t0:.1f} s")
-    train_f = [Field(U, s, a.m0) for U, s in zip(Us[:a.train], tseeds)]
-    for f in train_f:
-        f.bootstrap()
-        f.lat.release_workspace()   # keep only P, D_c and the links of each training field
-    log("bootstrap setups of the training fields done")
-    t1 = time.time()
-    W, hist = train(train_f, widths, a.steps, a.lr, a.samples, log=log)
-    torch.cuda.synchronize()
-    train_s = time.time() - t1
-    for f in train_f:
-        f.close()
-    eval_f = [Field(U, s, a.m0) for U, s in zip(Us[a.train:], eseeds)]
+    if a.weights:
+        hist, train_s = [np.nan], 0.0
+        eval_f = [Field(U, s, a.m0) for U, s in zip(Us[a.train:], eseeds)]
+        W = eval_f[0].lat.weights_to_dev([d[f"W{l}"] for l in range(len(widths) - 1)])
+    else:
+        train_f = [Field(U, s, a.m0) for U, s in zip(Us[:a.train], tseeds)]
+        for f in train_f:
+            f.bootstrap()
+            f.lat.release_workspace()   # keep only P, D_c and the links of each training field
+        log("bootstrap setups of the training fields done")
+        t1 = time.time()
+        W, hist = train(train_f, widths, a.steps, a.lr, a.samples, log=log)
+        torch.cuda.synchronize()
+        train_s = time.time() - t1
+        for f in train_f:
+            f.close()
+        eval_f = [Field(U, s, a.m0) for U, s in zip(Us[a.train:], eseeds)]
     nus = tuple(int(t) for t in a.nu_learned.split(","))
     res = evaluate(eval_f, widths, W, nus, log=log)
     for f in eval_f:

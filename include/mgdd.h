@@ -172,6 +172,21 @@ int mgdd_build_P(mgdd_ctx *ctx, const int agg[4], int ntv, const void *test_vect
  * to dst (device, ntv fine FP64 fields). */
 int mgdd_get_test_vectors(mgdd_ctx *ctx, void *dst);
 
+/* Checkpoint of the setup (the paper's amortisation of one setup over many
+ * solves, Section 4): writes the test vectors that define the current P to
+ * a file (a header with lattice, aggregate, ntv, m0, c_sw, payload size and a
+ * 64-bit FNV-1a checksum, then the vectors in canonical order, complex
+ * double). Synchronous. Errors: MGDD_ENOTREADY (no P), MGDD_EINVAL (file). */
+int mgdd_save_setup(mgdd_ctx *ctx, const char *path);
+
+/* Rebuilds P and D_c from a setup file written by mgdd_save_setup for the
+ * same lattice (the block shape may differ; the gauge field set on this
+ * context is used for D_c). Synchronous. Errors: MGDD_ENOTREADY (no gauge
+ * field), MGDD_ESHAPE (another lattice), MGDD_EINVAL (unreadable,
+ * truncated or corrupt file: the checksum is verified before anything is
+ * changed), and those of mgdd_build_P. */
+int mgdd_load_setup(mgdd_ctx *ctx, const char *path);
+
 /* coarse = P^H fine (restriction R = P^H, Section 3); nrhs fields. */
 int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coarse);
 

@@ -4,6 +4,8 @@
 #include <cstdio>
 #include <cmath>
 #include <cstring>
+#include <cstdint>
+#include <fstream>
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -401,6 +403,97 @@ int mgdd_get_test_vectors(mgdd_ctx *ctx, void *dst) {
     Ctx *c = &ctx->c;
     return hip_check(c, hipMemcpyAsync(dst, c->c.tv64, (size_t)c->c.N * 12 * c->g.V * 16, hipMemcpyDeviceToDevice,
                                        c->stream), "copy");
+}
+
+// ---------------------------------------------------------------- setup checkpoint
+
+namespace {
+struct SetupFileHeader {
+    char magic[8];        // "MGDDSET1"
+    int32_t dims[4];
+    int32_t agg[4];
+    int32_t ntv;
+    int32_t reserved;
+    double m0, csw;
+    uint64_t payload_bytes;
+    uint64_t checksum;    // FNV-1a (64 bit) of the payload
+};
+
+uint64_t fnv1a(const unsigned char *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    for (size_t i = 0; i < n; i++) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+}  // namespace
+
+int mgdd_save_setup(mgdd_ctx *ctx, const char *path) {
+    if (!ctx || !path) return MGDD_EINVAL;
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    const int N = c->c.N;
+    const size_t bytes = (size_t)N * 12 * c->g.V * 16;
+    double2 *canon = (double2 *)ensure_stage(c, bytes);
+    if (!canon) return MGDD_ENOMEM;
+    rc = launch_unpack(c, MGDD_F64, N, c->c.tv64, canon);
+    std::vector<unsigned char> host(bytes);
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(host.data(), canon, bytes, hipMemcpyDeviceToHost, c->stream), "copy");
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (rc) return rc;
+    SetupFileHeader h{};
+    std::memcpy(h.magic, "MGDDSET1", 8);
+    for (int m = 0; m < 4; m++) {
+        h.dims[m] = c->g.L[m];
+        h.agg[m] = c->c.agg[m];
+    }
+    h.ntv = N;
+    h.m0 = c->m0;
+    h.csw = c->csw;
+    h.payload_bytes = bytes;
+    h.checksum = fnv1a(host.data(), bytes);
+    std::ofstream f(path, std::ios::binary | std::ios::trunc);
+    if (!f) return fail(c, MGDD_EINVAL, "cannot open the setup file for writing");
+    f.write((const char *)&h, sizeof h);
+    f.write((const char *)host.data(), (std::streamsize)bytes);
+    if (!f) return fail(c, MGDD_EINVAL, "writing the setup file failed");
+    return MGDD_OK;
+    GUARD_END
+}
+
+int mgdd_load_setup(mgdd_ctx *ctx, const char *path) {
+    if (!ctx || !path) return MGDD_EINVAL;
+    if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(c, MGDD_EINVAL, "cannot open the setup file");
+    SetupFileHeader h{};
+    f.read((char *)&h, sizeof h);
+    if (!f || std::memcmp(h.magic, "MGDDSET1", 8) != 0) return fail(c, MGDD_EINVAL, "not a setup file");
+    for (int m = 0; m < 4; m++)
+        if (h.dims[m] != c->g.L[m]) return fail(c, MGDD_ESHAPE, "the setup file is for another lattice");
+    const size_t bytes = (size_t)h.ntv * 12 * c->g.V * 16;
+    if (h.ntv < 1 || h.ntv > 32 || h.payload_bytes != bytes) return fail(c, MGDD_EINVAL, "corrupt setup file (sizes)");
+    std::vector<unsigned char> host(bytes);
+    f.read((char *)host.data(), (std::streamsize)bytes);
+    if (!f) return fail(c, MGDD_EINVAL, "the setup file is truncated");
+    if (fnv1a(host.data(), bytes) != h.checksum) return fail(c, MGDD_EINVAL, "corrupt setup file (checksum)");
+    void *st = ensure_stage(c, bytes);
+    if (!st) return MGDD_ENOMEM;
+    c->c.ready = false;
+    c->c2.ready = false;
+    int rc = transfer_setup(c, h.agg, h.ntv);
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(st, host.data(), bytes, hipMemcpyHostToDevice, c->stream), "copy");
+    if (!rc) rc = launch_pack(c, MGDD_F64, h.ntv, (const double2 *)st, c->c.tv64);
+    if (!rc) rc = launch_build_P(c, c->c.tv64);
+    if (!rc) rc = launch_coarse_build(c);
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc) c->c.ready = true;
+    return rc;
+    GUARD_END
 }
 
 int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coarse) {

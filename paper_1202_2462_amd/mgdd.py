@@ -109,6 +109,8 @@ BLOCK_MR, BLOCK_GMRES = 0, 1
 PLAIN_F64, MIXED = 0, 1
 
 _sig("mgdd_release_workspace", ctypes.c_int, _vp)
+_sig("mgdd_save_setup", ctypes.c_int, _vp, ctypes.c_char_p)
+_sig("mgdd_load_setup", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("mgdd_net_weight_count", ctypes.c_size_t, ctypes.POINTER(NetShape))
 _sig("mgdd_net_apply", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c_int, _vp, _vp)
 _sig("mgdd_net_grad", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double),
@@ -496,6 +498,21 @@ class Lattice:
         self.N2 = ntv2
         self.ccdims = tuple(d // a for d, a in zip(self.cdims, self.agg2))
         self.Vcc = int(np.prod(self.ccdims))
+
+    def save_setup(self, path):
+        _check(self.ctx, _lib.mgdd_save_setup(self.ctx, os.fsencode(path)))
+
+    def load_setup(self, path):
+        """rebuilds P and D_c from a setup file written by save_setup"""
+        import struct
+        _check(self.ctx, _lib.mgdd_load_setup(self.ctx, os.fsencode(path)))
+        with open(path, "rb") as f:
+            head = struct.unpack("<8s4i4i2i2d2Q", f.read(80))
+        agg, ntv = head[5:9], head[9]
+        self.agg = tuple(agg)
+        self.N = ntv
+        self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
+        self.Vc = int(np.prod(self.cdims))
 
     def release_workspace(self):
         _check(self.ctx, _lib.mgdd_release_workspace(self.ctx))

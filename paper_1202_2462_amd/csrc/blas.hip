@@ -142,30 +142,30 @@ __global__ void rsqrt_kernel(const double2 *v, double2 *coef) {
 // ---- tall-skinny products of vector sets (bootstrap setup, FP64)
 //
 // gram: part[wg][i][j] = sum over the workgroup's elements of conj(x_i) y_j.
-// Elements are processed in tiles of GT; the tiles of x and y go through LDS.
-// The output is cut into 4x4 blocks (only those with bi <= bj when y is x:
-// the rest is the conjugate transpose); thread t owns block t % nblk for the
-// elements e = t / nblk, t / nblk + ngroups, ... of each tile, so that up to
-// 256 threads work also when there are few blocks; the ngroups partial
-// blocks are added in group order at the end.
+// Elements are processed in tiles of gt (a power of two, sized on the host
+// so that the tiles fit the dynamic LDS); the tiles of x (and of y unless y
+// is x) go through LDS. The output is cut into 4x4 blocks (only those with
+// bi <= bj when y is x: the rest is the conjugate transpose); thread t owns
+// block t % nblk for the elements e = t / nblk, t / nblk + ngroups, ... of
+// each tile, so that up to 256 threads work also when there are few blocks;
+// the ngroups partial blocks are added in group order at the end.
 constexpr int GMAX = 64;   // vectors per set
-constexpr int GT = 32;     // elements per tile
 
 struct PtrList64 {
     const void *p[GMAX];
 };
 
 __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int nx, PtrList64 ys, int ny, int sym,
-                                                   double2 *__restrict__ part) {
-    __shared__ double2 sm[2 * GMAX * GT];   // x and y tiles; reused for the group reduction
-    double2 (*xt)[GT] = (double2 (*)[GT])sm;
-    double2 (*yt)[GT] = (double2 (*)[GT])(sm + GMAX * GT);
+                                                   int gt, double2 *__restrict__ part) {
+    extern __shared__ double2 sm[];   // x and y tiles; reused for the group reduction
+    const double2 *yt = sym ? sm : sm + (size_t)nx * gt;
     const int tx = (nx + 3) / 4, ty = (ny + 3) / 4;
     const int nblk = sym ? tx * (tx + 1) / 2 : tx * ty;
     int ngroups = 1;
     while (ngroups < 8 && 2 * ngroups * nblk <= (int)blockDim.x) ngroups *= 2;
     const int t = threadIdx.x, blk = t % nblk, grp = t / nblk;
     const bool owner = t < nblk * ngroups;
+    const int nload = sym ? nx : nx + ny;
     int bi = 0, bj = 0;
     if (sym) {   // blk -> (bi, bj), bi <= bj, row by row
         int r = blk;
@@ -175,28 +175,35 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
         bi = blk / ty;
         bj = blk % ty;
     }
+    // rows past the set read row 0 (their products are never stored)
+    int xr[4], yr[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        xr[a] = 4 * bi + a < nx ? 4 * bi + a : 0;
+        yr[a] = 4 * bj + a < ny ? 4 * bj + a : 0;
+    }
     double2 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = make_double2(0, 0);
-    const size_t ntile = (n + GT - 1) / GT;
+    const size_t ntile = (n + gt - 1) / gt;
     for (size_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const size_t e0 = tile * GT;
-        for (int q = t; q < (nx + ny) * GT; q += blockDim.x) {
-            const int v = q / GT, e = q % GT;
+        const size_t e0 = tile * gt;
+        for (int q = t; q < nload * gt; q += blockDim.x) {
+            const int v = q / gt, e = q - v * gt;
             double2 val = make_double2(0, 0);
             if (e0 + e < n) val = v < nx ? ((const double2 *)xs.p[v])[e0 + e] : ((const double2 *)ys.p[v - nx])[e0 + e];
-            if (v < nx) xt[v][e] = val; else yt[v - nx][e] = val;
+            sm[q] = val;
         }
         __syncthreads();
         if (owner) {
-            for (int e = grp; e < GT; e += ngroups) {
+            for (int e = grp; e < gt; e += ngroups) {
                 double2 xv[4], yv[4];
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    xv[a] = xt[(4 * bi + a) & (GMAX - 1)][e];
-                    yv[a] = yt[(4 * bj + a) & (GMAX - 1)][e];
+                    xv[a] = sm[xr[a] * gt + e];
+                    yv[a] = yt[yr[a] * gt + e];
                 }
 #pragma unroll
                 for (int a = 0; a < 4; a++)
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
     }
     // add the groups' partial blocks in group order (through LDS)
     if (ngroups > 1) {
-        double2 *red = sm;   // [256][16]
+        double2 *red = sm;   // [nblk * ngroups][16]
         if (owner) {
 #pragma unroll
             for (int a = 0; a < 4; a++)
@@ -242,28 +249,76 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
         }
 }
 
-// out[q] = sum_wg part[wg][q] in workgroup order, q = i ny + j < nq; with sym
-// only the blocks with bi <= bj were formed, the others are the conjugates
-// of their transposes
+// out[q] = sum_wg part[wg][q], q = i ny + j, one workgroup per q: thread t
+// adds the partials wg = t, t + 256, ... in order, then the workgroup sum in a
+// fixed order; with sym only the blocks with bi <= bj were formed, the others
+// are the conjugates of their transposes
 __global__ __launch_bounds__(256) void gram_finish_kernel(int nwg, int nx, int ny, int sym,
                                                           const double2 *__restrict__ part, double2 *__restrict__ out) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nx * ny) return;
+    __shared__ double red[2 * 4];
+    const int q = blockIdx.x;
     const int i = q / ny, j = q % ny;
     const bool mirror = sym && (i / 4) > (j / 4);
     const int src = mirror ? j * ny + i : q;
     double a = 0, b = 0;
-    for (int w = 0; w < nwg; w++) {
+    for (int w = threadIdx.x; w < nwg; w += blockDim.x) {
         const double2 v = part[(size_t)w * nx * ny + src];
         a += v.x;
         b += v.y;
     }
-    out[q] = make_double2(a, mirror ? -b : b);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m, 64);
+        b += __shfl_xor(b, m, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[2 * wv] = a; red[2 * wv + 1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0, B = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) { A += red[2 * k]; B += red[2 * k + 1]; }
+        out[q] = make_double2(A, mirror ? -B : B);
+    }
 }
 
-// y_k = sum_{i < nx} M[i * ny + k] x_i for k < ny, over tiles of GT elements:
-// the tile of every x_i is read into LDS before any output of the tile is
+// y_k = sum_{i < nx} M[i * ny + k] x_i for k < ny, one element per thread
+// with the nx inputs of the element in registers (nx <= XMAX), so y may be x
+// itself (ny == nx, in place); M is read from LDS, the outputs formed in
+// chunks of 8.
+template <int XMAX>
+__global__ __launch_bounds__(256) void transform_reg_kernel(size_t n, PtrList64 xs, int nx,
+                                                            const double2 *__restrict__ M, int ny, PtrList64 ys) {
+    extern __shared__ double2 tsm[];   // M [nx * ny]
+    for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) tsm[q] = M[q];
+    __syncthreads();
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        double2 xv[XMAX];
+#pragma unroll
+        for (int i = 0; i < XMAX; i++) xv[i] = i < nx ? ((const double2 *)xs.p[i])[e] : make_double2(0, 0);
+        for (int k0 = 0; k0 < ny; k0 += 8) {
+            double2 acc[8];
+#pragma unroll
+            for (int kk = 0; kk < 8; kk++) acc[kk] = make_double2(0, 0);
+#pragma unroll
+            for (int i = 0; i < XMAX; i++) {
+                if (i < nx) {
+#pragma unroll
+                    for (int kk = 0; kk < 8; kk++)
+                        if (k0 + kk < ny) cfma(acc[kk], tsm[i * ny + k0 + kk], xv[i]);
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; kk++)
+                if (k0 + kk < ny) ((double2 *)ys.p[k0 + kk])[e] = acc[kk];
+        }
+    }
+}
+
+// the same product for nx > 32, over tiles of GT elements through LDS: the
+// tile of every x_i is read into LDS before any output of the tile is
 // written, so y may be x itself (ny == nx, in place).
+constexpr int GT = 32;     // elements per tile
+
 __global__ __launch_bounds__(256) void transform_kernel(size_t n, PtrList64 xs, int nx, const double2 *__restrict__ M,
                                                         int ny, PtrList64 ys) {
     extern __shared__ double2 tsm[];
@@ -376,28 +431,50 @@ int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double
 
 int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const *ys, int ny, double2 *out) {
     if (nx < 1 || ny < 1 || nx > GMAX || ny > GMAX) return fail(c, MGDD_EINVAL, "gram: bad vector count");
-    const size_t ntile = (n + GT - 1) / GT;
-    const int nwg = (int)(ntile < 512 ? ntile : 512);
-    double2 *part = (double2 *)ensure_red(c, (size_t)2 * nwg * nx * ny + 16);
-    if (!part) return MGDD_ENOMEM;
     PtrList64 px{}, py{};
     for (int i = 0; i < nx; i++) px.p[i] = xs[i];
     for (int j = 0; j < ny; j++) py.p[j] = ys[j];
     int sym = nx == ny;
     for (int i = 0; i < nx && sym; i++) sym = xs[i] == ys[i];
-    gram_kernel<<<nwg, 256, 0, c->stream>>>(n, px, nx, py, ny, sym, part);
-    const int nq = nx * ny;
-    gram_finish_kernel<<<(nq + 255) / 256, 256, 0, c->stream>>>(nwg, nx, ny, sym, part, out);
+    // tile length: the loaded rows fill at most 40 KB of LDS
+    const int nload = sym ? nx : nx + ny;
+    int gt = 128;
+    while (gt > 8 && (size_t)nload * gt * sizeof(double2) > 40960) gt >>= 1;
+    const int tx = (nx + 3) / 4, ty = (ny + 3) / 4;
+    const int nblk = sym ? tx * (tx + 1) / 2 : tx * ty;
+    int ngroups = 1;
+    while (ngroups < 8 && 2 * ngroups * nblk <= 256) ngroups *= 2;
+    size_t lds = (size_t)nload * gt * sizeof(double2);
+    if (ngroups > 1 && (size_t)nblk * ngroups * 16 * sizeof(double2) > lds)
+        lds = (size_t)nblk * ngroups * 16 * sizeof(double2);
+    const size_t ntile = (n + gt - 1) / gt;
+    const int nwg = (int)(ntile < 2048 ? ntile : 2048);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * nwg * nx * ny + 16);
+    if (!part) return MGDD_ENOMEM;
+    gram_kernel<<<nwg, 256, lds, c->stream>>>(n, px, nx, py, ny, sym, gt, part);
+    gram_finish_kernel<<<nx * ny, 256, 0, c->stream>>>(nwg, nx, ny, sym, part, out);
     return hip_check(c, hipGetLastError(), "gram");
 }
 
 int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys) {
     if (nx < 1 || ny < 1 || nx > GMAX || ny > GMAX) return fail(c, MGDD_EINVAL, "transform: bad vector count");
-    const size_t ntile = (n + GT - 1) / GT;
-    const int nwg = (int)(ntile < 4096 ? ntile : 4096);
     PtrList64 px{}, py{};
     for (int i = 0; i < nx; i++) px.p[i] = xs[i];
     for (int j = 0; j < ny; j++) py.p[j] = ys[j];
+    if (nx <= 32) {
+        const size_t nb = (n + 255) / 256;
+        const int nwg = (int)(nb < 8192 ? nb : 8192);
+        const size_t lds = (size_t)nx * ny * sizeof(double2);
+        if (nx <= 16)
+            transform_reg_kernel<16><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+        else if (nx <= 24)
+            transform_reg_kernel<24><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+        else
+            transform_reg_kernel<32><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+        return hip_check(c, hipGetLastError(), "transform");
+    }
+    const size_t ntile = (n + GT - 1) / GT;
+    const int nwg = (int)(ntile < 4096 ? ntile : 4096);
     const size_t lds = ((size_t)nx * ny + (size_t)nx * GT) * sizeof(double2);
     transform_kernel<<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
     return hip_check(c, hipGetLastError(), "transform");

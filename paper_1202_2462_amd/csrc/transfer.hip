@@ -242,12 +242,13 @@ __global__ __launch_bounds__(TPB) void dc_terms_kernel(Geom g, AggGeom ag, const
     for (int c = 0; c < 12; c++) w0.st(c, d, csub(ap[c], cscale(self[c], 0.5)));
 }
 
-// One workgroup per (aggregate a, column j = (chi', k')), one thread per
-// site x of a: the thread forms the 9 terms of D applied to the prolonged unit
-// vector P e_j at x (self term: clover plus the hops that stay in a; one face
-// term per direction, nonzero on that face only), then projects all 9 on every
-// P_k(x) of both chiralities in one pass over P. Wave butterflies and one LDS
-// exchange sum over the sites. Block layout [a][dir][col][row].
+// Fallback for aggregates with an extent of 1 in some direction (a site then
+// lies on both faces of that direction): one workgroup per (aggregate a,
+// column j = (chi', k')), one thread per site x of a: the thread forms the 9
+// terms of D applied to the prolonged unit vector P e_j at x (self term:
+// clover plus the hops that stay in a; one face term per direction, nonzero
+// on that face only), then projects all 9 on every P_k(x) of both
+// chiralities in one pass over P. Block layout [a][dir][col][row].
 template <int MU, bool FWD>
 __device__ inline void term_hop(const LinkViews<double> &U, const FieldView<double> &pj, int chi, int d, int dn,
                                 double2 *acc) {
@@ -276,7 +277,7 @@ __device__ inline void term_into(const LinkViews<double> &U, const FieldView<dou
     }
 }
 
-__global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N, int Va, const int *__restrict__ agg_sites,
+__global__ __launch_bounds__(256) void dc_build_thin_kernel(Geom g, AggGeom ag, int N, int Va, const int *__restrict__ agg_sites,
                                                        const double2 *__restrict__ Up, const double2 *__restrict__ Ap,
                                                        const double2 *__restrict__ P, double2 *__restrict__ Dc,
                                                        int nwg) {
@@ -380,6 +381,181 @@ __global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N
         int rchi = i / N, k = i % N;
         const double *o = res + (size_t)k * 36 + t * 4;
         Dc[((size_t)a * 9 + t) * blk + (size_t)j * n2 + i] = make_double2(o[2 * rchi], o[2 * rchi + 1]);
+    }
+}
+
+// D_c for aggregates of at most 256 sites with every extent >= 2: one
+// workgroup per (aggregate a, column j = (chi', k'), row chirality h), one
+// thread per site x of a. With extents >= 2 a site lies on at most one face
+// per direction, so the thread keeps five 6-component terms: the h half of
+// the self term (clover block h on P_j, which is zero unless h = chi', minus
+// 1/2 the hops that stay in a) and, per direction mu, the h half of -1/2 the
+// hop that leaves a through the face the site lies on (zero inside). For
+// each k the products with the h half of P_k(x) give 10 partial sums per
+// thread; each wave spreads them into its 18 sums (self, + face and - face of
+// each direction, re and im) through a wave-private LDS tile, read back by 54
+// lanes in three fixed row ranges, so the k loop has no workgroup barrier.
+// The per-wave sums are added in wave order at the end.
+constexpr int DCB_COLS = 18;   // per-wave sums for one k
+constexpr int DCB_LD = 65;     // tile row length in doubles (64 lanes + 1: no bank conflicts)
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one hop of D on P_j (test vector restricted to chirality chi), all 12
+// components, without the factor -1/2
+template <int MU, bool FWD>
+__device__ inline void col_hop(const LinkViews<double> &U, const FieldView<double> &pj, int chi, int d, int dn,
+                               double2 *t) {
+    double2 psi[12], u[9];
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        t[c] = make_double2(0, 0);
+        psi[c] = ((c >= 6) == (chi != 0)) ? pj.ld(c, dn) : make_double2(0, 0);
+    }
+    load_link<double, MU>(U, FWD ? d : dn, u);
+    hop<double, MU, FWD>(t, u, psi);
+}
+
+// both hops of direction MU: the one that leaves the aggregate (at most one
+// when the extent is >= 2) into face, the others into self (h halves)
+template <int MU>
+__device__ inline void col_dir(const LinkViews<double> &U, const FieldView<double> &pj, int chi, int h, int d,
+                               const int *nbr, bool last, bool first, double2 *self, double2 *face) {
+    double2 t[12];
+    col_hop<MU, true>(U, pj, chi, d, nbr[2 * MU], t);
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        const double2 v = h ? t[6 + c] : t[c];
+        if (last) face[c] = cscale(v, -0.5);
+        else self[c] = cadd(self[c], v);
+    }
+    col_hop<MU, false>(U, pj, chi, d, nbr[2 * MU + 1], t);
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        const double2 v = h ? t[6 + c] : t[c];
+        if (first) face[c] = cscale(v, -0.5);
+        else self[c] = cadd(self[c], v);
+    }
+}
+
+__global__ __launch_bounds__(256) void dc_build_kernel(Geom g, AggGeom ag, int N, int Va, const int *__restrict__ agg_sites,
+                                                       const double2 *__restrict__ Up, const double2 *__restrict__ Ap,
+                                                       const double2 *__restrict__ P, double2 *__restrict__ Dc,
+                                                       int nwg) {
+    extern __shared__ double dsm[];
+    const int n2 = 2 * N;
+    const int w = xcd_block(nwg);
+    const int h = w & 1, j = (w >> 1) % n2, a = (w >> 1) / n2, chi = j / N, kk = j % N;
+    const size_t V = g.V;
+    const int l = threadIdx.x, lane = l & 63, wave = l >> 6, nw = blockDim.x >> 6;
+    const bool active = l < Va;
+    double2 wt[5][6];
+#pragma unroll
+    for (int s = 0; s < 5; s++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) wt[s][c] = make_double2(0, 0);
+    bool last[4] = {false, false, false, false}, first[4] = {false, false, false, false};
+    int d = 0;
+    if (active) {
+        d = agg_sites[(size_t)a * Va + l];
+        int X[4], nbr[8];
+        site_coords(g, d, X);
+        site_neighbours(g, d, nbr);
+        LinkViews<double> U(Up, V);
+        FieldView<double> pj(P + (size_t)kk * 12 * V, V, 12);
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const int r = X[m] % ag.a[m];
+            last[m] = r == ag.a[m] - 1;   // the +m hop leaves the aggregate
+            first[m] = r == 0;            // the -m hop leaves the aggregate
+        }
+        double2 self[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) self[c] = make_double2(0, 0);
+        col_dir<0>(U, pj, chi, h, d, nbr, last[0], first[0], self, wt[1]);
+        col_dir<1>(U, pj, chi, h, d, nbr, last[1], first[1], self, wt[2]);
+        col_dir<2>(U, pj, chi, h, d, nbr, last[2], first[2], self, wt[3]);
+        col_dir<3>(U, pj, chi, h, d, nbr, last[3], first[3], self, wt[4]);
+        double2 ap[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) ap[c] = make_double2(0, 0);
+        if (h == chi) {   // the clover term is block diagonal in chirality
+            FieldView<double> ab(Ap + (size_t)h * 18 * V, V, 18);   // packed block h
+            double2 pa[18], in[6];
+#pragma unroll
+            for (int q = 0; q < 18; q++) pa[q] = ab.ld(q, d);
+#pragma unroll
+            for (int c = 0; c < 6; c++) in[c] = pj.ld(6 * h + c, d);
+            herm6_mv<double>(pa, in, ap);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) wt[0][c] = csub(ap[c], cscale(self[c], 0.5));
+    }
+    double *tile = dsm + (size_t)wave * DCB_COLS * DCB_LD;   // [18][65], this wave only
+    double *outw = dsm + (size_t)nw * DCB_COLS * DCB_LD;     // [N][nw][18]
+    const int col = lane % DCB_COLS, part = lane / DCB_COLS, r0 = 22 * part;
+    double2 pk[6];
+    {
+        FieldView<double> f0(P, V, 12);
+#pragma unroll
+        for (int c = 0; c < 6; c++) pk[c] = active ? f0.ld(6 * h + c, d) : make_double2(0, 0);
+    }
+    for (int k = 0; k < N; k++) {
+        double2 pn[6];
+        const bool more = active && k + 1 < N;
+        FieldView<double> fn(P + (size_t)(more ? k + 1 : k) * 12 * V, V, 12);
+#pragma unroll
+        for (int c = 0; c < 6; c++) pn[c] = more ? fn.ld(6 * h + c, d) : make_double2(0, 0);
+        double s[5][2];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                re += pk[c].x * wt[q][c].x + pk[c].y * wt[q][c].y;
+                im += pk[c].x * wt[q][c].y - pk[c].y * wt[q][c].x;
+            }
+            s[q][0] = re;
+            s[q][1] = im;
+        }
+        tile[0 * DCB_LD + lane] = s[0][0];
+        tile[1 * DCB_LD + lane] = s[0][1];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            tile[(2 + 4 * m) * DCB_LD + lane] = last[m] ? s[1 + m][0] : 0.0;
+            tile[(3 + 4 * m) * DCB_LD + lane] = last[m] ? s[1 + m][1] : 0.0;
+            tile[(4 + 4 * m) * DCB_LD + lane] = first[m] ? s[1 + m][0] : 0.0;
+            tile[(5 + 4 * m) * DCB_LD + lane] = first[m] ? s[1 + m][1] : 0.0;
+        }
+        wave_sync();
+        double acc = 0;
+        if (lane < 3 * DCB_COLS) {
+#pragma unroll
+            for (int q = 0; q < 22; q++)
+                if (r0 + q < 64) acc += tile[col * DCB_LD + r0 + q];
+        }
+        const double a1 = __shfl(acc, lane + DCB_COLS, 64), a2 = __shfl(acc, lane + 2 * DCB_COLS, 64);
+        if (lane < DCB_COLS) outw[((size_t)k * nw + wave) * DCB_COLS + lane] = (acc + a1) + a2;
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < 6; c++) pk[c] = pn[c];
+    }
+    __syncthreads();
+    const size_t blk = (size_t)n2 * n2;
+    for (int e = threadIdx.x; e < 9 * N; e += blockDim.x) {
+        const int t = e / N, k = e % N;
+        const int c0 = t == 0 ? 0 : 2 + 2 * (t - 1);   // + face of mu: 2 + 4 mu, - face: 4 + 4 mu
+        double re = 0, im = 0;
+        for (int q = 0; q < nw; q++) {
+            const double *o = outw + ((size_t)k * nw + q) * DCB_COLS + c0;
+            re += o[0];
+            im += o[1];
+        }
+        Dc[((size_t)a * 9 + t) * blk + (size_t)j * n2 + (size_t)h * N + k] = make_double2(re, im);
     }
 }
 
@@ -636,16 +812,27 @@ int launch_coarse_build(Ctx *c) {
     Level1 &L1 = c->c;
     const Geom &g = c->g;
     const int N = L1.N, n2 = 2 * N;
+    bool thin = false;
+    for (int m = 0; m < 4; m++) thin = thin || L1.agg[m] < 2;
     if (L1.Va <= 256) {
         AggGeom ag{};
         for (int m = 0; m < 4; m++) ag.a[m] = L1.agg[m];
         int threads = ((L1.Va + 63) / 64) * 64;
-        int nwg = L1.Vc * n2;
-        const int S = threads / 36 > 0 ? threads / 36 : 1;
-        size_t lds = ((size_t)36 * threads + 36 * S + (size_t)36 * N) * sizeof(double);
-        dc_build_kernel<<<nwg, threads, lds, c->stream>>>(g, ag, N, L1.Va, L1.agg_sites, (const double2 *)c->U64,
-                                                           (const double2 *)c->A64, (const double2 *)L1.P64,
-                                                           (double2 *)L1.Dc64, nwg);
+        if (!thin) {
+            const int nwg = L1.Vc * n2 * 2;
+            const size_t lds = ((size_t)(threads / 64) * DCB_COLS * DCB_LD + (size_t)N * (threads / 64) * DCB_COLS) *
+                               sizeof(double);
+            dc_build_kernel<<<nwg, threads, lds, c->stream>>>(g, ag, N, L1.Va, L1.agg_sites, (const double2 *)c->U64,
+                                                               (const double2 *)c->A64, (const double2 *)L1.P64,
+                                                               (double2 *)L1.Dc64, nwg);
+        } else {
+            const int nwg = L1.Vc * n2;
+            const int S = threads / 36 > 0 ? threads / 36 : 1;
+            size_t lds = ((size_t)36 * threads + 36 * S + (size_t)36 * N) * sizeof(double);
+            dc_build_thin_kernel<<<nwg, threads, lds, c->stream>>>(g, ag, N, L1.Va, L1.agg_sites,
+                                                                    (const double2 *)c->U64, (const double2 *)c->A64,
+                                                                    (const double2 *)L1.P64, (double2 *)L1.Dc64, nwg);
+        }
         int rc = hip_check(c, hipGetLastError(), "D_c build kernel");
         if (rc) return rc;
         size_t n = (size_t)L1.Vc * 9 * n2 * n2;

@@ -12,11 +12,13 @@ from oracle import solvers
 pytestmark = pytest.mark.gpu
 
 # (lattice, SAP block, aggregate, N): coarse extents 2 (the +/- neighbours
-# coincide), 1 and 2 mixed, and 4
+# coincide), 1 and 2 mixed, and 4; the last aggregate has an extent of 1 (each
+# of its sites lies on both faces of that direction)
 CASES = [
     ((8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 4, 4), 8),
     ((8, 8, 4, 8), (4, 4, 4, 4), (4, 4, 4, 2), 6),
     ((8, 8, 8, 8), (4, 4, 4, 4), (2, 2, 2, 2), 4),
+    ((8, 8, 8, 8), (4, 4, 4, 4), (4, 2, 1, 4), 4),
 ]
 
 

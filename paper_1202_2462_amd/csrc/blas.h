@@ -19,6 +19,11 @@ int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int n
 // y_s = beta y_s + alpha sum_i coef[i * nseg + s] x_i,s   (coef on the device)
 int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nvec, const double2 *coef, double alpha,
                  double beta, void *y, int nseg = 1);
+// y_s <- y_s - sum_i coef[i * nseg + s] x_i,s (same precision p for all), then
+// out[i * nseg + s] = <x_i, y>_s, or out[s] = ||y_s||^2 when norm_only;
+// nvec <= MAXV. The update is blas_lincomb's; the sums are deterministic.
+int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                    double2 *out, int norm_only, int nseg = 1);
 // y_s = (coef ? coef[s] * alpha : alpha) x_s   (x and y may alias)
 int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y,
                int nseg = 1);

@@ -112,6 +112,64 @@ __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int 
     }
 }
 
+// y <- y - sum_i coef[i * nseg + s] x_i, then the partial sums of the new y
+// against every x_i (or of ||y||^2 when norm_only) per workgroup into part,
+// laid out as multidot's: one pass over the x_i instead of a lincomb and a
+// multidot (the two later passes of classical Gram-Schmidt with one
+// re-orthogonalisation). The update arithmetic is that of lincomb_kernel.
+template <typename T, int NV>
+__global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, int nvec,
+                                                         const double2 *__restrict__ coef, C<T> *__restrict__ y,
+                                                         int norm_only, double2 *__restrict__ part) {
+    __shared__ double red[TPB / 64][2 * NV];
+    double2 c[NV], acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        c[i] = i < nvec ? cscale(coef[(size_t)i * gridDim.y + blockIdx.y], -1.0) : make_double2(0, 0);
+        acc[i] = make_double2(0, 0);
+    }
+    const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
+        C<T> yv = y[so + e];
+        double2 u = make_double2(1.0 * (double)yv.x, 1.0 * (double)yv.y);
+        double2 xv[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            if (i < nvec) {
+                const C<T> x = ((const C<T> *)xs.p[i])[so + e];
+                xv[i] = make_double2((double)x.x, (double)x.y);
+                cfma(u, c[i], xv[i]);
+            }
+        }
+        const C<T> un = mk<T>((T)u.x, (T)u.y);
+        y[so + e] = un;
+        const double2 ud = make_double2((double)un.x, (double)un.y);
+        if (norm_only) {
+            cfmac(acc[0], ud, ud);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                if (i < nvec) cfmac(acc[i], xv[i], ud);
+        }
+    }
+    const int nout = norm_only ? 1 : nvec;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        if (i < nout) {
+            double a = wave_sum(acc[i].x), b = wave_sum(acc[i].y);
+            if (lane == 0) { red[wv][2 * i] = a; red[wv][2 * i + 1] = b; }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nout) {
+        int i = threadIdx.x;
+        double a = 0, b = 0;
+        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * i]; b += red[k][2 * i + 1]; }
+        part[((size_t)i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
+    }
+}
+
 // y = s * x with s = alpha * coef[0] (coef on the device), or
 // s = alpha / sqrt(re nrm2[0]) (0 when that is 0) when inv_norm, or s = alpha
 // when coef == nullptr; x and y may alias
@@ -314,7 +372,32 @@ __global__ __launch_bounds__(256) void transform_reg_kernel(size_t n, PtrList64 
     }
 }
 
-// the same product for nx > 32, over tiles of GT elements through LDS: the
+// the same product when no y_k is one of the x_i: one element per thread
+// with the ny <= YMAX outputs in registers, the inputs streamed once
+template <int YMAX>
+__global__ __launch_bounds__(256) void transform_stream_kernel(size_t n, PtrList64 xs, int nx,
+                                                               const double2 *__restrict__ M, int ny, PtrList64 ys) {
+    extern __shared__ double2 tsm[];   // M [nx * ny]
+    for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) tsm[q] = M[q];
+    __syncthreads();
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        double2 acc[YMAX];
+#pragma unroll
+        for (int k = 0; k < YMAX; k++) acc[k] = make_double2(0, 0);
+#pragma unroll 4
+        for (int i = 0; i < nx; i++) {
+            const double2 x = ((const double2 *)xs.p[i])[e];
+#pragma unroll
+            for (int k = 0; k < YMAX; k++)
+                if (k < ny) cfma(acc[k], tsm[i * ny + k], x);
+        }
+#pragma unroll
+        for (int k = 0; k < YMAX; k++)
+            if (k < ny) ((double2 *)ys.p[k])[e] = acc[k];
+    }
+}
+
+// the same product for nx > 40, over tiles of GT elements through LDS: the
 // tile of every x_i is read into LDS before any output of the tile is
 // written, so y may be x itself (ny == nx, in place).
 constexpr int GT = 32;     // elements per tile
@@ -407,6 +490,26 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
     return MGDD_OK;
 }
 
+int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                    double2 *out, int norm_only, int nseg) {
+    if (nvec < 1 || nvec > MAXV) return fail(c, MGDD_EINVAL, "update_dot: bad vector count");
+    // about two elements per thread: every load of the update in flight at once
+    size_t g = (n + 2 * TPB - 1) / (2 * TPB);
+    const int nwg = (int)(g > 4096 ? 4096 : g < 1 ? 1 : g);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * MAXV * nseg * nwg + 16);
+    if (!part) return MGDD_ENOMEM;
+    PtrList pl{};
+    for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
+    dim3 grid(nwg, nseg);
+    if (p == MGDD_F64)
+        update_dot_kernel<double, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (double2 *)y, norm_only, part);
+    else
+        update_dot_kernel<float, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (float2 *)y, norm_only, part);
+    const int nout = norm_only ? 1 : nvec;
+    finish_kernel<<<nout * nseg, 64, 0, c->stream>>>(nwg, part, out);
+    return hip_check(c, hipGetLastError(), "update_dot");
+}
+
 static int scale_launch(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha,
                         int inv_norm, void *y, int nseg) {
     dim3 grid(lin_grid(n), nseg);
@@ -461,22 +564,31 @@ int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double
     PtrList64 px{}, py{};
     for (int i = 0; i < nx; i++) px.p[i] = xs[i];
     for (int j = 0; j < ny; j++) py.p[j] = ys[j];
-    if (nx <= 32) {
-        const size_t nb = (n + 255) / 256;
-        const int nwg = (int)(nb < 8192 ? nb : 8192);
-        const size_t lds = (size_t)nx * ny * sizeof(double2);
+    bool alias = false;
+    for (int i = 0; i < nx; i++)
+        for (int j = 0; j < ny; j++) alias = alias || xs[i] == ys[j];
+    const size_t nb = (n + 255) / 256;
+    const int nwg = (int)(nb < 8192 ? nb : 8192);
+    const size_t lds = (size_t)nx * ny * sizeof(double2);
+    if (!alias && ny <= 24) {   // outputs in registers, inputs streamed
+        transform_stream_kernel<24><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+        return hip_check(c, hipGetLastError(), "transform");
+    }
+    if (nx <= 40) {   // inputs in registers (in place allowed)
         if (nx <= 16)
             transform_reg_kernel<16><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
         else if (nx <= 24)
             transform_reg_kernel<24><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
-        else
+        else if (nx <= 32)
             transform_reg_kernel<32><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+        else
+            transform_reg_kernel<40><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
         return hip_check(c, hipGetLastError(), "transform");
     }
     const size_t ntile = (n + GT - 1) / GT;
-    const int nwg = (int)(ntile < 4096 ? ntile : 4096);
-    const size_t lds = ((size_t)nx * ny + (size_t)nx * GT) * sizeof(double2);
-    transform_kernel<<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+    const int nwt = (int)(ntile < 4096 ? ntile : 4096);
+    const size_t ldt = ((size_t)nx * ny + (size_t)nx * GT) * sizeof(double2);
+    transform_kernel<<<nwt, 256, ldt, c->stream>>>(n, px, nx, M, ny, py);
     return hip_check(c, hipGetLastError(), "transform");
 }
 

@@ -125,6 +125,14 @@ static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2
     // short vectors (the coarse level): three fused passes, launch count
     // matters more than bandwidth there
     if (k <= FUSED_CGS2_MAX && n <= (size_t)1 << 18) return fused_cgs2(c, p, n, nb, V, k, w, h1, h2, nrm);
+    // long vectors: the update of each pass and the dot products that follow
+    // it share one pass over V
+    if (k <= MAXV) {
+        int rc = blas_multidot(c, p, p, n, V, k, w, h1, nb);
+        if (!rc) rc = blas_update_dot(c, p, n, V, k, h1, w, h2, 0, nb);
+        if (!rc) rc = blas_update_dot(c, p, n, V, k, h2, w, nrm, 1, nb);
+        return rc;
+    }
     int rc = blas_multidot(c, p, p, n, V, k, w, h1, nb);
     if (!rc) rc = blas_lincomb(c, p, p, n, V, k, h1, -1.0, 1.0, w, nb);
     if (!rc) rc = blas_multidot(c, p, p, n, V, k, w, h2, nb);

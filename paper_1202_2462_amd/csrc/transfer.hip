@@ -92,6 +92,81 @@ __global__ __launch_bounds__(TPB) void build_P_kernel(int V, int Va, int N, cons
     }
 }
 
+// The same orthonormalisation for aggregates of at most TPB sites, one thread
+// per site holding the 6 components of the column being orthonormalised in
+// registers: each step loads one earlier column once, and each sum over the
+// block takes one barrier (two alternating LDS slots). Per-thread sums, the
+// butterfly and the order over waves are those of build_P_kernel.
+__device__ inline double2 block_sum2_1(double a, double b, double *red) {
+    a = wsum(a);
+    b = wsum(b);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+    __syncthreads();
+    double A = 0, B = 0;
+    for (int i = 0; i < nw; i++) { A += red[2 * i]; B += red[2 * i + 1]; }
+    return make_double2(A, B);
+}
+
+__global__ __launch_bounds__(TPB) void build_P_reg_kernel(int V, int Va, int N, const int *__restrict__ agg_sites,
+                                                          double2 *__restrict__ P, int *__restrict__ flag) {
+    __shared__ double red[2][2 * (TPB / 64)];
+    const int a = blockIdx.x, chi = blockIdx.y;
+    const bool active = (int)threadIdx.x < Va;
+    const int d = active ? agg_sites[(size_t)a * Va + threadIdx.x] : 0;
+    const size_t fs = (size_t)12 * V;  // field stride
+    int slot = 0;
+    for (int k = 0; k < N; k++) {
+        double2 *wp = P + (size_t)k * fs;
+        double2 w[6];
+        double n0 = 0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            w[c] = active ? wp[(size_t)(6 * chi + c) * V + d] : make_double2(0, 0);
+            n0 += w[c].x * w[c].x + w[c].y * w[c].y;
+        }
+        n0 = block_sum2_1(n0, 0, red[slot]).x;
+        slot ^= 1;
+        double2 q[6], qn[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) q[c] = active && k > 0 ? P[(size_t)(6 * chi + c) * V + d] : make_double2(0, 0);
+        for (int j = 0; j < k; j++) {
+            // prefetch column j + 1 while column j is used
+            const double2 *qp = P + (size_t)(j + 1 < k ? j + 1 : j) * fs;
+#pragma unroll
+            for (int c = 0; c < 6; c++) qn[c] = active ? qp[(size_t)(6 * chi + c) * V + d] : make_double2(0, 0);
+            double ra = 0, rb = 0;
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                ra += q[c].x * w[c].x + q[c].y * w[c].y;
+                rb += q[c].x * w[c].y - q[c].y * w[c].x;
+            }
+            const double2 r = block_sum2_1(ra, rb, red[slot]);
+            slot ^= 1;
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                w[c] = csub(w[c], cmul(r, q[c]));
+                q[c] = qn[c];
+            }
+        }
+        double nn = 0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) nn += w[c].x * w[c].x + w[c].y * w[c].y;
+        nn = block_sum2_1(nn, 0, red[slot]).x;
+        slot ^= 1;
+        double rkk = sqrt(nn);
+        if (!(rkk > 1e-12 * sqrt(n0)) || n0 == 0.0) {
+            if (threadIdx.x == 0) atomicExch(flag, 1);
+            rkk = 1.0;
+        }
+        const double inv = 1.0 / rkk;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) wp[(size_t)(6 * chi + c) * V + d] = cscale(w[c], inv);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- restriction c = P^H f
 //
 // One workgroup per (aggregate, field). out[a * ostride + r * rstride + chi * N + k].
@@ -764,7 +839,11 @@ int launch_build_P(Ctx *c, const void *tv64) {
     if (!flag) return MGDD_ENOMEM;
     rc = hip_check(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream), "memset");
     if (rc) return rc;
-    build_P_kernel<<<dim3(L1.Vc, 2), TPB, 0, c->stream>>>(g.V, L1.Va, L1.N, L1.agg_sites, (double2 *)L1.P64, flag);
+    if (L1.Va <= TPB)
+        build_P_reg_kernel<<<dim3(L1.Vc, 2), TPB, 0, c->stream>>>(g.V, L1.Va, L1.N, L1.agg_sites, (double2 *)L1.P64,
+                                                                  flag);
+    else
+        build_P_kernel<<<dim3(L1.Vc, 2), TPB, 0, c->stream>>>(g.V, L1.Va, L1.N, L1.agg_sites, (double2 *)L1.P64, flag);
     rc = hip_check(c, hipGetLastError(), "build_P kernel");
     if (rc) return rc;
     int hflag = 0;

@@ -121,6 +121,18 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
     const size_t so = (size_t)sg * n;
     __shared__ double2 coef[NV];
     __shared__ double red[TPB / 64][2 * NV];
+    // the thread's first element (the only one when G * TPB >= n) is loaded
+    // before the coefficients are summed: both loads are in flight together
+    const size_t e0 = (size_t)g * TPB + threadIdx.x;
+    C<T> y0 = mk<T>(0, 0), v0[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) v0[k] = mk<T>(0, 0);
+    if (e0 < n) {
+        y0 = y[so + e0];
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            if (k < nk) v0[k] = ((const C<T> *)V.p[k])[so + e0];
+    }
     // pin is laid out [k][segment][partial]. One wave per coefficient (wave
     // w takes k = w and w + 8): lane u adds the partials u, u + 64, ...
     // (four independent loads at a time), then a butterfly.
@@ -151,16 +163,11 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
     double2 acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; k++) acc[k] = make_double2(0, 0);
-    for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
-        C<T> yv = y[so + e];
+    auto element = [&](size_t e, const C<T> yv, const C<T> *vv) {
         double2 r = make_double2((double)yv.x, (double)yv.y);
 #pragma unroll
-        for (int k = 0; k < NV; k++) {
-            if (k < nk) {
-                C<T> v = ((const C<T> *)V.p[k])[so + e];
-                cfma(r, cneg(coef[k]), make_double2((double)v.x, (double)v.y));
-            }
-        }
+        for (int k = 0; k < NV; k++)
+            if (k < nk) cfma(r, cneg(coef[k]), make_double2((double)vv[k].x, (double)vv[k].y));
         const C<T> rt = mk<T>((T)r.x, (T)r.y);
         y[so + e] = rt;
         const double2 rd = make_double2((double)rt.x, (double)rt.y);
@@ -168,13 +175,16 @@ __global__ __launch_bounds__(TPB) void arnoldi_orth_kernel(size_t n, VecList V, 
             acc[0].x += rd.x * rd.x + rd.y * rd.y;
         } else {
 #pragma unroll
-            for (int k = 0; k < NV; k++) {
-                if (k < nk) {   // second read of v_k (a cache hit)
-                    C<T> v = ((const C<T> *)V.p[k])[so + e];
-                    cfmac(acc[k], make_double2((double)v.x, (double)v.y), rd);
-                }
-            }
+            for (int k = 0; k < NV; k++)
+                if (k < nk) cfmac(acc[k], make_double2((double)vv[k].x, (double)vv[k].y), rd);
         }
+    };
+    if (e0 < n) element(e0, y0, v0);
+    for (size_t e = e0 + (size_t)G * TPB; e < n; e += (size_t)G * TPB) {
+        C<T> vv[NV];
+#pragma unroll
+        for (int k = 0; k < NV; k++) vv[k] = k < nk ? ((const C<T> *)V.p[k])[so + e] : mk<T>(0, 0);
+        element(e, y[so + e], vv);
     }
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll

@@ -419,8 +419,11 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
     for (int i = 0; i < m; i++) Z[i] = A.take(nn * cs);
     void *w = A.take(nn * 16), *r = A.take(nn * 16);
     void *z64 = p == MGDD_F32 ? A.take(nn * 16) : nullptr;
-    double2 *h1 = (double2 *)A.take((size_t)(m + 1) * nb * 16), *h2 = (double2 *)A.take((size_t)(m + 1) * nb * 16);
-    double2 *nr = (double2 *)A.take((size_t)nb * 16), *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
+    // h1, h2 and the norms side by side, in the order of their pinned host
+    // copies, so that each Arnoldi step reads them back in one copy
+    double2 *h1 = (double2 *)A.take((size_t)(2 * (m + 1) + 1) * nb * 16);
+    double2 *h2 = h1 ? h1 + (size_t)(m + 1) * nb : nullptr, *nr = h1 ? h2 + (size_t)(m + 1) * nb : nullptr;
+    double2 *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
     double2 *pm = (double2 *)A.take((size_t)2 * nb * 16);
     if (!pm) return fail(c, MGDD_ENOMEM, "FGMRES workspace");
     // pinned scalars: [pm 2nb | h1 (m+1)nb | h2 (m+1)nb | norms nb | coefficients (m+1)nb]
@@ -511,9 +514,7 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
             }
             if (!rc) rc = cgs2(c, MGDD_F64, n, V.data(), j + 1, w, h1, h2, nr, nb);
             if (rc) return rc;
-            rc = hip_check(c, hipMemcpyAsync(Hb1, h1, (size_t)(j + 1) * nb * 16, hipMemcpyDeviceToHost, c->stream), "read");
-            if (!rc) rc = hip_check(c, hipMemcpyAsync(Hb2, h2, (size_t)(j + 1) * nb * 16, hipMemcpyDeviceToHost, c->stream), "read");
-            if (!rc) rc = read_dev(c, nr, nb, Nb);
+            rc = read_dev(c, h1, (size_t)(2 * (m + 1) + 1) * nb, Hb1);   // h1, h2 and the norms
             if (rc) return rc;
             kmax = j + 1;
             bool more = false;

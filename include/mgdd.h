@@ -85,6 +85,8 @@ typedef struct mgdd_ctx mgdd_ctx;
  * by the device site order: every b_mu a power of two >= 2 dividing L_mu,
  * and the number of blocks L_mu/b_mu even or 1 in every direction (a
  * two-colouring in which no two neighbouring blocks share a colour).
+ * The volume is at most 14 913 080 sites (device arrays are addressed with
+ * 32-bit byte offsets, 288 bytes per site at most; 48^3 x 96 fits).
  * hip_stream: a hipStream_t (NULL = the default stream). *out receives the
  * context. Errors: MGDD_ESHAPE, MGDD_EINVAL, MGDD_EHIP. */
 int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ctx **out);

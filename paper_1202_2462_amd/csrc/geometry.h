@@ -111,7 +111,10 @@ inline std::string geometry_tables(const int *dims, const int *block, Geom &g, s
         g.nb[mu] = nb;
     }
     long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-    if (V >= (1LL << 31)) return "lattice too large";
+    // the kernels address a per-site array with 32-bit byte offsets; the
+    // largest are 288 bytes per site (links or clover blocks of all
+    // directions in FP32, one chirality's clover block in FP64)
+    if (V * 288 >= (1LL << 32)) return "lattice too large (at most 14 913 080 sites)";
     g.V = (int)V;
     g.Vb = block[0] * block[1] * block[2] * block[3];
     g.lgVb = ilog2(g.Vb);

@@ -107,6 +107,8 @@ int main() {
         {{8, 8, 8, 16}, {2, 2, 2, 2}, true},  {{24, 8, 8, 8}, {4, 4, 4, 4}, true},
         {{8, 8, 8, 8}, {3, 4, 4, 4}, false},  {{8, 8, 8, 8}, {1, 4, 4, 4}, false},
         {{12, 8, 8, 8}, {4, 4, 4, 4}, false},
+        // the largest workload lattice, and one past the 32-bit offset limit
+        {{48, 48, 48, 96}, {4, 4, 4, 4}, true}, {{64, 64, 64, 64}, {4, 4, 4, 4}, false},
     };
     int bad = 0;
     for (const Case &c : cases) {

@@ -1,0 +1,117 @@
+"""GPU parity on the largest workload lattice, 48^3 x 96, in the launch
+configurations its solve uses: the Wilson-clover apply (FP64 and FP32) and
+one FP32 Schwarz sweep with 4 MR steps on 4^4 blocks, element by element over
+the whole lattice.
+
+The gauge field is the 16^3 x 32 workload field repeated three times in every
+direction, and each input is a 16^3 x 32 Gaussian field repeated the same way
+with the sign (-1)^k on the k-th copy in t. The operator maps such fields to
+fields of the same form: the small lattice's antiperiodic sign sits on the
+hops across t = 31 -> 0, the large lattice's only on the hops across
+t = 95 -> 0, and the copies' alternating signs supply it on the inner copy
+boundaries (three copies, so the outermost ones carry the same sign). The
+clover term is built from closed loops and repeats with the links. With an
+even number of 4^4 blocks per copy and direction, the blocks and their colours
+repeat as well, and inside a block the MR iteration is odd in the residual
+(its step length is unchanged when the residual changes sign), so the sweep
+also commutes with the repetition. The oracle's result on 16^3 x 32,
+repeated with the signs, is therefore the exact expected result on 48^3 x 96:
+a full-size comparison whose host work is that of the small lattice."""
+import numpy as np
+import pytest
+
+import latgen
+from gpu_common import TOL32, TOL64, rel, say
+from oracle.solvers import Operator
+
+SMALL = (16, 16, 16, 32)
+REPS = 3
+BIG = tuple(REPS * L for L in SMALL)
+M0 = -0.2   # any mass: these are operator applications
+
+
+def repeat_links(U, small=SMALL):
+    U4 = U.reshape(small[3], small[2], small[1], small[0], 4, 3, 3)
+    return np.ascontiguousarray(np.tile(U4, (REPS, REPS, REPS, REPS, 1, 1, 1)).reshape(-1, 4, 3, 3))
+
+
+def repeat_spinor(psi, small=SMALL):
+    """(V_small, 4, 3) -> (V_big, 4, 3) with the sign (-1)^k on the k-th copy in t"""
+    p4 = psi.reshape(small[3], small[2], small[1], small[0], 4, 3)
+    big = np.tile(p4, (REPS, REPS, REPS, REPS, 1, 1))
+    sign = np.where((np.arange(REPS * small[3]) // small[3]) % 2 == 1, -1.0, 1.0)
+    big *= sign[:, None, None, None, None, None]
+    return big.reshape(-1, 4, 3)
+
+
+def test_repetition_commutes_with_the_oracle():
+    """the premise, on the CPU: on 4^3 x 8 repeated to 12^3 x 24 (2^4 blocks,
+    an even number per copy and direction) the oracle's apply and Schwarz
+    sweep on the repeated inputs equal the repeated results"""
+    small = (4, 4, 4, 8)
+    big = tuple(REPS * L for L in small)
+    U = latgen.gauge_field(small, 0.5, 41)
+    op_s = Operator(small, U, M0, 1.0)
+    op_b = Operator(big, repeat_links(U, small), M0, 1.0)
+    psi = latgen.gaussian_fields(small, 1, 42)[0]
+    assert rel(op_b.apply(repeat_spinor(psi, small)), repeat_spinor(op_s.apply(psi), small)) < 1e-13
+    blk = (2, 2, 2, 2)
+    want = repeat_spinor(op_s.sap(blk, psi, np.zeros_like(psi), 1, 4), small)
+    x = repeat_spinor(psi, small)
+    got = op_b.sap(blk, x, np.zeros_like(x), 1, 4)
+    assert rel(got, want) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def c3():
+    from paper_1202_2462_amd.mgdd import Lattice
+    w = latgen.WORKLOADS["c1"]
+    say("generating the 16^3 x 32 gauge field")
+    U = latgen.workload_gauge("c1")
+    op = Operator(SMALL, U, M0, w["csw"])
+    say("48^3 x 96 lattice from the field repeated three times per direction")
+    lat = Lattice(BIG, w["block"])
+    lat.set_gauge(repeat_links(U), M0, w["csw"])
+    yield op, lat
+    lat.close()
+
+
+def test_c3_repetition_of_the_inputs():
+    """the construction itself: the repeated field has the big lattice's
+    volume, each t copy is the small field times its sign"""
+    psi = latgen.gaussian_fields(SMALL, 1, 31)[0]
+    big = repeat_spinor(psi).reshape(BIG[3], BIG[2], BIG[1], BIG[0], 4, 3)
+    small = psi.reshape(SMALL[3], SMALL[2], SMALL[1], SMALL[0], 4, 3)
+    assert big.shape[0] * big.shape[1] * big.shape[2] * big.shape[3] == int(np.prod(BIG))
+    for k in range(REPS):
+        blk = big[k * SMALL[3]:(k + 1) * SMALL[3], 16:32, 32:48, 0:16]
+        assert np.array_equal(blk, (-1) ** k * small)
+
+
+@pytest.mark.gpu
+def test_c3_dirac_full_lattice(c3):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    op, lat = c3
+    psi = latgen.gaussian_fields(SMALL, 1, 32)[0]
+    want = repeat_spinor(op.apply(psi))
+    x = repeat_spinor(psi)[None]
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        say("48^3x96 Wilson-clover apply, precision", prec)
+        got = lat.unpack(lat.dirac(lat.pack(x, prec)))[0]
+        assert rel(got, want) < tol, (prec, rel(got, want))
+        assert np.max(np.abs(got - want)) < 50 * tol * np.max(np.abs(want))
+
+
+@pytest.mark.gpu
+def test_c3_schwarz_sweep_full_lattice(c3):
+    from paper_1202_2462_amd.mgdd import F32
+    op, lat = c3
+    w = latgen.WORKLOADS["c3"]
+    b = latgen.gaussian_fields(SMALL, 1, 33)[0]
+    say("oracle Schwarz sweep on 16^3x32")
+    want = repeat_spinor(op.sap(w["block"], b, np.zeros_like(b), 1, w["mr"]))
+    say("48^3x96 FP32 Schwarz sweep, 4^4 blocks,", w["mr"], "MR steps")
+    z = lat.field(F32, 1)
+    lat.sap(lat.pack(repeat_spinor(b)[None], F32), z, 1, w["mr"])
+    got = lat.unpack(z)[0]
+    assert rel(got, want) < TOL32, rel(got, want)

@@ -222,6 +222,11 @@ typedef struct {
     int arnoldi_m;    /* Arnoldi steps for the harmonic Ritz pairs; 0 = min(dim D_c, 2N + 10) */
     int n_part2;      /* repetitions of the second part (the paper runs it once) */
     int prec;         /* precision of the Schwarz sweeps: MGDD_F64 or MGDD_F32 */
+    int chunk;        /* 0: automatic. Otherwise the memory-lean form with this many
+                         vectors per first-part sweep launch and columns per block
+                         of the second part's Gram matrix, formed as
+                         <w_i, D^H D w_j> without holding D W. Automatic is the full
+                         form below 2^22 sites and chunks of 4 from there on. */
 } mgdd_setup_params;
 
 /* Bootstrap setup (Section 3, "Bootstrap Setup"). Part 1: the ntv random

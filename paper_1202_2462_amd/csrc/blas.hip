@@ -372,8 +372,9 @@ __global__ __launch_bounds__(256) void transform_reg_kernel(size_t n, PtrList64 
     }
 }
 
-// the same product when no y_k is one of the x_i: one element per thread
-// with the ny <= YMAX outputs in registers, the inputs streamed once
+// the same product with the ny <= YMAX outputs of an element in registers and
+// its inputs streamed once (each read before any output of the element is
+// written, so y may alias x)
 template <int YMAX>
 __global__ __launch_bounds__(256) void transform_stream_kernel(size_t n, PtrList64 xs, int nx,
                                                                const double2 *__restrict__ M, int ny, PtrList64 ys) {
@@ -564,17 +565,17 @@ int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double
     PtrList64 px{}, py{};
     for (int i = 0; i < nx; i++) px.p[i] = xs[i];
     for (int j = 0; j < ny; j++) py.p[j] = ys[j];
-    bool alias = false;
-    for (int i = 0; i < nx; i++)
-        for (int j = 0; j < ny; j++) alias = alias || xs[i] == ys[j];
+    // every kernel below reads all inputs of an element before it writes an
+    // output of that element, and each element belongs to one thread (or, in
+    // the tiled form, one tile staged in LDS): outputs may alias inputs
     const size_t nb = (n + 255) / 256;
     const int nwg = (int)(nb < 8192 ? nb : 8192);
     const size_t lds = (size_t)nx * ny * sizeof(double2);
-    if (!alias && ny <= 24) {   // outputs in registers, inputs streamed
+    if (ny <= 24) {   // outputs in registers, inputs streamed
         transform_stream_kernel<24><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
         return hip_check(c, hipGetLastError(), "transform");
     }
-    if (nx <= 40) {   // inputs in registers (in place allowed)
+    if (nx <= 40) {   // inputs in registers
         if (nx <= 16)
             transform_reg_kernel<16><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
         else if (nx <= 24)

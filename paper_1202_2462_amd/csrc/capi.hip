@@ -682,7 +682,8 @@ int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const v
     if (!ctx || !params || !random_vectors || !arnoldi_start) return MGDD_EINVAL;
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     const mgdd_setup_params *sp = params;
-    if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0)
+    if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0 ||
+        sp->chunk < 0)
         return fail(&ctx->c, MGDD_EINVAL, "bad setup parameters");
     GUARD_BEGIN
     Ctx *c = &ctx->c;
@@ -765,7 +766,8 @@ int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *w
     if (!ctx || !shape || !weights || !params || !random_vectors) return MGDD_EINVAL;
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     const mgdd_setup_params *sp = params;
-    if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0)
+    if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0 ||
+        sp->chunk < 0)
         return fail(&ctx->c, MGDD_EINVAL, "bad setup parameters");
     if (sp->n_part2 > 0 && !arnoldi_start) return fail(&ctx->c, MGDD_EINVAL, "the second setup part needs a start vector");
     NetShape sh;

@@ -881,49 +881,76 @@ static int arnoldi_host(Ctx *c, int m, const void *v0, std::vector<void *> &Qv, 
     return MGDD_OK;
 }
 
+// Lattices from this volume on (or any, when the caller sets a chunk) take the
+// memory-lean form of the setup: the part-1 sweeps run over chunks of vectors
+// (a zero right-hand side and FP32 copies of that many fields instead of N),
+// and the second part forms its Gram matrix <D w_i, D w_j> as
+// <w_i, D^H D w_j> (D^H = g5 D g5) over chunks of columns instead of holding
+// D W. At 48^3 x 96 with 20 test vectors the full form needs more than the
+// 288 GB of one GPU.
+constexpr int LEAN_SITES = 1 << 22;
+constexpr int SETUP_CHUNK = 4;
+
 int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64) {
     const int N = sp->ntv, p = sp->prec;
     const size_t n = (size_t)12 * c->g.V;
     int rc = transfer_setup(c, sp->agg, N);
     if (rc) return rc;
+    const bool lean = sp->chunk > 0 || c->g.V >= LEAN_SITES;
+    const int chunk = sp->chunk > 0 ? sp->chunk : SETUP_CHUNK;
+    const int R = lean ? std::min(N, chunk) : N;   // vectors per part-1 sweep launch
     const size_t nc = (size_t)c->c.Vc * 2 * N;
     const int mA = sp->arnoldi_m > 0 ? sp->arnoldi_m : (int)std::min<size_t>(nc, 2 * (size_t)N + 10);
-    size_t bytes = (size_t)N * n * 16 * 2 + (p == MGDD_F32 ? (size_t)N * n * 8 * 2 : (size_t)N * n * 16) +
-                   (size_t)4 * N * n * 16 + (size_t)(mA + 3 + N) * nc * 16 + 64 * (size_t)(mA + 2) * (mA + 2) + (1 << 20);
+    // workspace: FP32 sweep copies and the zero right-hand side (R fields each),
+    // the N new vectors of the second part, D W (2N fields, or 2 chunk fields
+    // in the lean form), the coarse vectors
+    const size_t dw_fields = lean ? 2 * (size_t)chunk : 2 * (size_t)N;
+    size_t bytes = (p == MGDD_F32 ? (size_t)R * n * 8 + 256 : 0) + (size_t)R * n * csize(p) + 256 +
+                   (size_t)N * n * 16 + 256 + dw_fields * n * 16 + 256 + (p == MGDD_F32 ? n * 8 + 256 : 0) +
+                   (size_t)(mA + 3 + N) * (nc * 16 + 256) + 64 * (size_t)(mA + 2) * (mA + 2) + (1 << 20);
     Arena A;
     rc = arena_open(c, bytes, A);
     if (rc) return rc;
+    // the test vectors are worked on in place in the context's copy, which
+    // launch_build_P then keeps (a failed setup leaves the level not ready)
     std::vector<void *> Vt(N);
-    void *vt = A.take((size_t)N * n * 16);
-    void *vs = p == MGDD_F32 ? A.take((size_t)N * n * 8) : vt;
-    void *zero = A.take((size_t)N * n * csize(p));
+    void *vt = c->c.tv64;
+    void *vs = p == MGDD_F32 ? A.take((size_t)R * n * 8) : nullptr;
+    void *zero = A.take((size_t)R * n * csize(p));
     double2 *scal = (double2 *)A.take(4096);
     double2 *gdev = (double2 *)A.take((size_t)4 * N * N * 16 + 256), *ydev = (double2 *)A.take((size_t)4 * N * N * 16 + 256);
     if (!ydev) return fail(c, MGDD_ENOMEM, "setup workspace");
     for (int i = 0; i < N; i++) Vt[i] = (char *)vt + (size_t)i * n * 16;
     rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
-    if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, (size_t)N * n * csize(p), c->stream), "memset");
+    if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, (size_t)R * n * csize(p), c->stream), "memset");
     // part 1: nu rounds of (one SAP sweep with b = 0 on all vectors, global MGS)
     for (int it = 0; it < sp->nu && !rc; it++) {
-        if (p == MGDD_F32) rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)N * n, vt, vs);
-        if (!rc) rc = launch_sap(c, p, N, 1, sp->mr_iters, 0.0, 0.0, zero, vs);
-        if (!rc && p == MGDD_F32) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)N * n, vs, vt);
+        for (int r0 = 0; r0 < N && !rc; r0 += R) {
+            const int nr = std::min(R, N - r0);
+            void *vr = Vt[r0];
+            if (p == MGDD_F32) {
+                rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)nr * n, vr, vs);
+                if (!rc) rc = launch_sap(c, p, nr, 1, sp->mr_iters, 0.0, 0.0, zero, vs);
+                if (!rc) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)nr * n, vs, vr);
+            } else {
+                rc = launch_sap(c, p, nr, 1, sp->mr_iters, 0.0, 0.0, zero, vr);
+            }
+        }
         if (!rc) rc = orthonormalise(c, n, Vt.data(), N, gdev, ydev, scal);
     }
     if (!rc) rc = launch_build_P(c, vt);
     if (!rc) rc = launch_coarse_build(c);
     if (rc) return rc;
-    // part 2
-    std::vector<void *> W(2 * N), DW(2 * N);
-    void *wbuf = A.take((size_t)2 * N * n * 16), *dwbuf = A.take((size_t)2 * N * n * 16);
+    // part 2. W = (the nk new vectors, the N current test vectors): the second
+    // block is the test vectors themselves, which the final transform replaces
+    std::vector<void *> W(2 * N), DW(dw_fields);
+    void *wbuf = A.take((size_t)N * n * 16), *dwbuf = A.take(dw_fields * n * 16);
     void *tmp32 = p == MGDD_F32 ? A.take(n * 8) : nullptr;
     std::vector<void *> phi(N);
     for (int i = 0; i < N; i++) phi[i] = A.take(nc * 16);
     if (!dwbuf || !phi[N - 1]) return fail(c, MGDD_ENOMEM, "setup workspace");
-    for (int i = 0; i < 2 * N; i++) {
-        W[i] = (char *)wbuf + (size_t)i * n * 16;
-        DW[i] = (char *)dwbuf + (size_t)i * n * 16;
-    }
+    for (size_t i = 0; i < dw_fields; i++) DW[i] = (char *)dwbuf + i * n * 16;
+    for (int i = 0; i < N; i++) W[i] = (char *)wbuf + (size_t)i * n * 16;
     for (int rep = 0; rep < sp->n_part2; rep++) {
         const size_t mark = A.off;
         std::vector<void *> Qv;
@@ -980,14 +1007,41 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
         }
         if (rc) return rc;
         const int nw = nk + N;
-        for (int j = 0; j < N && !rc; j++)
-            rc = hip_check(c, hipMemcpyAsync(W[nk + j], Vt[j], n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
-        if (!rc) rc = orthonormalise(c, n, W.data(), nw, gdev, ydev, scal);
-        if (!rc) rc = launch_dirac(c, MGDD_F64, nw, wbuf, dwbuf);
+        for (int j = 0; j < N; j++) W[nk + j] = Vt[j];
+        rc = orthonormalise(c, n, W.data(), nw, gdev, ydev, scal);
         // G[i][j] = <DW_i, DW_j>
         la::Mat Gm((size_t)nw * nw);
-        if (!rc) rc = blas_gram(c, n, (const void *const *)DW.data(), nw, (const void *const *)DW.data(), nw, gdev);
-        if (!rc) rc = read_dev(c, gdev, (size_t)nw * nw, Gm.data());
+        if (!lean) {
+            if (!rc && nk > 0) rc = launch_dirac(c, MGDD_F64, nk, wbuf, DW[0]);
+            if (!rc) rc = launch_dirac(c, MGDD_F64, N, vt, DW[nk]);
+            if (!rc) rc = blas_gram(c, n, (const void *const *)DW.data(), nw, (const void *const *)DW.data(), nw, gdev);
+            if (!rc) rc = read_dev(c, gdev, (size_t)nw * nw, Gm.data());
+        } else {
+            // columns j0 .. j0 + cj - 1 (contiguous, inside one block of W):
+            // Y = g5 D g5 D W_j, then <W_i, Y_j> for all i
+            std::vector<cd> Gc((size_t)nw * chunk);
+            for (int j0 = 0; j0 < nw && !rc;) {
+                const int cj = std::min(chunk, (j0 < nk ? nk : nw) - j0);
+                void *tmp = DW[0], *Y = DW[chunk];
+                rc = launch_dirac(c, MGDD_F64, cj, W[j0], tmp);
+                if (!rc) rc = blas_gamma5(c, MGDD_F64, (size_t)c->g.V, cj, tmp, tmp);
+                if (!rc) rc = launch_dirac(c, MGDD_F64, cj, tmp, Y);
+                if (!rc) rc = blas_gamma5(c, MGDD_F64, (size_t)c->g.V, cj, Y, Y);
+                if (!rc) rc = blas_gram(c, n, (const void *const *)W.data(), nw,
+                                        (const void *const *)(DW.data() + chunk), cj, gdev);
+                if (!rc) rc = read_dev(c, gdev, (size_t)nw * cj, Gc.data());
+                for (int i = 0; i < nw && !rc; i++)
+                    for (int q = 0; q < cj; q++) Gm[(size_t)i * nw + j0 + q] = Gc[(size_t)i * cj + q];
+                j0 += cj;
+            }
+            // the Hermitian part (the two triangles agree up to rounding)
+            for (int i = 0; i < nw && !rc; i++)
+                for (int j = i; j < nw; j++) {
+                    const cd h = 0.5 * (Gm[(size_t)i * nw + j] + std::conj(Gm[(size_t)j * nw + i]));
+                    Gm[(size_t)i * nw + j] = h;
+                    Gm[(size_t)j * nw + i] = std::conj(h);
+                }
+        }
         if (rc) return rc;
         std::vector<double> sig;
         la::Mat Z;

@@ -66,7 +66,7 @@ _sig("mgdd_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ct
 class SetupParams(ctypes.Structure):
     _fields_ = [("agg", ctypes.c_int * 4), ("ntv", ctypes.c_int), ("nu", ctypes.c_int), ("iota", ctypes.c_int),
                 ("mr_iters", ctypes.c_int), ("arnoldi_m", ctypes.c_int), ("n_part2", ctypes.c_int),
-                ("prec", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("chunk", ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -556,9 +556,10 @@ class Lattice:
         self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
         self.Vc = int(np.prod(self.cdims))
 
-    def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64):
+    def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64,
+              chunk=0):
         N = random_vectors.shape[0]
-        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, arnoldi_m, n_part2, prec)
+        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, arnoldi_m, n_part2, prec, chunk)
         mgdd_setup_bootstrap(self.ctx, sp, random_vectors, arnoldi_start)
         self.agg = tuple(agg)
         self.N = N

@@ -1,7 +1,9 @@
 """GPU parity on the largest workload lattice, 48^3 x 96, in the launch
 configurations its solve uses: the Wilson-clover apply (FP64 and FP32) and
 one FP32 Schwarz sweep with 4 MR steps on 4^4 blocks, element by element over
-the whole lattice.
+the whole lattice; and the two-level solve of that size (bootstrap setup in
+its memory-lean form, mixed-precision FGMRES(30)), judged by the oracle's
+residual of the returned solution.
 
 The gauge field is the 16^3 x 32 workload field repeated three times in every
 direction, and each input is a 16^3 x 32 Gaussian field repeated the same way
@@ -17,6 +19,10 @@ repeat as well, and inside a block the MR iteration is odd in the residual
 also commutes with the repetition. The oracle's result on 16^3 x 32,
 repeated with the signs, is therefore the exact expected result on 48^3 x 96:
 a full-size comparison whose host work is that of the small lattice."""
+import json
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -115,3 +121,62 @@ def test_c3_schwarz_sweep_full_lattice(c3):
     lat.sap(lat.pack(repeat_spinor(b)[None], F32), z, 1, w["mr"])
     got = lat.unpack(z)[0]
     assert rel(got, want) < TOL32, rel(got, want)
+
+
+def tuned_m0(name):
+    with open(os.path.join(os.path.dirname(__file__), "golden", "m0.json")) as f:
+        d = json.load(f)
+    if name not in d:
+        pytest.skip(f"no tuned bare mass for {name} in tests/golden/m0.json")
+    return float(d[name]["m0"])
+
+
+@pytest.mark.gpu
+@pytest.mark.timeout(900)
+def test_c3_two_level_solve_residual():
+    """48^3 x 96 workload parameters (4^4 blocks and aggregates, 20 test
+    vectors, 3 + 3 bootstrap sweeps in FP32, FGMRES(30) to 1e-10, mixed
+    precision) on the repeated field, with the 16^3 x 32 field's tuned mass
+    (the repetition keeps its low modes); one Gaussian right-hand side on the
+    whole lattice. The random vectors of the setup come from torch's seeded
+    device generator (20 host-generated fields of this size take minutes);
+    the check is the oracle's residual, which needs none of them."""
+    import torch
+    from paper_1202_2462_amd.mgdd import F32, F64, MIXED, Lattice
+    w = latgen.WORKLOADS["c3"]
+    dims, block, agg, N = BIG, w["block"], w["agg"], w["ntv"]
+    m0 = tuned_m0("c1")
+    U = repeat_links(latgen.workload_gauge("c1"))
+    say("48^3x96 two-level solve, m0", m0)
+    lat = Lattice(dims, block)
+    lat.set_gauge(U, m0, w["csw"])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3000 + latgen.TAG_TV)
+    rnd = torch.randn(lat.field(F64, N).shape, dtype=torch.float64, device="cuda", generator=gen)
+    Vc = int(np.prod(dims)) // int(np.prod(agg))
+    st = latgen.gaussian_vector(Vc * 2 * N, 3000 + latgen.TAG_ARNOLDI)
+    start = torch.tensor(np.stack([st.real, st.imag], -1), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.setup(agg, rnd, start, nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], prec=F32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    del rnd
+    torch.cuda.empty_cache()
+    say("setup", round(t1 - t0, 2), "s")
+    b = latgen.gaussian_fields(dims, 1, 3000 + latgen.TAG_RHS)
+    bd = lat.pack(b, F64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    z, stats = lat.solve(bd, precision=MIXED, restart=w["restart"], tol=w["tol"], maxit=3000)
+    t3 = time.perf_counter()
+    say("solve", round(t3 - t2, 2), "s, iterations", stats[0].iters, "restarts", stats[0].restarts,
+        "GPU relres", stats[0].relres)
+    sol = lat.unpack(z)[0]
+    del z, bd
+    lat.close()
+    op = Operator(dims, U, m0, w["csw"])
+    res = np.linalg.norm(b[0] - op.apply(sol)) / np.linalg.norm(b[0])
+    say("oracle relres", res)
+    assert stats[0].converged
+    assert res <= 1.1e-10

@@ -152,23 +152,29 @@ def _boot_inputs(dims, N):
     return rnd, start, st
 
 
-def test_bootstrap_part1_matches_oracle():
+# chunk 0: the full form of the setup at this size; chunk 3: the memory-lean
+# form of large lattices (sweeps over chunks of vectors, the second part's
+# Gram matrix as <w_i, D^H D w_j> over column chunks), forced here, with
+# ragged chunks (8 vectors; 16 columns cut at the end of the 8 new ones)
+@pytest.mark.parametrize("chunk", [0, 3])
+def test_bootstrap_part1_matches_oracle(chunk):
     """First setup part only (nu rounds of one Schwarz sweep with b = 0 and a
     global Gram-Schmidt): a well-conditioned map, compared element-wise."""
     from paper_1202_2462_amd.mgdd import F32, F64
     dims, block, agg, N, op = small_problem(seed=11, m0=0.02)
-    say("bootstrap part 1", dims)
+    say("bootstrap part 1", dims, "chunk", chunk)
     lat = lattice(op, block)
     rnd, start, st = _boot_inputs(dims, N)
     tv_or, _ = solvers.bootstrap(op, block, agg, N, 3, 3, 4, rnd, start, n_part2=0)
-    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, n_part2=0, prec=F64)
+    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, n_part2=0, prec=F64, chunk=chunk)
     tv_gpu = lat.unpack(lat.test_vectors())
     assert rel(tv_gpu, tv_or) < 1e-10
-    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, n_part2=0, prec=F32)
+    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, n_part2=0, prec=F32, chunk=chunk)
     assert rel(lat.unpack(lat.test_vectors()), tv_or) < 1e-4
 
 
-def test_bootstrap_full_invariants():
+@pytest.mark.parametrize("chunk", [0, 3])
+def test_bootstrap_full_invariants(chunk):
     """Both setup parts. The second part starts from unconverged harmonic Ritz
     pairs of a short Arnoldi run, which amplify rounding: perturbing the input
     of the oracle's own setup by 1e-13 moves its Ritz values by up to 3e-4,
@@ -179,11 +185,11 @@ def test_bootstrap_full_invariants():
     setup need the same number of outer iterations within 2."""
     from paper_1202_2462_amd.mgdd import F64, PLAIN_F64
     dims, block, agg, N, op = small_problem(seed=11, m0=0.02)
-    say("bootstrap full", dims)
+    say("bootstrap full", dims, "chunk", chunk)
     lat = lattice(op, block)
     rnd, start, st = _boot_inputs(dims, N)
     tv_or, tl = solvers.bootstrap(op, block, agg, N, 3, 3, 4, rnd, start)
-    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, prec=F64)
+    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, prec=F64, chunk=chunk)
     tv_gpu = lat.unpack(lat.test_vectors())
     G = np.array([[np.vdot(a, b) for b in tv_gpu] for a in tv_gpu])
     assert np.max(np.abs(G - np.eye(N))) < 1e-10

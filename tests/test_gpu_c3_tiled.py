@@ -1,9 +1,9 @@
 """GPU parity on the largest workload lattice, 48^3 x 96, in the launch
 configurations its solve uses: the Wilson-clover apply (FP64 and FP32) and
 one FP32 Schwarz sweep with 4 MR steps on 4^4 blocks, element by element over
-the whole lattice; and the two-level solve of that size (bootstrap setup in
-its memory-lean form, mixed-precision FGMRES(30)), judged by the oracle's
-residual of the returned solution.
+the whole lattice; and the two- and three-level solves of that size
+(bootstrap setup in its memory-lean form, mixed-precision FGMRES(30)), judged
+by the oracle's residual of the returned solution.
 
 The gauge field is the 16^3 x 32 workload field repeated three times in every
 direction, and each input is a 16^3 x 32 Gaussian field repeated the same way
@@ -131,23 +131,31 @@ def tuned_m0(name):
     return float(d[name]["m0"])
 
 
+# the third level as in the 16^3 x 32 benchmark's three-level variant:
+# level-2 aggregates and Schwarz blocks 2^4 (a 6^3 x 12 level-3 lattice), 28
+# level-2 test vectors, 8 level-2 FGMRES steps per coarse solve
+LEVEL3 = dict(agg2=(2, 2, 2, 2), ntv2=28, block2=(2, 2, 2, 2), setup_nu2=2, k2=8, nu2=1, mr2=4)
+
+
 @pytest.mark.gpu
 @pytest.mark.timeout(900)
-def test_c3_two_level_solve_residual():
+@pytest.mark.parametrize("levels", [2, 3])
+def test_c3_multilevel_solve_residual(levels):
     """48^3 x 96 workload parameters (4^4 blocks and aggregates, 20 test
     vectors, 3 + 3 bootstrap sweeps in FP32, FGMRES(30) to 1e-10, mixed
     precision) on the repeated field, with the 16^3 x 32 field's tuned mass
     (the repetition keeps its low modes); one Gaussian right-hand side on the
-    whole lattice. The random vectors of the setup come from torch's seeded
-    device generator (20 host-generated fields of this size take minutes);
-    the check is the oracle's residual, which needs none of them."""
+    whole lattice; two levels, and three. The random vectors of the setup come
+    from torch's seeded device generator (20 host-generated fields of this size
+    take minutes); the check is the oracle's residual, which needs none of
+    them."""
     import torch
     from paper_1202_2462_amd.mgdd import F32, F64, MIXED, Lattice
     w = latgen.WORKLOADS["c3"]
     dims, block, agg, N = BIG, w["block"], w["agg"], w["ntv"]
     m0 = tuned_m0("c1")
     U = repeat_links(latgen.workload_gauge("c1"))
-    say("48^3x96 two-level solve, m0", m0)
+    say("48^3x96 solve,", levels, "levels, m0", m0)
     lat = Lattice(dims, block)
     lat.set_gauge(U, m0, w["csw"])
     gen = torch.Generator(device="cuda")
@@ -159,16 +167,22 @@ def test_c3_two_level_solve_residual():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat.setup(agg, rnd, start, nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], prec=F32)
+    del rnd
+    l3 = {}
+    if levels == 3:
+        q = LEVEL3
+        r2 = torch.randn((q["ntv2"] - N, Vc, 2, N, 2), dtype=torch.float64, device="cuda", generator=gen)
+        lat.setup_level2(q["agg2"], q["ntv2"], q["block2"], random2=r2, nu2=q["setup_nu2"], mr_iters=q["mr2"])
+        l3 = dict(levels=3, k2=q["k2"], nu2=q["nu2"], mr2=q["mr2"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    del rnd
     torch.cuda.empty_cache()
-    say("setup", round(t1 - t0, 2), "s")
+    say("levels", levels, "setup", round(t1 - t0, 2), "s")
     b = latgen.gaussian_fields(dims, 1, 3000 + latgen.TAG_RHS)
     bd = lat.pack(b, F64)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    z, stats = lat.solve(bd, precision=MIXED, restart=w["restart"], tol=w["tol"], maxit=3000)
+    z, stats = lat.solve(bd, precision=MIXED, restart=w["restart"], tol=w["tol"], maxit=3000, **l3)
     t3 = time.perf_counter()
     say("solve", round(t3 - t2, 2), "s, iterations", stats[0].iters, "restarts", stats[0].restarts,
         "GPU relres", stats[0].relres)

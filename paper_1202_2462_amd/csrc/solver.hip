@@ -897,7 +897,7 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     int rc = transfer_setup(c, sp->agg, N);
     if (rc) return rc;
     const bool lean = sp->chunk > 0 || c->g.V >= LEAN_SITES;
-    const int chunk = sp->chunk > 0 ? sp->chunk : SETUP_CHUNK;
+    const int chunk = std::min(sp->chunk > 0 ? sp->chunk : SETUP_CHUNK, 2 * N);   // at most the 2N columns
     const int R = lean ? std::min(N, chunk) : N;   // vectors per part-1 sweep launch
     const size_t nc = (size_t)c->c.Vc * 2 * N;
     const int mA = sp->arnoldi_m > 0 ? sp->arnoldi_m : (int)std::min<size_t>(nc, 2 * (size_t)N + 10);

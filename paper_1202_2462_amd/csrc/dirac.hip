@@ -1,6 +1,7 @@
 // Wilson-clover operator D = A - 1/2 H (Section 1): one thread per site,
 // site-major loads of the 8 neighbour spinors and links, spin projection to
 // half spinors before the SU(3) products.
+#include "dirac.h"
 #include "stencil.h"
 
 namespace mgdd {
@@ -43,7 +44,52 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
     store_spinor<T>(o, d, res);
 }
 
+// FP32 spinors read as FP64 (the widening is exact)
+struct WidenView {
+    FieldView<float> f;
+    __device__ WidenView(const float2 *base, size_t V, int ncomp) : f(base, V, ncomp) {}
+    __device__ double2 ld(int comp, int site, unsigned salt = 0) const {
+        const float2 v = f.ld(comp, site, salt);
+        return make_double2((double)v.x, (double)v.y);
+    }
+};
+
+// dirac_kernel<double> with FP32 input: the FP64 apply of an FP32 field
+// without a converted copy
+__global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 *__restrict__ Up,
+                                                          const double2 *__restrict__ Ap, const float2 *__restrict__ in,
+                                                          double2 *__restrict__ out, int nrhs, int nwg) {
+    const int w = xcd_block(nwg);
+    const int r = w % nrhs;
+    const int i = (w / nrhs) * TPB + threadIdx.x;
+    if (i >= g.V) return;
+    const int d = site_in_lex_block_order(g, i);
+    int nbr[8];
+    site_neighbours(g, d, nbr);
+    const size_t V = g.V;
+    LinkViews<double> U(Up, V);
+    CloverViews<double> A(Ap, V);
+    WidenView f(in + (size_t)r * 12 * V, V, 12);
+    FieldView<double> o(out + (size_t)r * 12 * V, V, 12);
+    double2 acc[12], psi[12], res[12];
+    hop_sum<double>(U, f, d, nbr, acc);
+    load_spinor<double>(f, d, psi);
+    clover_mv<double>(A, d, psi, res);
+#pragma unroll
+    for (int k = 0; k < 12; k++) res[k] = csub(res[k], cscale(acc[k], 0.5));
+    store_spinor<double>(o, d, res);
+}
+
 }  // namespace
+
+int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64) {
+    int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
+    const int slot = kt_begin(c);
+    dirac_widen_kernel<<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
+                                                   (const float2 *)in32, (double2 *)out64, nrhs, nwg);
+    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs);
+    return hip_check(c, hipGetLastError(), "dirac kernel");
+}
 
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;

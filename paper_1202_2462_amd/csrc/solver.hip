@@ -8,6 +8,7 @@
 #include <cmath>
 
 #include "blas.h"
+#include "dirac.h"
 #include "eo.h"
 #include "learn.h"
 #include "level2.h"
@@ -418,7 +419,6 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
     for (int i = 0; i <= m; i++) V[i] = A.take(nn * 16);
     for (int i = 0; i < m; i++) Z[i] = A.take(nn * cs);
     void *w = A.take(nn * 16), *r = A.take(nn * 16);
-    void *z64 = p == MGDD_F32 ? A.take(nn * 16) : nullptr;
     // h1, h2 and the norms side by side, in the order of their pinned host
     // copies, so that each Arnoldi step reads them back in one copy
     double2 *h1 = (double2 *)A.take((size_t)(2 * (m + 1) + 1) * nb * 16);
@@ -507,8 +507,7 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
         for (int j = 0; j < m; j++) {
             rc = mg_precond(c, p, nb, V[j], Z[j], mg_opts(sp), A);
             if (!rc && p == MGDD_F32) {
-                rc = launch_convert(c, MGDD_F32, MGDD_F64, nn, Z[j], z64);
-                if (!rc) rc = launch_dirac(c, MGDD_F64, nb, z64, w);
+                rc = launch_dirac_widen(c, nb, Z[j], w);
             } else if (!rc) {
                 rc = launch_dirac(c, MGDD_F64, nb, Z[j], w);
             }
@@ -807,7 +806,7 @@ size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb) {
     const int m = sp->restart;
     if (sp->solver == MGDD_SOLVER_FGMRES_MG) {
         int p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
-        return (size_t)(m + 4) * (n * nb * 16 + 256) + (size_t)m * (n * nb * csize(p) + 256) +
+        return (size_t)(m + 3) * (n * nb * 16 + 256) + (size_t)m * (n * nb * csize(p) + 256) +
                (3 * (size_t)m + 8) * nb * 16 + precond_bytes(c, p, mg_opts(sp), nb) + 65536;
     }
     return (size_t)(2 * m + 10) * (n * 16 + 256) + 65536;

@@ -173,6 +173,17 @@ def test_bootstrap_part1_matches_oracle(chunk):
     assert rel(lat.unpack(lat.test_vectors()), tv_or) < 1e-4
 
 
+def test_bootstrap_chunk_error():
+    """a negative chunk is refused before anything changes"""
+    from paper_1202_2462_amd.mgdd import EINVAL, F64, MgddError
+    dims, block, agg, N, op = small_problem(seed=11, m0=0.02)
+    lat = lattice(op, block)
+    rnd, start, st = _boot_inputs(dims, N)
+    with pytest.raises(MgddError) as e:
+        lat.setup(agg, lat.pack(rnd, F64), st, nu=1, iota=1, mr_iters=4, n_part2=0, prec=F64, chunk=-1)
+    assert e.value.code == EINVAL
+
+
 @pytest.mark.parametrize("chunk", [0, 3])
 def test_bootstrap_full_invariants(chunk):
     """Both setup parts. The second part starts from unconverged harmonic Ritz

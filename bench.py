@@ -286,7 +286,7 @@ def main():
     ap.add_argument("--m0", type=float, default=None, help="override the tuned bare mass")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU per process and bench.py on one GPU; run with --gpus 1"}))
         sys.exit(2)
 
     import torch

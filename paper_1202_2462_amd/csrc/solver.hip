@@ -946,8 +946,9 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     void *wbuf = A.take((size_t)N * n * 16), *dwbuf = A.take(dw_fields * n * 16);
     void *tmp32 = p == MGDD_F32 ? A.take(n * 8) : nullptr;
     std::vector<void *> phi(N);
-    for (int i = 0; i < N; i++) phi[i] = A.take(nc * 16);
-    if (!dwbuf || !phi[N - 1]) return fail(c, MGDD_ENOMEM, "setup workspace");
+    void *phib = A.take((size_t)N * nc * 16);   // the coarse Ritz vectors, contiguous
+    if (!dwbuf || !phib) return fail(c, MGDD_ENOMEM, "setup workspace");
+    for (int i = 0; i < N; i++) phi[i] = (char *)phib + (size_t)i * nc * 16;
     for (size_t i = 0; i < dw_fields; i++) DW[i] = (char *)dwbuf + i * n * 16;
     for (int i = 0; i < N; i++) W[i] = (char *)wbuf + (size_t)i * n * 16;
     for (int rep = 0; rep < sp->n_part2; rep++) {
@@ -994,7 +995,10 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
             const void *pp = phi[i];
             if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, nc, &pp, 1, phi[i], scal);
             if (!rc) rc = blas_normalize(c, MGDD_F64, MGDD_F64, nc, phi[i], scal, phi[i]);
-            if (!rc) rc = launch_prolong(c, MGDD_F64, 1, phi[i], W[i]);
+        }
+        // w_i = P phi_i for all i in one launch (P read once)
+        if (!rc && nk > 0) rc = launch_prolong(c, MGDD_F64, nk, phib, wbuf);
+        for (int i = 0; i < nk && !rc; i++) {
             cd lam = th[order[i]];
             if (p == MGDD_F32) {
                 if (!rc) rc = launch_convert(c, MGDD_F64, MGDD_F32, n, W[i], tmp32);

@@ -170,13 +170,18 @@ __global__ __launch_bounds__(TPB) void build_P_reg_kernel(int V, int Va, int N, 
 // ---------------------------------------------------------------- restriction c = P^H f
 //
 // One workgroup per (aggregate, field). out[a * ostride + r * rstride + chi * N + k].
+// The workgroups of the nrhs fields of one aggregate are consecutive and on
+// one XCD, so the aggregate's columns of P come from HBM once per launch and
+// from L2 for the other fields.
 template <typename T>
 __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, const int *__restrict__ agg_sites,
                                                        const C<T> *__restrict__ P, const C<T> *__restrict__ f,
-                                                       C<T> *__restrict__ out, size_t ostride, size_t rstride) {
+                                                       C<T> *__restrict__ out, size_t ostride, size_t rstride,
+                                                       int nrhs) {
     extern __shared__ unsigned char smem[];
     T *red = (T *)smem;  // [waves][N][4]
-    const int a = blockIdx.x, r = blockIdx.y;
+    const int wg = xcd_block(gridDim.x);
+    const int a = wg / nrhs, r = wg % nrhs;
     const int *sites = agg_sites + (size_t)a * Va;
     const size_t fs = (size_t)12 * V;
     const C<T> *fr = f + (size_t)r * fs;
@@ -221,13 +226,16 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
 }
 
 // ---------------------------------------------------------------- prolongation f = P c
+//
+// One thread per (site, field), the fields of one site in consecutive threads:
+// they read the same entries of P, so P comes from HBM once per launch.
 template <typename T>
 __global__ __launch_bounds__(TPB) void prolong_kernel(int V, int Vc, int N, const int *__restrict__ site_agg,
                                                       const C<T> *__restrict__ P, const C<T> *__restrict__ cin,
                                                       C<T> *__restrict__ f, int nrhs) {
     const size_t i = (size_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= (size_t)V * nrhs) return;
-    const int r = (int)(i / V), d = (int)(i % V);
+    const int r = (int)(i % nrhs), d = (int)(i / nrhs);
     const int a = site_agg[d];
     const size_t fs = (size_t)12 * V;
     const C<T> *x = cin + ((size_t)r * Vc + a) * 2 * N;
@@ -858,13 +866,15 @@ int launch_restrict_ex(Ctx *c, int prec, int nrhs, const void *P, const void *fi
                        size_t rstride) {
     const Level1 &L1 = c->c;
     size_t lds = (size_t)(TPB / 64) * L1.N * 4 * (prec == MGDD_F64 ? 8 : 4);
-    dim3 grid(L1.Vc, nrhs);
+    const unsigned grid = (unsigned)L1.Vc * (unsigned)nrhs;
     if (prec == MGDD_F64)
         restrict_kernel<double><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const double2 *)P,
-                                                               (const double2 *)fine, (double2 *)out, ostride, rstride);
+                                                               (const double2 *)fine, (double2 *)out, ostride, rstride,
+                                                               nrhs);
     else
         restrict_kernel<float><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const float2 *)P,
-                                                              (const float2 *)fine, (float2 *)out, ostride, rstride);
+                                                              (const float2 *)fine, (float2 *)out, ostride, rstride,
+                                                              nrhs);
     return hip_check(c, hipGetLastError(), "restrict kernel");
 }
 

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const
     __syncthreads();
     // dot products <v_k(a), y(a)>, k <= j: wave k (a second round for k >= 16)
     const int i = threadIdx.x & 63;
-    for (int k = threadIdx.x >> 6; k <= j; k += APB / 64) {
+    for (int k0 = threadIdx.x >> 6; k0 <= j; k0 += APB / 64) {
+        const int k = __builtin_amdgcn_readfirstlane(k0);   // one basis vector per wave: a scalar pointer
         C<T> xv = mk<T>(0, 0);
         if (i < n2) xv = k < j ? ((const C<T> *)V.p[k])[so + (size_t)a * n2 + i] : xs[i];
         const C<T> yv = ys[i];

@@ -202,7 +202,9 @@ __global__ void rsqrt_kernel(const double2 *v, double2 *coef) {
 // gram: part[wg][i][j] = sum over the workgroup's elements of conj(x_i) y_j.
 // Elements are processed in tiles of gt (a power of two, sized on the host
 // so that the tiles fit the dynamic LDS); the tiles of x (and of y unless y
-// is x) go through LDS. The output is cut into 4x4 blocks (only those with
+// is x) go through LDS, one row of gt + 1 per vector (the padding puts the rows
+// that the threads of a wave read at one element in different banks). The
+// output is cut into 4x4 blocks (only those with
 // bi <= bj when y is x: the rest is the conjugate transpose); thread t owns
 // block t % nblk for the elements e = t / nblk, t / nblk + ngroups, ... of
 // each tile, so that up to 256 threads work also when there are few blocks;
@@ -213,10 +215,12 @@ struct PtrList64 {
     const void *p[GMAX];
 };
 
+template <bool ROWS>   // ROWS: tiles of at least 64 elements, loaded one vector row per wave
 __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int nx, PtrList64 ys, int ny, int sym,
                                                    int gt, double2 *__restrict__ part) {
-    extern __shared__ double2 sm[];   // x and y tiles; reused for the group reduction
-    const double2 *yt = sym ? sm : sm + (size_t)nx * gt;
+    extern __shared__ double2 sm[];   // x and y tiles ([vector][gt + 1]); reused for the group reduction
+    const int ld = gt + 1;
+    const double2 *yt = sym ? sm : sm + (size_t)nx * ld;
     const int tx = (nx + 3) / 4, ty = (ny + 3) / 4;
     const int nblk = sym ? tx * (tx + 1) / 2 : tx * ty;
     int ngroups = 1;
@@ -248,11 +252,23 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
     const size_t ntile = (n + gt - 1) / gt;
     for (size_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const size_t e0 = tile * gt;
-        for (int q = t; q < nload * gt; q += blockDim.x) {
-            const int v = q / gt, e = q - v * gt;
-            double2 val = make_double2(0, 0);
-            if (e0 + e < n) val = v < nx ? ((const double2 *)xs.p[v])[e0 + e] : ((const double2 *)ys.p[v - nx])[e0 + e];
-            sm[q] = val;
+        if (ROWS) {
+            // one vector row per wave at a time: the row index, and so the
+            // vector's pointer, is the same in every lane (a scalar load)
+            for (int v0 = t >> 6; v0 < nload; v0 += blockDim.x >> 6) {
+                const int v = __builtin_amdgcn_readfirstlane(v0);
+                const double2 *src = v < nx ? (const double2 *)xs.p[v] : (const double2 *)ys.p[v - nx];
+                for (int e = t & 63; e < gt; e += 64) sm[v * ld + e] = e0 + e < n ? src[e0 + e] : make_double2(0, 0);
+            }
+        } else {
+            // short rows: several rows per wave, the pointer per lane
+            for (int q = t; q < nload * gt; q += blockDim.x) {
+                const int v = q / gt, e = q - v * gt;
+                double2 val = make_double2(0, 0);
+                if (e0 + e < n)
+                    val = v < nx ? ((const double2 *)xs.p[v])[e0 + e] : ((const double2 *)ys.p[v - nx])[e0 + e];
+                sm[v * ld + e] = val;
+            }
         }
         __syncthreads();
         if (owner) {
@@ -260,8 +276,8 @@ __global__ __launch_bounds__(256) void gram_kernel(size_t n, PtrList64 xs, int n
                 double2 xv[4], yv[4];
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    xv[a] = sm[xr[a] * gt + e];
-                    yv[a] = yt[yr[a] * gt + e];
+                    xv[a] = sm[xr[a] * ld + e];
+                    yv[a] = yt[yr[a] * ld + e];
                 }
 #pragma unroll
                 for (int a = 0; a < 4; a++)
@@ -540,22 +556,27 @@ int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const
     for (int j = 0; j < ny; j++) py.p[j] = ys[j];
     int sym = nx == ny;
     for (int i = 0; i < nx && sym; i++) sym = xs[i] == ys[i];
-    // tile length: the loaded rows fill at most 40 KB of LDS
+    // tile length: the loaded rows fill at most 40 KB of LDS, or the space
+    // the group reduction needs anyway when that is larger
     const int nload = sym ? nx : nx + ny;
-    int gt = 128;
-    while (gt > 8 && (size_t)nload * gt * sizeof(double2) > 40960) gt >>= 1;
     const int tx = (nx + 3) / 4, ty = (ny + 3) / 4;
     const int nblk = sym ? tx * (tx + 1) / 2 : tx * ty;
     int ngroups = 1;
     while (ngroups < 8 && 2 * ngroups * nblk <= 256) ngroups *= 2;
-    size_t lds = (size_t)nload * gt * sizeof(double2);
-    if (ngroups > 1 && (size_t)nblk * ngroups * 16 * sizeof(double2) > lds)
-        lds = (size_t)nblk * ngroups * 16 * sizeof(double2);
+    const size_t red_bytes = ngroups > 1 ? (size_t)nblk * ngroups * 16 * sizeof(double2) : 0;
+    const size_t cap = red_bytes > 40960 ? red_bytes : 40960;
+    int gt = 128;
+    while (gt > 8 && (size_t)nload * (gt + 1) * sizeof(double2) > cap) gt >>= 1;
+    size_t lds = (size_t)nload * (gt + 1) * sizeof(double2);
+    if (red_bytes > lds) lds = red_bytes;
     const size_t ntile = (n + gt - 1) / gt;
     const int nwg = (int)(ntile < 2048 ? ntile : 2048);
     double2 *part = (double2 *)ensure_red(c, (size_t)2 * nwg * nx * ny + 16);
     if (!part) return MGDD_ENOMEM;
-    gram_kernel<<<nwg, 256, lds, c->stream>>>(n, px, nx, py, ny, sym, gt, part);
+    if (gt >= 64)
+        gram_kernel<true><<<nwg, 256, lds, c->stream>>>(n, px, nx, py, ny, sym, gt, part);
+    else
+        gram_kernel<false><<<nwg, 256, lds, c->stream>>>(n, px, nx, py, ny, sym, gt, part);
     gram_finish_kernel<<<nx * ny, 256, 0, c->stream>>>(nwg, nx, ny, sym, part, out);
     return hip_check(c, hipGetLastError(), "gram");
 }

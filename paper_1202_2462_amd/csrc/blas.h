@@ -32,7 +32,10 @@ int blas_normalize(Ctx *c, int px, int py, size_t n, const void *x, const double
 // FP64 vector sets (at most 64 each, length n): out[i * ny + j] = <x_i, y_j>
 int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const *ys, int ny, double2 *out);
 // FP64: y_k = sum_i M[i * ny + k] x_i for k < ny (M on the device); any y_k may be one of the x_i
-int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys);
+// upper: M is upper triangular (M[i * ny + k] = 0 for i > k), which lets some
+// of the kernels skip those terms
+int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys,
+                   int upper = 0);
 // y = gamma_5 x for nrhs fine fields of V sites (x and y may alias)
 int blas_gamma5(Ctx *c, int p, size_t V, int nrhs, const void *x, void *y);
 // coef[0] = 1/sqrt(re v[0])

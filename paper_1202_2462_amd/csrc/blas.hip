@@ -358,10 +358,12 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(int nwg, int nx, int n
 // y_k = sum_{i < nx} M[i * ny + k] x_i for k < ny, one element per thread
 // with the nx inputs of the element in registers (nx <= XMAX), so y may be x
 // itself (ny == nx, in place); M is read from LDS, the outputs formed in
-// chunks of 8.
+// chunks of 8. With upper set M is upper triangular and the zero terms below
+// its diagonal are skipped (the same sums, about half the work).
 template <int XMAX>
 __global__ __launch_bounds__(256) void transform_reg_kernel(size_t n, PtrList64 xs, int nx,
-                                                            const double2 *__restrict__ M, int ny, PtrList64 ys) {
+                                                            const double2 *__restrict__ M, int ny, PtrList64 ys,
+                                                            int upper) {
     extern __shared__ double2 tsm[];   // M [nx * ny]
     for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) tsm[q] = M[q];
     __syncthreads();
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void transform_reg_kernel(size_t n, PtrList64 
             for (int kk = 0; kk < 8; kk++) acc[kk] = make_double2(0, 0);
 #pragma unroll
             for (int i = 0; i < XMAX; i++) {
-                if (i < nx) {
+                if (i < nx && (!upper || i < k0 + 8)) {   // upper: M[i][k] = 0 for i > k
 #pragma unroll
                     for (int kk = 0; kk < 8; kk++)
                         if (k0 + kk < ny) cfma(acc[kk], tsm[i * ny + k0 + kk], xv[i]);
@@ -581,7 +583,8 @@ int blas_gram(Ctx *c, size_t n, const void *const *xs, int nx, const void *const
     return hip_check(c, hipGetLastError(), "gram");
 }
 
-int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys) {
+int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double2 *M, int ny, void *const *ys,
+                   int upper) {
     if (nx < 1 || ny < 1 || nx > GMAX || ny > GMAX) return fail(c, MGDD_EINVAL, "transform: bad vector count");
     PtrList64 px{}, py{};
     for (int i = 0; i < nx; i++) px.p[i] = xs[i];
@@ -598,13 +601,13 @@ int blas_transform(Ctx *c, size_t n, const void *const *xs, int nx, const double
     }
     if (nx <= 40) {   // inputs in registers
         if (nx <= 16)
-            transform_reg_kernel<16><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+            transform_reg_kernel<16><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py, upper);
         else if (nx <= 24)
-            transform_reg_kernel<24><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+            transform_reg_kernel<24><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py, upper);
         else if (nx <= 32)
-            transform_reg_kernel<32><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+            transform_reg_kernel<32><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py, upper);
         else
-            transform_reg_kernel<40><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py);
+            transform_reg_kernel<40><<<nwg, 256, lds, c->stream>>>(n, px, nx, M, ny, py, upper);
         return hip_check(c, hipGetLastError(), "transform");
     }
     const size_t ntile = (n + GT - 1) / GT;

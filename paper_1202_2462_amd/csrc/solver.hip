@@ -168,7 +168,7 @@ static int orthonormalise(Ctx *c, size_t n, void *const *X, int nv, double2 *gbu
             if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");
             for (size_t q = 0; q < (size_t)nv * nv; q++) hb[q] = Ri[q];   // M[i][k] = R^{-1}[i][k]
             rc = write_dev(c, hb, (size_t)nv * nv, mbuf);
-            if (!rc) rc = blas_transform(c, n, (const void *const *)X, nv, mbuf, nv, X);
+            if (!rc) rc = blas_transform(c, n, (const void *const *)X, nv, mbuf, nv, X, 1);
             if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");   // hb is reused
             if (rc) return rc;
         }

@@ -177,11 +177,14 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, const int *__restrict__ agg_sites,
                                                        const C<T> *__restrict__ P, const C<T> *__restrict__ f,
                                                        C<T> *__restrict__ out, size_t ostride, size_t rstride,
-                                                       int nrhs) {
+                                                       int nrhs, int ks) {
     extern __shared__ unsigned char smem[];
     T *red = (T *)smem;  // [waves][N][4]
     const int wg = xcd_block(gridDim.x);
-    const int a = wg / nrhs, r = wg % nrhs;
+    // ks workgroups per (aggregate, field), each for a contiguous range of k
+    const int part = wg % ks, af = wg / ks;
+    const int a = af / nrhs, r = af % nrhs;
+    const int kper = (N + ks - 1) / ks, kb = part * kper, ke = kb + kper < N ? kb + kper : N;
     const int *sites = agg_sites + (size_t)a * Va;
     const size_t fs = (size_t)12 * V;
     const C<T> *fr = f + (size_t)r * fs;
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
 #pragma unroll
         for (int c = 0; c < 12; c++) f0[c] = threadIdx.x < Va ? fr[(size_t)c * V + d] : mk<T>(0, 0);
     }
-    for (int k = 0; k < N; k++) {
+    for (int k = kb; k < ke; k++) {
         const C<T> *pk = P + (size_t)k * fs;
         T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         for (int l = threadIdx.x; l < Va; l += blockDim.x) {
@@ -216,6 +219,7 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
     const int nw = blockDim.x >> 6;
     for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
         int chi = i / N, k = i % N;
+        if (k < kb || k >= ke) continue;
         T re = 0, im = 0;
         for (int q = 0; q < nw; q++) {
             re += red[((size_t)q * N + k) * 4 + 2 * chi];
@@ -866,15 +870,19 @@ int launch_restrict_ex(Ctx *c, int prec, int nrhs, const void *P, const void *fi
                        size_t rstride) {
     const Level1 &L1 = c->c;
     size_t lds = (size_t)(TPB / 64) * L1.N * 4 * (prec == MGDD_F64 ? 8 : 4);
-    const unsigned grid = (unsigned)L1.Vc * (unsigned)nrhs;
+    // few (aggregate, field) pairs: split the test vectors over up to 4
+    // workgroups each, so that the launch fills the chip
+    int ks = 1;
+    while (ks < 4 && ks < L1.N && (size_t)L1.Vc * nrhs * ks < 1024) ks *= 2;
+    const unsigned grid = (unsigned)L1.Vc * (unsigned)nrhs * (unsigned)ks;
     if (prec == MGDD_F64)
         restrict_kernel<double><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const double2 *)P,
                                                                (const double2 *)fine, (double2 *)out, ostride, rstride,
-                                                               nrhs);
+                                                               nrhs, ks);
     else
         restrict_kernel<float><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const float2 *)P,
                                                               (const float2 *)fine, (float2 *)out, ostride, rstride,
-                                                              nrhs);
+                                                              nrhs, ks);
     return hip_check(c, hipGetLastError(), "restrict kernel");
 }
 

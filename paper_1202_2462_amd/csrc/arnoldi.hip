@@ -455,6 +455,134 @@ __global__ __launch_bounds__(64) void hessenberg_lsq_kernel(int m, int nb, const
     if (l < m) coef[(size_t)l * nb + s] = l < k ? y[l] : make_double2(0, 0);
 }
 
+// The same two passes for up to 64 vectors (the long Arnoldi runs of the
+// setup's second part), in chunks of 16 vectors inside the kernels: the dot
+// partials of each chunk are reduced and written before the next chunk.
+constexpr int LMAX = 64;
+
+struct VecList64 {
+    const void *p[LMAX];
+};
+
+template <typename T>
+__device__ inline void chunk_partials(const double2 (&acc)[16], int nq, int q0, int nb, int sg, int G, int g,
+                                      double (*red)[32], double2 *__restrict__ pout) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        if (q < nq) {
+            const double a = wave_sum(acc[q].x), b = wave_sum(acc[q].y);
+            if (lane == 0) { red[wv][2 * q] = a; red[wv][2 * q + 1] = b; }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nq) {
+        const int q = threadIdx.x;
+        double a = 0, b = 0;
+        for (int u = 0; u < TPB / 64; u++) { a += red[u][2 * q]; b += red[u][2 * q + 1]; }
+        pout[((size_t)(q0 + q) * nb + sg) * G + g] = make_double2(a, b);
+    }
+    __syncthreads();
+}
+
+// partial sums of <v_k, w> per workgroup, k < nk <= 64: pout[(k * nb + segment) * G + g]
+template <typename T>
+__global__ __launch_bounds__(TPB) void dot_partials_long_kernel(size_t n, VecList64 V, int nk,
+                                                                const C<T> *__restrict__ w,
+                                                                double2 *__restrict__ pout) {
+    const int sg = blockIdx.y, nb = gridDim.y, G = gridDim.x, g = blockIdx.x;
+    const size_t so = (size_t)sg * n;
+    __shared__ double red[TPB / 64][32];
+    for (int q0 = 0; q0 < nk; q0 += 16) {
+        const int nq = nk - q0 < 16 ? nk - q0 : 16;
+        double2 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) acc[q] = make_double2(0, 0);
+        for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
+            const C<T> wv = w[so + e];
+            const double2 wd = make_double2((double)wv.x, (double)wv.y);
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                if (q < nq) {
+                    const C<T> v = ((const C<T> *)V.p[q0 + q])[so + e];
+                    cfmac(acc[q], make_double2((double)v.x, (double)v.y), wd);
+                }
+            }
+        }
+        chunk_partials<T>(acc, nq, q0, nb, sg, G, g, red, pout);
+    }
+}
+
+// y <- y - sum_k coef_k v_k over k < nk <= 64, coef summed from pin (npin
+// partials each, [k][segment][partial]); then the partials of <v_k, y> (or of
+// ||y||^2 when last) per workgroup into pout
+template <typename T>
+__global__ __launch_bounds__(TPB) void orth_long_kernel(size_t n, VecList64 V, int nk, const double2 *__restrict__ pin,
+                                                        int npin, C<T> *__restrict__ y, double2 *__restrict__ pout,
+                                                        int last) {
+    const int sg = blockIdx.y, nb = gridDim.y, G = gridDim.x, g = blockIdx.x;
+    const size_t so = (size_t)sg * n;
+    __shared__ double2 coef[LMAX];
+    __shared__ double red[TPB / 64][32];
+    // one wave per coefficient (wave w takes k = w, w + 8, ...): lane u adds
+    // the partials u, u + 64, ... in order, then a butterfly
+    for (int k = threadIdx.x >> 6; k < nk; k += TPB / 64) {
+        const int u = threadIdx.x & 63;
+        const double2 *pk = pin + ((size_t)k * nb + sg) * npin;
+        double a = 0, b = 0;
+        for (int q = u; q < npin; q += 64) {
+            a += pk[q].x;
+            b += pk[q].y;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (u == 0) coef[k] = make_double2(a, b);
+    }
+    __syncthreads();
+    double nacc = 0;
+    for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
+        const C<T> yv = y[so + e];
+        double2 r = make_double2((double)yv.x, (double)yv.y);
+        for (int q0 = 0; q0 < nk; q0 += 16) {
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                if (q0 + q < nk) {
+                    const C<T> v = ((const C<T> *)V.p[q0 + q])[so + e];
+                    cfma(r, cneg(coef[q0 + q]), make_double2((double)v.x, (double)v.y));
+                }
+            }
+        }
+        const C<T> rt = mk<T>((T)r.x, (T)r.y);
+        y[so + e] = rt;
+        nacc += (double)rt.x * rt.x + (double)rt.y * rt.y;
+    }
+    if (last) {
+        double2 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) acc[q] = make_double2(q == 0 ? nacc : 0.0, 0);
+        chunk_partials<T>(acc, 1, 0, nb, sg, G, g, red, pout);
+        return;
+    }
+    for (int q0 = 0; q0 < nk; q0 += 16) {
+        const int nq = nk - q0 < 16 ? nk - q0 : 16;
+        double2 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) acc[q] = make_double2(0, 0);
+        for (size_t e = (size_t)g * TPB + threadIdx.x; e < n; e += (size_t)G * TPB) {
+            const C<T> yv = y[so + e];   // this thread's own updated element
+            const double2 yd = make_double2((double)yv.x, (double)yv.y);
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                if (q < nq) {
+                    const C<T> v = ((const C<T> *)V.p[q0 + q])[so + e];
+                    cfmac(acc[q], make_double2((double)v.x, (double)v.y), yd);
+                }
+            }
+        }
+        chunk_partials<T>(acc, nq, q0, nb, sg, G, g, red, pout);
+    }
+}
+
 size_t fused_cgs2_red_doubles(size_t n, int k, int nb) {
     return 2 * (2 * (size_t)k + 1) * nb * (size_t)orth_grid(n) + 16;
 }
@@ -466,11 +594,28 @@ size_t fused_cgs2_red_doubles(size_t n, int k, int nb) {
 // of the squared norm. Outputs: h1[i][s], h2[i][s], nrm[s] (device).
 int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, double2 *h1, double2 *h2,
                double2 *nrm) {
-    if (k < 1 || k > VMAX) return fail(c, MGDD_EINVAL, "fused Gram-Schmidt: bad vector count");
+    if (k < 1 || k > LMAX) return fail(c, MGDD_EINVAL, "fused Gram-Schmidt: bad vector count");
     const int G = orth_grid(n);
     double2 *part = (double2 *)ensure_red(c, fused_cgs2_red_doubles(n, k, nb));
     if (!part) return MGDD_ENOMEM;
     double2 *part2 = part + (size_t)k * nb * G;
+    if (k > VMAX) {
+        VecList64 vl{};
+        for (int i = 0; i < k; i++) vl.p[i] = V[i];
+        dim3 grid(G, nb);
+#define CGSL(T)                                                                                                   \
+    do {                                                                                                          \
+        dot_partials_long_kernel<T><<<grid, TPB, 0, c->stream>>>(n, vl, k, (const C<T> *)w, part);                 \
+        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part, h1);                                                    \
+        orth_long_kernel<T><<<grid, TPB, 0, c->stream>>>(n, vl, k, h1, 1, (C<T> *)w, part2, 0);                   \
+        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part2, h2);                                                   \
+        orth_long_kernel<T><<<grid, TPB, 0, c->stream>>>(n, vl, k, h2, 1, (C<T> *)w, part, 1);                    \
+        sum_kernel<<<nb, 64, 0, c->stream>>>(G, part, nrm);                                                       \
+    } while (0)
+        if (p == MGDD_F64) CGSL(double); else CGSL(float);
+#undef CGSL
+        return hip_check(c, hipGetLastError(), "fused Gram-Schmidt");
+    }
     VecList vl{};
     for (int i = 0; i < k; i++) vl.p[i] = V[i];
     dim3 grid(G, nb);

@@ -52,8 +52,8 @@ int launch_coarse_apply(Ctx *c, int prec, int nrhs, const void *in, void *out);
 // Fused Arnoldi process on D_c for the coarse GMRES (arnoldi.hip); m <= 15.
 constexpr int ARNOLDI_FUSED_MAX_STEPS = 15;
 size_t coarse_arnoldi_scratch(const StencilOp &op, int m, int nb);
-// w <- w - V V^H w twice (nb segments of n), three passes; k <= 16 vectors.
-constexpr int FUSED_CGS2_MAX = 16;
+// w <- w - V V^H w twice (nb segments of n), three passes; k <= 64 vectors.
+constexpr int FUSED_CGS2_MAX = 64;
 int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, double2 *h1, double2 *h2,
                double2 *nrm);
 int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *const *V,

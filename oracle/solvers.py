@@ -38,17 +38,22 @@ def mgs(vectors):
 
 # --------------------------------------------------------------------- GMRES
 
-def arnoldi(apply, v0, m):
+def arnoldi(apply, v0, m, reorth=False):
     """m steps of Arnoldi with modified Gram-Schmidt. Returns (V list, H[(k+1), k], k)
-    where k <= m is the number of steps done (k < m on an exact breakdown)."""
+    where k <= m is the number of steps done (k < m on an exact breakdown).
+    reorth: a second Gram-Schmidt pass per step (its coefficients added to
+    H), so that V stays orthonormal to rounding even when the Krylov space
+    fills the whole space; the same H and V in exact arithmetic."""
     beta = norm(v0)
     V = [v0 / beta]
     H = np.zeros((m + 1, m), dtype=np.complex128)
     for j in range(m):
         w = apply(V[j])
-        for i in range(j + 1):
-            H[i, j] = dot(V[i], w)
-            w = w - H[i, j] * V[i]
+        for _ in range(2 if reorth else 1):
+            for i in range(j + 1):
+                h = dot(V[i], w)
+                H[i, j] += h
+                w = w - h * V[i]
         H[j + 1, j] = norm(w)
         if H[j + 1, j] == 0.0:
             return V, H[: j + 2, : j + 1], j + 1
@@ -366,9 +371,12 @@ def harmonic_ritz(apply, v0, m, nkeep):
     """Harmonic Ritz pairs for target 0 from m Arnoldi steps: eigenpairs of
     H_m + |h_{m+1,m}|^2 H_m^{-H} e_m e_m^T; the nkeep of smallest modulus
     (ties broken by real part, then imaginary part, so that the choice does
-    not depend on the order an eigensolver returns them in).
+    not depend on the order an eigensolver returns them in). The formula
+    assumes an orthonormal Krylov basis (H_m = V_m^H A V_m), so the Arnoldi
+    run re-orthogonalises: with one Gram-Schmidt pass the basis of a run as
+    long as the space loses its orthogonality and the pairs their meaning.
     Returns (theta[nkeep], vectors list)."""
-    V, H, k = arnoldi(apply, v0, m)
+    V, H, k = arnoldi(apply, v0, m, reorth=True)
     Hm = H[:k, :k]
     T = Hm.copy()
     if H.shape[0] > k:

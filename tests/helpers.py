@@ -53,3 +53,17 @@ def sort_spectrum(ev):
     ev = np.asarray(ev)
     key = np.lexsort((np.round(ev.imag, 8), np.round(ev.real, 8)))
     return ev[key]
+
+
+def aligned_difference(a, ref) -> float:
+    """Relative difference of two sets of vectors that are unique up to one
+    phase per vector: each vector of a is rotated onto its partner in ref
+    before the difference is taken."""
+    num = den = 0.0
+    for x, r in zip(a, ref):
+        x, r = np.ravel(x), np.ravel(r)
+        ph = np.vdot(x, r)
+        x = x * (ph / abs(ph))
+        num += np.linalg.norm(x - r) ** 2
+        den += np.linalg.norm(r) ** 2
+    return float(np.sqrt(num / den))

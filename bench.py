@@ -243,7 +243,7 @@ class Bench:
         b = self.lat.field(mg.F32, 1)
         b.normal_()
         z = self.lat.field(mg.F32, 1)
-        t = self.time_calls(lambda: mg.mgdd_sap(self.lat.ctx, mg.F32, 1, 1, self.w["mr"], 0.0, b, z), 50)
+        t = self.time_calls(lambda: mg.mgdd_sap(self.lat.ctx, mg.F32, 1, None, 1, self.w["mr"], 0.0, b, z), 50)
         return t / 2.0
 
 

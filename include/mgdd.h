@@ -30,7 +30,8 @@
  *                                   coarse lattice L/agg), chi = 0 for
  *                                   spins 0,1 (gamma_5 = +1) and 1 for spins
  *                                   2,3, k = test-vector index
- *  Boundary conditions: periodic in x, y, z and antiperiodic in t.
+ *  Boundary conditions: periodic in x, y, z; antiperiodic in t unless the
+ *  context was created with t_antiperiodic = 0 (then periodic in t).
  *  Gamma matrices: chiral basis, gamma_k = [[0,-i s_k],[i s_k,0]],
  *  gamma_t = [[0,-1],[-1,0]], gamma_5 = diag(1,1,-1,-1).
  *  Operator (Section 1 of the paper; clover term named in its abstract):
@@ -84,12 +85,30 @@ typedef struct mgdd_ctx mgdd_ctx;
  * lattice block decomposition of Section 2 used by the Schwarz smoother and
  * by the device site order: every b_mu a power of two >= 2 dividing L_mu,
  * and the number of blocks L_mu/b_mu even or 1 in every direction (a
- * two-colouring in which no two neighbouring blocks share a colour).
+ * two-colouring in which no two neighbouring blocks share a colour). The
+ * device site order is built from these blocks (a colour step of the
+ * smoother reads one contiguous half of every field), so the Schwarz block
+ * of a context is fixed; another block shape needs another context.
+ * t_antiperiodic: 1 for antiperiodic boundary conditions in time (the hops
+ * across the time boundary carry a sign -1), 0 for periodic ones.
  * The volume is at most 14 913 080 sites (device arrays are addressed with
  * 32-bit byte offsets, 288 bytes per site at most; 48^3 x 96 fits).
  * hip_stream: a hipStream_t (NULL = the default stream). *out receives the
  * context. Errors: MGDD_ESHAPE, MGDD_EINVAL, MGDD_EHIP. */
-int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ctx **out);
+int mgdd_create(const int dims[4], const int block[4], int t_antiperiodic, void *hip_stream, mgdd_ctx **out);
+
+/* Device memory of the context (links, clover term, P, D_c, workspace)
+ * taken from a caller's allocator instead of hipMalloc / hipFree, so that for
+ * example PyTorch's caching allocator can own it: alloc(bytes, user) returns
+ * a device pointer (aligned to at least 256 bytes) or NULL, free(ptr, user)
+ * releases one. Every allocation made after this call goes through the pair
+ * and is released through it (by mgdd_release_workspace, by a rebuild of P,
+ * or at the latest by mgdd_destroy); earlier allocations keep hipFree.
+ * alloc = free = NULL restores hipMalloc / hipFree for later allocations.
+ * Both or neither must be given. Errors: MGDD_EINVAL. */
+typedef void *(*mgdd_alloc_fn)(size_t bytes, void *user);
+typedef void (*mgdd_free_fn)(void *ptr, void *user);
+int mgdd_set_allocator(mgdd_ctx *ctx, mgdd_alloc_fn alloc, mgdd_free_fn free_fn, void *user);
 
 /* Frees everything the context owns. Safe on NULL. */
 int mgdd_destroy(mgdd_ctx *ctx);
@@ -126,12 +145,14 @@ int mgdd_unpack(mgdd_ctx *ctx, int prec, int nrhs, const void *src, double *dst,
 int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *out);
 
 /* nsweeps sweeps of Red-Black Schwarz (Section 2, Algorithm 2.1) on
- * (D - shift) z = b, z in/out, over the blocks of mgdd_create; each block
- * system I^T (D - shift) I e = I^T r is approximated by mr_iters minimal
- * residual steps from e = 0 (the shifted block inverses B_j(lambda) of the
- * second setup part use shift = lambda). Asynchronous. */
-int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, double shift_re, double shift_im,
-             const void *b, void *z);
+ * (D - shift) z = b, z in/out, over the lattice blocks `block` (NULL: the
+ * blocks of mgdd_create; otherwise they must be those blocks, see
+ * mgdd_create, else MGDD_ESHAPE); each block system I^T (D - shift) I e =
+ * I^T r is approximated by mr_iters minimal residual steps from e = 0 (the
+ * shifted block inverses B_j(lambda) of the second setup part use shift =
+ * lambda). Asynchronous. */
+int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], int nsweeps, int mr_iters, double shift_re,
+             double shift_im, const void *b, void *z);
 
 /* Schwarz variants of Section 2 and of the paper's experiments (Section 4:
  * 3 GMRES steps per block system). block_solver: MGDD_BLOCK_MR (k steps of
@@ -140,11 +161,11 @@ int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, doubl
  * problem, per block). additive = 0: red-black multiplicative sweeps
  * (Algorithm 2.1); additive = 1: additive Schwarz (the first propagator of
  * eq. (2.1)): per sweep one residual r = b - D z, every block system solved
- * for it, z += the sum of the corrections (needs shift = 0). b, z: nrhs
- * fields of precision prec, z in/out, not aliased. Uses the context's
- * workspace (additive). Errors: MGDD_EINVAL (bad parameters), MGDD_ESHAPE
- * (block volume outside 64..256), MGDD_ENOTREADY (no gauge field).
- * Asynchronous. */
+ * for it, z += the sum of the corrections (needs shift = 0). block: as for
+ * mgdd_sap. b, z: nrhs fields of precision prec, z in/out, not aliased. Uses
+ * the context's workspace (additive). Errors: MGDD_EINVAL (bad parameters),
+ * MGDD_ESHAPE (block volume outside 64..256, or not the context's blocks),
+ * MGDD_ENOTREADY (no gauge field). Asynchronous. */
 enum { MGDD_BLOCK_MR = 0, MGDD_BLOCK_GMRES = 1 };
 typedef struct {
     int nsweeps;
@@ -153,7 +174,8 @@ typedef struct {
     int additive;          /* 0 red-black multiplicative, 1 additive */
     double shift_re, shift_im;
 } mgdd_schwarz_params;
-int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const mgdd_schwarz_params *params, const void *b, void *z);
+int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], const mgdd_schwarz_params *params,
+                 const void *b, void *z);
 
 /* ------------------------------------------------------------------ coarse level (Section 3) */
 
@@ -165,7 +187,10 @@ int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const mgdd_schwarz_params *p
  * orthonormalised by modified Gram-Schmidt in column order (P^H P = 1, the
  * unique thin QR with positive diagonal of R). Then builds the coarse operator
  * D_c = P^H D P (a 9-point stencil of 2N x 2N blocks) in FP64, with FP32
- * copies of P and D_c. test_vectors: ntv FP64 device fields (read only).
+ * copies of P and D_c: both precisions are always stored (the FP64 pair
+ * serves the plain FP64 solve and the FP64 parts of the setup, the FP32 pair
+ * the mixed-precision preconditioner), so there is no storage-precision
+ * argument. test_vectors: ntv FP64 device fields (read only).
  * Synchronous. Errors: MGDD_ERANK (ntv > 6 * vol(agg) or a piece is rank
  * deficient), MGDD_ESHAPE, MGDD_EINVAL (ntv not in 1..32). */
 int mgdd_build_P(mgdd_ctx *ctx, const int agg[4], int ntv, const void *test_vectors);

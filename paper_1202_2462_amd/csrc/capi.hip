@@ -28,27 +28,44 @@ int hip_check(Ctx *c, hipError_t e, const char *what) {
     return fail(c, MGDD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device allocations go through the caller's allocator when one is set
+// (mgdd_set_allocator), else hipMalloc; each remembers how it is released.
 void *dalloc(Ctx *c, size_t bytes) {
     void *p = nullptr;
     if (bytes == 0) bytes = 16;
+    if (c->ualloc) {
+        p = c->ualloc(bytes, c->uuser);
+        if (!p) {
+            fail(c, MGDD_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (caller's allocator)");
+            return nullptr;
+        }
+        c->owned.push_back(Owned{p, c->ufree, c->uuser});
+        return p;
+    }
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        fail(c, MGDD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        fail(c, MGDD_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (hipMalloc)");
         return nullptr;
     }
-    c->owned.push_back(p);
+    c->owned.push_back(Owned{p, nullptr, nullptr});
     return p;
+}
+
+void release_owned(const Owned &o) {
+    if (o.free_fn) o.free_fn(o.p, o.user);
+    else (void)hipFree(o.p);
 }
 
 void dfree(Ctx *c, void *p) {
     if (!p) return;
     for (size_t i = 0; i < c->owned.size(); i++)
-        if (c->owned[i] == p) {
+        if (c->owned[i].p == p) {
+            const Owned o = c->owned[i];
             c->owned[i] = c->owned.back();
             c->owned.pop_back();
-            break;
+            release_owned(o);
+            return;
         }
-    (void)hipFree(p);
 }
 
 void *ensure_stage(Ctx *c, size_t bytes) {
@@ -168,7 +185,7 @@ static bool valid_fine_prec(int p) { return valid_prec(p) || p == MGDD_F16; }
 // batch may fit); clears the HIP error state
 static bool alloc_failed(Ctx *c) {
     (void)hipGetLastError();
-    return c->err.rfind("hipMalloc", 0) == 0;
+    return c->err.rfind("device allocation", 0) == 0;
 }
 
 }  // namespace mgdd
@@ -191,13 +208,14 @@ struct mgdd_ctx {
 
 extern "C" {
 
-int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ctx **out) {
-    if (!dims || !block || !out) return MGDD_EINVAL;
+int mgdd_create(const int dims[4], const int block[4], int t_antiperiodic, void *hip_stream, mgdd_ctx **out) {
+    if (!dims || !block || !out || (t_antiperiodic != 0 && t_antiperiodic != 1)) return MGDD_EINVAL;
     *out = nullptr;
     mgdd_ctx *ctx = nullptr;
     GUARD_BEGIN
     ctx = new mgdd_ctx();
     ctx->c.stream = (hipStream_t)hip_stream;
+    ctx->c.t_antiperiodic = t_antiperiodic == 1;
     (void)hipGetDevice(&ctx->c.dev);
     {
         int v = 0;
@@ -208,7 +226,7 @@ int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ct
     if (rc) {
         // keep the context so that the caller can read the error, then free it
         std::string msg = ctx->c.err;
-        for (void *p : ctx->c.owned) (void)hipFree(p);
+        for (const Owned &o : ctx->c.owned) release_owned(o);
         delete ctx;
         fprintf(stderr, "mgdd_create: %s\n", msg.c_str());
         return rc;
@@ -218,11 +236,19 @@ int mgdd_create(const int dims[4], const int block[4], void *hip_stream, mgdd_ct
     GUARD_END
 }
 
+int mgdd_set_allocator(mgdd_ctx *ctx, mgdd_alloc_fn alloc, mgdd_free_fn free_fn, void *user) {
+    if (!ctx || (alloc == nullptr) != (free_fn == nullptr)) return MGDD_EINVAL;
+    ctx->c.ualloc = alloc;
+    ctx->c.ufree = free_fn;
+    ctx->c.uuser = alloc ? user : nullptr;
+    return MGDD_OK;
+}
+
 int mgdd_destroy(mgdd_ctx *ctx) {
     if (!ctx) return MGDD_OK;
     (void)hipStreamSynchronize(ctx->c.stream);
     kt_release(&ctx->c);
-    for (void *p : ctx->c.owned) (void)hipFree(p);
+    for (const Owned &o : ctx->c.owned) release_owned(o);
     if (ctx->c.red_host) (void)hipHostFree(ctx->c.red_host);
     if (ctx->c.hbuf) (void)hipHostFree(ctx->c.hbuf);
     delete ctx;
@@ -337,20 +363,34 @@ int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *ou
     GUARD_END
 }
 
-int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, int nsweeps, int mr_iters, double shift_re, double shift_im,
-             const void *b, void *z) {
+// the Schwarz blocks of a call: NULL or the blocks the device site order was built from
+static int check_block(Ctx *c, const int *block) {
+    if (!block) return MGDD_OK;
+    for (int mu = 0; mu < 4; mu++)
+        if (block[mu] != (1 << c->g.lb[mu]))
+            return fail(c, MGDD_ESHAPE,
+                        "the Schwarz blocks are the blocks of mgdd_create (the device site order is built from "
+                        "them); create a context with this block shape");
+    return MGDD_OK;
+}
+
+int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], int nsweeps, int mr_iters, double shift_re,
+             double shift_im, const void *b, void *z) {
     if (!ctx || !b || !z || !valid_prec(prec) || nrhs <= 0 || nsweeps < 0 || mr_iters < 0) return MGDD_EINVAL;
     if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
+    if (check_block(&ctx->c, block)) return MGDD_ESHAPE;
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     GUARD_BEGIN
     return launch_sap(&ctx->c, prec, nrhs, nsweeps, mr_iters, shift_re, shift_im, b, z);
     GUARD_END
 }
 
-int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const mgdd_schwarz_params *params, const void *b, void *z) {
+int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], const mgdd_schwarz_params *params,
+                 const void *b, void *z) {
     if (!ctx || !params || !b || !z || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     const mgdd_schwarz_params *q = params;
     if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
+    if (check_block(&ctx->c, block)) return MGDD_ESHAPE;
     if (q->nsweeps < 0 || q->block_iters < 0 || (q->block_solver != MGDD_BLOCK_MR && q->block_solver != MGDD_BLOCK_GMRES))
         return fail(&ctx->c, MGDD_EINVAL, "bad Schwarz parameters");
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");

@@ -49,7 +49,7 @@ __global__ void convert_kernel(size_t n, const C<S> *__restrict__ src, C<D> *__r
 // ---------------------------------------------------------------- gauge ingest
 
 __global__ void links_kernel(Geom g, const double2 *__restrict__ Uc, double2 *__restrict__ U64, float2 *__restrict__ U32,
-                             int *__restrict__ bad) {
+                             int *__restrict__ bad, int antiperiodic) {
     int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= g.V) return;
     int X[4];
@@ -57,7 +57,7 @@ __global__ void links_kernel(Geom g, const double2 *__restrict__ Uc, double2 *__
     int s = X[0] + g.L[0] * (X[1] + g.L[1] * (X[2] + g.L[2] * X[3]));
     for (int mu = 0; mu < 4; mu++) {
         // antiperiodic in t: the hop across the time boundary carries a sign
-        double sg = (mu == 3 && X[3] == g.L[3] - 1) ? -1.0 : 1.0;
+        double sg = (antiperiodic && mu == 3 && X[3] == g.L[3] - 1) ? -1.0 : 1.0;
         for (int k = 0; k < 9; k++) {
             double2 u = Uc[((size_t)s * 4 + mu) * 9 + k];
             if (!isfinite(u.x) || !isfinite(u.y)) atomicOr(bad, 2);
@@ -268,7 +268,8 @@ int launch_gauge_ingest(Ctx *c, const double2 *Ucanon) {
     if (!bad) return MGDD_ENOMEM;
     int rc = hip_check(c, hipMemsetAsync(bad, 0, sizeof(int), c->stream), "memset");
     if (rc) return rc;
-    links_kernel<<<nblk(c->g.V), TPB, 0, c->stream>>>(c->g, Ucanon, (double2 *)c->U64, (float2 *)c->U32, bad);
+    links_kernel<<<nblk(c->g.V), TPB, 0, c->stream>>>(c->g, Ucanon, (double2 *)c->U64, (float2 *)c->U32, bad,
+                                                 c->t_antiperiodic ? 1 : 0);
     rc = hip_check(c, hipGetLastError(), "links kernel");
     if (rc) return rc;
     clover_kernel<<<nblk(c->g.V, 128), 128, 0, c->stream>>>(c->g, Ucanon, c->m0, c->csw, (double2 *)c->A64,

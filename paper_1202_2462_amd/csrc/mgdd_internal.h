@@ -121,8 +121,17 @@ struct KTimer {
     long long launches[KF_COUNT][3] = {};
 };
 
+// one device allocation of a context and the routine that releases it
+// (hipFree when free_fn is null, else the caller's allocator)
+struct Owned {
+    void *p;
+    mgdd_free_fn free_fn;
+    void *user;
+};
+
 struct Ctx {
     Geom g{};
+    bool t_antiperiodic = true;             // sign -1 on the hops across the time boundary
     hipStream_t stream = nullptr;
     std::string err;
     int dev = 0;
@@ -139,7 +148,10 @@ struct Ctx {
     Level1 c;
     Level2 c2;
     // workspace
-    std::vector<void *> owned;
+    std::vector<Owned> owned;
+    mgdd_alloc_fn ualloc = nullptr;         // caller's allocator (mgdd_set_allocator), or hipMalloc
+    mgdd_free_fn ufree = nullptr;
+    void *uuser = nullptr;
     void *stage = nullptr;                  // canonical staging buffer
     size_t stage_bytes = 0;
     double *red = nullptr;                  // reduction partials
@@ -157,6 +169,7 @@ int fail(Ctx *c, int code, const std::string &msg);
 int hip_check(Ctx *c, hipError_t e, const char *what);
 void *dalloc(Ctx *c, size_t bytes);
 void dfree(Ctx *c, void *p);
+void release_owned(const Owned &o);
 void *ensure_stage(Ctx *c, size_t bytes);
 void *ensure_scratch(Ctx *c, size_t bytes);
 double *ensure_red(Ctx *c, size_t ndoubles);

@@ -51,7 +51,11 @@ def _sig(name, restype, *args):
     return f
 
 
-_sig("mgdd_create", ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _vp, ctypes.POINTER(_vp))
+_sig("mgdd_create", ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp,
+     ctypes.POINTER(_vp))
+ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp)
+FREE_FN = ctypes.CFUNCTYPE(None, _vp, _vp)
+_sig("mgdd_set_allocator", ctypes.c_int, _vp, ALLOC_FN, FREE_FN, _vp)
 _sig("mgdd_destroy", ctypes.c_int, _vp)
 _sig("mgdd_last_error", ctypes.c_char_p, _vp)
 _sig("mgdd_field_bytes", ctypes.c_size_t, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int)
@@ -59,8 +63,8 @@ _sig("mgdd_set_gauge", ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_double, ct
 _sig("mgdd_pack", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp)
 _sig("mgdd_unpack", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
 _sig("mgdd_dirac_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
-_sig("mgdd_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-     ctypes.c_double, _vp, _vp)
+_sig("mgdd_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+     ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp)
 
 
 class SetupParams(ctypes.Structure):
@@ -117,7 +121,8 @@ _sig("mgdd_net_grad", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.c
      _vp)
 _sig("mgdd_net_adam", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double)
 _sig("mgdd_setup_learned", ctypes.c_int, _vp, ctypes.POINTER(NetShape), _vp, ctypes.POINTER(SetupParams), _vp, _vp)
-_sig("mgdd_schwarz", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SchwarzParams), _vp, _vp)
+_sig("mgdd_schwarz", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+     ctypes.POINTER(SchwarzParams), _vp, _vp)
 _sig("mgdd_build_P", ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp)
 _sig("mgdd_get_test_vectors", ctypes.c_int, _vp, _vp)
 _sig("mgdd_restrict", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
@@ -170,7 +175,7 @@ def _check(ctx, rc):
 
 # --------------------------------------------------------------------- entry points
 
-def mgdd_create(dims, block, stream=None):
+def mgdd_create(dims, block, stream=None, t_antiperiodic=True):
     """Returns the context handle. stream: a torch.cuda.Stream, a raw
     hipStream_t int, or None for torch's current stream."""
     if stream is None:
@@ -179,7 +184,7 @@ def mgdd_create(dims, block, stream=None):
     elif hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     out = _vp()
-    rc = _lib.mgdd_create(_i4(*dims), _i4(*block), stream, ctypes.byref(out))
+    rc = _lib.mgdd_create(_i4(*dims), _i4(*block), 1 if t_antiperiodic else 0, stream, ctypes.byref(out))
     if rc != OK:
         raise MgddError(rc, "mgdd_create failed (dims/block do not fit)")
     return out.value
@@ -223,9 +228,17 @@ def mgdd_dirac_apply(ctx, prec, nrhs, x, y):
     return _check(ctx, _lib.mgdd_dirac_apply(ctx, prec, nrhs, _ptr(x), _ptr(y)))
 
 
-def mgdd_sap(ctx, prec, nrhs, nsweeps, mr_iters, shift, b, z):
+def mgdd_set_allocator(ctx, alloc, free, user=None):
+    """alloc, free: ALLOC_FN / FREE_FN instances (kept alive by the caller),
+    or None for both."""
+    return _check(ctx, _lib.mgdd_set_allocator(ctx, alloc or ALLOC_FN(), free or FREE_FN(), user))
+
+
+def mgdd_sap(ctx, prec, nrhs, block, nsweeps, mr_iters, shift, b, z):
     shift = complex(shift)
-    return _check(ctx, _lib.mgdd_sap(ctx, prec, nrhs, nsweeps, mr_iters, shift.real, shift.imag, _ptr(b), _ptr(z)))
+    blk = None if block is None else _i4(*block)
+    return _check(ctx, _lib.mgdd_sap(ctx, prec, nrhs, blk, nsweeps, mr_iters, shift.real, shift.imag, _ptr(b),
+                                     _ptr(z)))
 
 
 def mgdd_build_P(ctx, agg, ntv, test_vectors):
@@ -286,8 +299,9 @@ def mgdd_setup_learned(ctx, widths, weights, params, random_vectors, arnoldi_sta
                                                None if arnoldi_start is None else _ptr(arnoldi_start)))
 
 
-def mgdd_schwarz(ctx, prec, nrhs, params: SchwarzParams, b, z):
-    return _check(ctx, _lib.mgdd_schwarz(ctx, prec, nrhs, ctypes.byref(params), _ptr(b), _ptr(z)))
+def mgdd_schwarz(ctx, prec, nrhs, block, params: SchwarzParams, b, z):
+    blk = None if block is None else _i4(*block)
+    return _check(ctx, _lib.mgdd_schwarz(ctx, prec, nrhs, blk, ctypes.byref(params), _ptr(b), _ptr(z)))
 
 
 def mgdd_precondition3(ctx, prec, nrhs, nu, mr_iters, k2, nu2, mr2, coarse_iters, r, z):
@@ -350,12 +364,13 @@ class Lattice:
     """Owns one context; fields are torch tensors shaped (nrhs, 12, V, 2) of
     float64 (F64) or float32 (F32) in the device layout."""
 
-    def __init__(self, dims, block, stream=None):
+    def __init__(self, dims, block, stream=None, t_antiperiodic=True):
         import torch
         self.torch = torch
         self.dims = tuple(int(d) for d in dims)
+        self.block = tuple(int(b) for b in block)
         self.V = int(np.prod(self.dims))
-        self.ctx = mgdd_create(self.dims, block, stream)
+        self.ctx = mgdd_create(self.dims, block, stream, t_antiperiodic)
 
     def close(self):
         if self.ctx:
@@ -402,14 +417,14 @@ class Lattice:
         return y
 
     def sap(self, b, z, nsweeps, mr_iters, shift=0.0):
-        mgdd_sap(self.ctx, self.prec_of(b), b.shape[0], nsweeps, mr_iters, shift, b, z)
+        mgdd_sap(self.ctx, self.prec_of(b), b.shape[0], self.block, nsweeps, mr_iters, shift, b, z)
         return z
 
     def schwarz(self, b, z, nsweeps=1, k=3, block_solver=BLOCK_GMRES, additive=False, shift=0.0):
         """Schwarz sweeps on (D - shift) z = b (z updated in place): red-black or
         additive, MR(k) or GMRES(k) block solves."""
         q = SchwarzParams(nsweeps, k, block_solver, 1 if additive else 0, complex(shift).real, complex(shift).imag)
-        mgdd_schwarz(self.ctx, self.prec_of(b), b.shape[0], q, b, z)
+        mgdd_schwarz(self.ctx, self.prec_of(b), b.shape[0], self.block, q, b, z)
         return z
 
     # coarse level -------------------------------------------------------

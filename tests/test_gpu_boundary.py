@@ -1,0 +1,117 @@
+"""The arguments of the C ABI beyond the operators themselves: the time
+boundary condition of mgdd_create, the block argument of mgdd_sap /
+mgdd_schwarz, and mgdd_set_allocator (device memory from the caller's
+allocator), each through ctypes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import latgen
+from gpu_common import TOL32, TOL64, lattice, problem, rel, say
+from oracle import solvers
+
+pytestmark = pytest.mark.gpu
+
+
+def test_periodic_time_boundary():
+    """t_antiperiodic = 0: D with periodic time boundary on links U equals the
+    antiperiodic D (the oracle's) on links U' whose t-links on the last time
+    slice are negated: the sign of the hops across the boundary cancels, and
+    every plaquette holds two t-links of one time slice, so the clover term is
+    the same. Checked for the Wilson-clover apply and a Schwarz sweep."""
+    from paper_1202_2462_amd.mgdd import F32, F64, Lattice
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    say("periodic time boundary", dims)
+    U = latgen.gauge_field(dims, 0.5, 21)
+    Uf = U.reshape(dims[3], -1, 4, 3, 3).copy()
+    Uf[-1, :, 3] *= -1.0
+    op_flip = solvers.Operator(dims, Uf.reshape(-1, 4, 3, 3), 0.1, 1.0)
+    lat = Lattice(dims, block, t_antiperiodic=False)
+    lat.set_gauge(U, 0.1, 1.0)
+    x = latgen.gaussian_fields(dims, 2, 22)
+    want = np.stack([op_flip.apply(x[i]) for i in range(2)])
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        got = lat.unpack(lat.dirac(lat.pack(x, prec)))
+        assert rel(got, want) < tol, (prec, rel(got, want))
+    z = lat.pack(np.zeros_like(x[:1]), F64)
+    lat.sap(lat.pack(x[:1], F64), z, 1, 4)
+    want_s = op_flip.sap(block, x[0], np.zeros_like(x[0]), 1, 4)
+    assert rel(lat.unpack(z)[0], want_s) < TOL64
+    # and the antiperiodic context differs from it
+    lat_a = lattice(solvers.Operator(dims, U, 0.1, 1.0), block)
+    got_a = lat_a.unpack(lat_a.dirac(lat_a.pack(x, F64)))
+    assert rel(got_a, want) > 1e-3
+    lat.close()
+    lat_a.close()
+
+
+def test_block_argument():
+    """The Schwarz calls take the block shape; NULL and the context's blocks
+    are the same sweep, any other shape is refused with ESHAPE."""
+    from paper_1202_2462_amd.mgdd import (BLOCK_MR, ESHAPE, F64, MgddError, SchwarzParams, mgdd_sap,
+                                           mgdd_schwarz)
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    op = problem(dims, seed=23, m0=0.1)
+    lat = lattice(op, block)
+    b = lat.pack(latgen.gaussian_fields(dims, 1, 24), F64)
+    z1, z2 = lat.field(F64, 1), lat.field(F64, 1)
+    mgdd_sap(lat.ctx, F64, 1, None, 1, 4, 0.0, b, z1)
+    mgdd_sap(lat.ctx, F64, 1, block, 1, 4, 0.0, b, z2)
+    assert bool((z1 == z2).all())
+    with pytest.raises(MgddError) as e:
+        mgdd_sap(lat.ctx, F64, 1, (2, 4, 4, 4), 1, 4, 0.0, b, z2)
+    assert e.value.code == ESHAPE
+    q = SchwarzParams(1, 4, BLOCK_MR, 0, 0.0, 0.0)
+    z3 = lat.field(F64, 1)
+    mgdd_schwarz(lat.ctx, F64, 1, block, q, b, z3)
+    assert bool((z3 == z1).all())
+    with pytest.raises(MgddError) as e:
+        mgdd_schwarz(lat.ctx, F64, 1, (4, 4, 4, 8), q, b, z3)
+    assert e.value.code == ESHAPE
+    lat.close()
+
+
+def test_caller_allocator():
+    """mgdd_set_allocator with PyTorch's caching allocator: the context's
+    links, clover term, P, D_c and workspace come from it, the results equal
+    those of a context that uses hipMalloc, and every block handed out is
+    handed back by the time the context is destroyed."""
+    import torch
+    from paper_1202_2462_amd.mgdd import ALLOC_FN, F64, FREE_FN, MIXED, mgdd_set_allocator
+    dims, block, agg, N = (8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 4, 4), 8
+    op = problem(dims, seed=25, m0=0.05, eps=0.5)
+    dev = torch.cuda.current_device()
+    live = {}
+    counts = {"alloc": 0, "free": 0}
+
+    def alloc(nbytes, user):
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+        live[p] = int(nbytes)
+        counts["alloc"] += 1
+        return p
+
+    def free(p, user):
+        counts["free"] += 1
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    afn, ffn = ALLOC_FN(alloc), FREE_FN(free)
+    from paper_1202_2462_amd.mgdd import Lattice
+    lat = Lattice(dims, block)
+    mgdd_set_allocator(lat.ctx, afn, ffn)
+    lat.set_gauge(op.U, op.m0, op.csw)
+    tv = latgen.gaussian_fields(dims, N, 26)
+    lat.build_P(agg, lat.pack(tv, F64))
+    b = lat.pack(latgen.gaussian_fields(dims, 1, 27), F64)
+    z, st = lat.solve(b, precision=MIXED, restart=20, tol=1e-10, maxit=400)
+    say("allocations through the caller", counts)
+    assert counts["alloc"] > 0 and st[0].converged
+    ref = lattice(op, block)
+    ref.build_P(agg, ref.pack(tv, F64))
+    zr, str_ = ref.solve(b, precision=MIXED, restart=20, tol=1e-10, maxit=400)
+    assert st[0].iters == str_[0].iters
+    assert rel(lat.unpack(z), ref.unpack(zr)) < 1e-14
+    lat.close()
+    ref.close()
+    assert counts["free"] == counts["alloc"] and not live

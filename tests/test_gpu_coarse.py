@@ -156,3 +156,39 @@ def test_rank_deficient_test_vectors_rejected():
     with pytest.raises(MgddError) as e:
         lat.build_P((4, 4, 4, 4), lat.pack(tv, F64))
     assert e.value.code == ERANK
+
+
+# many aggregates: 1024 coarse sites (the restriction then runs one workgroup
+# per (aggregate, field), the launch form of the 32^3 x 64 and 48^3 x 96
+# workloads), and the 16^3 x 32 shape with 20 test vectors (512 coarse sites,
+# 40 x 40 blocks)
+LARGE = [((32, 16, 16, 32), (4, 4, 4, 4), (4, 4, 4, 4), 8),
+         ((16, 16, 16, 32), (4, 4, 4, 4), (4, 4, 4, 4), 20)]
+
+
+@pytest.mark.parametrize("dims,block,agg,N", LARGE)
+def test_transfer_and_coarse_parity_many_aggregates(dims, block, agg, N):
+    from paper_1202_2462_amd.mgdd import F32, F64
+    say("transfer and coarse parity, many aggregates", dims, agg, N)
+    op, lat, tl, tv = setup(dims, block, agg, N)
+    Vc = lat.Vc
+    f = latgen.gaussian_fields(dims, 2, 5)
+    c = latgen.gaussian_vector(2 * Vc * 2 * N, 6).reshape(2, Vc, 2, N)
+    want_r = np.stack([tl.restrict(f[i]) for i in range(2)])
+    want_p = np.stack([tl.prolong(c[i]) for i in range(2)])
+    for prec, tol in ((F64, TOL64), (F32, TOL32)):
+        for nr in (1, 2):
+            got_r = to_np_coarse(lat.restrict(lat.pack(f[:nr], prec)))
+            assert rel(got_r, want_r[:nr]) < tol, (prec, nr, rel(got_r, want_r[:nr]))
+        got_p = lat.unpack(lat.prolong(to_dev_coarse(lat, c, prec)))
+        assert rel(got_p, want_p) < tol, (prec, rel(got_p, want_p))
+    back = lat.unpack(lat.prolong(lat.restrict(lat.pack(tv[:2], F64))))
+    assert rel(back, tv[:2]) < 1e-12
+    for nrhs in (1, 12):
+        x = latgen.gaussian_vector(nrhs * Vc * 2 * N, 30 + nrhs).reshape(nrhs, Vc, 2, N)
+        want = np.stack([tl.coarse_apply(x[i]) for i in range(nrhs)])
+        for prec, tol in ((F64, TOL64), (F32, TOL32)):
+            got = to_np_coarse(lat.coarse_apply(to_dev_coarse(lat, x, prec)))
+            err = max(rel(got[i], want[i]) for i in range(nrhs))
+            say("  D_c", nrhs, "rhs", prec, err)
+            assert err < tol, (nrhs, prec, err)

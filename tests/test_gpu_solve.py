@@ -5,6 +5,7 @@ import pytest
 
 import latgen
 from gpu_common import lattice, problem, rel, say
+from helpers import aligned_difference
 from oracle import solvers
 
 pytestmark = pytest.mark.gpu
@@ -220,3 +221,92 @@ def test_bootstrap_full_invariants(chunk):
     z, stats = lat.solve(lat.pack(b, F64), precision=PLAIN_F64, restart=20, tol=1e-10, maxit=400)
     say("bootstrap solve iters gpu", stats[0].iters, "oracle", st_or.iters)
     assert stats[0].converged and abs(stats[0].iters - st_or.iters) <= 2
+
+
+def test_bootstrap_full_dimension_matches_oracle():
+    """Both setup parts element by element (Section 3, "Bootstrap Setup"): with
+    as many Arnoldi steps as D_c has rows (4^3 x 8, 4^4 blocks and aggregates,
+    N = 8: 32 rows) the harmonic Ritz pairs are the exact eigenpairs of D_c,
+    so the second part is a well-conditioned map and the GPU's test vectors
+    (unique up to one phase each) must equal the oracle's, which are pinned by
+    a step-by-step dense reconstruction in test_oracle_bootstrap.py."""
+    import torch
+    from paper_1202_2462_amd.mgdd import F64
+    dims, block, N = (4, 4, 4, 8), (4, 4, 4, 4), 8
+    op = problem(dims, seed=17, eps=0.5, m0=0.05, csw=1.0)
+    say("bootstrap full dimension", dims)
+    rnd = latgen.gaussian_fields(dims, N, 50)
+    nc = 2 * 2 * N
+    start = latgen.gaussian_vector(nc, 51)
+    st = torch.tensor(np.stack([start.real, start.imag], -1), dtype=torch.float64, device="cuda")
+    tv_or, tl = solvers.bootstrap(op, block, block, N, 3, 3, 4, rnd, start, m_arnoldi=nc)
+    lat = lattice(op, block)
+    lat.setup(block, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, arnoldi_m=nc, prec=F64)
+    tv_gpu = lat.unpack(lat.test_vectors())
+    diff = aligned_difference(tv_gpu, tv_or)
+    say("test vectors (phase aligned)", diff)
+    assert diff < 1e-8
+    x = latgen.gaussian_fields(dims, 1, 52)
+    proj_or = tl.prolong(tl.restrict(x[0]))
+    proj_gpu = lat.unpack(lat.prolong(lat.restrict(lat.pack(x, F64))))[0]
+    say("projector", rel(proj_gpu, proj_or))
+    assert rel(proj_gpu, proj_or) < 1e-8
+
+
+def test_c0_recipe_two_level_solve():
+    """The 8^4 workload exactly as its recipe states it: links exp(0.35 i H),
+    c_sw = 1.0, the bare mass from tests/golden/m0.json (leftmost eigenvalue
+    of D at real part 0.05), SAP blocks and aggregates 4^4, N = 8, nu = iota =
+    3, MR(4), FGMRES(20), plain FP64, tolerance 1e-10, one Gaussian right-hand
+    side (seeds of the workload). The GPU's residual is recomputed by the
+    oracle; its solution is compared with an oracle solution converged to
+    1e-12 (the bound ||z - z*|| / ||z*|| <= kappa(D) ||r|| / ||b|| is reported
+    beside the measured difference, kappa from power and inverse iterations of
+    the oracle)."""
+    import json
+    import os
+
+    import torch
+    from paper_1202_2462_amd.mgdd import F64, PLAIN_F64
+    w = latgen.WORKLOADS["c0"]
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "m0.json")
+    m0 = json.load(open(path))["c0"]["m0"]
+    dims, block, agg, N = tuple(w["dims"]), tuple(w["block"]), tuple(w["agg"]), w["ntv"]
+    say("c0 recipe", dims, "m0", m0)
+    op = solvers.Operator(dims, latgen.workload_gauge("c0"), m0, w["csw"])
+    rnd = latgen.gaussian_fields(dims, N, latgen.TAG_TV)
+    Vc = int(np.prod(dims) // np.prod(agg))
+    start = latgen.gaussian_vector(Vc * 2 * N, latgen.TAG_ARNOLDI)
+    b = latgen.gaussian_fields(dims, 1, latgen.TAG_RHS)
+    _, tl = solvers.bootstrap(op, block, agg, N, w["nu"], w["iota"], w["mr"], rnd, start)
+    z_ref, st_ref = solvers.fgmres(op.apply, tl.precond, b[0], w["restart"], 1e-12, 2000)
+    _, st_or = solvers.fgmres(op.apply, tl.precond, b[0], w["restart"], w["tol"], 2000)
+    assert st_ref.converged
+    lat = lattice(op, block)
+    st = torch.tensor(np.stack([start.real, start.imag], -1), dtype=torch.float64, device="cuda")
+    lat.setup(agg, lat.pack(rnd, F64), st, nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], prec=F64)
+    z, stats = lat.solve(lat.pack(b, F64), precision=PLAIN_F64, restart=w["restart"], tol=w["tol"], maxit=2000)
+    zg = lat.unpack(z)[0]
+    res = np.linalg.norm(b[0] - op.apply(zg)) / np.linalg.norm(b[0])
+    diff = rel(zg, z_ref)
+    # kappa(D) = sigma_max / sigma_min: power iteration on D^H D, inverse
+    # iteration through oracle solves of D and D^H = gamma_5 D gamma_5
+    g5 = np.array([1, 1, -1, -1], dtype=float)[None, :, None]
+    x = latgen.gaussian_fields(dims, 1, 77)[0]
+    for _ in range(30):
+        x = op.apply_dag(op.apply(x))
+        smax2 = np.linalg.norm(x)
+        x /= smax2
+    y = latgen.gaussian_fields(dims, 1, 78)[0]
+    y /= np.linalg.norm(y)
+    for _ in range(4):
+        u, _ = solvers.fgmres(op.apply, tl.precond, g5 * y, w["restart"], 1e-12, 2000)
+        u, _ = solvers.fgmres(op.apply, tl.precond, g5 * u, w["restart"], 1e-12, 2000)
+        smin2 = 1.0 / np.linalg.norm(u)
+        y = u / np.linalg.norm(u)
+    kappa = np.sqrt(smax2 / smin2)
+    say(f"c0: GPU {stats[0].iters} iterations (oracle {st_or.iters}), residual {res:.3e}, "
+        f"|z - z*| / |z*| = {diff:.3e}, kappa ~ {kappa:.1f}, bound kappa * res = {kappa * res:.3e}")
+    assert stats[0].converged and res <= 1e-10
+    assert abs(stats[0].iters - st_or.iters) <= 2
+    assert diff <= 1e-8

@@ -229,6 +229,19 @@ int mgdd_coarse_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *o
  * shared launches; synchronous (one host read of the Hessenberg matrices). */
 int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * mgdd_coarse_solve, with every buffer of the solve (Krylov basis, Hessenberg
+ * matrices, partial sums, status flag) in a fixed 64 MiB device array of the
+ * library instead of the context's workspace; it calls no hipMalloc, hipFree
+ * or allocating library routine. One copy of the array exists per GPU and is
+ * shared by every context and call on that GPU: calls that overlap on one GPU
+ * (two streams, two host threads) race and must not be issued. iters <= 15.
+ * Errors: MGDD_EINVAL (more than 15 steps, or the solve would need more than
+ * the 64 MiB: (iters + 3) * nrhs coarse fields plus small terms), those of
+ * mgdd_coarse_solve. Synchronous. */
+int mgdd_coarse_solve_noalloc(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x);
+
 /* Two-level preconditioner (Section 3: smoother and coarse-grid correction
  * alternate): z = P GMRES_iters(D_c, P^H r) followed by nu Schwarz sweeps
  * (mr_iters MR steps per block) on D z = r. r: FP64 fine fields; z: fine

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <fstream>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,6 +16,21 @@
 #include "mgdd_internal.h"
 #include "solver.h"
 #include "transfer.h"
+
+// Workspace of mgdd_coarse_solve_noalloc: a fixed device array, one copy on
+// every GPU the library runs on, held until the process ends. Host code never
+// passes `scratch` itself to a kernel (in host code the name is a stand-in,
+// not a device address); it uses the address hipGetSymbolAddress returns for
+// the current device, recorded per device when a context is created.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static void *scratch_dev[NOALLOC_MAX_DEVICES];
+static std::mutex scratch_mu;
+
+__global__ void zero_int_kernel(int *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
 
 namespace mgdd {
 
@@ -222,7 +238,21 @@ int mgdd_create(const int dims[4], const int block[4], int t_antiperiodic, void 
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->c.dev) == hipSuccess && v > 0)
             ctx->c.lds_max = (size_t)v;
     }
-    int rc = setup_geometry(&ctx->c, dims, block);
+    int rc = MGDD_OK;
+    {
+        // device address of the allocation-free workspace on this device
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        const int dv = ctx->c.dev;
+        if (dv < 0 || dv >= NOALLOC_MAX_DEVICES) {
+            rc = fail(&ctx->c, MGDD_EINVAL, "device index beyond the supported range");
+        } else if (!scratch_dev[dv]) {
+            void *p = nullptr;
+            rc = hip_check(&ctx->c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the scratch array");
+            if (!rc && !p) rc = fail(&ctx->c, MGDD_EHIP, "address of the scratch array is null");
+            if (!rc) scratch_dev[dv] = p;
+        }
+    }
+    if (!rc) rc = setup_geometry(&ctx->c, dims, block);
     if (rc) {
         // keep the context so that the caller can read the error, then free it
         std::string msg = ctx->c.err;
@@ -689,6 +719,41 @@ int mgdd_coarse_solve(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *
     if (!rc && !status) rc = fail(c, MGDD_ENOMEM, "coarse solve workspace");
     if (!rc) rc = hip_check(c, hipMemsetAsync(status, 0, sizeof(int), c->stream), "memset");
     if (!rc) rc = coarse_gmres(c, prec, iters, nrhs, b, x, A, status);
+    int hstatus = 0;
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, c->stream), "read");
+    if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!rc && hstatus) rc = fail(c, MGDD_ENAN, "NaN in the coarse solve");
+    return rc;
+    GUARD_END
+}
+
+int mgdd_coarse_solve_noalloc(mgdd_ctx *ctx, int prec, int nrhs, int iters, const void *b, void *x) {
+    if (!ctx || !b || !x || !valid_prec(prec) || nrhs <= 0 || iters < 1) return MGDD_EINVAL;
+    if (b == x) return fail(&ctx->c, MGDD_EINVAL, "b and x alias");
+    if (iters > ARNOLDI_FUSED_MAX_STEPS || iters > LSQ_MAX_STEPS)
+        return fail(&ctx->c, MGDD_EINVAL,
+                    "the allocation-free coarse solve takes at most " + std::to_string(ARNOLDI_FUSED_MAX_STEPS) +
+                        " GMRES steps");
+    int rc = need_coarse(ctx);
+    if (rc) return rc;
+    GUARD_BEGIN
+    Ctx *c = &ctx->c;
+    void *base = (c->dev >= 0 && c->dev < NOALLOC_MAX_DEVICES) ? scratch_dev[c->dev] : nullptr;
+    if (!base) return fail(c, MGDD_ENOTREADY, "no scratch array on this device");
+    const size_t need = coarse_gmres_bytes(c, prec, iters, nrhs) + 256;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(c, MGDD_EINVAL,
+                    "the allocation-free coarse solve needs " + std::to_string(need) + " bytes of scratch, more than its " +
+                        std::to_string(NOALLOC_SCRATCH_BYTES) + " (fewer right-hand sides or steps per call)");
+    Arena A;
+    A.base = (char *)base;
+    A.cap = NOALLOC_SCRATCH_BYTES;
+    int *status = (int *)A.take(sizeof(int));
+    // cleared by a kernel, not by a memset node
+    zero_int_kernel<<<1, 64, 0, c->stream>>>(status);
+    rc = hip_check(c, hipGetLastError(), "zero kernel");
+    if (!rc) rc = coarse_gmres(c, prec, iters, nrhs, b, x, A, status);
+    if (!rc && A.need) rc = fail(c, MGDD_EINVAL, "scratch estimate of the coarse solve too small");
     int hstatus = 0;
     if (!rc) rc = hip_check(c, hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, c->stream), "read");
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");

@@ -129,6 +129,7 @@ _sig("mgdd_restrict", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_prolong", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_coarse_apply", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_coarse_solve", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp)
+_sig("mgdd_coarse_solve_noalloc", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp)
 _sig("mgdd_precondition", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
      _vp, _vp)
 _sig("mgdd_setup_bootstrap", ctypes.c_int, _vp, ctypes.POINTER(SetupParams), _vp, _vp)
@@ -263,6 +264,10 @@ def mgdd_coarse_apply(ctx, prec, nrhs, x, y):
 
 def mgdd_coarse_solve(ctx, prec, nrhs, iters, b, x):
     return _check(ctx, _lib.mgdd_coarse_solve(ctx, prec, nrhs, iters, _ptr(b), _ptr(x)))
+
+
+def mgdd_coarse_solve_noalloc(ctx, prec, nrhs, iters, b, x):
+    return _check(ctx, _lib.mgdd_coarse_solve_noalloc(ctx, prec, nrhs, iters, _ptr(b), _ptr(x)))
 
 
 def mgdd_precondition(ctx, prec, nrhs, nu, mr_iters, coarse_iters, r, z):

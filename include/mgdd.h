@@ -265,10 +265,17 @@ typedef struct {
                          of the second part's Gram matrix, formed as
                          <w_i, D^H D w_j> without holding D W. Automatic is the full
                          form below 2^22 sites and chunks of 4 from there on. */
+    unsigned long long seed;  /* stream of the random vectors drawn by the library when
+                                 mgdd_setup_bootstrap gets random_vectors = NULL */
 } mgdd_setup_params;
 
 /* Bootstrap setup (Section 3, "Bootstrap Setup"). Part 1: the ntv random
- * fields (random_vectors: ntv FP64 device fields, read only) get nu rounds of
+ * fields (random_vectors: ntv FP64 device fields, read only; or NULL: drawn
+ * by the library from stream params->seed of the counter-based generator
+ * SplitMix64 (Steele, Lea, Flood 2014), value i = mix64(seed G + (i+1) G),
+ * G = 0x9E3779B97F4A7C15, uniforms from the top 53 bits, complex Gaussian
+ * element e = sqrt(-2 ln(1 - u_2e)) exp(2 pi i u_2e+1), e counted in the
+ * canonical order ((field V + site) 12 + component)) get nu rounds of
  * one Schwarz sweep with b = 0, each followed by a global modified
  * Gram-Schmidt in index order; then P and D_c. Part 2 (n_part2 times):
  * harmonic Ritz pairs (lambda_i, phi_i) of D_c (target 0, the ntv of smallest
@@ -487,15 +494,21 @@ enum { MGDD_KERNEL_DIRAC = 0, MGDD_KERNEL_SAP = 1 };
 /* on: nonzero to enable, 0 to disable. Errors: MGDD_EHIP (event creation). */
 int mgdd_timing_enable(mgdd_ctx *ctx, int on);
 
-/* Totals for one kernel family (MGDD_KERNEL_*) and precision (MGDD_F64 or
- * MGDD_F32), after a synchronisation of the context's stream. Outputs (each
- * may be NULL): total_ms = sum of launch durations in milliseconds;
- * site_updates = sum over launches of sites times right-hand sides processed
- * (the sites of one colour for a Schwarz launch); launches = number of
- * launches. reset: nonzero to zero these totals afterwards. Errors:
+/* Totals for one kernel family (MGDD_KERNEL_*) and precision (MGDD_F64,
+ * MGDD_F32 or MGDD_F16), after a synchronisation of the context's stream.
+ * Outputs (each may be NULL): total_ms = sum of launch durations in
+ * milliseconds; site_updates = sum over launches of sites times right-hand
+ * sides processed (the sites of one colour for a Schwarz launch); launches =
+ * number of launches; alg_bytes = sum over launches of the algorithmic HBM
+ * bytes of each launch (links and clover term read once per launch, the
+ * spinors of every right-hand side read and written once: per site
+ * 1152 + 384 n bytes for an FP64 apply of n fields, 1152 + 288 n for the FP64
+ * apply of FP32 fields, 576 + 192 n (FP32) or 576 + 96 n (half) otherwise;
+ * per site of a Schwarz colour step 576 + 288 n (FP32) or 1152 + 576 n
+ * (FP64)). reset: nonzero to zero these totals afterwards. Errors:
  * MGDD_EINVAL (bad kernel or precision). */
 int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *total_ms, double *site_updates,
-                     long long *launches);
+                     long long *launches, double *alg_bytes);
 
 #ifdef __cplusplus
 }

@@ -138,6 +138,7 @@ int kt_flush(Ctx *c) {
         const int f = k.fam[i] / 3, p = k.fam[i] % 3;
         k.ms[f][p] += ms;
         k.usum[f][p] += k.units[i];
+        k.bsum[f][p] += k.bytes[i];
         k.launches[f][p]++;
     }
     k.used = 0;
@@ -157,12 +158,13 @@ int kt_begin(Ctx *c) {
     return s;
 }
 
-void kt_end(Ctx *c, int slot, int family, int prec, double units) {
+void kt_end(Ctx *c, int slot, int family, int prec, double units, double bytes) {
     if (slot < 0) return;
     KTimer &k = c->kt;
     (void)hipEventRecord(k.ev[2 * slot + 1], c->stream);
     k.fam[slot] = family * 3 + prec;
     k.units[slot] = units;
+    k.bytes[slot] = bytes;
 }
 
 static void kt_release(Ctx *c) {
@@ -784,7 +786,7 @@ int mgdd_precondition(mgdd_ctx *ctx, int prec, int nrhs, int nu, int mr_iters, i
 
 int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const void *random_vectors,
                          const void *arnoldi_start) {
-    if (!ctx || !params || !random_vectors || !arnoldi_start) return MGDD_EINVAL;
+    if (!ctx || !params || !arnoldi_start) return MGDD_EINVAL;
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     const mgdd_setup_params *sp = params;
     if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0 ||
@@ -959,6 +961,7 @@ int mgdd_timing_enable(mgdd_ctx *ctx, int on) {
         }
         c->kt.fam.assign(KT_SLOTS, 0);
         c->kt.units.assign(KT_SLOTS, 0.0);
+        c->kt.bytes.assign(KT_SLOTS, 0.0);
     }
     c->kt.on = true;
     return MGDD_OK;
@@ -966,7 +969,7 @@ int mgdd_timing_enable(mgdd_ctx *ctx, int on) {
 }
 
 int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *total_ms, double *site_updates,
-                     long long *launches) {
+                     long long *launches, double *alg_bytes) {
     if (!ctx || kernel < 0 || kernel >= KF_COUNT || !valid_fine_prec(prec)) return MGDD_EINVAL;
     GUARD_BEGIN
     Ctx *c = &ctx->c;
@@ -976,9 +979,11 @@ int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *tot
     if (total_ms) *total_ms = c->kt.ms[kernel][p];
     if (site_updates) *site_updates = c->kt.usum[kernel][p];
     if (launches) *launches = c->kt.launches[kernel][p];
+    if (alg_bytes) *alg_bytes = c->kt.bsum[kernel][p];
     if (reset) {
         c->kt.ms[kernel][p] = 0;
         c->kt.usum[kernel][p] = 0;
+        c->kt.bsum[kernel][p] = 0;
         c->kt.launches[kernel][p] = 0;
     }
     return MGDD_OK;

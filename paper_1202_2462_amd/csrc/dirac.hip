@@ -87,7 +87,8 @@ int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64) {
     const int slot = kt_begin(c);
     dirac_widen_kernel<<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
                                                    (const float2 *)in32, (double2 *)out64, nrhs, nwg);
-    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs);
+    // links and clover term once per launch, FP32 in and FP64 out per field
+    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs, (double)c->g.V * (1152.0 + 288.0 * nrhs));
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
 
@@ -104,7 +105,10 @@ int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
         dirac_kernel<float, _Float16><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32,
                                                                   (const float2 *)c->A32, (const half_cx *)in,
                                                                   (half_cx *)out, nrhs, nwg);
-    kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs);
+    // links and clover term once per launch (FP64, or FP32 for FP32 and half
+    // spinors), spinor in and out per field
+    const double lc = prec == MGDD_F64 ? 1152.0 : 576.0, sp = 2.0 * 12 * csize(prec);
+    kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs, (double)c->g.V * (lc + sp * nrhs));
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
 

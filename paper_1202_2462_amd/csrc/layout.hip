@@ -232,6 +232,44 @@ __global__ void clover_kernel(Geom g, const double2 *__restrict__ Uc, double m0,
 
 }  // namespace
 
+// Gaussian random fields from a counter-based generator: SplitMix64 (Steele,
+// Lea, Flood, "Fast splittable pseudorandom number generators", 2014) with
+// value i of stream `seed` = mix64(seed G + (i + 1) G), G = 0x9E3779B97F4A7C15
+// (64-bit wrap-around), a uniform in [0, 1) from its top 53 bits, and the
+// Box-Muller transform (1958) of the pair (u1, u2) = (value 2e, value 2e + 1):
+// element e = sqrt(-2 ln(1 - u1)) (cos 2 pi u2 + i sin 2 pi u2), e counted in
+// the canonical order ((field * V + lexicographic site) * 12 + component).
+__device__ inline uint64_t splitmix_value(uint64_t seed, uint64_t i) {
+    const uint64_t G = 0x9E3779B97F4A7C15ull;
+    uint64_t z = seed * G + (i + 1) * G;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void gaussian_fields_kernel(Geom g, int nf, uint64_t seed, double2 *__restrict__ dst) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)nf * g.V) return;
+    const int f = (int)(i / g.V), d = (int)(i % g.V);
+    const size_t s = (size_t)lex_of(g, d);
+    double2 *o = dst + (size_t)f * 12 * g.V + d;
+    for (int k = 0; k < 12; k++) {
+        const uint64_t e = ((size_t)f * g.V + s) * 12 + k;
+        const double u1 = (double)(splitmix_value(seed, 2 * e) >> 11) * (1.0 / 9007199254740992.0);
+        const double u2 = (double)(splitmix_value(seed, 2 * e + 1) >> 11) * (1.0 / 9007199254740992.0);
+        const double r = sqrt(-2.0 * log1p(-u1));
+        double sn, cs;
+        sincos(2.0 * M_PI * u2, &sn, &cs);
+        o[(size_t)k * g.V] = make_double2(r * cs, r * sn);
+    }
+}
+
+int launch_gaussian_fields(Ctx *c, int nf, unsigned long long seed, void *dst) {
+    size_t n = (size_t)nf * c->g.V;
+    gaussian_fields_kernel<<<nblk(n), TPB, 0, c->stream>>>(c->g, nf, (uint64_t)seed, (double2 *)dst);
+    return hip_check(c, hipGetLastError(), "random fields kernel");
+}
+
 int launch_pack(Ctx *c, int prec, int nrhs, const double2 *canon, void *dst) {
     size_t n = (size_t)nrhs * c->g.V;
     if (prec == MGDD_F64)

@@ -115,9 +115,11 @@ struct KTimer {
     std::vector<hipEvent_t> ev;      // 2 per slot
     std::vector<int> fam;            // family * 3 + precision code, per used slot
     std::vector<double> units;       // site-rhs updates, per used slot
+    std::vector<double> bytes;       // algorithmic bytes, per used slot
     int used = 0;
     double ms[KF_COUNT][3] = {};
     double usum[KF_COUNT][3] = {};
+    double bsum[KF_COUNT][3] = {};
     long long launches[KF_COUNT][3] = {};
 };
 
@@ -175,7 +177,7 @@ void *ensure_scratch(Ctx *c, size_t bytes);
 double *ensure_red(Ctx *c, size_t ndoubles);
 // kt_begin returns a slot (or -1 when timing is off); kt_end closes it.
 int kt_begin(Ctx *c);
-void kt_end(Ctx *c, int slot, int family, int prec, double units);
+void kt_end(Ctx *c, int slot, int family, int prec, double units, double bytes);
 int kt_flush(Ctx *c);
 inline size_t csize(int prec) { return prec == MGDD_F64 ? 16 : prec == MGDD_F32 ? 8 : 4; }
 inline size_t fine_elems(const Ctx *c, int nrhs) { return (size_t)nrhs * 12 * c->g.V; }
@@ -187,6 +189,8 @@ int launch_pack(Ctx *c, int prec, int nrhs, const double2 *canon, void *dst);
 int launch_unpack(Ctx *c, int prec, int nrhs, const void *src, double2 *canon);
 int launch_gauge_ingest(Ctx *c, const double2 *Ucanon);
 int launch_convert(Ctx *c, int from, int to, size_t n, const void *src, void *dst);
+// nf FP64 Gaussian random fields (device layout) from the counter-based generator of stream seed
+int launch_gaussian_fields(Ctx *c, int nf, unsigned long long seed, void *dst);
 
 // dirac.hip
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out);

@@ -920,7 +920,10 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     double2 *gdev = (double2 *)A.take((size_t)4 * N * N * 16 + 256), *ydev = (double2 *)A.take((size_t)4 * N * N * 16 + 256);
     if (!ydev) return fail(c, MGDD_ENOMEM, "setup workspace");
     for (int i = 0; i < N; i++) Vt[i] = (char *)vt + (size_t)i * n * 16;
-    rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+    if (rv64)
+        rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+    else
+        rc = launch_gaussian_fields(c, N, sp->seed, vt);
     if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, (size_t)R * n * csize(p), c->stream), "memset");
     // part 1: nu rounds of (one SAP sweep with b = 0 on all vectors, global MGS)
     for (int it = 0; it < sp->nu && !rc; it++) {

@@ -70,7 +70,7 @@ _sig("mgdd_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(c
 class SetupParams(ctypes.Structure):
     _fields_ = [("agg", ctypes.c_int * 4), ("ntv", ctypes.c_int), ("nu", ctypes.c_int), ("iota", ctypes.c_int),
                 ("mr_iters", ctypes.c_int), ("arnoldi_m", ctypes.c_int), ("n_part2", ctypes.c_int),
-                ("prec", ctypes.c_int), ("chunk", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("chunk", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
 
 
 class SolveParams(ctypes.Structure):
@@ -145,7 +145,7 @@ _sig("mgdd_coarse_sap", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.PO
      _vp, _vp)
 _sig("mgdd_timing_enable", ctypes.c_int, _vp, ctypes.c_int)
 _sig("mgdd_timing_read", ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong))
+     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double))
 
 
 def declared_symbols() -> list[str]:
@@ -357,10 +357,10 @@ def mgdd_timing_enable(ctx, on=True):
 
 def mgdd_timing_read(ctx, kernel, prec, reset=False):
     """Returns (total_ms, site_updates, launches) for one kernel family."""
-    ms, units, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+    ms, units, n, nbytes = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
     _check(ctx, _lib.mgdd_timing_read(ctx, kernel, prec, 1 if reset else 0, ctypes.byref(ms), ctypes.byref(units),
-                                      ctypes.byref(n)))
-    return ms.value, units.value, n.value
+                                      ctypes.byref(n), ctypes.byref(nbytes)))
+    return ms.value, units.value, n.value, nbytes.value
 
 
 # --------------------------------------------------------------------- convenience wrapper
@@ -577,9 +577,11 @@ class Lattice:
         self.Vc = int(np.prod(self.cdims))
 
     def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64,
-              chunk=0):
-        N = random_vectors.shape[0]
-        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, arnoldi_m, n_part2, prec, chunk)
+              chunk=0, ntv=None, seed=0):
+        """random_vectors: N FP64 fields, or None to have the library draw
+        ntv of them from stream `seed`"""
+        N = random_vectors.shape[0] if random_vectors is not None else int(ntv)
+        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, arnoldi_m, n_part2, prec, chunk, seed)
         mgdd_setup_bootstrap(self.ctx, sp, random_vectors, arnoldi_start)
         self.agg = tuple(agg)
         self.N = N

@@ -310,3 +310,31 @@ def test_c0_recipe_two_level_solve():
     assert stats[0].converged and res <= 1e-10
     assert abs(stats[0].iters - st_or.iters) <= 2
     assert diff <= 1e-8
+
+
+@pytest.mark.parametrize("seed", [12345, 2 ** 63 + 977])
+def test_setup_draws_its_random_vectors(seed):
+    """random_vectors = NULL: the library draws the setup's random fields from
+    stream `seed` of its counter-based generator (SplitMix64 + Box-Muller).
+    With no smoothing round and no second part the test vectors are those
+    fields, equal to latgen.gaussian_fields of the same stream (the same
+    published generator written in numpy; the transcendental functions may
+    differ in the last bit); a first setup part from them equals the one from
+    the host-drawn fields."""
+    import torch
+    from paper_1202_2462_amd.mgdd import F64
+    dims, block, agg, N, op = small_problem(seed=11, m0=0.02)
+    say("library-drawn random vectors, seed", seed)
+    lat = lattice(op, block)
+    rnd = latgen.gaussian_fields(dims, N, seed)
+    start = latgen.gaussian_vector(16 * 2 * N, 91)
+    st = torch.tensor(np.stack([start.real, start.imag], -1), dtype=torch.float64, device="cuda")
+    lat.setup(agg, None, st, nu=0, iota=0, mr_iters=4, n_part2=0, prec=F64, ntv=N, seed=seed)
+    tv = lat.unpack(lat.test_vectors())
+    say("drawn vs latgen", rel(tv, rnd), np.max(np.abs(tv - rnd)))
+    assert rel(tv, rnd) < 1e-14
+    lat.setup(agg, None, st, nu=3, iota=3, mr_iters=4, n_part2=0, prec=F64, ntv=N, seed=seed)
+    a = lat.unpack(lat.test_vectors())
+    lat.setup(agg, lat.pack(rnd, F64), st, nu=3, iota=3, mr_iters=4, n_part2=0, prec=F64)
+    b = lat.unpack(lat.test_vectors())
+    assert rel(a, b) < 1e-12

@@ -263,18 +263,36 @@ __global__ __launch_bounds__(TPB) void norm_partials_kernel(size_t n, const C<T>
     }
 }
 
-// out[q] = sum_g part[q * np + g]
-__global__ __launch_bounds__(64) void sum_kernel(int np, const double2 *__restrict__ part, double2 *__restrict__ out) {
-    const int q = blockIdx.x, lane = threadIdx.x;
+// out[q] = sum_g part[q * np + g], in a fixed order: thread t adds the
+// entries t, t + NT, ..., then the waves' sums are added in wave order. NT =
+// 64 for a few hundred partials, 1024 for one per coarse site (tens of
+// thousands: one wave would wait on hundreds of dependent loads)
+template <int NT>
+__global__ __launch_bounds__(NT) void sum_kernel(int np, const double2 *__restrict__ part, double2 *__restrict__ out) {
+    __shared__ double2 red[NT / 64];
+    const int q = blockIdx.x, t = threadIdx.x;
     double a = 0, b = 0;
-    for (int g = lane; g < np; g += 64) {
+    for (int g = t; g < np; g += NT) {
         double2 v = part[(size_t)q * np + g];
         a += v.x;
         b += v.y;
     }
     a = wave_sum(a);
     b = wave_sum(b);
-    if (lane == 0) out[q] = make_double2(a, b);
+    if (NT == 64) {
+        if (t == 0) out[q] = make_double2(a, b);
+        return;
+    }
+    if ((t & 63) == 0) red[t >> 6] = make_double2(a, b);
+    __syncthreads();
+    if (t == 0) {
+        double2 s = make_double2(0, 0);
+        for (int w = 0; w < NT / 64; w++) {
+            s.x += red[w].x;
+            s.y += red[w].y;
+        }
+        out[q] = s;
+    }
 }
 
 // one element per thread up to 1024 workgroups: these passes are short and
@@ -329,7 +347,7 @@ int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, con
         const double2 *pin = part1;
         int npin = Vc;
         if (presum) {
-            sum_kernel<<<(j + 1) * nb, 64, 0, c->stream>>>(Vc, part1, part1s);
+            sum_kernel<1024><<<(j + 1) * nb, 1024, 0, c->stream>>>(Vc, part1, part1s);
             pin = part1s;
             npin = 1;
         }
@@ -348,7 +366,7 @@ int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, con
         w = y;
     }
     if (!rc) {
-        sum_kernel<<<nb, 64, 0, c->stream>>>(G, part3, NR + (size_t)m * nb);
+        sum_kernel<64><<<nb, 64, 0, c->stream>>>(G, part3, NR + (size_t)m * nb);
         rc = hip_check(c, hipGetLastError(), "arnoldi");
     }
     return rc;
@@ -606,11 +624,11 @@ int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, 
 #define CGSL(T)                                                                                                   \
     do {                                                                                                          \
         dot_partials_long_kernel<T><<<grid, TPB, 0, c->stream>>>(n, vl, k, (const C<T> *)w, part);                 \
-        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part, h1);                                                    \
+        sum_kernel<64><<<k * nb, 64, 0, c->stream>>>(G, part, h1);                                                    \
         orth_long_kernel<T><<<grid, TPB, 0, c->stream>>>(n, vl, k, h1, 1, (C<T> *)w, part2, 0);                   \
-        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part2, h2);                                                   \
+        sum_kernel<64><<<k * nb, 64, 0, c->stream>>>(G, part2, h2);                                                   \
         orth_long_kernel<T><<<grid, TPB, 0, c->stream>>>(n, vl, k, h2, 1, (C<T> *)w, part, 1);                    \
-        sum_kernel<<<nb, 64, 0, c->stream>>>(G, part, nrm);                                                       \
+        sum_kernel<64><<<nb, 64, 0, c->stream>>>(G, part, nrm);                                                       \
     } while (0)
         if (p == MGDD_F64) CGSL(double); else CGSL(float);
 #undef CGSL
@@ -622,11 +640,11 @@ int fused_cgs2(Ctx *c, int p, size_t n, int nb, void *const *V, int k, void *w, 
 #define CGS(T, NV)                                                                                                 \
     do {                                                                                                           \
         dot_partials_kernel<T, NV><<<grid, TPB, 0, c->stream>>>(n, vl, k, (const C<T> *)w, part);                  \
-        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part, h1);                                                     \
+        sum_kernel<64><<<k * nb, 64, 0, c->stream>>>(G, part, h1);                                                     \
         arnoldi_orth_kernel<T, NV><<<grid, TPB, 0, c->stream>>>(n, vl, k, h1, 1, (C<T> *)w, part2, 0, nullptr);  \
-        sum_kernel<<<k * nb, 64, 0, c->stream>>>(G, part2, h2);                                                    \
+        sum_kernel<64><<<k * nb, 64, 0, c->stream>>>(G, part2, h2);                                                    \
         arnoldi_orth_kernel<T, NV><<<grid, TPB, 0, c->stream>>>(n, vl, k, h2, 1, (C<T> *)w, part, 1, nullptr);   \
-        sum_kernel<<<nb, 64, 0, c->stream>>>(G, part, nrm);                                                        \
+        sum_kernel<64><<<nb, 64, 0, c->stream>>>(G, part, nrm);                                                        \
     } while (0)
     if (p == MGDD_F64) {
         if (k <= 4) CGS(double, 4); else if (k <= 8) CGS(double, 8); else CGS(double, 16);

@@ -19,10 +19,13 @@ constexpr int TPB = 256;
 template <typename T, typename S = T> struct SpinorView { using type = FieldView<T>; };
 template <> struct SpinorView<float, _Float16> { using type = HalfFieldView; };
 
-template <typename T, typename S = T>
+// RECON: the links are special unitary, rows 0 and 1 are read and row 2 is
+// rebuilt (a third fewer link bytes); antiperiodic: the sign of the time
+// links at the boundary, which the rebuilt row must carry
+template <typename T, typename S = T, bool RECON = false>
 __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restrict__ Up, const C<T> *__restrict__ Ap,
                                                     const C<S> *__restrict__ in, C<S> *__restrict__ out, int nrhs,
-                                                    int nwg) {
+                                                    int nwg, int antiperiodic) {
     const int w = xcd_block(nwg);
     const int r = w % nrhs;
     const int i = (w / nrhs) * TPB + threadIdx.x;
@@ -30,13 +33,15 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
     const int d = site_in_lex_block_order(g, i);
     int nbr[8];
     site_neighbours(g, d, nbr);
+    T sf = 1, sb = 1;
+    if (RECON) time_link_signs<T>(g, d, antiperiodic, sf, sb);
     const size_t V = g.V;
     LinkViews<T> U(Up, V);
     CloverViews<T> A(Ap, V);
     using FV = typename SpinorView<T, S>::type;
     FV f(in + (size_t)r * 12 * V, V, 12), o(out + (size_t)r * 12 * V, V, 12);
     C<T> acc[12], psi[12], res[12];
-    hop_sum<T>(U, f, d, nbr, acc);
+    hop_sum<T, RECON>(U, f, d, nbr, acc, sf, sb);
     load_spinor<T>(f, d, psi);
     clover_mv<T>(A, d, psi, res);
 #pragma unroll
@@ -56,9 +61,11 @@ struct WidenView {
 
 // dirac_kernel<double> with FP32 input: the FP64 apply of an FP32 field
 // without a converted copy
+template <bool RECON>
 __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 *__restrict__ Up,
                                                           const double2 *__restrict__ Ap, const float2 *__restrict__ in,
-                                                          double2 *__restrict__ out, int nrhs, int nwg) {
+                                                          double2 *__restrict__ out, int nrhs, int nwg,
+                                                          int antiperiodic) {
     const int w = xcd_block(nwg);
     const int r = w % nrhs;
     const int i = (w / nrhs) * TPB + threadIdx.x;
@@ -66,13 +73,15 @@ __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 
     const int d = site_in_lex_block_order(g, i);
     int nbr[8];
     site_neighbours(g, d, nbr);
+    double sf = 1, sb = 1;
+    if (RECON) time_link_signs<double>(g, d, antiperiodic, sf, sb);
     const size_t V = g.V;
     LinkViews<double> U(Up, V);
     CloverViews<double> A(Ap, V);
     WidenView f(in + (size_t)r * 12 * V, V, 12);
     FieldView<double> o(out + (size_t)r * 12 * V, V, 12);
     double2 acc[12], psi[12], res[12];
-    hop_sum<double>(U, f, d, nbr, acc);
+    hop_sum<double, RECON>(U, f, d, nbr, acc, sf, sb);
     load_spinor<double>(f, d, psi);
     clover_mv<double>(A, d, psi, res);
 #pragma unroll
@@ -82,33 +91,46 @@ __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 
 
 }  // namespace
 
+// algorithmic bytes of one apply per site: links (two rows of each when they
+// are rebuilt) and clover term once per launch, spinors in and out per field
+static double dirac_launch_bytes(const Ctx *c, int prec, size_t in_bytes, size_t out_bytes, int nrhs) {
+    const double real = prec == MGDD_F64 ? 8.0 : 4.0;
+    const double links = 4 * (c->links_su3 ? 6 : 9) * 2 * real, clover = 72 * real;
+    return (double)c->g.V * (links + clover + (double)(in_bytes + out_bytes) * nrhs);
+}
+
 int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
+    const int anti = c->t_antiperiodic ? 1 : 0;
     const int slot = kt_begin(c);
-    dirac_widen_kernel<<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
-                                                   (const float2 *)in32, (double2 *)out64, nrhs, nwg);
-    // links and clover term once per launch, FP32 in and FP64 out per field
-    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs, (double)c->g.V * (1152.0 + 288.0 * nrhs));
+    if (c->links_su3)
+        dirac_widen_kernel<true><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
+                                                             (const float2 *)in32, (double2 *)out64, nrhs, nwg, anti);
+    else
+        dirac_widen_kernel<false><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
+                                                              (const float2 *)in32, (double2 *)out64, nrhs, nwg, anti);
+    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs, dirac_launch_bytes(c, MGDD_F64, 96, 192, nrhs));
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
 
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
+    const int anti = c->t_antiperiodic ? 1 : 0;
     const int slot = kt_begin(c);
-    if (prec == MGDD_F64)
-        dirac_kernel<double><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
-                                                         (const double2 *)in, (double2 *)out, nrhs, nwg);
-    else if (prec == MGDD_F32)
-        dirac_kernel<float><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32, (const float2 *)c->A32,
-                                                        (const float2 *)in, (float2 *)out, nrhs, nwg);
-    else
-        dirac_kernel<float, _Float16><<<nwg, TPB, 0, c->stream>>>(c->g, (const float2 *)c->U32,
-                                                                  (const float2 *)c->A32, (const half_cx *)in,
-                                                                  (half_cx *)out, nrhs, nwg);
-    // links and clover term once per launch (FP64, or FP32 for FP32 and half
-    // spinors), spinor in and out per field
-    const double lc = prec == MGDD_F64 ? 1152.0 : 576.0, sp = 2.0 * 12 * csize(prec);
-    kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs, (double)c->g.V * (lc + sp * nrhs));
+#define DIRAC(T, S, R)                                                                                                \
+    dirac_kernel<T, S, R><<<nwg, TPB, 0, c->stream>>>(c->g, (const C<T> *)(prec == MGDD_F64 ? c->U64 : c->U32),       \
+                                                      (const C<T> *)(prec == MGDD_F64 ? c->A64 : c->A32),             \
+                                                      (const C<S> *)in, (C<S> *)out, nrhs, nwg, anti)
+    if (prec == MGDD_F64) {
+        if (c->links_su3) DIRAC(double, double, true); else DIRAC(double, double, false);
+    } else if (prec == MGDD_F32) {
+        if (c->links_su3) DIRAC(float, float, true); else DIRAC(float, float, false);
+    } else {
+        if (c->links_su3) DIRAC(float, _Float16, true); else DIRAC(float, _Float16, false);
+    }
+#undef DIRAC
+    const size_t sp = 12 * csize(prec);
+    kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs, dirac_launch_bytes(c, prec, sp, sp, nrhs));
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
 

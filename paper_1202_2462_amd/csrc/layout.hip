@@ -58,13 +58,22 @@ __global__ void links_kernel(Geom g, const double2 *__restrict__ Uc, double2 *__
     for (int mu = 0; mu < 4; mu++) {
         // antiperiodic in t: the hop across the time boundary carries a sign
         double sg = (antiperiodic && mu == 3 && X[3] == g.L[3] - 1) ? -1.0 : 1.0;
+        double2 r[9];
         for (int k = 0; k < 9; k++) {
             double2 u = Uc[((size_t)s * 4 + mu) * 9 + k];
             if (!isfinite(u.x) || !isfinite(u.y)) atomicOr(bad, 2);
+            r[k] = u;
             u.x *= sg;
             u.y *= sg;
             U64[((size_t)mu * 9 + k) * g.V + d] = u;
             U32[((size_t)mu * 9 + k) * g.V + d] = make_float2((float)u.x, (float)u.y);
+        }
+        // a special unitary link has row 2 = conj(row 0 x row 1): the stencil
+        // kernels then read rows 0 and 1 only (flag 4 when some link is not)
+        for (int a = 0; a < 3; a++) {
+            const int b = (a + 1) % 3, c = (a + 2) % 3;
+            const double2 x = csub(cmul(r[b], r[3 + c]), cmul(r[c], r[3 + b]));
+            if (fabs(x.x - r[6 + a].x) > 1e-12 || fabs(-x.y - r[6 + a].y) > 1e-12) atomicOr(bad, 4);
         }
     }
 }
@@ -319,8 +328,9 @@ int launch_gauge_ingest(Ctx *c, const double2 *Ucanon) {
     if (rc) return rc;
     rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     if (rc) return rc;
+    c->links_su3 = !(hbad & 4);
     if (hbad & 2) return fail(c, MGDD_ENAN, "gauge field holds NaN or Inf");
-    if (hbad) return fail(c, MGDD_EINVAL, "clover term is singular on some site");
+    if (hbad & 1) return fail(c, MGDD_EINVAL, "clover term is singular on some site");
     return MGDD_OK;
 }
 

@@ -143,6 +143,7 @@ struct Ctx {
     int *d_blk_nbr = nullptr;
     // operator
     bool gauge_ready = false;
+    bool links_su3 = false;                 // every link special unitary: row 2 = conj(row 0 x row 1)
     double m0 = 0, csw = 0;
     void *U64 = nullptr, *U32 = nullptr;    // [4][9][V] complex
     void *A64 = nullptr, *A32 = nullptr;    // [36][V] complex pairs (packed Hermitian 6x6 x 2 chiralities)

@@ -519,6 +519,338 @@ __global__ __launch_bounds__(1024) void sap4_kernel(Geom g, const C<T> *__restri
     for (int c = 0; c < 3; c++) zf.st_lane(c, d, 3u * m * zf.cs, cadd(zf.ld_lane(c, d, 3u * m * zf.cs), e[c]));
 }
 
+// ---------------------------------------------------------------- two lanes per site
+//
+// Lane h = threadIdx & 1 of a site owns chirality h (spins 2h and 2h + 1:
+// components 6h .. 6h + 5) of r, rho, e and q, applies that chirality's 6 x 6
+// block of the clover term, and does the hops along directions 2h and 2h + 1
+// (x and y for h = 0, z and t for h = 1). Its hop partial sum has all 12
+// components; one exchange with the other lane of the site (a DPP quad
+// permutation) leaves each lane the sum for its chirality. The links are
+// special unitary (checked at ingest), so the block's forward links are
+// staged in LDS as their first two rows and row 2 is rebuilt where it is used:
+// rho and the links then take about 73 KB of LDS for a 4^4 block, and with at
+// most 128 VGPRs per lane two blocks run on one CU at a time, one block's
+// memory phase overlapping the other's MR steps.
+//
+// The spin projection has no lane-dependent branch: with gamma_mu =
+// [[0, B_mu], [B_mu^H, 0]] and (B l)_s = beta_s l_pi(s), the lane's first
+// direction (x or z) has beta = (-i, -i sig) and its second (y or t)
+// beta = (-1, sig), sig = +1 for h = 0 and -1 for h = 1; pi swaps the two
+// spins for x and y (h = 0) and is the identity for z and t (h = 1). The
+// swap enters through LDS addresses and two selects per component.
+
+// h = (1 -+ gamma) psi projected to its upper half (FWD: 1 - gamma) for the
+// lane's first (FIRST) or second direction; u: upper spins of psi, la / lb:
+// the lower spins l_pi(0), l_pi(1)
+template <bool FIRST, bool FWD>
+__device__ inline void project2(const float2 *u, const float2 *la, const float2 *lb, float sig, float2 *h) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const float2 u0 = u[a], u1 = u[3 + a], p = la[a], q = lb[a];
+        if (FIRST) {          // beta l = (-i l_a, -i sig l_b)
+            h[a] = FWD ? make_float2(u0.x - p.y, u0.y + p.x) : make_float2(u0.x + p.y, u0.y - p.x);
+            h[3 + a] = FWD ? make_float2(fmaf(-sig, q.y, u1.x), fmaf(sig, q.x, u1.y))
+                           : make_float2(fmaf(sig, q.y, u1.x), fmaf(-sig, q.x, u1.y));
+        } else {              // beta l = (-l_a, sig l_b)
+            h[a] = FWD ? make_float2(u0.x + p.x, u0.y + p.y) : make_float2(u0.x - p.x, u0.y - p.y);
+            h[3 + a] = FWD ? make_float2(fmaf(-sig, q.x, u1.x), fmaf(-sig, q.y, u1.y))
+                           : make_float2(fmaf(sig, q.x, u1.x), fmaf(sig, q.y, u1.y));
+        }
+    }
+}
+
+// w = U h (FWD) or U^H h on the two colour vectors of h, then up += w and
+// L_t -+= conj(beta_t) w_t (the lower spins, kept in pi order: lower spin s
+// receives L_pi(s)); forward hops subtract, backward hops add
+template <bool FIRST, bool FWD>
+__device__ inline void accumulate_hop(const float2 *u, const float2 *h, float sig, float2 *up, float2 *L) {
+    float2 w[6];
+    su3_mv<float, !FWD>(u, h, w);
+    su3_mv<float, !FWD>(u, h + 3, w + 3);
+#pragma unroll
+    for (int a = 0; a < 6; a++) up[a] = cadd(up[a], w[a]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const float2 w0 = w[a], w1 = w[3 + a];
+        // FIRST: conj(beta) = (i, i sig); second: (-1, sig)
+        const float2 c0 = FIRST ? make_float2(-w0.y, w0.x) : make_float2(-w0.x, -w0.y);
+        const float2 c1 = FIRST ? make_float2(-sig * w1.y, sig * w1.x) : make_float2(sig * w1.x, sig * w1.y);
+        L[a] = FWD ? csub(L[a], c0) : cadd(L[a], c0);
+        L[3 + a] = FWD ? csub(L[3 + a], c1) : cadd(L[3 + a], c1);
+    }
+}
+
+// rows 0 and 1 of a link from LDS ([6][LS] entries of its direction), row 2 rebuilt
+template <int LS> __device__ inline void link_from_lds(const float2 *lk, int site, float sign, float2 *u) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) u[k] = lk[k * LS + site];
+    su3_row2<float>(u, sign);
+}
+
+// the spinor at `site` of a field in LDS ([12][RS]): upper spins, and the
+// lower spins in pi order (component blocks src0, src1 chosen per lane)
+template <int RS>
+__device__ inline void spinor_from_lds(const float2 *rl, int site, int src0, int src1, float2 *u, float2 *la, float2 *lb) {
+#pragma unroll
+    for (int c = 0; c < 6; c++) u[c] = rl[c * RS + site];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        la[a] = rl[(src0 + a) * RS + site];
+        lb[a] = rl[(src1 + a) * RS + site];
+    }
+}
+
+// the same from a field in memory (device site dn)
+__device__ inline void spinor_from_field(const FieldView<float> &f, int dn, int src0, int src1, float2 *u, float2 *la,
+                                         float2 *lb) {
+#pragma unroll
+    for (int c = 0; c < 6; c++) u[c] = f.ld(c, dn);
+    // src0, src1 in {6, 9}: the lane's choice enters through the vector offset
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        la[a] = f.ld_lane(a, dn, (unsigned)src0 * f.cs);
+        lb[a] = f.ld_lane(a, dn, (unsigned)src1 * f.cs);
+    }
+}
+
+// c ? a : b on values (a select of two array elements' addresses would keep
+// the arrays in scratch memory)
+__device__ inline float2 sel2(bool c, float2 a, float2 b) { return make_float2(c ? a.x : b.x, c ? a.y : b.y); }
+
+// the lane's chirality of the hop sum: lane 0 keeps the upper spins and sends
+// its lower sums (kept in swapped order) to lane 1; lane 1 keeps the lower
+// spins and sends its upper sums
+__device__ inline void exchange_chirality(bool h, const float2 *up, const float2 *L, float2 *hs) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int kp = k < 3 ? k + 3 : k - 3;
+        const float2 send = sel2(h, up[k], L[kp]);
+        const float2 mine = sel2(h, L[k], up[k]);
+        hs[k] = make_float2(mine.x + quad_xor<1>(send.x), mine.y + quad_xor<1>(send.y));
+    }
+}
+
+// the lane's hops whose neighbour lies in the block: the neighbour's spinor
+// from the LDS field fl ([12][RS]), links from LDS (rows 0 and 1 of each
+// site's forward links, [4][6][LS]); up / L accumulate as in accumulate_hop
+template <int RS, int LS>
+__device__ inline void block_hops(const float2 *fl, const float2 *lnk, int h, int l, const int *lnf, const int *lnb,
+                                  int src0, int src1, float sig, float sgf, float sgb, float2 *up, float2 *L) {
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const float2 *lk = lnk + (2 * h + i) * 6 * LS;
+        const float sf = i ? sgf : 1.f, sb = i ? sgb : 1.f;
+        float2 u[9], ps[6], la[3], lb[3], hh[6];
+        if (lnf[i] >= 0) {
+            spinor_from_lds<RS>(fl, lnf[i], src0, src1, ps, la, lb);
+            link_from_lds<LS>(lk, l, sf, u);
+            if (i == 0) {
+                project2<true, true>(ps, la, lb, sig, hh);
+                accumulate_hop<true, true>(u, hh, sig, up, L);
+            } else {
+                project2<false, true>(ps, la, lb, sig, hh);
+                accumulate_hop<false, true>(u, hh, sig, up, L);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (lnb[i] >= 0) {
+            spinor_from_lds<RS>(fl, lnb[i], src0, src1, ps, la, lb);
+            link_from_lds<LS>(lk, lnb[i], sb, u);
+            if (i == 0) {
+                project2<true, false>(ps, la, lb, sig, hh);
+                accumulate_hop<true, false>(u, hh, sig, up, L);
+            } else {
+                project2<false, false>(ps, la, lb, sig, hh);
+                accumulate_hop<false, false>(u, hh, sig, up, L);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int VB>
+__global__ __launch_bounds__(2 * VB) __attribute__((amdgpu_waves_per_eu(4))) void sapc_kernel(
+    Geom g, const float2 *__restrict__ Up, const float2 *__restrict__ Ap, const float2 *__restrict__ b,
+    float2 *__restrict__ z, int colour, int mr, float sre, float sim, int antiperiodic) {
+    extern __shared__ unsigned char smem[];
+    constexpr int Vb = VB, RS = VB + 4, LS = VB + 2;
+    float2 *rho_lds = (float2 *)smem;                   // [12][RS]
+    float2 *lnk = rho_lds + 12 * RS;                    // [4][6][LS]: rows 0, 1 of each site's forward links
+    float *red = (float *)(lnk + 24 * LS);              // [3 * waves]
+    const size_t V = g.V;
+    const int pos = (colour ? g.ncol0 : 0) + xcd_block(gridDim.x);
+    const int h = threadIdx.x & 1, l = threadIdx.x >> 1;
+    const int d = (pos << g.lgVb) + l;
+    const size_t roff = (size_t)blockIdx.y * 12 * V;
+    const FieldView<float> Uall(Up, V, 36), Aall(Ap, V, 36);
+    const FieldView<float> bf(b + roff, V, 12), zf(z + roff, V, 12);
+    const unsigned aoff = (unsigned)h * 18u * Aall.cs, coff = (unsigned)h * 6u * zf.cs;
+    const bool swp = h == 0;
+    const float sig = h ? -1.f : 1.f;
+    const int src0 = swp ? 9 : 6, src1 = swp ? 6 : 9;   // LDS component blocks of l_pi(0), l_pi(1)
+    const float2 shift = make_float2(sre, sim);
+
+    // neighbours along the lane's two directions mu = 2h + i (every private
+    // array index a compile-time constant)
+    int x[4];
+    local_coords(g, l, x);
+    int nf[2], nbk[2], lnf[2], lnb[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const int m = 2 * h + i;
+        int xm = 0, lbm = 0, nbm = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++)
+            if (mu == m) { xm = x[mu]; lbm = g.lb[mu]; nbm = g.nb[mu]; }
+        const int bm = 1 << lbm;
+        const bool wrap = nbm == 1;
+        const int yf = xm + 1, yb = xm - 1;
+        const bool fin = yf < bm, bin = yb >= 0;
+        int xf[4], xb[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            xf[mu] = mu == m ? (yf & (bm - 1)) : x[mu];
+            xb[mu] = mu == m ? ((yb + bm) & (bm - 1)) : x[mu];
+        }
+        const int lf = local_index(g, xf), lbk = local_index(g, xb);
+        lnf[i] = (fin || wrap) ? lf : -1;
+        lnb[i] = (bin || wrap) ? lbk : -1;
+        const int pf = fin ? pos : g.blk_nbr[pos * 8 + 2 * m];
+        const int pb = bin ? pos : g.blk_nbr[pos * 8 + 2 * m + 1];
+        nf[i] = (pf << g.lgVb) + lf;
+        nbk[i] = (pb << g.lgVb) + lbk;
+    }
+    // signs of the rebuilt time links (second direction of lane 1): -1 on the
+    // link across the antiperiodic time boundary
+    float sgf = 1.f, sgb = 1.f;
+    {
+        const int t = (int)((g.blk_coord[pos] >> 24) << g.lb[3]) + x[3];
+        if (antiperiodic && h == 1 && t == g.L[3] - 1) sgf = -1.f;
+        if (antiperiodic && h == 1 && t == 0) sgb = -1.f;
+    }
+
+    // stage rows 0 and 1 of the site's forward links of the lane's
+    // directions, and the lane's chirality of z, in LDS
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const unsigned uo = (unsigned)(2 * h + i) * 9u * Uall.cs;
+        float2 *lk = lnk + (2 * h + i) * 6 * LS;
+#pragma unroll
+        for (int k = 0; k < 6; k++) lk[k * LS + l] = Uall.ld_lane(k, d, uo);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; c++) rho_lds[(6 * h + c) * RS + l] = zf.ld_lane(c, d, coff);
+    __syncthreads();
+
+    // r = b - (D - shift) z on the lane's chirality: the hops inside the
+    // block from LDS, then those that leave it (spinor and, backward, link
+    // from memory)
+    float2 rho[6], e[6];
+    {
+        float2 up[6], L[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) up[k] = L[k] = make_float2(0.f, 0.f);
+        block_hops<RS, LS>(rho_lds, lnk, h, l, lnf, lnb, src0, src1, sig, sgf, sgb, up, L);
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const float sf = i ? sgf : 1.f, sb = i ? sgb : 1.f;
+            float2 u[9], ps[6], la[3], lb[3], hh[6];
+            if (lnf[i] < 0) {
+                spinor_from_field(zf, nf[i], src0, src1, ps, la, lb);
+                link_from_lds<LS>(lnk + (2 * h + i) * 6 * LS, l, sf, u);
+                if (i == 0) {
+                    project2<true, true>(ps, la, lb, sig, hh);
+                    accumulate_hop<true, true>(u, hh, sig, up, L);
+                } else {
+                    project2<false, true>(ps, la, lb, sig, hh);
+                    accumulate_hop<false, true>(u, hh, sig, up, L);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (lnb[i] < 0) {
+                spinor_from_field(zf, nbk[i], src0, src1, ps, la, lb);
+                const unsigned uo = (unsigned)(2 * h + i) * 9u * Uall.cs;
+#pragma unroll
+                for (int k = 0; k < 6; k++) u[k] = Uall.ld_lane(k, nbk[i], uo);
+                su3_row2<float>(u, sb);
+                if (i == 0) {
+                    project2<true, false>(ps, la, lb, sig, hh);
+                    accumulate_hop<true, false>(u, hh, sig, up, L);
+                } else {
+                    project2<false, false>(ps, la, lb, sig, hh);
+                    accumulate_hop<false, false>(u, hh, sig, up, L);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        float2 hs[6], zc[6], az[6];
+        exchange_chirality(h, up, L, hs);
+#pragma unroll
+        for (int c = 0; c < 6; c++) zc[c] = rho_lds[(6 * h + c) * RS + l];
+        {
+            float2 ap[18];
+#pragma unroll
+            for (int k = 0; k < 18; k++) ap[k] = Aall.ld_lane(k, d, aoff);
+            herm6_mv<float>(ap, zc, az);
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            const float2 bs = bf.ld_lane(c, d, coff);
+            const float2 dz = csub(csub(az[c], cscale(hs[c], 0.5f)), cmul(shift, zc[c]));
+            rho[c] = csub(bs, dz);
+            e[c] = make_float2(0.f, 0.f);
+        }
+    }
+    // every lane has read z from LDS before rho replaces it
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 6; c++) rho_lds[(6 * h + c) * RS + l] = rho[c];
+    __syncthreads();
+
+    for (int it = 0; it < mr; it++) {
+        const unsigned salt = opaque_zero();
+        float2 up[6], L[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) up[k] = L[k] = make_float2(0.f, 0.f);
+        block_hops<RS, LS>(rho_lds, lnk, h, l, lnf, lnb, src0, src1, sig, sgf, sgb, up, L);
+        float2 hs[6], ax[6], q[6];
+        exchange_chirality(h, up, L, hs);
+        {
+            float2 ap[18];
+#pragma unroll
+            for (int k = 0; k < 18; k++) ap[k] = Aall.ld_lane(k, d, aoff, salt);
+            herm6_mv<float>(ap, rho, ax);
+        }
+        Red3<float> part{0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            q[c] = csub(csub(ax[c], cscale(hs[c], 0.5f)), cmul(shift, rho[c]));
+            part.a += q[c].x * q[c].x + q[c].y * q[c].y;
+            part.b += q[c].x * rho[c].x + q[c].y * rho[c].y;   // conj(q) rho
+            part.c += q[c].x * rho[c].y - q[c].y * rho[c].x;
+        }
+        // the barrier after the rho update below (or the end of the loop) comes
+        // before any thread writes red again
+        Red3<float> sm = block_sum3<float, false>(part, red);
+        if (sm.a == 0.f) break;
+        const float inv = 1.f / sm.a;
+        const float2 alpha = make_float2(sm.b * inv, sm.c * inv);
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            cfma(e[c], alpha, rho[c]);
+            rho[c] = csub(rho[c], cmul(alpha, q[c]));
+        }
+        if (it + 1 < mr) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) rho_lds[(6 * h + c) * RS + l] = rho[c];
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; c++) zf.st_lane(c, d, coff, cadd(zf.ld_lane(c, d, coff), e[c]));
+}
+
 }  // namespace
 
 int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, double sim, const void *b, void *z) {
@@ -530,9 +862,21 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
     size_t lds = (prec == MGDD_F64 ? 16 : 8) * 12 * (size_t)g.Vb + (prec == MGDD_F64 ? 8 : 4) * 3 * (g.Vb / 64);
     // four lanes per site with the block's links staged in LDS (FP32)
     const size_t lds4 = 8 * (12 * ((size_t)g.Vb + 4) + 4 * (9 * (size_t)g.Vb + 4)) + 4 * 3 * (4 * g.Vb / 64);
+    // two lanes per site, the links' first two rows staged (special unitary links)
+    const size_t ldsc = 8 * (12 * ((size_t)g.Vb + 4) + 24 * ((size_t)g.Vb + 2)) + 4 * 3 * (2 * g.Vb / 64);
     dim3 grid(nblocks, nrhs);
     const int slot = kt_begin(c);
-    if (prec == MGDD_F64) {
+    if (prec == MGDD_F32 && c->links_su3 && ldsc <= c->lds_max) {
+        const int anti = c->t_antiperiodic ? 1 : 0;
+#define SAPC(VB)                                                                                                  \
+    sapc_kernel<VB><<<grid, 2 * VB, ldsc, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,         \
+                                                       (const float2 *)b, (float2 *)z, col, mr, (float)sre,       \
+                                                       (float)sim, anti)
+        if (g.Vb == 256) SAPC(256);
+        else if (g.Vb == 128) SAPC(128);
+        else SAPC(64);
+#undef SAPC
+    } else if (prec == MGDD_F64) {
         sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64, (const double2 *)c->A64,
                                                                   (const double2 *)b, (double2 *)z, col, mr, sre, sim);
     } else if (lds4 <= c->lds_max) {

@@ -109,10 +109,26 @@ template <typename T> struct LinkViews {
     }
 };
 
-template <typename T, int MU> __device__ inline void load_link(const LinkViews<T> &U, int d, C<T> *u, unsigned salt = 0) {
+// row 2 of a special unitary link from rows 0 and 1: u_2a = s conj(u_0b u_1c -
+// u_0c u_1b) with (a, b, c) cyclic; s = -1 on the links that carry the
+// antiperiodic time-boundary sign (the folded sign makes the determinant -1)
+template <typename T> __device__ inline void su3_row2(C<T> *u, T s) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        const C<T> x = csub(cmul(u[b], u[3 + c]), cmul(u[c], u[3 + b]));
+        u[6 + a] = mk<T>(s * x.x, -s * x.y);
+    }
+}
+
+// RECON: the links are special unitary (checked at ingest); rows 0 and 1 are
+// read and row 2 is rebuilt (sign: see su3_row2), a third fewer link bytes
+template <typename T, int MU, bool RECON = false>
+__device__ inline void load_link(const LinkViews<T> &U, int d, C<T> *u, unsigned salt = 0, T sign = 1) {
     const FieldView<T> &f = U.template get<MU>();
 #pragma unroll
-    for (int k = 0; k < 9; k++) u[k] = f.ld(k, d, salt);
+    for (int k = 0; k < (RECON ? 6 : 9); k++) u[k] = f.ld(k, d, salt);
+    if (RECON) su3_row2<T>(u, sign);
 }
 
 // A zero the compiler cannot see through: added to the offsets of loads inside
@@ -224,11 +240,11 @@ __device__ inline void clover_mv(const CloverViews<T> &A, int d, const C<T> *in,
     herm6_mv<T>(p, in + 6, out + 6);
 }
 
-template <typename T, int MU, bool FWD, typename FV>
-__device__ inline void hop_from(const LinkViews<T> &U, const FV &f, int d, int dn, C<T> *acc) {
+template <typename T, int MU, bool FWD, bool RECON = false, typename FV>
+__device__ inline void hop_from(const LinkViews<T> &U, const FV &f, int d, int dn, C<T> *acc, T sign = 1) {
     C<T> psi[12], u[9];
     load_spinor<T>(f, dn, psi);
-    load_link<T, MU>(U, FWD ? d : dn, u);
+    load_link<T, MU, RECON>(U, FWD ? d : dn, u, 0, sign);
     hop<T, MU, FWD>(acc, u, psi);
     // keep the scheduler from hoisting the loads of all eight hops at once
     __builtin_amdgcn_sched_barrier(0);
@@ -236,18 +252,31 @@ __device__ inline void hop_from(const LinkViews<T> &U, const FV &f, int d, int d
 
 // sum over the 8 hops of the Wilson term, without the factor -1/2:
 // H psi(x) = sum_mu (1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^H psi(x-mu)
-template <typename T, typename FV>
-__device__ inline void hop_sum(const LinkViews<T> &U, const FV &f, int d, const int *nbr, C<T> *acc) {
+// RECON: links rebuilt from two rows; sf, sb: the signs of the forward and
+// backward time links of this site (-1 where the hop crosses the
+// antiperiodic time boundary)
+template <typename T, bool RECON = false, typename FV>
+__device__ inline void hop_sum(const LinkViews<T> &U, const FV &f, int d, const int *nbr, C<T> *acc, T sf = 1,
+                               T sb = 1) {
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
-    hop_from<T, 0, true>(U, f, d, nbr[0], acc);
-    hop_from<T, 0, false>(U, f, d, nbr[1], acc);
-    hop_from<T, 1, true>(U, f, d, nbr[2], acc);
-    hop_from<T, 1, false>(U, f, d, nbr[3], acc);
-    hop_from<T, 2, true>(U, f, d, nbr[4], acc);
-    hop_from<T, 2, false>(U, f, d, nbr[5], acc);
-    hop_from<T, 3, true>(U, f, d, nbr[6], acc);
-    hop_from<T, 3, false>(U, f, d, nbr[7], acc);
+    hop_from<T, 0, true, RECON>(U, f, d, nbr[0], acc);
+    hop_from<T, 0, false, RECON>(U, f, d, nbr[1], acc);
+    hop_from<T, 1, true, RECON>(U, f, d, nbr[2], acc);
+    hop_from<T, 1, false, RECON>(U, f, d, nbr[3], acc);
+    hop_from<T, 2, true, RECON>(U, f, d, nbr[4], acc);
+    hop_from<T, 2, false, RECON>(U, f, d, nbr[5], acc);
+    hop_from<T, 3, true, RECON>(U, f, d, nbr[6], acc, sf);
+    hop_from<T, 3, false, RECON>(U, f, d, nbr[7], acc, sb);
+}
+
+// signs of the time links of site d when they are rebuilt from two rows: -1
+// on the link that crosses the antiperiodic time boundary
+template <typename T> __device__ inline void time_link_signs(const Geom &g, int d, int antiperiodic, T &sf, T &sb) {
+    int X[4];
+    site_coords(g, d, X);
+    sf = (antiperiodic && X[3] == g.L[3] - 1) ? (T)-1 : (T)1;
+    sb = (antiperiodic && X[3] == 0) ? (T)-1 : (T)1;
 }
 
 __device__ inline void site_neighbours(const Geom &g, int d, int *nbr) {

@@ -12,6 +12,7 @@ CASES = [
     ((8, 8, 8, 8), (4, 4, 4, 4)),      # 16 blocks, 2 per direction
     ((4, 8, 4, 16), (4, 4, 2, 4)),     # one block in x (wrap kept), uneven shape
     ((8, 4, 4, 8), (2, 4, 4, 2)),      # block of 64 sites, one block in y and z
+    ((8, 8, 4, 4), (4, 4, 4, 4)),      # one block in z and t: the antiperiodic time hop inside the block
 ]
 
 

@@ -68,8 +68,9 @@ def test_half_timing_and_errors():
     lat.dirac(x)
     ms, units, n, nbytes = mgdd_timing_read(lat.ctx, KERNEL_DIRAC, F16)
     mgdd_timing_enable(lat.ctx, False)
-    # algorithmic bytes: FP32 links and clover term once, half spinor in and out
-    assert n == 2 and units == 2 * lat.V and ms > 0 and nbytes == 2 * lat.V * (576 + 96)
+    # algorithmic bytes: FP32 links (two rows each: special unitary links) and
+    # clover term once, half spinor in and out
+    assert n == 2 and units == 2 * lat.V and ms > 0 and nbytes == 2 * lat.V * (192 + 288 + 96)
     with pytest.raises(MgddError) as e:   # half precision is a storage format of fine fields only
         lat.sap(x, lat.field(F16, 1), 1, 4)
     assert e.value.code == EINVAL

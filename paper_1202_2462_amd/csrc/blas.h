@@ -24,6 +24,9 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
 // nvec <= MAXV. The update is blas_lincomb's; the sums are deterministic.
 int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
                     double2 *out, int norm_only, int nseg = 1);
+// the same with both sums: out[i * nseg + s] = <x_i, y>_s and nrm[s] = ||y_s||^2
+int blas_update_dot_norm(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                         double2 *out, double2 *nrm, int nseg = 1);
 // y_s = (coef ? coef[s] * alpha : alpha) x_s   (x and y may alias)
 int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y,
                int nseg = 1);

@@ -113,16 +113,19 @@ __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int 
 }
 
 // y <- y - sum_i coef[i * nseg + s] x_i, then the partial sums of the new y
-// against every x_i (or of ||y||^2 when norm_only) per workgroup into part,
-// laid out as multidot's: one pass over the x_i instead of a lincomb and a
-// multidot (the two later passes of classical Gram-Schmidt with one
-// re-orthogonalisation). The update arithmetic is that of lincomb_kernel.
+// against every x_i (mode 0), of ||y||^2 (mode 1), or both (mode 2: the norm
+// after the nvec dot products) per workgroup into part, laid out as
+// multidot's: one pass over the x_i instead of a lincomb and a multidot (the
+// later passes of classical Gram-Schmidt). The update arithmetic is that of
+// lincomb_kernel.
 template <typename T, int NV>
 __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, int nvec,
                                                          const double2 *__restrict__ coef, C<T> *__restrict__ y,
-                                                         int norm_only, double2 *__restrict__ part) {
-    __shared__ double red[TPB / 64][2 * NV];
+                                                         int mode, double2 *__restrict__ part) {
+    const int norm_only = mode == 1;
+    __shared__ double red[TPB / 64][2 * NV + 1];
     double2 c[NV], acc[NV];
+    double accn = 0;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         c[i] = i < nvec ? cscale(coef[(size_t)i * gridDim.y + blockIdx.y], -1.0) : make_double2(0, 0);
@@ -150,6 +153,7 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
 #pragma unroll
             for (int i = 0; i < NV; i++)
                 if (i < nvec) cfmac(acc[i], xv[i], ud);
+            if (mode == 2) accn += ud.x * ud.x + ud.y * ud.y;
         }
     }
     const int nout = norm_only ? 1 : nvec;
@@ -161,12 +165,21 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
             if (lane == 0) { red[wv][2 * i] = a; red[wv][2 * i + 1] = b; }
         }
     }
+    if (mode == 2) {
+        const double a = wave_sum(accn);
+        if (lane == 0) red[wv][2 * NV] = a;
+    }
     __syncthreads();
     if ((int)threadIdx.x < nout) {
         int i = threadIdx.x;
         double a = 0, b = 0;
         for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * i]; b += red[k][2 * i + 1]; }
         part[((size_t)i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
+    }
+    if (mode == 2 && threadIdx.x == 0) {
+        double a = 0;
+        for (int k = 0; k < TPB / 64; k++) a += red[k][2 * NV];
+        part[((size_t)nvec * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, 0);
     }
 }
 
@@ -509,24 +522,35 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
     return MGDD_OK;
 }
 
-int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
-                    double2 *out, int norm_only, int nseg) {
+static int update_dot_launch(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                             double2 *out, int mode, double2 *nrm, int nseg) {
     if (nvec < 1 || nvec > MAXV) return fail(c, MGDD_EINVAL, "update_dot: bad vector count");
     // about two elements per thread: every load of the update in flight at once
     size_t g = (n + 2 * TPB - 1) / (2 * TPB);
     const int nwg = (int)(g > 4096 ? 4096 : g < 1 ? 1 : g);
-    double2 *part = (double2 *)ensure_red(c, (size_t)2 * MAXV * nseg * nwg + 16);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * (MAXV + 1) * nseg * nwg + 16);
     if (!part) return MGDD_ENOMEM;
     PtrList pl{};
     for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
     dim3 grid(nwg, nseg);
     if (p == MGDD_F64)
-        update_dot_kernel<double, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (double2 *)y, norm_only, part);
+        update_dot_kernel<double, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (double2 *)y, mode, part);
     else
-        update_dot_kernel<float, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (float2 *)y, norm_only, part);
-    const int nout = norm_only ? 1 : nvec;
+        update_dot_kernel<float, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (float2 *)y, mode, part);
+    const int nout = mode == 1 ? 1 : nvec;
     finish_kernel<<<nout * nseg, 64, 0, c->stream>>>(nwg, part, out);
+    if (mode == 2) finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part + (size_t)nvec * nseg * nwg, nrm);
     return hip_check(c, hipGetLastError(), "update_dot");
+}
+
+int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                    double2 *out, int norm_only, int nseg) {
+    return update_dot_launch(c, p, n, xs, nvec, coef, y, out, norm_only ? 1 : 0, nullptr, nseg);
+}
+
+int blas_update_dot_norm(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                         double2 *out, double2 *nrm, int nseg) {
+    return update_dot_launch(c, p, n, xs, nvec, coef, y, out, 2, nrm, nseg);
 }
 
 static int scale_launch(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha,

@@ -143,6 +143,38 @@ static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2
     return rc;
 }
 
+// Outer Gram-Schmidt step of the flexible GMRES (FP64, long vectors):
+// classical Gram-Schmidt whose second pass runs only where the first leaves a
+// measurable component in span(V). First part: h1 = V^H w, then
+// w' = w - V h1 with h2 = V^H w' and ||w'||^2 summed in the same pass over V.
+// Second part (only when the caller's test asks for it): w'' = w' - V h2 and
+// ||w''||^2. The caller reads h1, h2 and the norm between the two parts.
+static int cgs_first(Ctx *c, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm,
+                     int nb) {
+    int rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, V, k, w, h1, nb);
+    if (rc) return rc;
+    if (k <= MAXV) return blas_update_dot_norm(c, MGDD_F64, n, V, k, h1, w, h2, nrm, nb);
+    rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, V, k, h1, -1.0, 1.0, w, nb);
+    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, V, k, w, h2, nb);
+    const void *wp = w;
+    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &wp, 1, w, nrm, nb);
+    return rc;
+}
+
+static int cgs_second(Ctx *c, size_t n, void *const *V, int k, void *w, const double2 *h2, double2 *nrm, int nb) {
+    if (k <= MAXV) return blas_update_dot(c, MGDD_F64, n, V, k, h2, w, nrm, 1, nb);
+    int rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, V, k, h2, -1.0, 1.0, w, nb);
+    const void *wp = w;
+    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &wp, 1, w, nrm, nb);
+    return rc;
+}
+
+// the second pass is taken when the component the first pass left in span(V)
+// exceeds this fraction of the new vector, ||V^H w'|| > REORTH_TOL ||w'||
+// (the basis then stays orthonormal to about this level; the test follows
+// Daniel, Gragg, Kaufman and Stewart, 1976, with the measured component)
+constexpr double REORTH_TOL = 1e-12;
+
 // Orthonormalisation of nv FP64 vectors in index order (global
 // orthonormalisation): the Q of X = Q R with R upper triangular and a
 // positive real diagonal, the result of Gram-Schmidt in index order. Computed
@@ -511,17 +543,33 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
             } else if (!rc) {
                 rc = launch_dirac(c, MGDD_F64, nb, Z[j], w);
             }
-            if (!rc) rc = cgs2(c, MGDD_F64, n, V.data(), j + 1, w, h1, h2, nr, nb);
+            if (!rc) rc = cgs_first(c, n, V.data(), j + 1, w, h1, h2, nr, nb);
             if (rc) return rc;
             rc = read_dev(c, h1, (size_t)(2 * (m + 1) + 1) * nb, Hb1);   // h1, h2 and the norms
             if (rc) return rc;
+            // second pass when any right-hand side of the cycle needs it
+            // (then for all of them: it is the second pass of CGS2)
+            bool reorth = false;
+            for (int sg = 0; sg < nb && !reorth; sg++) {
+                if (!incycle[sg]) continue;
+                double s2 = 0.0;
+                for (int i = 0; i <= j; i++) s2 += std::norm(Hb2[(size_t)i * nb + sg]);
+                const double w2 = Nb[sg].real();
+                if (!(s2 <= REORTH_TOL * REORTH_TOL * w2)) reorth = true;
+            }
+            if (reorth) {
+                rc = cgs_second(c, n, V.data(), j + 1, w, h2, nr, nb);
+                if (!rc) rc = read_dev(c, nr, nb, Nb);
+                if (rc) return rc;
+            }
             kmax = j + 1;
             bool more = false;
             for (int sg = 0; sg < nb; sg++) {
                 Cb[sg] = 0.0;
                 if (!incycle[sg]) continue;
                 cd *col = &Hc[sg][(size_t)j * (m + 1)];
-                for (int i = 0; i <= j; i++) col[i] = Hb1[(size_t)i * nb + sg] + Hb2[(size_t)i * nb + sg];
+                for (int i = 0; i <= j; i++)
+                    col[i] = reorth ? Hb1[(size_t)i * nb + sg] + Hb2[(size_t)i * nb + sg] : Hb1[(size_t)i * nb + sg];
                 const double h = std::sqrt(std::max(Nb[sg].real(), 0.0));
                 if (!std::isfinite(h)) return fail(c, MGDD_ENAN, "NaN in the Arnoldi step");
                 col[j + 1] = h;

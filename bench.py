@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (published)
-REPS = 3                       # 48^3 x 96 = the 16^3 x 32 field repeated three times per direction
+REPS = {"c3": 3, "c2": 2}      # 48^3 x 96 and 32^3 x 64: the 16^3 x 32 field repeated per direction
 
 
 def log(*a):
@@ -107,9 +107,9 @@ class Bench:
         self.name = name
         w = dict(latgen.WORKLOADS[name])
         self.w = w
-        base = "c1" if name == "c3" else name      # the field the workload is made of
+        base = "c1" if name in REPS else name      # the field the workload is made of
         small = tuple(latgen.WORKLOADS[base]["dims"])
-        self.reps = REPS if name == "c3" else 1
+        self.reps = REPS.get(name, 1)
         self.dims = tuple(self.reps * L for L in small)
         assert self.dims == tuple(w["dims"])
         self.block, self.agg, self.N = tuple(w["block"]), tuple(w["agg"]), w["ntv"]
@@ -234,7 +234,7 @@ def cpu_baseline(bench, gpu_split):
     import oracle
     from oracle import solvers
     w = bench.w
-    base = "c1" if bench.name == "c3" else bench.name
+    base = "c1" if bench.name in REPS else bench.name
     small = tuple(latgen.WORKLOADS[base]["dims"])
     scale = bench.V / int(np.prod(small))
     op = solvers.Operator(small, bench.U_small, bench.m0, bench.csw)
@@ -294,10 +294,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["c3", "c1"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c2", "c1"], default="c3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--kernel-only", choices=["step", "sap", "dirac"], default=None)
+    ap.add_argument("--kernel-only", choices=["step", "sap", "dirac", "coarse12"], default=None)
     ap.add_argument("--m0", type=float, default=None, help="override the tuned bare mass")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -315,6 +315,16 @@ def main():
         lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
         if args.kernel_only == "step":
             bench.step()
+        elif args.kernel_only == "coarse12":
+            # D_c from the workload's number of random test vectors (no
+            # smoothing), applied to 12 FP32 right-hand sides: the matrix-core path
+            lat.setup(bench.agg, None, bench.start, nu=0, iota=0, mr_iters=4, n_part2=0, prec=mg.F32,
+                      ntv=bench.N, seed=bench.tv_seed)
+            x = lat.coarse_field(mg.F32, 12)
+            x.normal_()
+            y = torch.empty_like(x)
+            for _ in range(10):
+                mg.mgdd_coarse_apply(lat.ctx, mg.F32, 12, x, y)
         elif args.kernel_only == "sap":
             b = lat.field(mg.F32, 1)
             b.normal_()
@@ -332,7 +342,9 @@ def main():
         x = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda").normal_()
         y = torch.empty_like(x)
         for _ in range(5):
-            y.copy_(x)    # reference copy kernel: 256 MiB read + 256 MiB written
+            y.copy_(x)    # reference copy (runtime blit kernel): 256 MiB read + 256 MiB written
+        for _ in range(5):
+            torch.add(x, 0.5, out=y)    # reference elementwise kernel: 256 MiB read + 256 MiB written
         torch.cuda.synchronize()
         print(json.dumps({"kernel_only": args.kernel_only, "workload": bench.name,
                           "copy_bytes_each_way": x.numel() * 4}))

@@ -34,24 +34,28 @@ __device__ inline double wave_sum(double v) {
 // needs a device-scope release by every workgroup, which writes back L2 on
 // every XCD and made the kernel five times slower; a second small kernel
 // adds the partials instead.)
-template <typename TX, typename TW, int NV>
-__global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PtrList xs, int nvec, const C<TW> *__restrict__ w,
+template <typename TX, typename TW, int NV, typename PL = PtrList>
+__global__ __launch_bounds__(TPB) void multidot_kernel(size_t n, PL xs, int nvec, const C<TW> *__restrict__ w,
                                                        double2 *__restrict__ part) {
     __shared__ double red[TPB / 64][2 * NV];
     double2 acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; i++) acc[i] = make_double2(0, 0);
+    // slots past nvec read the last vector again (from cache) and their sums
+    // are dropped: the loads of one element carry no branches between them and
+    // are all in flight at once
+    const C<TX> *xp[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) xp[i] = (const C<TX> *)xs.p[i < nvec ? i : nvec - 1];
     const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
         C<TW> wv = w[so + e];
         double2 wd = make_double2((double)wv.x, (double)wv.y);
+        C<TX> xv[NV];
 #pragma unroll
-        for (int i = 0; i < NV; i++) {
-            if (i < nvec) {
-                C<TX> xv = ((const C<TX> *)xs.p[i])[so + e];
-                cfmac(acc[i], make_double2((double)xv.x, (double)xv.y), wd);
-            }
-        }
+        for (int i = 0; i < NV; i++) xv[i] = xp[i][so + e];
+#pragma unroll
+        for (int i = 0; i < NV; i++) cfmac(acc[i], make_double2((double)xv[i].x, (double)xv[i].y), wd);
     }
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -94,6 +98,11 @@ __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int 
 #pragma unroll
     for (int i = 0; i < NV; i++)
         c[i] = i < nvec ? cscale(coef[(size_t)i * cstride + blockIdx.y], alpha) : make_double2(0, 0);
+    // slots past nvec read the last vector again (from cache) with
+    // coefficient 0, so that no branch separates the loads of one element
+    const C<TX> *xp[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) xp[i] = (const C<TX> *)xs.p[i < nvec ? i : (nvec > 0 ? nvec - 1 : 0)];
     const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
         double2 acc = make_double2(0, 0);
@@ -101,12 +110,12 @@ __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int 
             C<TY> yv = y[so + e];
             acc = make_double2(beta * (double)yv.x, beta * (double)yv.y);
         }
+        if (nvec > 0) {
+            C<TX> xv[NV];
 #pragma unroll
-        for (int i = 0; i < NV; i++) {
-            if (i < nvec) {
-                C<TX> xv = ((const C<TX> *)xs.p[i])[so + e];
-                cfma(acc, c[i], make_double2((double)xv.x, (double)xv.y));
-            }
+            for (int i = 0; i < NV; i++) xv[i] = xp[i][so + e];
+#pragma unroll
+            for (int i = 0; i < NV; i++) cfma(acc, c[i], make_double2((double)xv[i].x, (double)xv[i].y));
         }
         y[so + e] = mk<TY>((TY)acc.x, (TY)acc.y);
     }
@@ -131,18 +140,22 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
         c[i] = i < nvec ? cscale(coef[(size_t)i * gridDim.y + blockIdx.y], -1.0) : make_double2(0, 0);
         acc[i] = make_double2(0, 0);
     }
+    // slots past nvec: the last vector again with coefficient 0 (see lincomb)
+    const C<T> *xp[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) xp[i] = (const C<T> *)xs.p[i < nvec ? i : nvec - 1];
     const size_t stride = (size_t)gridDim.x * TPB, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
         C<T> yv = y[so + e];
         double2 u = make_double2(1.0 * (double)yv.x, 1.0 * (double)yv.y);
+        C<T> xr[NV];
         double2 xv[NV];
 #pragma unroll
+        for (int i = 0; i < NV; i++) xr[i] = xp[i][so + e];
+#pragma unroll
         for (int i = 0; i < NV; i++) {
-            if (i < nvec) {
-                const C<T> x = ((const C<T> *)xs.p[i])[so + e];
-                xv[i] = make_double2((double)x.x, (double)x.y);
-                cfma(u, c[i], xv[i]);
-            }
+            xv[i] = make_double2((double)xr[i].x, (double)xr[i].y);
+            cfma(u, c[i], xv[i]);
         }
         const C<T> un = mk<T>((T)u.x, (T)u.y);
         y[so + e] = un;
@@ -151,8 +164,7 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
             cfmac(acc[0], ud, ud);
         } else {
 #pragma unroll
-            for (int i = 0; i < NV; i++)
-                if (i < nvec) cfmac(acc[i], xv[i], ud);
+            for (int i = 0; i < NV; i++) cfmac(acc[i], xv[i], ud);
             if (mode == 2) accn += ud.x * ud.x + ud.y * ud.y;
         }
     }
@@ -180,6 +192,101 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
         double a = 0;
         for (int k = 0; k < TPB / 64; k++) a += red[k][2 * NV];
         part[((size_t)nvec * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, 0);
+    }
+}
+
+struct PtrListW {
+    const void *p[WIDE];
+};
+
+// update_dot_kernel in FP64 for MAXV < nvec <= 2 MAXV with G lanes per
+// element, so that no lane holds more than 2 MAXV / G vectors' values and
+// sums. A wave is G groups of 64 / G lanes; lane l of group g takes element
+// l of the wave's range and the vectors g NG ... g NG + NG - 1 (NG =
+// 2 MAXV / G). The groups swap their partial updates in a butterfly, so that
+// every lane forms the same
+// y' = (u_0 + u_1) + (u_2 + u_3) (G = 4) or u_0 + u_1 (G = 2), with
+// u_0 = y - sum_{i < NG} c_i x_i and u_g = -sum c_i x_i over group g's vectors,
+// which the lane of group 0 stores. Modes and the layout of part are those of
+// update_dot_kernel.
+template <int G>
+__global__ __launch_bounds__(TPB) void update_dot2_kernel(size_t n, PtrListW xs, int nvec,
+                                                          const double2 *__restrict__ coef, double2 *__restrict__ y,
+                                                          int mode, double2 *__restrict__ part) {
+    constexpr int NG = 2 * MAXV / G, LG = 64 / G;
+    __shared__ double2 cs[2 * MAXV];
+    __shared__ double red[TPB / 64][4 * MAXV + 1];
+    if ((int)threadIdx.x < 2 * MAXV)
+        cs[threadIdx.x] = (int)threadIdx.x < nvec ? cscale(coef[(size_t)threadIdx.x * gridDim.y + blockIdx.y], -1.0)
+                                                  : make_double2(0, 0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, grp = lane / LG, gl = lane % LG;
+    const int norm_only = mode == 1;
+    // a lane whose group has run out of vectors reads vector i of group 0
+    // (the address group 0's lane reads, so no extra memory traffic) with
+    // coefficient 0: every lane issues all loads, without branches between
+    const double2 *xp[NG];
+#pragma unroll
+    for (int i = 0; i < NG; i++) xp[i] = (const double2 *)(grp * NG + i < nvec ? xs.p[grp * NG + i] : xs.p[i]);
+    double2 acc[NG];
+    double accn = 0;
+#pragma unroll
+    for (int i = 0; i < NG; i++) acc[i] = make_double2(0, 0);
+    const size_t per = TPB / G, stride = (size_t)gridDim.x * per, so = (size_t)blockIdx.y * n;
+    for (size_t e = (size_t)blockIdx.x * per + wv * LG + gl; e < n; e += stride) {
+        const double2 yv = y[so + e];
+        double2 xv[NG];
+#pragma unroll
+        for (int i = 0; i < NG; i++) xv[i] = xp[i][so + e];
+        double2 u = grp == 0 ? yv : make_double2(0, 0);
+#pragma unroll
+        for (int i = 0; i < NG; i++) cfma(u, cs[grp * NG + i], xv[i]);
+#pragma unroll
+        for (int m = LG; m < 64; m <<= 1) {
+            const double ox = __shfl_xor(u.x, m, 64), oy = __shfl_xor(u.y, m, 64);
+            u = make_double2(u.x + ox, u.y + oy);
+        }
+        if (grp == 0) {
+            y[so + e] = u;
+            if (mode != 0) accn += u.x * u.x + u.y * u.y;
+        }
+        if (!norm_only) {
+#pragma unroll
+            for (int i = 0; i < NG; i++) cfmac(acc[i], xv[i], u);
+        }
+    }
+    if (!norm_only) {
+#pragma unroll
+        for (int i = 0; i < NG; i++) {
+            double a = acc[i].x, b = acc[i].y;
+#pragma unroll
+            for (int m = LG / 2; m >= 1; m >>= 1) {
+                a += __shfl_xor(a, m, 64);
+                b += __shfl_xor(b, m, 64);
+            }
+            const int q = grp * NG + i;
+            if (gl == 0 && q < nvec) {
+                red[wv][2 * q] = a;
+                red[wv][2 * q + 1] = b;
+            }
+        }
+    }
+    if (mode != 0) {
+        const double a = wave_sum(accn);
+        if (lane == 0) red[wv][4 * MAXV] = a;
+    }
+    __syncthreads();
+    const int nout = norm_only ? 0 : nvec;
+    if ((int)threadIdx.x < nout) {
+        const int q = threadIdx.x;
+        double a = 0, b = 0;
+        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * q]; b += red[k][2 * q + 1]; }
+        part[((size_t)q * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
+    }
+    if (mode != 0 && threadIdx.x == 0) {
+        double a = 0;
+        for (int k = 0; k < TPB / 64; k++) a += red[k][4 * MAXV];
+        part[((size_t)nout * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, 0);
     }
 }
 
@@ -479,12 +586,17 @@ int blas_multidot(Ctx *c, int px, int pw, size_t n, const void *const *xs, int n
         PtrList pl{};
         for (int i = 0; i < nv; i++) pl.p[i] = xs[i0 + i];
         dim3 grid(nwg, nseg);
-#define MD(TX, TW) multidot_kernel<TX, TW, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nv, (const C<TW> *)w, part)
+#define MD1(TX, TW, NB) multidot_kernel<TX, TW, NB><<<grid, TPB, 0, c->stream>>>(n, pl, nv, (const C<TW> *)w, part)
+#define MD(TX, TW)                                                                                                    \
+    do {                                                                                                              \
+        if (nv <= 4) MD1(TX, TW, 4); else if (nv <= 8) MD1(TX, TW, 8); else MD1(TX, TW, MAXV);                         \
+    } while (0)
         if (px == MGDD_F64 && pw == MGDD_F64) MD(double, double);
         else if (px == MGDD_F32 && pw == MGDD_F32) MD(float, float);
         else if (px == MGDD_F32 && pw == MGDD_F64) MD(float, double);
         else MD(double, float);
 #undef MD
+#undef MD1
         finish_kernel<<<nv * nseg, 64, 0, c->stream>>>(nwg, part, out + (size_t)i0 * nseg);
         int rc = hip_check(c, hipGetLastError(), "multidot");
         if (rc) return rc;
@@ -508,12 +620,17 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
         PtrList pl{};
         for (int i = 0; i < nv; i++) pl.p[i] = xs[i0 + i];
         double b = i0 == 0 ? beta : 1.0;
-#define LC2(TX, TY) lincomb_kernel<TX, TY, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nv, coef + (size_t)i0 * nseg, nseg, \
-                                                                                 alpha, b, (C<TY> *)y)
+#define LC3(TX, TY, NB) lincomb_kernel<TX, TY, NB><<<grid, TPB, 0, c->stream>>>(n, pl, nv, coef + (size_t)i0 * nseg, \
+                                                                                 nseg, alpha, b, (C<TY> *)y)
+#define LC2(TX, TY)                                                                                                   \
+    do {                                                                                                              \
+        if (nv <= 4) LC3(TX, TY, 4); else if (nv <= 8) LC3(TX, TY, 8); else LC3(TX, TY, MAXV);                         \
+    } while (0)
         if (px == MGDD_F64 && py == MGDD_F64) LC2(double, double);
         else if (px == MGDD_F32 && py == MGDD_F32) LC2(float, float);
         else if (px == MGDD_F32 && py == MGDD_F64) LC2(float, double);
         else LC2(double, float);
+#undef LC3
 #undef LC2
 #undef LC
         int rc = hip_check(c, hipGetLastError(), "lincomb");
@@ -522,8 +639,33 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
     return MGDD_OK;
 }
 
+#ifndef UPDATE_DOT2_LANES
+#define UPDATE_DOT2_LANES 4
+#endif
+static int update_dot2_launch(Ctx *c, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                              double2 *out, int mode, double2 *nrm, int nseg) {
+    constexpr int G = UPDATE_DOT2_LANES;
+    size_t g = (n + TPB / G - 1) / (TPB / G);   // one element per lane group
+    const int nwg = (int)(g > 4096 ? 4096 : g < 1 ? 1 : g);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * (WIDE + 1) * nseg * nwg + 16);
+    if (!part) return MGDD_ENOMEM;
+    PtrListW pl{};
+    for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
+    dim3 grid(nwg, nseg);
+    update_dot2_kernel<G><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (double2 *)y, mode, part);
+    if (mode == 1) {
+        finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part, out);
+    } else {
+        finish_kernel<<<nvec * nseg, 64, 0, c->stream>>>(nwg, part, out);
+        if (mode == 2) finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part + (size_t)nvec * nseg * nwg, nrm);
+    }
+    return hip_check(c, hipGetLastError(), "update_dot");
+}
+
 static int update_dot_launch(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
                              double2 *out, int mode, double2 *nrm, int nseg) {
+    if (p == MGDD_F64 && nvec > MAXV && nvec <= 2 * MAXV)
+        return update_dot2_launch(c, n, xs, nvec, coef, y, out, mode, nrm, nseg);
     if (nvec < 1 || nvec > MAXV) return fail(c, MGDD_EINVAL, "update_dot: bad vector count");
     // about two elements per thread: every load of the update in flight at once
     size_t g = (n + 2 * TPB - 1) / (2 * TPB);
@@ -533,14 +675,32 @@ static int update_dot_launch(Ctx *c, int p, size_t n, const void *const *xs, int
     PtrList pl{};
     for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
     dim3 grid(nwg, nseg);
-    if (p == MGDD_F64)
-        update_dot_kernel<double, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (double2 *)y, mode, part);
-    else
-        update_dot_kernel<float, MAXV><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (float2 *)y, mode, part);
+#define UD1(T, NB) update_dot_kernel<T, NB><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (C<T> *)y, mode, part)
+#define UD(T)                                                                                                         \
+    do {                                                                                                              \
+        if (nvec <= 4) UD1(T, 4); else if (nvec <= 8) UD1(T, 8); else UD1(T, MAXV);                                    \
+    } while (0)
+    if (p == MGDD_F64) UD(double); else UD(float);
+#undef UD
+#undef UD1
     const int nout = mode == 1 ? 1 : nvec;
     finish_kernel<<<nout * nseg, 64, 0, c->stream>>>(nwg, part, out);
     if (mode == 2) finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part + (size_t)nvec * nseg * nwg, nrm);
     return hip_check(c, hipGetLastError(), "update_dot");
+}
+
+int blas_multidot_wide(Ctx *c, size_t n, const void *const *xs, int nvec, const void *w, double2 *out, int nseg) {
+    if (nvec < 1 || nvec > WIDE) return fail(c, MGDD_EINVAL, "multidot: bad vector count");
+    int nwg = red_grid(n);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * (WIDE + 1) * nseg * nwg + 16);
+    if (!part) return MGDD_ENOMEM;
+    PtrListW pl{};
+    for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
+    dim3 grid(nwg, nseg);
+    multidot_kernel<double, double, WIDE, PtrListW><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, (const double2 *)w,
+                                                                                 part);
+    finish_kernel<<<nvec * nseg, 64, 0, c->stream>>>(nwg, part, out);
+    return hip_check(c, hipGetLastError(), "multidot");
 }
 
 int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,

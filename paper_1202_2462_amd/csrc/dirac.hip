@@ -19,17 +19,22 @@ constexpr int TPB = 256;
 template <typename T, typename S = T> struct SpinorView { using type = FieldView<T>; };
 template <> struct SpinorView<float, _Float16> { using type = HalfFieldView; };
 
+// STAGE (lattice blocks of TPB sites, so that a workgroup is one block): the
+// workgroup first puts its own spinors in LDS, and the neighbours inside the
+// block (three quarters of them for 4^4 blocks) are read from there; only the
+// neighbours outside the block are read from memory, where the cache need not
+// have kept them since another workgroup read them.
 // RECON: the links are special unitary, rows 0 and 1 are read and row 2 is
 // rebuilt (a third fewer link bytes); antiperiodic: the sign of the time
 // links at the boundary, which the rebuilt row must carry
-template <typename T, typename S = T, bool RECON = false>
+template <typename T, typename S = T, bool RECON = false, bool STAGE = false>
 __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restrict__ Up, const C<T> *__restrict__ Ap,
                                                     const C<S> *__restrict__ in, C<S> *__restrict__ out, int nrhs,
                                                     int nwg, int antiperiodic) {
     const int w = xcd_block(nwg);
     const int r = w % nrhs;
     const int i = (w / nrhs) * TPB + threadIdx.x;
-    if (i >= g.V) return;
+    if (!STAGE && i >= g.V) return;  // staged: V is a multiple of TPB
     const int d = site_in_lex_block_order(g, i);
     int nbr[8];
     site_neighbours(g, d, nbr);
@@ -41,8 +46,17 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
     using FV = typename SpinorView<T, S>::type;
     FV f(in + (size_t)r * 12 * V, V, 12), o(out + (size_t)r * 12 * V, V, 12);
     C<T> acc[12], psi[12], res[12];
-    hop_sum<T, RECON>(U, f, d, nbr, acc, sf, sb);
     load_spinor<T>(f, d, psi);
+    if (STAGE) {
+        __shared__ C<T> sp[12 * TPB];
+#pragma unroll
+        for (int k = 0; k < 12; k++) sp[k * TPB + (d & (TPB - 1))] = psi[k];
+        __syncthreads();
+        hop_sum_staged<T, T, RECON, TPB>(U, (const C<T> *)in + (size_t)r * 12 * V, V, sp, d >> g.lgVb, g.lgVb, d,
+                                         nbr, acc, sf, sb);
+    } else {
+        hop_sum<T, RECON>(U, f, d, nbr, acc, sf, sb);
+    }
     clover_mv<T>(A, d, psi, res);
 #pragma unroll
     for (int k = 0; k < 12; k++) res[k] = csub(res[k], cscale(acc[k], (T)0.5));
@@ -61,7 +75,7 @@ struct WidenView {
 
 // dirac_kernel<double> with FP32 input: the FP64 apply of an FP32 field
 // without a converted copy
-template <bool RECON>
+template <bool RECON, bool STAGE>
 __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 *__restrict__ Up,
                                                           const double2 *__restrict__ Ap, const float2 *__restrict__ in,
                                                           double2 *__restrict__ out, int nrhs, int nwg,
@@ -69,7 +83,7 @@ __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 
     const int w = xcd_block(nwg);
     const int r = w % nrhs;
     const int i = (w / nrhs) * TPB + threadIdx.x;
-    if (i >= g.V) return;
+    if (!STAGE && i >= g.V) return;
     const int d = site_in_lex_block_order(g, i);
     int nbr[8];
     site_neighbours(g, d, nbr);
@@ -81,8 +95,21 @@ __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 
     WidenView f(in + (size_t)r * 12 * V, V, 12);
     FieldView<double> o(out + (size_t)r * 12 * V, V, 12);
     double2 acc[12], psi[12], res[12];
-    hop_sum<double, RECON>(U, f, d, nbr, acc, sf, sb);
-    load_spinor<double>(f, d, psi);
+    if (STAGE) {
+        __shared__ float2 sp[12 * TPB];
+        const float2 *fin = in + (size_t)r * 12 * V;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const float2 v = f.f.ld(k, d);
+            sp[k * TPB + (d & (TPB - 1))] = v;
+            psi[k] = make_double2((double)v.x, (double)v.y);
+        }
+        __syncthreads();
+        hop_sum_staged<double, float, RECON, TPB>(U, fin, V, sp, d >> g.lgVb, g.lgVb, d, nbr, acc, sf, sb);
+    } else {
+        hop_sum<double, RECON>(U, f, d, nbr, acc, sf, sb);
+        load_spinor<double>(f, d, psi);
+    }
     clover_mv<double>(A, d, psi, res);
 #pragma unroll
     for (int k = 0; k < 12; k++) res[k] = csub(res[k], cscale(acc[k], 0.5));
@@ -99,16 +126,23 @@ static double dirac_launch_bytes(const Ctx *c, int prec, size_t in_bytes, size_t
     return (double)c->g.V * (links + clover + (double)(in_bytes + out_bytes) * nrhs);
 }
 
+// The staged kernels take one workgroup per lattice block: blocks of TPB sites
+static bool dirac_staged(const Ctx *c) { return c->g.Vb == TPB; }
+
 int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
     const int anti = c->t_antiperiodic ? 1 : 0;
+    const bool stage = dirac_staged(c);
     const int slot = kt_begin(c);
-    if (c->links_su3)
-        dirac_widen_kernel<true><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
-                                                             (const float2 *)in32, (double2 *)out64, nrhs, nwg, anti);
-    else
-        dirac_widen_kernel<false><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,
-                                                              (const float2 *)in32, (double2 *)out64, nrhs, nwg, anti);
+#define WIDEN(R, G)                                                                                                   \
+    dirac_widen_kernel<R, G><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,     \
+                                                         (const float2 *)in32, (double2 *)out64, nrhs, nwg, anti)
+    if (c->links_su3) {
+        if (stage) WIDEN(true, true); else WIDEN(true, false);
+    } else {
+        if (stage) WIDEN(false, true); else WIDEN(false, false);
+    }
+#undef WIDEN
     kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs, dirac_launch_bytes(c, MGDD_F64, 96, 192, nrhs));
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
@@ -116,18 +150,28 @@ int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64) {
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
     const int anti = c->t_antiperiodic ? 1 : 0;
+    const bool stage = dirac_staged(c);
     const int slot = kt_begin(c);
-#define DIRAC(T, S, R)                                                                                                \
-    dirac_kernel<T, S, R><<<nwg, TPB, 0, c->stream>>>(c->g, (const C<T> *)(prec == MGDD_F64 ? c->U64 : c->U32),       \
-                                                      (const C<T> *)(prec == MGDD_F64 ? c->A64 : c->A32),             \
-                                                      (const C<S> *)in, (C<S> *)out, nrhs, nwg, anti)
+#define DIRAC(T, S, R, G)                                                                                             \
+    dirac_kernel<T, S, R, G><<<nwg, TPB, 0, c->stream>>>(c->g, (const C<T> *)(prec == MGDD_F64 ? c->U64 : c->U32),    \
+                                                         (const C<T> *)(prec == MGDD_F64 ? c->A64 : c->A32),          \
+                                                         (const C<S> *)in, (C<S> *)out, nrhs, nwg, anti)
+#define DIRAC_STAGED(T)                                                                                               \
+    do {                                                                                                              \
+        if (c->links_su3) {                                                                                           \
+            if (stage) DIRAC(T, T, true, true); else DIRAC(T, T, true, false);                                        \
+        } else {                                                                                                      \
+            if (stage) DIRAC(T, T, false, true); else DIRAC(T, T, false, false);                                      \
+        }                                                                                                             \
+    } while (0)
     if (prec == MGDD_F64) {
-        if (c->links_su3) DIRAC(double, double, true); else DIRAC(double, double, false);
+        DIRAC_STAGED(double);
     } else if (prec == MGDD_F32) {
-        if (c->links_su3) DIRAC(float, float, true); else DIRAC(float, float, false);
+        DIRAC_STAGED(float);
     } else {
-        if (c->links_su3) DIRAC(float, _Float16, true); else DIRAC(float, _Float16, false);
+        if (c->links_su3) DIRAC(float, _Float16, true, false); else DIRAC(float, _Float16, false, false);
     }
+#undef DIRAC_STAGED
 #undef DIRAC
     const size_t sp = 12 * csize(prec);
     kt_end(c, slot, KF_DIRAC, prec, (double)c->g.V * nrhs, dirac_launch_bytes(c, prec, sp, sp, nrhs));

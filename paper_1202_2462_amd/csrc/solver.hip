@@ -151,6 +151,13 @@ static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2
 // ||w''||^2. The caller reads h1, h2 and the norm between the two parts.
 static int cgs_first(Ctx *c, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm,
                      int nb) {
+    if (k > MAXV && k <= 2 * MAXV) {
+        // one pass for h1 (all k vectors at once), one for the update, h2
+        // and the norm
+        int rc = blas_multidot_wide(c, n, V, k, w, h1, nb);
+        if (!rc) rc = blas_update_dot_norm(c, MGDD_F64, n, V, k, h1, w, h2, nrm, nb);
+        return rc;
+    }
     int rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, V, k, w, h1, nb);
     if (rc) return rc;
     if (k <= MAXV) return blas_update_dot_norm(c, MGDD_F64, n, V, k, h1, w, h2, nrm, nb);
@@ -162,7 +169,7 @@ static int cgs_first(Ctx *c, size_t n, void *const *V, int k, void *w, double2 *
 }
 
 static int cgs_second(Ctx *c, size_t n, void *const *V, int k, void *w, const double2 *h2, double2 *nrm, int nb) {
-    if (k <= MAXV) return blas_update_dot(c, MGDD_F64, n, V, k, h2, w, nrm, 1, nb);
+    if (k <= 2 * MAXV) return blas_update_dot(c, MGDD_F64, n, V, k, h2, w, nrm, 1, nb);
     int rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, V, k, h2, -1.0, 1.0, w, nb);
     const void *wp = w;
     if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &wp, 1, w, nrm, nb);

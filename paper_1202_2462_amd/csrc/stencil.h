@@ -270,6 +270,45 @@ __device__ inline void hop_sum(const LinkViews<T> &U, const FV &f, int d, const 
     hop_from<T, 3, false, RECON>(U, f, d, nbr[7], acc, sb);
 }
 
+// The hop sum for a workgroup that holds the spinors of its own lattice block
+// in LDS (sp: [12][NT] complex numbers of type S, the block at device position
+// pos, NT sites). The neighbour's spinor is read through a generic pointer
+// that points into LDS for a neighbour inside the block and into memory (the
+// field in, [12][V]) for one outside it, so that all lanes run the same
+// instructions; S is FP32 or FP64, widened to T on the way.
+__device__ inline float2 widen_to(float2 v, float) { return v; }
+__device__ inline double2 widen_to(double2 v, double) { return v; }
+__device__ inline double2 widen_to(float2 v, double) { return make_double2((double)v.x, (double)v.y); }
+
+template <typename T, typename S, int MU, bool FWD, bool RECON, int NT>
+__device__ inline void hop_from_staged(const LinkViews<T> &U, const C<S> *in, size_t V, const C<S> *sp, int pos,
+                                       int lgVb, int d, int dn, C<T> *acc, T sign) {
+    C<T> psi[12], u[9];
+    const bool inside = (dn >> lgVb) == pos;
+    const C<S> *src = inside ? sp + (dn & (NT - 1)) : in + dn;
+    const size_t stride = inside ? (size_t)NT : V;
+#pragma unroll
+    for (int k = 0; k < 12; k++) psi[k] = widen_to(src[k * stride], T());
+    load_link<T, MU, RECON>(U, FWD ? d : dn, u, 0, sign);
+    hop<T, MU, FWD>(acc, u, psi);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename T, typename S, bool RECON, int NT>
+__device__ inline void hop_sum_staged(const LinkViews<T> &U, const C<S> *in, size_t V, const C<S> *sp, int pos,
+                                      int lgVb, int d, const int *nbr, C<T> *acc, T sf, T sb) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = mk<T>(0, 0);
+    hop_from_staged<T, S, 0, true, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[0], acc, (T)1);
+    hop_from_staged<T, S, 0, false, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[1], acc, (T)1);
+    hop_from_staged<T, S, 1, true, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[2], acc, (T)1);
+    hop_from_staged<T, S, 1, false, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[3], acc, (T)1);
+    hop_from_staged<T, S, 2, true, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[4], acc, (T)1);
+    hop_from_staged<T, S, 2, false, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[5], acc, (T)1);
+    hop_from_staged<T, S, 3, true, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[6], acc, sf);
+    hop_from_staged<T, S, 3, false, RECON, NT>(U, in, V, sp, pos, lgVb, d, nbr[7], acc, sb);
+}
+
 // signs of the time links of site d when they are rebuilt from two rows: -1
 // on the link that crosses the antiperiodic time boundary
 template <typename T> __device__ inline void time_link_signs(const Geom &g, int d, int antiperiodic, T &sf, T &sb) {

@@ -58,30 +58,48 @@ __device__ inline void sum_partials(const double2 *__restrict__ part, int nq, in
 
 // apply step. Grid (Vc, nb), 1024 threads share the 9 2N products of y(a)
 // (dc_row_partial); wave 0 then forms y(a), row i in lane i, and wave k
-// the dot product of basis vector k at site a with it.
-template <typename T>
+// the dot product of basis vector k at site a with it. HC: Dc holds the
+// compact blocks [Vc][5] (self and forward hops); the backward hops are the
+// conjugate transposes of the forward hops of the four backward neighbours
+// (dch_row_partial). Those blocks are the ones the neighbours read for their
+// own forward hops, so that only 5 of the 9 blocks per site have to come from
+// memory when the cache holds the rest.
+template <typename T, bool HC = false>
 __global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
                                                             const C<T> *__restrict__ Dc, const C<T> *__restrict__ w,
                                                             const double2 *__restrict__ npart, int nnp, VecList V,
                                                             int j, C<T> *__restrict__ vj, C<T> *__restrict__ y,
                                                             double2 *__restrict__ part1, double2 *__restrict__ nr) {
-    const int a = blockIdx.x, sg = blockIdx.y, nb = gridDim.y;
+    // consecutive coarse sites on one XCD: the x and y neighbours' blocks and
+    // vectors are read again from that XCD's L2
+    const int a = xcd_block(Vc), sg = blockIdx.y, nb = gridDim.y;
     const int n2 = 2 * N;
     const size_t so = (size_t)sg * Vc * n2;
     __shared__ double2 red[1];
     __shared__ C<T> xs[9 * 64];
     __shared__ C<T> part[APB];
+    __shared__ C<T> partb[HC ? APB : 1];
     sum_partials(npart + (size_t)sg * nnp, 1, nnp, red);
     const double nn = red[0].x;
     const T sc = (T)(nn > 0 ? 1.0 / sqrt(nn) : 0.0);
-    if (a == 0 && threadIdx.x == 0) nr[sg] = make_double2(nn, 0);
+    if (nr && a == 0 && threadIdx.x == 0) nr[sg] = make_double2(nn, 0);
     for (int e = threadIdx.x; e < 9 * n2; e += blockDim.x) {
         const int dd = e / n2, jj = e % n2;
-        C<T> v = w[so + (size_t)cnbr[a * 9 + dd] * n2 + jj];
+        // HC term order: self, forward hops (directions 1, 3, 5, 7), backward
+        const int dir = !HC ? dd : dd == 0 ? 0 : dd <= 4 ? 2 * dd - 1 : 2 * dd - 8;
+        C<T> v = w[so + (size_t)cnbr[a * 9 + dir] * n2 + jj];
         xs[e] = mk<T>(v.x * sc, v.y * sc);
     }
+    const size_t blk = (size_t)n2 * n2;
     __syncthreads();
-    dc_row_partial<T>(Dc + (size_t)a * 9 * n2 * n2, xs, n2, part);
+    if (HC) {
+        const C<T> *Fb[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) Fb[mu] = Dc + ((size_t)cnbr[a * 9 + 2 + 2 * mu] * 5 + 1 + mu) * blk;
+        dch_row_partial<T>(Dc + (size_t)a * 5 * blk, Fb, xs, n2, part, partb);
+    } else {
+        dc_row_partial<T>(Dc + (size_t)a * 9 * blk, xs, n2, part);
+    }
     __syncthreads();
     // wave 0 forms y(a) (row i in lane i) and stores it with v_j(a)
     __shared__ C<T> ys[64];
@@ -90,6 +108,8 @@ __global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const
         C<T> yv = mk<T>(0, 0);
         if (i < n2) {
             for (int q = 0; q < nparts; q++) yv = cadd(yv, part[q * n2 + i]);
+            if (HC)
+                for (int q = 0; q < nparts; q++) yv = cadd(yv, partb[q * n2 + i]);
             y[so + (size_t)a * n2 + i] = yv;
             vj[so + (size_t)a * n2 + i] = xs[i];   // v_j at this site (direction 0 is the site itself)
         }
@@ -338,11 +358,23 @@ int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, con
         for (int k = 0; k <= j; k++) vl.p[k] = V[k];
         void *y = work[j & 1];
         dim3 gapp(Vc, nb);
-#define APPLY(T)                                                                                                  \
-    arnoldi_apply_kernel<T><<<gapp, APB, 0, c->stream>>>(Vc, N, op.nbr, (const C<T> *)(p == MGDD_F64 ? op.D64 : op.D32), \
-                                                         (const C<T> *)w, part3, G, vl, j, (C<T> *)V[j], (C<T> *)y,  \
-                                                         part1, NR + (size_t)j * nb)
-        if (p == MGDD_F64) APPLY(double); else APPLY(float);
+        // the norm of w: summed once here when every workgroup of the apply
+        // would otherwise add many partials, else by each workgroup
+        const double2 *np = part3;
+        int nnp = G;
+        double2 *nrj = NR + (size_t)j * nb;
+        if ((size_t)G * Vc > ((size_t)1 << 20)) {
+            sum_kernel<64><<<nb, 64, 0, c->stream>>>(G, part3, nrj);
+            np = nrj;
+            nnp = 1;
+            nrj = nullptr;
+        }
+#define APPLY(T, HC, D, LDS)                                                                                       \
+    arnoldi_apply_kernel<T, HC><<<gapp, APB, LDS, c->stream>>>(Vc, N, op.nbr, (const C<T> *)(D), (const C<T> *)w, \
+                                                               np, nnp, vl, j, (C<T> *)V[j], (C<T> *)y, part1, nrj)
+        if (p == MGDD_F64) APPLY(double, false, op.D64, 0);
+        else if (op.H32) APPLY(float, true, op.H32, 0);
+        else APPLY(float, false, op.D32, 0);
 #undef APPLY
         const double2 *pin = part1;
         int npin = Vc;

@@ -78,6 +78,9 @@ struct Level1 {  // coarse level of the current P
     int Vc = 0, Va = 0, N = 0;
     void *P64 = nullptr, *P32 = nullptr;    // N fine fields, device layout
     void *Dc64 = nullptr, *Dc32 = nullptr;  // [Vc][9][2N (col)][2N (row)] complex
+    // [Vc][5][2N (col)][2N (row)] FP32: the self block and the forward hops
+    // D_c(a, a + mu); the backward hops follow from gamma5^c-hermiticity
+    void *Dh32 = nullptr;
     int *cnbr = nullptr;                    // [Vc][9] coarse neighbour (self first)
     int *agg_sites = nullptr;               // [Vc][Va] device site of each local site of an aggregate
     int *site_agg = nullptr;                // [V] aggregate of each device site

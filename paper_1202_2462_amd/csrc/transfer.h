@@ -17,6 +17,7 @@ struct StencilOp {
     int V = 0, N = 0;
     const int *nbr = nullptr;
     const void *D64 = nullptr, *D32 = nullptr;
+    const void *H32 = nullptr;   // [V][5][col][row] FP32 self and forward blocks, or null
 };
 inline StencilOp level1_op(const Ctx *c) {
     StencilOp o;
@@ -25,6 +26,7 @@ inline StencilOp level1_op(const Ctx *c) {
     o.nbr = c->c.cnbr;
     o.D64 = c->c.Dc64;
     o.D32 = c->c.Dc32;
+    o.H32 = c->c.Dh32;
     return o;
 }
 inline StencilOp level2_op(const Ctx *c) {

@@ -756,6 +756,31 @@ __global__ void dc_to_f32(int Vc, int n2, const double2 *__restrict__ src, C<T> 
     if (e < n) dst[e] = mk<T>((T)src[e].x, (T)src[e].y);
 }
 
+// FP32 copy of the self block and the four forward-hop blocks of every
+// coarse site, [Vc][5][col][row] (block q: direction 0 for q = 0, the +mu hop
+// 1 + 2 mu for q = 1 + mu)
+__global__ void dc_compact_f32(int Vc, int n2, const double2 *__restrict__ src, float2 *__restrict__ dst) {
+    const size_t blk = (size_t)n2 * n2;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)Vc * 5 * blk) return;
+    const size_t a = e / (5 * blk), r = e % (5 * blk);
+    const int q = (int)(r / blk);
+    const int t = q == 0 ? 0 : 2 * q - 1;
+    const double2 v = src[(a * 9 + t) * blk + r % blk];
+    dst[e] = make_float2((float)v.x, (float)v.y);
+}
+
+static int coarse_to_f32(Ctx *c) {
+    Level1 &L1 = c->c;
+    const int n2 = 2 * L1.N;
+    const size_t blk = (size_t)n2 * n2, n = (size_t)L1.Vc * 9 * blk, nh = (size_t)L1.Vc * 5 * blk;
+    dc_to_f32<float><<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(L1.Vc, n2, (const double2 *)L1.Dc64,
+                                                                        (float2 *)L1.Dc32);
+    dc_compact_f32<<<(unsigned)((nh + 255) / 256), 256, 0, c->stream>>>(L1.Vc, n2, (const double2 *)L1.Dc64,
+                                                                      (float2 *)L1.Dh32);
+    return hip_check(c, hipGetLastError(), "D_c convert");
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -779,7 +804,7 @@ int transfer_setup(Ctx *c, const int *agg, int N) {
     if (same) return MGDD_OK;
     // free the previous level (and the third level built on it)
     level2_free(c);
-    void *old[] = {L1.P64, L1.P32, L1.Dc64, L1.Dc32, L1.cnbr, L1.agg_sites, L1.site_agg, L1.tv64};
+    void *old[] = {L1.P64, L1.P32, L1.Dc64, L1.Dc32, L1.Dh32, L1.cnbr, L1.agg_sites, L1.site_agg, L1.tv64};
     (void)hipStreamSynchronize(c->stream);
     for (void *p : old) dfree(c, p);
     L1 = Level1();
@@ -824,10 +849,13 @@ int transfer_setup(Ctx *c, const int *agg, int N) {
     L1.P32 = dalloc(c, fsz * 8);
     L1.Dc64 = dalloc(c, dsz * 16);
     L1.Dc32 = dalloc(c, dsz * 8);
+    L1.Dh32 = dalloc(c, dsz / 9 * 5 * 8);
     L1.cnbr = (int *)dalloc(c, cnbr.size() * sizeof(int));
     L1.agg_sites = (int *)dalloc(c, agg_sites.size() * sizeof(int));
     L1.site_agg = (int *)dalloc(c, site_agg.size() * sizeof(int));
-    if (!L1.P64 || !L1.tv64 || !L1.P32 || !L1.Dc64 || !L1.Dc32 || !L1.cnbr || !L1.agg_sites || !L1.site_agg) return MGDD_ENOMEM;
+    if (!L1.P64 || !L1.tv64 || !L1.P32 || !L1.Dc64 || !L1.Dc32 || !L1.Dh32 || !L1.cnbr || !L1.agg_sites ||
+        !L1.site_agg)
+        return MGDD_ENOMEM;
     int rc = hip_check(c, hipMemcpy(L1.cnbr, cnbr.data(), cnbr.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
     if (!rc) rc = hip_check(c, hipMemcpy(L1.agg_sites, agg_sites.data(), agg_sites.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
     if (!rc) rc = hip_check(c, hipMemcpy(L1.site_agg, site_agg.data(), site_agg.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
@@ -932,10 +960,7 @@ int launch_coarse_build(Ctx *c) {
         }
         int rc = hip_check(c, hipGetLastError(), "D_c build kernel");
         if (rc) return rc;
-        size_t n = (size_t)L1.Vc * 9 * n2 * n2;
-        dc_to_f32<float><<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(L1.Vc, n2, (const double2 *)L1.Dc64,
-                                                                            (float2 *)L1.Dc32);
-        return hip_check(c, hipGetLastError(), "D_c convert");
+        return coarse_to_f32(c);
     }
     // aggregates of more than 256 sites: terms of each column as 9 fine
     // fields, then a restriction of those fields
@@ -956,10 +981,7 @@ int launch_coarse_build(Ctx *c) {
             rc = launch_restrict_ex(c, MGDD_F64, 9, L1.P64, W, (double2 *)L1.Dc64 + (size_t)j * n2, 9 * blk, blk);
             if (rc) return rc;
         }
-    size_t n = (size_t)L1.Vc * 9 * blk;
-    dc_to_f32<float><<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(L1.Vc, n2, (const double2 *)L1.Dc64,
-                                                                                       (float2 *)L1.Dc32);
-    return hip_check(c, hipGetLastError(), "D_c convert");
+    return coarse_to_f32(c);
 }
 
 int launch_stencil_apply(Ctx *c, const StencilOp &op, int prec, int nrhs, const void *in, void *out) {

@@ -192,3 +192,13 @@ def test_transfer_and_coarse_parity_many_aggregates(dims, block, agg, N):
             err = max(rel(got[i], want[i]) for i in range(nrhs))
             say("  D_c", nrhs, "rhs", prec, err)
             assert err < tol, (nrhs, prec, err)
+    # 12 coarse GMRES steps (the fused Arnoldi kernels; in FP32 from the
+    # compact blocks, whose backward hops are the gamma5^c conjugate
+    # transposes of the neighbours' forward hops) on 1 and 2 right-hand sides
+    b = latgen.gaussian_vector(2 * Vc * 2 * N, 40).reshape(2, Vc, 2, N)
+    want = np.stack([solvers.gmres_fixed(tl.coarse_apply, b[i], 12) for i in range(2)])
+    for nr in (1, 2):
+        for prec, tol in ((F64, 1e-10), (F32, 1e-4)):
+            got = to_np_coarse(lat.coarse_solve(to_dev_coarse(lat, b[:nr], prec), 12))
+            say("  coarse GMRES(12)", nr, "rhs", prec, rel(got, want[:nr]))
+            assert rel(got, want[:nr]) < tol, (nr, prec, rel(got, want[:nr]))

@@ -398,6 +398,14 @@ def main():
         result["time_to_solution"]["mg_mixed"]["converged_in_timed_steps"] = bool(last.converged)
 
     if not args.no_compare:
+        log("multilevel with half-precision storage in the preconditioner")
+        s16 = {}
+        try:
+            bench.step(solve_prec=mg.MIXED_F16, split=s16)
+        except mg.MgddError as e:
+            s16 = {"error": str(e)}
+        result["time_to_solution"]["mg_mixed_f16"] = s16
+        lat.release_workspace()
         log("plain FP64 multilevel")
         s64 = {}
         try:
@@ -448,7 +456,7 @@ def main():
         achieved = bytes_launch / t_launch / 1e9
         tps = counter_traffic(TRAFFIC_FILE, SAP_SOURCES) if big else None
         result["roofline"] = {
-            "bound": "hbm", "kernel": "sap4_kernel<float> (Schwarz colour step, 4 MR steps)",
+            "bound": "hbm", "kernel": "sapc_kernel<256> (FP32 Schwarz colour step, 4 MR steps)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": None if tps is None else tps * units_launch,
             "launches": sap_n, "us_per_launch": t_launch * 1e6, "site_updates_per_launch": units_launch,

@@ -52,8 +52,11 @@
  *  Precision codes: MGDD_F64 (complex double), MGDD_F32 (complex float),
  *    MGDD_F16 (complex stored as two IEEE binary16 values, 4 bytes; a storage
  *    format of fine fields only: accepted by mgdd_field_bytes (level 0),
- *    mgdd_pack, mgdd_unpack, mgdd_dirac_apply and mgdd_timing_read, whose
- *    arithmetic is FP32; values are rounded to nearest even when stored).
+ *    mgdd_pack, mgdd_unpack, mgdd_dirac_apply, mgdd_sap and mgdd_schwarz
+ *    (red-black, MR block solves, special unitary links), mgdd_restrict and
+ *    mgdd_prolong (the coarse field then in FP32, P read in half precision)
+ *    and mgdd_timing_read, whose arithmetic is FP32; values are rounded to
+ *    nearest even when stored).
  */
 #ifndef MGDD_H
 #define MGDD_H
@@ -150,7 +153,9 @@ int mgdd_dirac_apply(mgdd_ctx *ctx, int prec, int nrhs, const void *in, void *ou
  * mgdd_create, else MGDD_ESHAPE); each block system I^T (D - shift) I e =
  * I^T r is approximated by mr_iters minimal residual steps from e = 0 (the
  * shifted block inverses B_j(lambda) of the second setup part use shift =
- * lambda). Asynchronous. */
+ * lambda). prec MGDD_F16: b and z in half precision, the sweep in FP32 (z
+ * rounded once per colour step when it is stored); needs special unitary
+ * links, else MGDD_EINVAL. Asynchronous. */
 int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], int nsweeps, int mr_iters, double shift_re,
              double shift_im, const void *b, void *z);
 
@@ -187,10 +192,15 @@ int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], const mg
  * orthonormalised by modified Gram-Schmidt in column order (P^H P = 1, the
  * unique thin QR with positive diagonal of R). Then builds the coarse operator
  * D_c = P^H D P (a 9-point stencil of 2N x 2N blocks) in FP64, with FP32
- * copies of P and D_c: both precisions are always stored (the FP64 pair
- * serves the plain FP64 solve and the FP64 parts of the setup, the FP32 pair
- * the mixed-precision preconditioner), so there is no storage-precision
- * argument. test_vectors: ntv FP64 device fields (read only).
+ * copies of P and D_c and a half-precision copy of P: every precision is
+ * always stored (the FP64 pair serves the plain FP64 solve and the FP64 parts
+ * of the setup, the FP32 pair the mixed-precision preconditioner, the half
+ * P the half-storage transfers), so there is no storage-precision argument.
+ * The FP32 copy of D_c used by the coarse GMRES keeps the self block and the
+ * four forward hops of each coarse site; its backward hops are the
+ * gamma5^c-conjugate transposes D_c(a, a - mu) = g5c D_c(a - mu, a)^H g5c
+ * (D_c is gamma5^c-hermitian because D is gamma5-hermitian and
+ * gamma_5 P = P gamma_5^c). test_vectors: ntv FP64 device fields (read only).
  * Synchronous. Errors: MGDD_ERANK (ntv > 6 * vol(agg) or a piece is rank
  * deficient), MGDD_ESHAPE, MGDD_EINVAL (ntv not in 1..32). */
 int mgdd_build_P(mgdd_ctx *ctx, const int agg[4], int ntv, const void *test_vectors);
@@ -214,10 +224,13 @@ int mgdd_save_setup(mgdd_ctx *ctx, const char *path);
  * changed), and those of mgdd_build_P. */
 int mgdd_load_setup(mgdd_ctx *ctx, const char *path);
 
-/* coarse = P^H fine (restriction R = P^H, Section 3); nrhs fields. */
+/* coarse = P^H fine (restriction R = P^H, Section 3); nrhs fields. prec
+ * MGDD_F16: fine field and P in half precision, coarse field and arithmetic
+ * in FP32. */
 int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coarse);
 
-/* fine = P coarse (interpolation, Section 3); nrhs fields. */
+/* fine = P coarse (interpolation, Section 3); nrhs fields. prec MGDD_F16:
+ * coarse field FP32, P and the fine field (rounded once) in half precision. */
 int mgdd_prolong(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *fine);
 
 /* out = D_c in, D_c = P^H D P (eq. (3.1)); nrhs coarse fields. */
@@ -289,14 +302,19 @@ int mgdd_setup_bootstrap(mgdd_ctx *ctx, const mgdd_setup_params *params, const v
                          const void *arnoldi_start);
 
 enum { MGDD_SOLVER_FGMRES_MG = 0, MGDD_SOLVER_GCR = 1, MGDD_SOLVER_GCR_EO = 2, MGDD_SOLVER_CGN = 3 };
-enum { MGDD_PLAIN_F64 = 0, MGDD_MIXED = 1 };
+enum { MGDD_PLAIN_F64 = 0, MGDD_MIXED = 1, MGDD_MIXED_F16 = 2 };
 
 typedef struct {
     int solver;        /* MGDD_SOLVER_* */
     int precision;     /* MGDD_PLAIN_F64, or MGDD_MIXED: the preconditioner (SAP,
                           restriction, prolongation, coarse solve) in FP32, the
                           outer orthogonalisation, true residual and solution
-                          update in FP64 */
+                          update in FP64; or MGDD_MIXED_F16: as MGDD_MIXED with
+                          the preconditioner's fine fields (its copy of the
+                          residual, the Schwarz iterate, the flexible basis Z)
+                          and P stored in half precision, arithmetic in FP32,
+                          the coarse level in FP32 (red-black Schwarz with MR
+                          block solves and special unitary links only) */
     int restart;       /* Krylov restart length m */
     double tol;        /* stop when ||b - D z|| <= tol ||b|| (true residual, FP64) */
     int maxit;         /* maximal number of outer iterations */

@@ -629,6 +629,7 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
         if (px == MGDD_F64 && py == MGDD_F64) LC2(double, double);
         else if (px == MGDD_F32 && py == MGDD_F32) LC2(float, float);
         else if (px == MGDD_F32 && py == MGDD_F64) LC2(float, double);
+        else if (px == MGDD_F16 && py == MGDD_F64) LC2(_Float16, double);
         else LC2(double, float);
 #undef LC3
 #undef LC2

@@ -408,7 +408,7 @@ static int check_block(Ctx *c, const int *block) {
 
 int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], int nsweeps, int mr_iters, double shift_re,
              double shift_im, const void *b, void *z) {
-    if (!ctx || !b || !z || !valid_prec(prec) || nrhs <= 0 || nsweeps < 0 || mr_iters < 0) return MGDD_EINVAL;
+    if (!ctx || !b || !z || !valid_fine_prec(prec) || nrhs <= 0 || nsweeps < 0 || mr_iters < 0) return MGDD_EINVAL;
     if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
     if (check_block(&ctx->c, block)) return MGDD_ESHAPE;
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
@@ -419,8 +419,10 @@ int mgdd_sap(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], int nsweeps,
 
 int mgdd_schwarz(mgdd_ctx *ctx, int prec, int nrhs, const int block[4], const mgdd_schwarz_params *params,
                  const void *b, void *z) {
-    if (!ctx || !params || !b || !z || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (!ctx || !params || !b || !z || !valid_fine_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     const mgdd_schwarz_params *q = params;
+    if (prec == MGDD_F16 && (q->additive || q->block_solver != MGDD_BLOCK_MR))
+        return fail(&ctx->c, MGDD_EINVAL, "half-precision storage: red-black Schwarz with MR block solves only");
     if (b == z) return fail(&ctx->c, MGDD_EINVAL, "b and z alias");
     if (check_block(&ctx->c, block)) return MGDD_ESHAPE;
     if (q->nsweeps < 0 || q->block_iters < 0 || (q->block_solver != MGDD_BLOCK_MR && q->block_solver != MGDD_BLOCK_GMRES))
@@ -569,7 +571,7 @@ int mgdd_load_setup(mgdd_ctx *ctx, const char *path) {
 }
 
 int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coarse) {
-    if (!ctx || !fine || !coarse || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (!ctx || !fine || !coarse || !valid_fine_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     int rc = need_coarse(ctx);
     if (rc) return rc;
     GUARD_BEGIN
@@ -578,7 +580,7 @@ int mgdd_restrict(mgdd_ctx *ctx, int prec, int nrhs, const void *fine, void *coa
 }
 
 int mgdd_prolong(mgdd_ctx *ctx, int prec, int nrhs, const void *coarse, void *fine) {
-    if (!ctx || !fine || !coarse || !valid_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
+    if (!ctx || !fine || !coarse || !valid_fine_prec(prec) || nrhs <= 0) return MGDD_EINVAL;
     int rc = need_coarse(ctx);
     if (rc) return rc;
     GUARD_BEGIN
@@ -897,7 +899,7 @@ int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const v
     if (sp->restart < 1 || sp->restart > 256 || sp->maxit < 0 || !(sp->tol > 0) ||
         (sp->solver != MGDD_SOLVER_FGMRES_MG && sp->solver != MGDD_SOLVER_GCR && sp->solver != MGDD_SOLVER_GCR_EO &&
          sp->solver != MGDD_SOLVER_CGN) ||
-        (sp->precision != MGDD_PLAIN_F64 && sp->precision != MGDD_MIXED))
+        (sp->precision != MGDD_PLAIN_F64 && sp->precision != MGDD_MIXED && sp->precision != MGDD_MIXED_F16))
         return fail(&ctx->c, MGDD_EINVAL, "bad solve parameters");
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     if (sp->solver == MGDD_SOLVER_FGMRES_MG) {

@@ -63,21 +63,21 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
     store_spinor<T>(o, d, res);
 }
 
-// FP32 spinors read as FP64 (the widening is exact)
-struct WidenView {
-    FieldView<float> f;
-    __device__ WidenView(const float2 *base, size_t V, int ncomp) : f(base, V, ncomp) {}
+// FP32 or half-precision spinors (S) read as FP64 (the widening is exact)
+template <typename S> struct WidenView {
+    typename F32Store<S>::view f;
+    __device__ WidenView(const C<S> *base, size_t V, int ncomp) : f((const float2 *)base, V, ncomp) {}
     __device__ double2 ld(int comp, int site, unsigned salt = 0) const {
         const float2 v = f.ld(comp, site, salt);
         return make_double2((double)v.x, (double)v.y);
     }
 };
 
-// dirac_kernel<double> with FP32 input: the FP64 apply of an FP32 field
-// without a converted copy
-template <bool RECON, bool STAGE>
+// dirac_kernel<double> with FP32 or half-precision input (S): the FP64 apply
+// of such a field without a converted copy
+template <bool RECON, bool STAGE, typename S = float>
 __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 *__restrict__ Up,
-                                                          const double2 *__restrict__ Ap, const float2 *__restrict__ in,
+                                                          const double2 *__restrict__ Ap, const C<S> *__restrict__ in,
                                                           double2 *__restrict__ out, int nrhs, int nwg,
                                                           int antiperiodic) {
     const int w = xcd_block(nwg);
@@ -92,20 +92,20 @@ __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 
     const size_t V = g.V;
     LinkViews<double> U(Up, V);
     CloverViews<double> A(Ap, V);
-    WidenView f(in + (size_t)r * 12 * V, V, 12);
+    WidenView<S> f(in + (size_t)r * 12 * V, V, 12);
     FieldView<double> o(out + (size_t)r * 12 * V, V, 12);
     double2 acc[12], psi[12], res[12];
     if (STAGE) {
-        __shared__ float2 sp[12 * TPB];
-        const float2 *fin = in + (size_t)r * 12 * V;
+        __shared__ C<S> sp[12 * TPB];
+        const C<S> *fin = in + (size_t)r * 12 * V;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            const float2 v = f.f.ld(k, d);
-            sp[k * TPB + (d & (TPB - 1))] = v;
+            const float2 v = f.f.ld(k, d);   // exact: back to S unchanged below
+            sp[k * TPB + (d & (TPB - 1))] = mk<S>((S)v.x, (S)v.y);
             psi[k] = make_double2((double)v.x, (double)v.y);
         }
         __syncthreads();
-        hop_sum_staged<double, float, RECON, TPB>(U, fin, V, sp, d >> g.lgVb, g.lgVb, d, nbr, acc, sf, sb);
+        hop_sum_staged<double, S, RECON, TPB>(U, fin, V, sp, d >> g.lgVb, g.lgVb, d, nbr, acc, sf, sb);
     } else {
         hop_sum<double, RECON>(U, f, d, nbr, acc, sf, sb);
         load_spinor<double>(f, d, psi);
@@ -129,21 +129,27 @@ static double dirac_launch_bytes(const Ctx *c, int prec, size_t in_bytes, size_t
 // The staged kernels take one workgroup per lattice block: blocks of TPB sites
 static bool dirac_staged(const Ctx *c) { return c->g.Vb == TPB; }
 
-int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64) {
+int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64, int in_prec) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
     const int anti = c->t_antiperiodic ? 1 : 0;
     const bool stage = dirac_staged(c);
     const int slot = kt_begin(c);
-#define WIDEN(R, G)                                                                                                   \
-    dirac_widen_kernel<R, G><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,     \
-                                                         (const float2 *)in32, (double2 *)out64, nrhs, nwg, anti)
-    if (c->links_su3) {
-        if (stage) WIDEN(true, true); else WIDEN(true, false);
-    } else {
-        if (stage) WIDEN(false, true); else WIDEN(false, false);
-    }
+#define WIDEN(R, G, S)                                                                                                \
+    dirac_widen_kernel<R, G, S><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,  \
+                                                            (const C<S> *)in32, (double2 *)out64, nrhs, nwg, anti)
+#define WIDEN_S(S)                                                                                                    \
+    do {                                                                                                              \
+        if (c->links_su3) {                                                                                           \
+            if (stage) WIDEN(true, true, S); else WIDEN(true, false, S);                                              \
+        } else {                                                                                                      \
+            if (stage) WIDEN(false, true, S); else WIDEN(false, false, S);                                            \
+        }                                                                                                             \
+    } while (0)
+    if (in_prec == MGDD_F16) WIDEN_S(_Float16); else WIDEN_S(float);
+#undef WIDEN_S
 #undef WIDEN
-    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs, dirac_launch_bytes(c, MGDD_F64, 96, 192, nrhs));
+    kt_end(c, slot, KF_DIRAC, MGDD_F64, (double)c->g.V * nrhs,
+           dirac_launch_bytes(c, MGDD_F64, 12 * csize(in_prec), 192, nrhs));
     return hip_check(c, hipGetLastError(), "dirac kernel");
 }
 

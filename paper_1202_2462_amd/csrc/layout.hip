@@ -40,6 +40,7 @@ __global__ void unpack_kernel(Geom g, int nrhs, const C<T> *__restrict__ src, do
     }
 }
 
+// (to half precision: one rounding, to nearest even, from FP64 or FP32)
 template <typename S, typename D>
 __global__ void convert_kernel(size_t n, const C<S> *__restrict__ src, C<D> *__restrict__ dst) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -303,10 +304,14 @@ int launch_unpack(Ctx *c, int prec, int nrhs, const void *src, double2 *canon) {
 
 int launch_convert(Ctx *c, int from, int to, size_t n, const void *src, void *dst) {
     if (from == to) return hip_check(c, hipMemcpyAsync(dst, src, n * csize(from), hipMemcpyDeviceToDevice, c->stream), "copy");
-    if (from == MGDD_F64)
-        convert_kernel<double, float><<<nblk(n), TPB, 0, c->stream>>>(n, (const double2 *)src, (float2 *)dst);
-    else
-        convert_kernel<float, double><<<nblk(n), TPB, 0, c->stream>>>(n, (const float2 *)src, (double2 *)dst);
+#define CONV(S, D) convert_kernel<S, D><<<nblk(n), TPB, 0, c->stream>>>(n, (const C<S> *)src, (C<D> *)dst)
+    if (from == MGDD_F64 && to == MGDD_F32) CONV(double, float);
+    else if (from == MGDD_F32 && to == MGDD_F64) CONV(float, double);
+    else if (from == MGDD_F64 && to == MGDD_F16) CONV(double, _Float16);
+    else if (from == MGDD_F32 && to == MGDD_F16) CONV(float, _Float16);
+    else if (from == MGDD_F16 && to == MGDD_F32) CONV(_Float16, float);
+    else CONV(_Float16, double);
+#undef CONV
     return hip_check(c, hipGetLastError(), "convert kernel");
 }
 

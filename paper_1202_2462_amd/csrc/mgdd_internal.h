@@ -77,6 +77,7 @@ struct Level1 {  // coarse level of the current P
     int Lc[4] = {0, 0, 0, 0};
     int Vc = 0, Va = 0, N = 0;
     void *P64 = nullptr, *P32 = nullptr;    // N fine fields, device layout
+    void *P16 = nullptr;                    // the same in half precision (FP16-storage transfers)
     void *Dc64 = nullptr, *Dc32 = nullptr;  // [Vc][9][2N (col)][2N (row)] complex
     // [Vc][5][2N (col)][2N (row)] FP32: the self block and the forward hops
     // D_c(a, a + mu); the backward hops follow from gamma5^c-hermiticity

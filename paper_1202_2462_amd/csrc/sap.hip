@@ -601,8 +601,9 @@ __device__ inline void spinor_from_lds(const float2 *rl, int site, int src0, int
     }
 }
 
-// the same from a field in memory (device site dn)
-__device__ inline void spinor_from_field(const FieldView<float> &f, int dn, int src0, int src1, float2 *u, float2 *la,
+// the same from a field in memory (device site dn; FV: FP32 or half storage)
+template <typename FV>
+__device__ inline void spinor_from_field(const FV &f, int dn, int src0, int src1, float2 *u, float2 *la,
                                          float2 *lb) {
 #pragma unroll
     for (int c = 0; c < 6; c++) u[c] = f.ld(c, dn);
@@ -669,10 +670,13 @@ __device__ inline void block_hops(const float2 *fl, const float2 *lnk, int h, in
     }
 }
 
-template <int VB>
+// S: storage of the spinor fields b and z (float, or _Float16: half-precision
+// storage with the same FP32 arithmetic, z rounded once when it is stored)
+template <int VB, typename S = float>
 __global__ __launch_bounds__(2 * VB) __attribute__((amdgpu_waves_per_eu(4))) void sapc_kernel(
-    Geom g, const float2 *__restrict__ Up, const float2 *__restrict__ Ap, const float2 *__restrict__ b,
-    float2 *__restrict__ z, int colour, int mr, float sre, float sim, int antiperiodic) {
+    Geom g, const float2 *__restrict__ Up, const float2 *__restrict__ Ap, const void *__restrict__ b,
+    void *__restrict__ z, int colour, int mr, float sre, float sim, int antiperiodic) {
+    using FV = typename F32Store<S>::view;
     extern __shared__ unsigned char smem[];
     constexpr int Vb = VB, RS = VB + 4, LS = VB + 2;
     float2 *rho_lds = (float2 *)smem;                   // [12][RS]
@@ -682,9 +686,9 @@ __global__ __launch_bounds__(2 * VB) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int pos = (colour ? g.ncol0 : 0) + xcd_block(gridDim.x);
     const int h = threadIdx.x & 1, l = threadIdx.x >> 1;
     const int d = (pos << g.lgVb) + l;
-    const size_t roff = (size_t)blockIdx.y * 12 * V;
+    const size_t roff = (size_t)blockIdx.y * 12 * V * F32Store<S>::ESZ;   // bytes
     const FieldView<float> Uall(Up, V, 36), Aall(Ap, V, 36);
-    const FieldView<float> bf(b + roff, V, 12), zf(z + roff, V, 12);
+    const FV bf((const float2 *)((const char *)b + roff), V, 12), zf((const float2 *)((const char *)z + roff), V, 12);
     const unsigned aoff = (unsigned)h * 18u * Aall.cs, coff = (unsigned)h * 6u * zf.cs;
     const bool swp = h == 0;
     const float sig = h ? -1.f : 1.f;
@@ -865,16 +869,26 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
     // two lanes per site, the links' first two rows staged (special unitary links)
     const size_t ldsc = 8 * (12 * ((size_t)g.Vb + 4) + 24 * ((size_t)g.Vb + 2)) + 4 * 3 * (2 * g.Vb / 64);
     dim3 grid(nblocks, nrhs);
+    const bool two_lane = c->links_su3 && ldsc <= c->lds_max;
+    if (prec == MGDD_F16 && !two_lane)
+        return fail(c, MGDD_EINVAL,
+                    "half-precision spinor storage in the Schwarz sweep needs special unitary links (the "
+                    "two-lanes-per-site kernel)");
     const int slot = kt_begin(c);
-    if (prec == MGDD_F32 && c->links_su3 && ldsc <= c->lds_max) {
+    if ((prec == MGDD_F32 || prec == MGDD_F16) && two_lane) {
         const int anti = c->t_antiperiodic ? 1 : 0;
-#define SAPC(VB)                                                                                                  \
-    sapc_kernel<VB><<<grid, 2 * VB, ldsc, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,         \
-                                                       (const float2 *)b, (float2 *)z, col, mr, (float)sre,       \
-                                                       (float)sim, anti)
-        if (g.Vb == 256) SAPC(256);
-        else if (g.Vb == 128) SAPC(128);
-        else SAPC(64);
+#define SAPC(VB, S)                                                                                               \
+    sapc_kernel<VB, S><<<grid, 2 * VB, ldsc, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32, b, z, \
+                                                          col, mr, (float)sre, (float)sim, anti)
+        if (prec == MGDD_F32) {
+            if (g.Vb == 256) SAPC(256, float);
+            else if (g.Vb == 128) SAPC(128, float);
+            else SAPC(64, float);
+        } else {
+            if (g.Vb == 256) SAPC(256, _Float16);
+            else if (g.Vb == 128) SAPC(128, _Float16);
+            else SAPC(64, _Float16);
+        }
 #undef SAPC
     } else if (prec == MGDD_F64) {
         sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64, (const double2 *)c->A64,
@@ -895,7 +909,7 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
     }
     // per site of the colour: links and clover term once per launch; z in,
     // b in and z out per field (the halo comes from cache)
-    const double lc = prec == MGDD_F64 ? 1152.0 : 576.0, sp = 3.0 * 12 * csize(prec);
+    const double lc = prec == MGDD_F64 ? 1152.0 : 576.0, sp = 3.0 * 12 * csize(prec);   // FP16: FP32 links
     kt_end(c, slot, KF_SAP, prec, (double)nblocks * g.Vb * nrhs, (double)nblocks * g.Vb * (lc + sp * nrhs));
     return hip_check(c, hipGetLastError(), "sap kernel");
 }

@@ -42,6 +42,7 @@ size_t stencil_gmres_bytes(const StencilOp &op, int p, int m, int nb);
 int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void *b, void *x, Arena &A,
                   int *status = nullptr);
 int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o, Arena &A);
+int solve_prec(const mgdd_solve_params *sp);
 int solve_batch(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st);
 int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void *start64);
 int level2_bootstrap(Ctx *c, const mgdd_level2_params *lp, const void *random2);

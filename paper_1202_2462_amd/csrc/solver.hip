@@ -334,6 +334,11 @@ int stencil_gmres(Ctx *c, const StencilOp &op, int p, int m, int nb, const void 
 
 // ---------------------------------------------------------------- multilevel preconditioner
 
+// the precision of the preconditioner's fine fields in a solve
+int solve_prec(const mgdd_solve_params *sp) {
+    return sp->precision == MGDD_MIXED ? MGDD_F32 : sp->precision == MGDD_MIXED_F16 ? MGDD_F16 : MGDD_F64;
+}
+
 MgOpts mg_opts(const mgdd_solve_params *sp) {
     MgOpts o;
     o.nu = sp->nu;
@@ -406,30 +411,38 @@ static int level2_fgmres(Ctx *c, int p, const MgOpts &o, int nb, const void *b, 
     return rc;
 }
 
+// the precision of the coarse level under fine precision p: half-precision
+// storage of the fine fields keeps the coarse level in FP32
+static int coarse_prec(int p) { return p == MGDD_F16 ? MGDD_F32 : p; }
+
 size_t precond_bytes(const Ctx *c, int p, const MgOpts &o, int nb) {
     size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
-    const size_t inner = o.levels == 3 ? level2_fgmres_bytes(c, p, o, nb) : coarse_gmres_bytes(c, p, o.cit, nb);
-    return n * 8 + 2 * nc * csize(p) + inner + schwarz_work_bytes(c, p, nb, smoother_opts(o)) + 4096;
+    const int pc = coarse_prec(p);
+    const size_t inner = o.levels == 3 ? level2_fgmres_bytes(c, pc, o, nb) : coarse_gmres_bytes(c, pc, o.cit, nb);
+    return n * 8 + 2 * nc * csize(pc) + inner + schwarz_work_bytes(c, p, nb, smoother_opts(o)) + 4096;
 }
 
 // z = SAP^nu(D, r, z0 = P x_c) for nb right-hand sides at once, x_c the
 // coarse solve of P^H r: GMRES_cit on D_c (two levels) or the level-2
-// flexible GMRES (three levels); r in FP64, z in precision p.
+// flexible GMRES (three levels); r in FP64, z in precision p (MGDD_F16:
+// half-precision storage of r's copy, z and P, FP32 arithmetic, the coarse
+// level in FP32).
 int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o, Arena &A) {
     const size_t n = (size_t)12 * c->g.V * nb, nc = (size_t)c->c.Vc * 2 * c->c.N * nb;
     const size_t mark = A.off;
+    const int pc = coarse_prec(p);
     const void *rp = r64;
     int rc = MGDD_OK;
-    if (p == MGDD_F32) {
-        void *r32 = A.take(n * 8);
-        if (!r32) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
-        rc = launch_convert(c, MGDD_F64, MGDD_F32, n, r64, r32);
-        rp = r32;
+    if (p != MGDD_F64) {
+        void *rs = A.take(n * csize(p));
+        if (!rs) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
+        rc = launch_convert(c, MGDD_F64, p, n, r64, rs);
+        rp = rs;
     }
-    void *cb = A.take(nc * csize(p)), *cx = A.take(nc * csize(p));
+    void *cb = A.take(nc * csize(pc)), *cx = A.take(nc * csize(pc));
     if (!cx) return fail(c, MGDD_ENOMEM, "preconditioner workspace");
     if (!rc) rc = launch_restrict(c, p, nb, rp, cb);
-    if (!rc) rc = o.levels == 3 ? level2_fgmres(c, p, o, nb, cb, cx, A) : coarse_gmres(c, p, o.cit, nb, cb, cx, A);
+    if (!rc) rc = o.levels == 3 ? level2_fgmres(c, pc, o, nb, cb, cx, A) : coarse_gmres(c, pc, o.cit, nb, cb, cx, A);
     if (!rc) rc = launch_prolong(c, p, nb, cx, z);
     if (!rc && o.nu > 0) {
         const SchwarzOpts so = smoother_opts(o);
@@ -452,7 +465,7 @@ int mg_precond(Ctx *c, int p, int nb, const void *r64, void *z, const MgOpts &o,
 // restart and its iterate no longer changes.
 static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, void *z, mgdd_solve_stats *st,
                   Arena &A) {
-    const int m = sp->restart, p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
+    const int m = sp->restart, p = solve_prec(sp);
     const size_t n = (size_t)12 * c->g.V, cs = csize(p), nn = n * nb;
     std::vector<void *> V(m + 1), Z(m);
     for (int i = 0; i <= m; i++) V[i] = A.take(nn * 16);
@@ -545,8 +558,8 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
         int kmax = 0;
         for (int j = 0; j < m; j++) {
             rc = mg_precond(c, p, nb, V[j], Z[j], mg_opts(sp), A);
-            if (!rc && p == MGDD_F32) {
-                rc = launch_dirac_widen(c, nb, Z[j], w);
+            if (!rc && p != MGDD_F64) {
+                rc = launch_dirac_widen(c, nb, Z[j], w, p);
             } else if (!rc) {
                 rc = launch_dirac(c, MGDD_F64, nb, Z[j], w);
             }
@@ -860,7 +873,7 @@ size_t solve_bytes(const Ctx *c, const mgdd_solve_params *sp, int nb) {
     const size_t n = (size_t)12 * c->g.V;
     const int m = sp->restart;
     if (sp->solver == MGDD_SOLVER_FGMRES_MG) {
-        int p = sp->precision == MGDD_MIXED ? MGDD_F32 : MGDD_F64;
+        const int p = solve_prec(sp);
         return (size_t)(m + 3) * (n * nb * 16 + 256) + (size_t)m * (n * nb * csize(p) + 256) +
                (3 * (size_t)m + 8) * nb * 16 + precond_bytes(c, p, mg_opts(sp), nb) + 65536;
     }

@@ -86,6 +86,31 @@ struct HalfFieldView {
         h.y = (_Float16)v.y;
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, (unsigned)site * 4u, comp * cs, 0);
     }
+    // with an extra per-lane byte offset, as FieldView's
+    __device__ float2 ld_lane(int comp, int site, unsigned lane_off, unsigned salt = 0) const {
+        const half_cx h = __builtin_bit_cast(
+            half_cx, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)site * 4u + lane_off, comp * cs + salt, 0));
+        return make_float2((float)h.x, (float)h.y);
+    }
+    __device__ void st_lane(int comp, int site, unsigned lane_off, float2 v) const {
+        half_cx h;
+        h.x = (_Float16)v.x;
+        h.y = (_Float16)v.y;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, (unsigned)site * 4u + lane_off,
+                                              comp * cs, 0);
+    }
+};
+
+// the view of a fine field stored as S (float: FieldView<float>, _Float16:
+// HalfFieldView), arithmetic in FP32; ESZ: bytes of one complex value
+template <typename S> struct F32Store;
+template <> struct F32Store<float> {
+    using view = FieldView<float>;
+    static constexpr size_t ESZ = 8;
+};
+template <> struct F32Store<_Float16> {
+    using view = HalfFieldView;
+    static constexpr size_t ESZ = 4;
 };
 
 // FV: FieldView<T>, or HalfFieldView with T = float
@@ -275,10 +300,11 @@ __device__ inline void hop_sum(const LinkViews<T> &U, const FV &f, int d, const 
 // pos, NT sites). The neighbour's spinor is read through a generic pointer
 // that points into LDS for a neighbour inside the block and into memory (the
 // field in, [12][V]) for one outside it, so that all lanes run the same
-// instructions; S is FP32 or FP64, widened to T on the way.
+// instructions; S is FP64, FP32 or half precision, widened to T on the way.
 __device__ inline float2 widen_to(float2 v, float) { return v; }
 __device__ inline double2 widen_to(double2 v, double) { return v; }
 __device__ inline double2 widen_to(float2 v, double) { return make_double2((double)v.x, (double)v.y); }
+__device__ inline double2 widen_to(half_cx v, double) { return make_double2((double)v.x, (double)v.y); }
 
 template <typename T, typename S, int MU, bool FWD, bool RECON, int NT>
 __device__ inline void hop_from_staged(const LinkViews<T> &U, const C<S> *in, size_t V, const C<S> *sp, int pos,

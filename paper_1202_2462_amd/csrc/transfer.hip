@@ -172,10 +172,11 @@ __global__ __launch_bounds__(TPB) void build_P_reg_kernel(int V, int Va, int N, 
 // One workgroup per (aggregate, field). out[a * ostride + r * rstride + chi * N + k].
 // The workgroups of the nrhs fields of one aggregate are consecutive and on
 // one XCD, so the aggregate's columns of P come from HBM once per launch and
-// from L2 for the other fields.
-template <typename T>
+// from L2 for the other fields. T: arithmetic and coarse precision; SP, SF:
+// storage of P and of the fine field (T, or half precision with T = float).
+template <typename T, typename SP = T, typename SF = T>
 __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, const int *__restrict__ agg_sites,
-                                                       const C<T> *__restrict__ P, const C<T> *__restrict__ f,
+                                                       const C<SP> *__restrict__ P, const C<SF> *__restrict__ f,
                                                        C<T> *__restrict__ out, size_t ostride, size_t rstride,
                                                        int nrhs, int ks) {
     extern __shared__ unsigned char smem[];
@@ -187,24 +188,25 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
     const int kper = (N + ks - 1) / ks, kb = part * kper, ke = kb + kper < N ? kb + kper : N;
     const int *sites = agg_sites + (size_t)a * Va;
     const size_t fs = (size_t)12 * V;
-    const C<T> *fr = f + (size_t)r * fs;
+    const C<SF> *fr = f + (size_t)r * fs;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    auto wide = [](auto v) { return mk<T>((T)v.x, (T)v.y); };
     // one site per thread when Va <= blockDim (the field values stay in registers)
     C<T> f0[12];
     const bool one = Va <= (int)blockDim.x;
     if (one) {
         int d = threadIdx.x < Va ? sites[threadIdx.x] : 0;
 #pragma unroll
-        for (int c = 0; c < 12; c++) f0[c] = threadIdx.x < Va ? fr[(size_t)c * V + d] : mk<T>(0, 0);
+        for (int c = 0; c < 12; c++) f0[c] = threadIdx.x < Va ? wide(fr[(size_t)c * V + d]) : mk<T>(0, 0);
     }
     for (int k = kb; k < ke; k++) {
-        const C<T> *pk = P + (size_t)k * fs;
+        const C<SP> *pk = P + (size_t)k * fs;
         T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
         for (int l = threadIdx.x; l < Va; l += blockDim.x) {
             int d = sites[l];
 #pragma unroll
             for (int c = 0; c < 12; c++) {
-                C<T> pv = pk[(size_t)c * V + d], fv = one ? f0[c] : fr[(size_t)c * V + d];
+                C<T> pv = wide(pk[(size_t)c * V + d]), fv = one ? f0[c] : wide(fr[(size_t)c * V + d]);
                 T re = pv.x * fv.x + pv.y * fv.y, im = pv.x * fv.y - pv.y * fv.x;
                 if (c < 6) { p0 += re; p1 += im; } else { p2 += re; p3 += im; }
             }
@@ -233,10 +235,12 @@ __global__ __launch_bounds__(TPB) void restrict_kernel(int V, int Va, int N, con
 //
 // One thread per (site, field), the fields of one site in consecutive threads:
 // they read the same entries of P, so P comes from HBM once per launch.
-template <typename T>
+// T: arithmetic and coarse precision; SP, SF: storage of P and of the fine
+// field (rounded once to nearest even when half precision).
+template <typename T, typename SP = T, typename SF = T>
 __global__ __launch_bounds__(TPB) void prolong_kernel(int V, int Vc, int N, const int *__restrict__ site_agg,
-                                                      const C<T> *__restrict__ P, const C<T> *__restrict__ cin,
-                                                      C<T> *__restrict__ f, int nrhs) {
+                                                      const C<SP> *__restrict__ P, const C<T> *__restrict__ cin,
+                                                      C<SF> *__restrict__ f, int nrhs) {
     const size_t i = (size_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= (size_t)V * nrhs) return;
     const int r = (int)(i % nrhs), d = (int)(i / nrhs);
@@ -247,14 +251,17 @@ __global__ __launch_bounds__(TPB) void prolong_kernel(int V, int Vc, int N, cons
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = mk<T>(0, 0);
     for (int k = 0; k < N; k++) {
-        const C<T> *pk = P + (size_t)k * fs;
+        const C<SP> *pk = P + (size_t)k * fs;
         C<T> x0 = x[k], x1 = x[N + k];
 #pragma unroll
-        for (int c = 0; c < 12; c++) cfma(acc[c], pk[(size_t)c * V + d], c < 6 ? x0 : x1);
+        for (int c = 0; c < 12; c++) {
+            const C<SP> pv = pk[(size_t)c * V + d];
+            cfma(acc[c], mk<T>((T)pv.x, (T)pv.y), c < 6 ? x0 : x1);
+        }
     }
-    C<T> *fr = f + (size_t)r * fs;
+    C<SF> *fr = f + (size_t)r * fs;
 #pragma unroll
-    for (int c = 0; c < 12; c++) fr[(size_t)c * V + d] = acc[c];
+    for (int c = 0; c < 12; c++) fr[(size_t)c * V + d] = mk<SF>((SF)acc[c].x, (SF)acc[c].y);
 }
 
 // ---------------------------------------------------------------- terms of D for one column of D_c
@@ -804,7 +811,7 @@ int transfer_setup(Ctx *c, const int *agg, int N) {
     if (same) return MGDD_OK;
     // free the previous level (and the third level built on it)
     level2_free(c);
-    void *old[] = {L1.P64, L1.P32, L1.Dc64, L1.Dc32, L1.Dh32, L1.cnbr, L1.agg_sites, L1.site_agg, L1.tv64};
+    void *old[] = {L1.P64, L1.P32, L1.P16, L1.Dc64, L1.Dc32, L1.Dh32, L1.cnbr, L1.agg_sites, L1.site_agg, L1.tv64};
     (void)hipStreamSynchronize(c->stream);
     for (void *p : old) dfree(c, p);
     L1 = Level1();
@@ -847,13 +854,14 @@ int transfer_setup(Ctx *c, const int *agg, int N) {
     L1.P64 = dalloc(c, fsz * 16);
     L1.tv64 = dalloc(c, fsz * 16);
     L1.P32 = dalloc(c, fsz * 8);
+    L1.P16 = dalloc(c, fsz * 4);
     L1.Dc64 = dalloc(c, dsz * 16);
     L1.Dc32 = dalloc(c, dsz * 8);
     L1.Dh32 = dalloc(c, dsz / 9 * 5 * 8);
     L1.cnbr = (int *)dalloc(c, cnbr.size() * sizeof(int));
     L1.agg_sites = (int *)dalloc(c, agg_sites.size() * sizeof(int));
     L1.site_agg = (int *)dalloc(c, site_agg.size() * sizeof(int));
-    if (!L1.P64 || !L1.tv64 || !L1.P32 || !L1.Dc64 || !L1.Dc32 || !L1.Dh32 || !L1.cnbr || !L1.agg_sites ||
+    if (!L1.P64 || !L1.tv64 || !L1.P32 || !L1.P16 || !L1.Dc64 || !L1.Dc32 || !L1.Dh32 || !L1.cnbr || !L1.agg_sites ||
         !L1.site_agg)
         return MGDD_ENOMEM;
     int rc = hip_check(c, hipMemcpy(L1.cnbr, cnbr.data(), cnbr.size() * sizeof(int), hipMemcpyHostToDevice), "copy");
@@ -891,7 +899,9 @@ int launch_build_P(Ctx *c, const void *tv64) {
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
     if (rc) return rc;
     if (hflag) return fail(c, MGDD_ERANK, "test vectors are rank deficient on some aggregate");
-    return launch_convert(c, MGDD_F64, MGDD_F32, fsz, L1.P64, L1.P32);
+    rc = launch_convert(c, MGDD_F64, MGDD_F32, fsz, L1.P64, L1.P32);
+    if (!rc) rc = launch_convert(c, MGDD_F64, MGDD_F16, fsz, L1.P64, L1.P16);
+    return rc;
 }
 
 int launch_restrict_ex(Ctx *c, int prec, int nrhs, const void *P, const void *fine, void *out, size_t ostride,
@@ -907,17 +917,22 @@ int launch_restrict_ex(Ctx *c, int prec, int nrhs, const void *P, const void *fi
         restrict_kernel<double><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const double2 *)P,
                                                                (const double2 *)fine, (double2 *)out, ostride, rstride,
                                                                nrhs, ks);
-    else
+    else if (prec == MGDD_F32)
         restrict_kernel<float><<<grid, TPB, lds, c->stream>>>(c->g.V, L1.Va, L1.N, L1.agg_sites, (const float2 *)P,
                                                               (const float2 *)fine, (float2 *)out, ostride, rstride,
                                                               nrhs, ks);
+    else   // half-precision fine field and P, FP32 coarse field
+        restrict_kernel<float, _Float16, _Float16><<<grid, TPB, lds, c->stream>>>(
+            c->g.V, L1.Va, L1.N, L1.agg_sites, (const half_cx *)P, (const half_cx *)fine, (float2 *)out, ostride,
+            rstride, nrhs, ks);
     return hip_check(c, hipGetLastError(), "restrict kernel");
 }
 
 int launch_restrict(Ctx *c, int prec, int nrhs, const void *fine, void *coarse) {
     const Level1 &L1 = c->c;
     size_t n2 = 2 * (size_t)L1.N;
-    return launch_restrict_ex(c, prec, nrhs, prec == MGDD_F64 ? L1.P64 : L1.P32, fine, coarse, n2, n2 * L1.Vc);
+    return launch_restrict_ex(c, prec, nrhs, prec == MGDD_F64 ? L1.P64 : prec == MGDD_F32 ? L1.P32 : L1.P16, fine,
+                              coarse, n2, n2 * L1.Vc);
 }
 
 int launch_prolong(Ctx *c, int prec, int nrhs, const void *coarse, void *fine) {
@@ -927,9 +942,12 @@ int launch_prolong(Ctx *c, int prec, int nrhs, const void *coarse, void *fine) {
     if (prec == MGDD_F64)
         prolong_kernel<double><<<nwg, TPB, 0, c->stream>>>(c->g.V, L1.Vc, L1.N, L1.site_agg, (const double2 *)L1.P64,
                                                            (const double2 *)coarse, (double2 *)fine, nrhs);
-    else
+    else if (prec == MGDD_F32)
         prolong_kernel<float><<<nwg, TPB, 0, c->stream>>>(c->g.V, L1.Vc, L1.N, L1.site_agg, (const float2 *)L1.P32,
                                                           (const float2 *)coarse, (float2 *)fine, nrhs);
+    else   // FP32 coarse field, half-precision P and fine field
+        prolong_kernel<float, _Float16, _Float16><<<nwg, TPB, 0, c->stream>>>(
+            c->g.V, L1.Vc, L1.N, L1.site_agg, (const half_cx *)L1.P16, (const float2 *)coarse, (half_cx *)fine, nrhs);
     return hip_check(c, hipGetLastError(), "prolong kernel");
 }
 

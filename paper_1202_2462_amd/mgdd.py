@@ -110,7 +110,7 @@ class SolveStats(ctypes.Structure):
 
 SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO, SOLVER_CGN = 0, 1, 2, 3
 BLOCK_MR, BLOCK_GMRES = 0, 1
-PLAIN_F64, MIXED = 0, 1
+PLAIN_F64, MIXED, MIXED_F16 = 0, 1, 2
 
 _sig("mgdd_release_workspace", ctypes.c_int, _vp)
 _sig("mgdd_save_setup", ctypes.c_int, _vp, ctypes.c_char_p)
@@ -481,13 +481,17 @@ class Lattice:
         return t.zeros((nrhs, self.Vc, 2, self.N, 2), dtype=dt, device="cuda")
 
     def restrict(self, f, c=None):
-        c = self.coarse_field(self.prec_of(f), f.shape[0]) if c is None else c
-        mgdd_restrict(self.ctx, self.prec_of(f), f.shape[0], f, c)
+        """coarse = P^H f; a half-precision f gives an FP32 coarse field."""
+        p = self.prec_of(f)
+        c = self.coarse_field(F32 if p == F16 else p, f.shape[0]) if c is None else c
+        mgdd_restrict(self.ctx, p, f.shape[0], f, c)
         return c
 
     def prolong(self, c, f=None):
+        """f = P c; f in the precision of c, or of the given f (half precision
+        from an FP32 c)."""
         f = self.field(self.prec_of(c), c.shape[0]) if f is None else f
-        mgdd_prolong(self.ctx, self.prec_of(c), c.shape[0], c, f)
+        mgdd_prolong(self.ctx, self.prec_of(f), c.shape[0], c, f)
         return f
 
     def coarse_apply(self, x, y=None):

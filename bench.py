@@ -299,6 +299,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--kernel-only", choices=["step", "sap", "dirac", "coarse12"], default=None)
     ap.add_argument("--m0", type=float, default=None, help="override the tuned bare mass")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the Schwarz block-shape and lanes-per-site autotuner on the workload's batched "
+                         "12-point-source solve instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the library drives one device per process and "
@@ -309,6 +312,25 @@ def main():
     bench = Bench(args.workload, m0=args.m0)
     mg = bench.mgdd
     lat = bench.lat
+
+    if args.autotune:
+        from paper_1202_2462_amd.autotune import tune_sap_block
+        w = bench.w
+        k = int(bench.name[1:])
+        b = bench.latgen.point_sources(bench.dims, 1000 * k + bench.latgen.TAG_RHS)
+        cands = [(4, 4, 4, 4), (2, 4, 4, 4), (4, 4, 4, 2), (4, 4, 2, 2)]
+        lat.close()
+        t0 = time.time()
+        res = tune_sap_block(bench.dims, bench.U_dev, bench.m0, bench.csw, bench.agg, None, bench.start, b,
+                             nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], restart=w["restart"], tol=w["tol"],
+                             maxit=3000, lanes=(2, 4), candidates=cands,
+                             setup_kwargs=dict(ntv=bench.N, seed=bench.tv_seed), log=log)
+        print(json.dumps({"autotune": "Schwarz block shape x lanes per site", "workload": bench.name,
+                          "dims": bench.dims, "rhs": "12 point sources (one site, every spin and colour), batched",
+                          "setup": "bootstrap, FP32 sweeps, N = %d, nu = iota = %d" % (bench.N, w["nu"]),
+                          "solve": "FGMRES(%d) mixed precision, tol %g" % (w["restart"], w["tol"]),
+                          "seconds_total": time.time() - t0, **res}))
+        return
 
     if args.kernel_only:
         # short run of one kernel family for hardware counters (rocprofv3 --pmc)

@@ -113,6 +113,28 @@ typedef void *(*mgdd_alloc_fn)(size_t bytes, void *user);
 typedef void (*mgdd_free_fn)(void *ptr, void *user);
 int mgdd_set_allocator(mgdd_ctx *ctx, mgdd_alloc_fn alloc, mgdd_free_fn free_fn, void *user);
 
+/* Thread tiles of the kernels, the knobs an autotuner searches beside the
+ * Schwarz block shape (they change the schedule, never the arithmetic of a
+ * site beyond the summation order of the FP32 Schwarz kernels):
+ *   sap_lanes: lanes per site of the FP32 Schwarz colour kernel (Algorithm
+ *     2.1): 0 automatic (2 when the links are special unitary and the
+ *     staged links fit in LDS, else 4 when the staged links fit, else 1),
+ *     1 (one lane per site, spinors in LDS), 2 (two lanes per site, one per
+ *     chirality, rows 0 and 1 of the block's links staged in LDS; needs
+ *     special unitary links) or 4 (four lanes per site, the whole links
+ *     staged). Half-precision storage runs with 2 lanes only; FP64 sweeps
+ *     always use 1.
+ *   dirac_stage: Wilson-clover apply with blocks of 256 sites: 0 automatic
+ *     (the workgroup's block of spinors staged in LDS), 1 staged, -1 not
+ *     staged (every neighbour read from memory).
+ * A variant the context cannot run fails at launch with MGDD_ESHAPE.
+ * Errors: MGDD_EINVAL (values outside these sets). */
+typedef struct {
+    int sap_lanes;
+    int dirac_stage;
+} mgdd_kernel_options;
+int mgdd_set_kernel_options(mgdd_ctx *ctx, const mgdd_kernel_options *options);
+
 /* Frees everything the context owns. Safe on NULL. */
 int mgdd_destroy(mgdd_ctx *ctx);
 

@@ -276,6 +276,16 @@ int mgdd_set_allocator(mgdd_ctx *ctx, mgdd_alloc_fn alloc, mgdd_free_fn free_fn,
     return MGDD_OK;
 }
 
+int mgdd_set_kernel_options(mgdd_ctx *ctx, const mgdd_kernel_options *o) {
+    if (!ctx || !o) return MGDD_EINVAL;
+    const int l = o->sap_lanes, s = o->dirac_stage;
+    if ((l != 0 && l != 1 && l != 2 && l != 4) || s < -1 || s > 1)
+        return fail(&ctx->c, MGDD_EINVAL, "kernel options: sap_lanes in {0, 1, 2, 4}, dirac_stage in {-1, 0, 1}");
+    ctx->c.sap_lanes = l;
+    ctx->c.dirac_stage = s;
+    return MGDD_OK;
+}
+
 int mgdd_destroy(mgdd_ctx *ctx) {
     if (!ctx) return MGDD_OK;
     (void)hipStreamSynchronize(ctx->c.stream);

@@ -126,13 +126,22 @@ static double dirac_launch_bytes(const Ctx *c, int prec, size_t in_bytes, size_t
     return (double)c->g.V * (links + clover + (double)(in_bytes + out_bytes) * nrhs);
 }
 
-// The staged kernels take one workgroup per lattice block: blocks of TPB sites
-static bool dirac_staged(const Ctx *c) { return c->g.Vb == TPB; }
+// The staged kernels take one workgroup per lattice block: blocks of TPB
+// sites. -1: an option the context cannot run.
+static int dirac_staged(Ctx *c) {
+    if (c->dirac_stage == 1 && c->g.Vb != TPB) {
+        fail(c, MGDD_ESHAPE, "the staged Wilson-clover apply needs blocks of 256 sites");
+        return -1;
+    }
+    return c->dirac_stage >= 0 && c->g.Vb == TPB ? 1 : 0;
+}
 
 int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64, int in_prec) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
     const int anti = c->t_antiperiodic ? 1 : 0;
-    const bool stage = dirac_staged(c);
+    const int st = dirac_staged(c);
+    if (st < 0) return MGDD_ESHAPE;
+    const bool stage = st == 1;
     const int slot = kt_begin(c);
 #define WIDEN(R, G, S)                                                                                                \
     dirac_widen_kernel<R, G, S><<<nwg, TPB, 0, c->stream>>>(c->g, (const double2 *)c->U64, (const double2 *)c->A64,  \
@@ -156,7 +165,9 @@ int launch_dirac_widen(Ctx *c, int nrhs, const void *in32, void *out64, int in_p
 int launch_dirac(Ctx *c, int prec, int nrhs, const void *in, void *out) {
     int nwg = ((c->g.V + TPB - 1) / TPB) * nrhs;
     const int anti = c->t_antiperiodic ? 1 : 0;
-    const bool stage = dirac_staged(c);
+    const int st = dirac_staged(c);
+    if (st < 0) return MGDD_ESHAPE;
+    const bool stage = st == 1;
     const int slot = kt_begin(c);
 #define DIRAC(T, S, R, G)                                                                                             \
     dirac_kernel<T, S, R, G><<<nwg, TPB, 0, c->stream>>>(c->g, (const C<T> *)(prec == MGDD_F64 ? c->U64 : c->U32),    \

@@ -142,6 +142,8 @@ struct Ctx {
     std::string err;
     int dev = 0;
     size_t lds_max = 65536;                 // LDS bytes one workgroup may take
+    int sap_lanes = 0;                      // mgdd_kernel_options: 0 automatic, 1, 2, 4
+    int dirac_stage = 0;                    // 0 automatic, 1 staged, -1 not staged
     // geometry tables
     uint32_t *d_blk_coord = nullptr;
     int *d_blk_nbr = nullptr;

@@ -869,13 +869,20 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
     // two lanes per site, the links' first two rows staged (special unitary links)
     const size_t ldsc = 8 * (12 * ((size_t)g.Vb + 4) + 24 * ((size_t)g.Vb + 2)) + 4 * 3 * (2 * g.Vb / 64);
     dim3 grid(nblocks, nrhs);
-    const bool two_lane = c->links_su3 && ldsc <= c->lds_max;
-    if (prec == MGDD_F16 && !two_lane)
+    const bool two_ok = c->links_su3 && ldsc <= c->lds_max, four_ok = lds4 <= c->lds_max;
+    // lanes per site of the FP32 kernels: the context's choice, else automatic
+    int lanes = c->sap_lanes ? c->sap_lanes : two_ok ? 2 : four_ok ? 4 : 1;
+    if (prec == MGDD_F64) lanes = 1;
+    if (prec == MGDD_F16 && lanes != 2)
         return fail(c, MGDD_EINVAL,
-                    "half-precision spinor storage in the Schwarz sweep needs special unitary links (the "
-                    "two-lanes-per-site kernel)");
+                    "half-precision spinor storage in the Schwarz sweep runs on the two-lanes-per-site kernel");
+    if ((lanes == 2 && !two_ok) || (lanes == 4 && !four_ok))
+        return fail(c, MGDD_ESHAPE,
+                    lanes == 2 ? "the two-lanes-per-site Schwarz kernel needs special unitary links and the block's "
+                                 "link rows in LDS"
+                               : "the four-lanes-per-site Schwarz kernel needs the block's links in LDS");
     const int slot = kt_begin(c);
-    if ((prec == MGDD_F32 || prec == MGDD_F16) && two_lane) {
+    if ((prec == MGDD_F32 || prec == MGDD_F16) && lanes == 2) {
         const int anti = c->t_antiperiodic ? 1 : 0;
 #define SAPC(VB, S)                                                                                               \
     sapc_kernel<VB, S><<<grid, 2 * VB, ldsc, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32, b, z, \
@@ -893,7 +900,7 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
     } else if (prec == MGDD_F64) {
         sap_colour_kernel<double><<<grid, g.Vb, lds, c->stream>>>(g, (const double2 *)c->U64, (const double2 *)c->A64,
                                                                   (const double2 *)b, (double2 *)z, col, mr, sre, sim);
-    } else if (lds4 <= c->lds_max) {
+    } else if (lanes == 4) {
 #define SAP4(VB)                                                                                               \
     sap4_kernel<float, VB><<<grid, 4 * VB, lds4, c->stream>>>(g, (const float2 *)c->U32, (const float2 *)c->A32,  \
                                                               (const float2 *)b, (float2 *)z, col, mr, (float)sre, \

@@ -188,8 +188,9 @@ constexpr double REORTH_TOL = 1e-12;
 // as Cholesky QR applied twice: G = X^H X (one pass over the vectors),
 // G = R^H R on the host, X <- X R^{-1} (one pass, in place); the second
 // application removes the loss of orthogonality of the first. When a
-// Cholesky factorisation fails (X nearly rank deficient), the vectors are
-// orthonormalised one by one with two classical Gram-Schmidt passes instead.
+// Cholesky factorisation fails or the first R shows X to be ill-conditioned
+// (min r_ii < 1e-7 max r_ii), the vectors are orthonormalised one by one with
+// two classical Gram-Schmidt passes instead.
 // gbuf, mbuf: device space for nv^2 values each; scal: 2 nv + 1 values.
 static int orthonormalise(Ctx *c, size_t n, void *const *X, int nv, double2 *gbuf, double2 *mbuf, double2 *scal) {
     if (nv <= 64) {
@@ -202,6 +203,21 @@ static int orthonormalise(Ctx *c, size_t n, void *const *X, int nv, double2 *gbu
             la::Mat R;
             ok = la::cholesky_upper(nv, G, R);
             if (!ok) break;
+            if (pass == 0) {
+                // Cholesky QR twice is orthonormal to rounding only while
+                // cond(X) stays below about u^{-1/2} = 1e8; min r_ii / max r_ii
+                // bounds cond(X) from below, so a ratio under 1e-7 takes the
+                // Gram-Schmidt path before X is touched
+                double dmin = R[0].real(), dmax = R[0].real();
+                for (int i = 1; i < nv; i++) {
+                    dmin = std::min(dmin, R[(size_t)i * nv + i].real());
+                    dmax = std::max(dmax, R[(size_t)i * nv + i].real());
+                }
+                if (dmin < 1e-7 * dmax) {
+                    ok = false;
+                    break;
+                }
+            }
             la::Mat Ri = la::upper_inverse(nv, R);
             cd *hb = host_buf(c, (size_t)nv * nv);
             if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer");

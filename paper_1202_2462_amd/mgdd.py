@@ -86,6 +86,10 @@ class SchwarzParams(ctypes.Structure):
                 ("additive", ctypes.c_int), ("shift_re", ctypes.c_double), ("shift_im", ctypes.c_double)]
 
 
+class KernelOptions(ctypes.Structure):
+    _fields_ = [("sap_lanes", ctypes.c_int), ("dirac_stage", ctypes.c_int)]
+
+
 class Level2Params(ctypes.Structure):
     _fields_ = [("agg2", ctypes.c_int * 4), ("ntv2", ctypes.c_int), ("block2", ctypes.c_int * 4),
                 ("nu2", ctypes.c_int), ("mr_iters", ctypes.c_int)]
@@ -112,6 +116,7 @@ SOLVER_FGMRES_MG, SOLVER_GCR, SOLVER_GCR_EO, SOLVER_CGN = 0, 1, 2, 3
 BLOCK_MR, BLOCK_GMRES = 0, 1
 PLAIN_F64, MIXED, MIXED_F16 = 0, 1, 2
 
+_sig("mgdd_set_kernel_options", ctypes.c_int, _vp, _vp)
 _sig("mgdd_release_workspace", ctypes.c_int, _vp)
 _sig("mgdd_save_setup", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("mgdd_load_setup", ctypes.c_int, _vp, ctypes.c_char_p)
@@ -233,6 +238,12 @@ def mgdd_set_allocator(ctx, alloc, free, user=None):
     """alloc, free: ALLOC_FN / FREE_FN instances (kept alive by the caller),
     or None for both."""
     return _check(ctx, _lib.mgdd_set_allocator(ctx, alloc or ALLOC_FN(), free or FREE_FN(), user))
+
+
+def mgdd_set_kernel_options(ctx, sap_lanes=0, dirac_stage=0):
+    """lanes per site of the FP32 Schwarz kernel (0 automatic, 1, 2, 4) and
+    the LDS staging of the Wilson-clover apply (0 automatic, 1, -1)."""
+    return _check(ctx, _lib.mgdd_set_kernel_options(ctx, ctypes.byref(KernelOptions(sap_lanes, dirac_stage))))
 
 
 def mgdd_sap(ctx, prec, nrhs, block, nsweeps, mr_iters, shift, b, z):

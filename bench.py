@@ -57,7 +57,10 @@ def dirac_bytes(prec_name, nrhs=1):
     return lc + sp * nrhs
 
 
-SAP_BYTES_PER_SITE = 864       # one colour step, FP32, per site of the colour: links 288 + clover 288 + z, b, z 288
+# one colour step, FP32, per site of the colour: links 192 (rows 0 and 1 of the
+# four forward links, the third row rebuilt: the fields here are special
+# unitary) + clover 288 + z in, b, z out 288
+SAP_BYTES_PER_SITE = 768
 
 
 def sap_flops_per_site(k):
@@ -67,7 +70,7 @@ def sap_flops_per_site(k):
 
 # HBM traffic of the Schwarz kernel from hardware counters at this workload,
 # and the sources it was taken from (the figure is dropped when they changed)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sap4_kernel_f32_48x48x48x96_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sapc_kernel_f32_48x48x48x96_hbm_traffic.md")
 SAP_SOURCES = ["paper_1202_2462_amd/csrc/sap.hip", "paper_1202_2462_amd/csrc/stencil.h",
                "paper_1202_2462_amd/csrc/mgdd_internal.h", "paper_1202_2462_amd/csrc/geometry.h"]
 
@@ -467,9 +470,10 @@ def main():
             "note": "FP64 applies of the solve (FP32 input widened in the kernel) and of the setup, each launch "
                     "charged its own algorithmic bytes (links and clover term once per launch)"}
     # roofline of the FP32 Schwarz colour kernel over the timed steps (HIP
-    # events around each launch on the library's stream): 864 algorithmic
-    # bytes and sap_flops_per_site(4) = 10 824 flops per site update for one
-    # right-hand side, 12.5 flop/B, below the FP32 ridge of 157.3 TFLOP/s /
+    # events around each launch on the library's stream): 768 algorithmic
+    # bytes (the library's count for the two-lanes kernel: links as two rows)
+    # and sap_flops_per_site(4) = 10 824 flops per site update for one
+    # right-hand side, 14.1 flop/B, below the FP32 ridge of 157.3 TFLOP/s /
     # 8 TB/s = 19.7 flop/B: bound by HBM bandwidth
     if sap_n:
         t_launch = sap_ms * 1e-3 / sap_n

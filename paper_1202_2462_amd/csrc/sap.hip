@@ -914,9 +914,10 @@ int launch_sap_colour(Ctx *c, int prec, int nrhs, int col, int mr, double sre, d
                                                                  (const float2 *)b, (float2 *)z, col, mr, (float)sre,
                                                                  (float)sim);
     }
-    // per site of the colour: links and clover term once per launch; z in,
-    // b in and z out per field (the halo comes from cache)
-    const double lc = prec == MGDD_F64 ? 1152.0 : 576.0, sp = 3.0 * 12 * csize(prec);   // FP16: FP32 links
+    // per site of the colour: links (two rows each on the two-lanes kernel,
+    // which rebuilds the third) and clover term once per launch; z in, b in
+    // and z out per field (the halo comes from cache). FP16: FP32 links.
+    const double lc = prec == MGDD_F64 ? 1152.0 : lanes == 2 ? 480.0 : 576.0, sp = 3.0 * 12 * csize(prec);
     kt_end(c, slot, KF_SAP, prec, (double)nblocks * g.Vb * nrhs, (double)nblocks * g.Vb * (lc + sp * nrhs));
     return hip_check(c, hipGetLastError(), "sap kernel");
 }

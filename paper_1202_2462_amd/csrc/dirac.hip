@@ -57,10 +57,10 @@ __global__ __launch_bounds__(TPB) void dirac_kernel(Geom g, const C<T> *__restri
     } else {
         hop_sum<T, RECON>(U, f, d, nbr, acc, sf, sb);
     }
-    clover_mv<T>(A, d, psi, res);
+    clover_mv<T, true>(A, d, psi, res);
 #pragma unroll
     for (int k = 0; k < 12; k++) res[k] = csub(res[k], cscale(acc[k], (T)0.5));
-    store_spinor<T>(o, d, res);
+    store_spinor<T, true>(o, d, res);
 }
 
 // FP32 or half-precision spinors (S) read as FP64 (the widening is exact)
@@ -110,10 +110,10 @@ __global__ __launch_bounds__(TPB) void dirac_widen_kernel(Geom g, const double2 
         hop_sum<double, RECON>(U, f, d, nbr, acc, sf, sb);
         load_spinor<double>(f, d, psi);
     }
-    clover_mv<double>(A, d, psi, res);
+    clover_mv<double, true>(A, d, psi, res);
 #pragma unroll
     for (int k = 0; k < 12; k++) res[k] = csub(res[k], cscale(acc[k], 0.5));
-    store_spinor<double>(o, d, res);
+    store_spinor<double, true>(o, d, res);
 }
 
 }  // namespace

@@ -21,22 +21,24 @@ __device__ inline rsrc_t make_rsrc(const void *p, size_t bytes) {
 }
 
 template <typename T> struct BIO;
+// NT: the non-temporal cache policy (data read or written once: the caches
+// evict it first, which keeps data that is read again in them)
 template <> struct BIO<float> {
-    __device__ static float2 ld(rsrc_t r, unsigned vo, unsigned so) {
-        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    template <bool NT = false> __device__ static float2 ld(rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, NT ? 2 : 0));
     }
-    __device__ static void st(float2 v, rsrc_t r, unsigned vo, unsigned so) {
+    template <bool NT = false> __device__ static void st(float2 v, rsrc_t r, unsigned vo, unsigned so) {
         using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, vo, so, NT ? 2 : 0);
     }
 };
 template <> struct BIO<double> {
-    __device__ static double2 ld(rsrc_t r, unsigned vo, unsigned so) {
-        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+    template <bool NT = false> __device__ static double2 ld(rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, NT ? 2 : 0));
     }
-    __device__ static void st(double2 v, rsrc_t r, unsigned vo, unsigned so) {
+    template <bool NT = false> __device__ static void st(double2 v, rsrc_t r, unsigned vo, unsigned so) {
         using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, vo, so, NT ? 2 : 0);
     }
 };
 
@@ -48,20 +50,20 @@ template <typename T> struct FieldView {
         r = make_rsrc(base, (size_t)ncomp * V * sizeof(C<T>));
         cs = (unsigned)(V * sizeof(C<T>));
     }
-    __device__ C<T> ld(int comp, int site, unsigned salt = 0) const {
-        return BIO<T>::ld(r, (unsigned)site * (unsigned)sizeof(C<T>), comp * cs + salt);
+    template <bool NT = false> __device__ C<T> ld(int comp, int site, unsigned salt = 0) const {
+        return BIO<T>::template ld<NT>(r, (unsigned)site * (unsigned)sizeof(C<T>), comp * cs + salt);
     }
-    __device__ void st(int comp, int site, C<T> v) const {
-        BIO<T>::st(v, r, (unsigned)site * (unsigned)sizeof(C<T>), comp * cs);
+    template <bool NT = false> __device__ void st(int comp, int site, C<T> v) const {
+        BIO<T>::template st<NT>(v, r, (unsigned)site * (unsigned)sizeof(C<T>), comp * cs);
     }
     // load / store with an extra per-lane byte offset (the descriptor and the
     // scalar offset stay wave-uniform; a lane-dependent scalar offset would
     // make the compiler loop over the distinct values)
-    __device__ C<T> ld_lane(int comp, int site, unsigned lane_off, unsigned salt = 0) const {
-        return BIO<T>::ld(r, (unsigned)site * (unsigned)sizeof(C<T>) + lane_off, comp * cs + salt);
+    template <bool NT = false> __device__ C<T> ld_lane(int comp, int site, unsigned lane_off, unsigned salt = 0) const {
+        return BIO<T>::template ld<NT>(r, (unsigned)site * (unsigned)sizeof(C<T>) + lane_off, comp * cs + salt);
     }
-    __device__ void st_lane(int comp, int site, unsigned lane_off, C<T> v) const {
-        BIO<T>::st(v, r, (unsigned)site * (unsigned)sizeof(C<T>) + lane_off, comp * cs);
+    template <bool NT = false> __device__ void st_lane(int comp, int site, unsigned lane_off, C<T> v) const {
+        BIO<T>::template st<NT>(v, r, (unsigned)site * (unsigned)sizeof(C<T>) + lane_off, comp * cs);
     }
 };
 
@@ -75,29 +77,30 @@ struct HalfFieldView {
         r = make_rsrc(base, (size_t)ncomp * V * 4);
         cs = (unsigned)(V * 4);
     }
-    __device__ float2 ld(int comp, int site, unsigned salt = 0) const {
-        const half_cx h =
-            __builtin_bit_cast(half_cx, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)site * 4u, comp * cs + salt, 0));
+    template <bool NT = false> __device__ float2 ld(int comp, int site, unsigned salt = 0) const {
+        const half_cx h = __builtin_bit_cast(
+            half_cx, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)site * 4u, comp * cs + salt, NT ? 2 : 0));
         return make_float2((float)h.x, (float)h.y);
     }
-    __device__ void st(int comp, int site, float2 v) const {
+    template <bool NT = false> __device__ void st(int comp, int site, float2 v) const {
         half_cx h;
         h.x = (_Float16)v.x;
         h.y = (_Float16)v.y;
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, (unsigned)site * 4u, comp * cs, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, (unsigned)site * 4u, comp * cs,
+                                              NT ? 2 : 0);
     }
     // with an extra per-lane byte offset, as FieldView's
-    __device__ float2 ld_lane(int comp, int site, unsigned lane_off, unsigned salt = 0) const {
-        const half_cx h = __builtin_bit_cast(
-            half_cx, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)site * 4u + lane_off, comp * cs + salt, 0));
+    template <bool NT = false> __device__ float2 ld_lane(int comp, int site, unsigned lane_off, unsigned salt = 0) const {
+        const half_cx h = __builtin_bit_cast(half_cx, __builtin_amdgcn_raw_buffer_load_b32(
+                                                          r, (unsigned)site * 4u + lane_off, comp * cs + salt, NT ? 2 : 0));
         return make_float2((float)h.x, (float)h.y);
     }
-    __device__ void st_lane(int comp, int site, unsigned lane_off, float2 v) const {
+    template <bool NT = false> __device__ void st_lane(int comp, int site, unsigned lane_off, float2 v) const {
         half_cx h;
         h.x = (_Float16)v.x;
         h.y = (_Float16)v.y;
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, h), r, (unsigned)site * 4u + lane_off,
-                                              comp * cs, 0);
+                                              comp * cs, NT ? 2 : 0);
     }
 };
 
@@ -119,9 +122,10 @@ template <typename T, typename FV> __device__ inline void load_spinor(const FV &
     for (int k = 0; k < 12; k++) s[k] = f.ld(k, d);
 }
 
-template <typename T, typename FV> __device__ inline void store_spinor(const FV &f, int d, const C<T> *s) {
+// NT: written once (non-temporal cache policy)
+template <typename T, bool NT = false, typename FV> __device__ inline void store_spinor(const FV &f, int d, const C<T> *s) {
 #pragma unroll
-    for (int k = 0; k < 12; k++) f.st(k, d, s[k]);
+    for (int k = 0; k < 12; k++) f.template st<NT>(k, d, s[k]);
 }
 
 // links: one view per direction ([9][V] complex each)
@@ -253,15 +257,16 @@ template <typename T> __device__ inline void herm6_mv(const C<T> *p /*18 pairs*/
         }
 }
 
-// out = A in for the two chirality blocks of site d
-template <typename T>
+// out = A in for the two chirality blocks of site d. NT: the clover term is
+// read once (non-temporal cache policy)
+template <typename T, bool NT = false>
 __device__ inline void clover_mv(const CloverViews<T> &A, int d, const C<T> *in, C<T> *out, unsigned salt = 0) {
     C<T> p[18];
 #pragma unroll
-    for (int k = 0; k < 18; k++) p[k] = A.a0.ld(k, d, salt);
+    for (int k = 0; k < 18; k++) p[k] = A.a0.template ld<NT>(k, d, salt);
     herm6_mv<T>(p, in, out);
 #pragma unroll
-    for (int k = 0; k < 18; k++) p[k] = A.a1.ld(k, d, salt);
+    for (int k = 0; k < 18; k++) p[k] = A.a1.template ld<NT>(k, d, salt);
     herm6_mv<T>(p, in + 6, out + 6);
 }
 

@@ -13,15 +13,20 @@ One step = one pass of the whole hot path: gauge ingest with the clover term,
 the bootstrap setup (memory-lean form) and the mixed-precision FGMRES solve.
 `value` is solves per second (setup included). The same JSON line carries the
 time-to-1e-10 of plain FP64 multigrid, even-odd FP64 GCR(16) and FP64 CGN on
-the same lattice; the Wilson-clover apply and Schwarz sweep rates at this size
+the same lattice, and the solve with half-precision storage in the
+preconditioner; the Wilson-clover apply and Schwarz sweep rates at this size
 (median of 100 launches after 10, algorithmic GB/s against 8 TB/s); the
-roofline of the Schwarz kernel over the timed steps; and the oracle on the
-host cores as a CPU baseline.
+roofline of the kernel family with the largest share of the timed steps
+(`roofline`: the coarse GMRES step or the Schwarz colour step) and of the
+other one (`roofline_other`); and the oracle on the host cores as a CPU
+baseline.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c1] [--no-cpu] [--no-compare]
-       python bench.py --kernel-only step|sap|dirac   (short runs for hardware counters: one
-           step, Schwarz sweeps alone, Wilson-clover applies alone, each followed by five
-           256 MiB device copies that calibrate the traffic counters)
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1] [--no-cpu] [--no-compare]
+       python bench.py --kernel-only step|sap|dirac|coarse|coarse12   (short runs for hardware
+           counters: one step, Schwarz sweeps alone, Wilson-clover applies alone, coarse
+           GMRES(12) solves alone, the 12-RHS coarse apply; each followed by five 256 MiB
+           device copies and additions that calibrate the traffic counters)
+       python bench.py --workload c2 --autotune   (Schwarz block shape x lanes per site)
 """
 from __future__ import annotations
 
@@ -53,7 +58,11 @@ def load_m0(name):
 # algorithmic HBM bytes per site (links and clover term read once per launch,
 # each field read / written once)
 def dirac_bytes(prec_name, nrhs=1):
-    lc, sp = {"f64": (1152, 384), "f32": (576, 192), "f16": (576, 96)}[prec_name]
+    """algorithmic bytes per site of one Wilson-clover launch on special unitary
+    links (the library reads two rows of each and rebuilds the third): links
+    4 x 6 complex and the clover term's 72 reals once per launch, the spinor
+    in and out per field; the library's own count (mgdd_timing_read)"""
+    lc, sp = {"f64": (384 + 576, 384), "f32": (192 + 288, 192), "f16": (192 + 288, 96)}[prec_name]
     return lc + sp * nrhs
 
 
@@ -73,6 +82,9 @@ def sap_flops_per_site(k):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sapc_kernel_f32_48x48x48x96_hbm_traffic.md")
 SAP_SOURCES = ["paper_1202_2462_amd/csrc/sap.hip", "paper_1202_2462_amd/csrc/stencil.h",
                "paper_1202_2462_amd/csrc/mgdd_internal.h", "paper_1202_2462_amd/csrc/geometry.h"]
+COARSE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "arnoldi_apply_f32_48x48x48x96_hbm_traffic.md")
+COARSE_SOURCES = ["paper_1202_2462_amd/csrc/arnoldi.hip", "paper_1202_2462_amd/csrc/coarse.h",
+                  "paper_1202_2462_amd/csrc/mgdd_internal.h", "paper_1202_2462_amd/csrc/transfer.h"]
 
 
 def sources_digest(files):
@@ -95,9 +107,10 @@ def counter_traffic(path, files):
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip().strip("`* ")] = v.strip().strip("`")
-    if vals.get("kernel_sources_sha256") != sources_digest(files) or "hbm_bytes_per_site_update" not in vals:
+    if vals.get("kernel_sources_sha256") != sources_digest(files) or not (
+            "hbm_bytes_per_site_update" in vals or "hbm_bytes_per_unit" in vals):
         return None
-    return float(vals["hbm_bytes_per_site_update"])
+    return float(vals.get("hbm_bytes_per_site_update", vals.get("hbm_bytes_per_unit")))
 
 
 class Bench:
@@ -300,7 +313,7 @@ def main():
     ap.add_argument("--workload", choices=["c3", "c2", "c1"], default="c3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--kernel-only", choices=["step", "sap", "dirac", "coarse12"], default=None)
+    ap.add_argument("--kernel-only", choices=["step", "sap", "dirac", "coarse", "coarse12"], default=None)
     ap.add_argument("--m0", type=float, default=None, help="override the tuned bare mass")
     ap.add_argument("--autotune", action="store_true",
                     help="run the Schwarz block-shape and lanes-per-site autotuner on the workload's batched "
@@ -340,6 +353,16 @@ def main():
         lat.set_gauge(bench.U_dev, bench.m0, bench.csw)
         if args.kernel_only == "step":
             bench.step()
+        elif args.kernel_only == "coarse":
+            # five coarse GMRES(12) solves of one FP32 right-hand side (the
+            # coarse step kernel of the solve, on the compact FP32 D_c), D_c
+            # from the workload's number of random test vectors
+            lat.setup(bench.agg, None, bench.start, nu=0, iota=0, mr_iters=4, n_part2=0, prec=mg.F32,
+                      ntv=bench.N, seed=bench.tv_seed)
+            cb = lat.coarse_field(mg.F32, 1)
+            cb.normal_()
+            for _ in range(5):
+                lat.coarse_solve(cb, 12)
         elif args.kernel_only == "coarse12":
             # D_c from the workload's number of random test vectors (no
             # smoothing), applied to 12 FP32 right-hand sides: the matrix-core path
@@ -381,7 +404,7 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup}: {time.perf_counter() - t0:.2f} s")
     ctx = lat.ctx
-    for kern, prec in ((mg.KERNEL_SAP, mg.F32), (mg.KERNEL_DIRAC, mg.F64)):
+    for kern, prec in ((mg.KERNEL_SAP, mg.F32), (mg.KERNEL_DIRAC, mg.F64), (mg.KERNEL_COARSE, mg.F32)):
         mg.mgdd_timing_read(ctx, kern, prec, reset=True)
     mg.mgdd_timing_enable(ctx, True)    # HIP events around each launch, on the library's stream
     torch.cuda.synchronize()
@@ -395,6 +418,7 @@ def main():
     elapsed = time.perf_counter() - t0
     mg.mgdd_timing_enable(ctx, False)
     sap_ms, sap_units, sap_n, sap_bytes = mg.mgdd_timing_read(ctx, mg.KERNEL_SAP, mg.F32, reset=True)
+    c_ms, c_units, c_n, c_bytes = mg.mgdd_timing_read(ctx, mg.KERNEL_COARSE, mg.F32, reset=True)
     d_ms, d_units, d_n, d_bytes = mg.mgdd_timing_read(ctx, mg.KERNEL_DIRAC, mg.F64, reset=True)
     ms = elapsed / args.steps * 1e3
     split = {}
@@ -469,27 +493,53 @@ def main():
             "algorithmic_gbs": d_bytes / (d_ms * 1e-3) / 1e9,
             "note": "FP64 applies of the solve (FP32 input widened in the kernel) and of the setup, each launch "
                     "charged its own algorithmic bytes (links and clover term once per launch)"}
-    # roofline of the FP32 Schwarz colour kernel over the timed steps (HIP
-    # events around each launch on the library's stream): 768 algorithmic
-    # bytes (the library's count for the two-lanes kernel: links as two rows)
-    # and sap_flops_per_site(4) = 10 824 flops per site update for one
-    # right-hand side, 14.1 flop/B, below the FP32 ridge of 157.3 TFLOP/s /
-    # 8 TB/s = 19.7 flop/B: bound by HBM bandwidth
+    # rooflines over the timed steps (HIP events around each launch on the
+    # library's stream). The Schwarz colour kernel: 768 algorithmic bytes (the
+    # library's count for the two-lanes kernel: links as two rows) and
+    # sap_flops_per_site(4) = 10 824 flops per site update for one right-hand
+    # side, 14.1 flop/B, below the FP32 ridge of 157.3 TFLOP/s / 8 TB/s =
+    # 19.7 flop/B. The coarse GMRES step (y = D_c v_j on the compact FP32
+    # blocks with the Arnoldi dot products): per coarse site 5 (2N)^2 complex
+    # FP32 block entries (read once per launch) and (3 + j) 2N vector entries,
+    # 8 (2N)^2 * 9 / (5 (2N)^2 8) = 1.8 flop/B. Both bound by HBM bandwidth.
+    lines = {}
     if sap_n:
         t_launch = sap_ms * 1e-3 / sap_n
         units_launch = sap_units / sap_n
         bytes_launch = sap_bytes / sap_n
         achieved = bytes_launch / t_launch / 1e9
         tps = counter_traffic(TRAFFIC_FILE, SAP_SOURCES) if big else None
-        result["roofline"] = {
+        lines["sap"] = (sap_ms, {
             "bound": "hbm", "kernel": "sapc_kernel<256> (FP32 Schwarz colour step, 4 MR steps)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": None if tps is None else tps * units_launch,
-            "launches": sap_n, "us_per_launch": t_launch * 1e6, "site_updates_per_launch": units_launch,
+            "launches": sap_n, "us_per_launch": t_launch * 1e6, "total_ms_in_timed_steps": sap_ms,
+            "site_updates_per_launch": units_launch,
             "algorithmic_bytes_per_launch": bytes_launch,
             "algorithmic_flops_per_launch": sap_flops_per_site(bench.w["mr"]) * units_launch,
             "tflops": sap_flops_per_site(bench.w["mr"]) * units_launch / t_launch / 1e12,
-            "fp32_peak_tflops": FP32_PEAK_TFLOPS}
+            "fp32_peak_tflops": FP32_PEAK_TFLOPS})
+    if c_n:
+        t_launch = c_ms * 1e-3 / c_n
+        units_launch = c_units / c_n
+        bytes_launch = c_bytes / c_n
+        achieved = bytes_launch / t_launch / 1e9
+        tpc = counter_traffic(COARSE_TRAFFIC_FILE, COARSE_SOURCES) if big else None
+        n2 = 2 * bench.N
+        lines["coarse"] = (c_ms, {
+            "bound": "hbm", "kernel": "arnoldi_apply_kernel<float, true> (coarse GMRES step on the compact FP32 "
+                                      "D_c: self block and forward hops stored, backward hops from "
+                                      "gamma5^c-hermiticity)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if tpc is None else tpc * units_launch,
+            "launches": c_n, "us_per_launch": t_launch * 1e6, "total_ms_in_timed_steps": c_ms,
+            "coarse_sites_per_launch": units_launch, "algorithmic_bytes_per_launch": bytes_launch,
+            "tflops": 8.0 * 9 * n2 * n2 * units_launch / t_launch / 1e12})
+    if lines:
+        order = sorted(lines, key=lambda k: -lines[k][0])
+        result["roofline"] = lines[order[0]][1]
+        if len(order) > 1:
+            result["roofline_other"] = lines[order[1]][1]
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

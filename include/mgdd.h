@@ -522,14 +522,17 @@ int mgdd_release_workspace(mgdd_ctx *ctx);
 /* ------------------------------------------------------------------ kernel timing
  * Instrumentation, not part of the method. While timing is enabled the
  * library brackets every launch of the Wilson-clover kernel
- * (MGDD_KERNEL_DIRAC, used by mgdd_dirac_apply and inside the solvers) and
- * of the Schwarz colour kernel (MGDD_KERNEL_SAP, one launch per colour step
- * of Alg. 2.1) with a pair of HIP events on the context's stream, and adds up
- * the durations per kernel family and precision. Enabling creates a fixed
+ * (MGDD_KERNEL_DIRAC, used by mgdd_dirac_apply and inside the solvers), of
+ * the Schwarz colour kernel (MGDD_KERNEL_SAP, one launch per colour step of
+ * Alg. 2.1) and of the coarse operator step of the coarse GMRES
+ * (MGDD_KERNEL_COARSE: y = D_c v_j with the dot products of the Arnoldi
+ * step, one launch per GMRES step of Section 4) with a pair of HIP events on
+ * the context's stream, and adds up the durations per kernel family and
+ * precision. Enabling creates a fixed
  * pool of events (owned by the context, released by mgdd_destroy);
  * disabling keeps the totals. The pool is drained with a stream
  * synchronisation when it is full or when the totals are read. */
-enum { MGDD_KERNEL_DIRAC = 0, MGDD_KERNEL_SAP = 1 };
+enum { MGDD_KERNEL_DIRAC = 0, MGDD_KERNEL_SAP = 1, MGDD_KERNEL_COARSE = 2 };
 
 /* on: nonzero to enable, 0 to disable. Errors: MGDD_EHIP (event creation). */
 int mgdd_timing_enable(mgdd_ctx *ctx, int on);
@@ -538,15 +541,20 @@ int mgdd_timing_enable(mgdd_ctx *ctx, int on);
  * MGDD_F32 or MGDD_F16), after a synchronisation of the context's stream.
  * Outputs (each may be NULL): total_ms = sum of launch durations in
  * milliseconds; site_updates = sum over launches of sites times right-hand
- * sides processed (the sites of one colour for a Schwarz launch); launches =
- * number of launches; alg_bytes = sum over launches of the algorithmic HBM
- * bytes of each launch (links and clover term read once per launch, the
- * spinors of every right-hand side read and written once: per site
- * 1152 + 384 n bytes for an FP64 apply of n fields, 1152 + 288 n for the FP64
- * apply of FP32 fields, 576 + 192 n (FP32) or 576 + 96 n (half) otherwise;
- * per site of a Schwarz colour step 576 + 288 n (FP32) or 1152 + 576 n
- * (FP64)). reset: nonzero to zero these totals afterwards. Errors:
- * MGDD_EINVAL (bad kernel or precision). */
+ * sides processed (the sites of one colour for a Schwarz launch, coarse sites
+ * for a coarse step); launches = number of launches; alg_bytes = sum over
+ * launches of the algorithmic HBM bytes of each launch: links and clover term
+ * read once per launch (links as two rows, 4 x 6 complex, when every link is
+ * special unitary, else 4 x 9; the clover term 72 reals), the spinors of every
+ * right-hand side read and written once. Per site: an FP64 apply of n fields
+ * 960 + 384 n (1152 + 384 n with full links), of n FP32 fields 960 + 288 n,
+ * of n half fields 960 + 240 n; FP32 480 + 192 n (576 + 192 n), half
+ * 480 + 96 n; per site of a Schwarz colour step 480 + 288 n (FP32, two lanes
+ * per site), 576 + 288 n (FP32, 1 or 4 lanes), 480 + 144 n (half), 1152 + 576 n
+ * (FP64); per coarse site of a coarse step with N test vectors and j earlier
+ * basis vectors 5 (2N)^2 blocks (the compact FP32 D_c, else 9) plus
+ * (3 + j) 2N values per right-hand side. reset: nonzero to zero these totals
+ * afterwards. Errors: MGDD_EINVAL (bad kernel or precision). */
 int mgdd_timing_read(mgdd_ctx *ctx, int kernel, int prec, int reset, double *total_ms, double *site_updates,
                      long long *launches, double *alg_bytes);
 

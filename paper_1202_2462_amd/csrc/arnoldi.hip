@@ -372,9 +372,17 @@ int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, con
 #define APPLY(T, HC, D, LDS)                                                                                       \
     arnoldi_apply_kernel<T, HC><<<gapp, APB, LDS, c->stream>>>(Vc, N, op.nbr, (const C<T> *)(D), (const C<T> *)w, \
                                                                np, nnp, vl, j, (C<T> *)V[j], (C<T> *)y, part1, nrj)
+        // algorithmic bytes: the blocks once per launch (5 per coarse site when
+        // compact, else 9), per right-hand side w read, y and v_j written and
+        // the j earlier basis vectors read for the dot products
+        const bool compact = p == MGDD_F32 && op.H32;
+        const double cs = p == MGDD_F64 ? 16.0 : 8.0, n2d = 2.0 * N;
+        const double abytes = (double)Vc * ((compact ? 5.0 : 9.0) * n2d * n2d * cs + nb * (3.0 + j) * n2d * cs);
+        const int slot = kt_begin(c);
         if (p == MGDD_F64) APPLY(double, false, op.D64, 0);
-        else if (op.H32) APPLY(float, true, op.H32, 0);
+        else if (compact) APPLY(float, true, op.H32, 0);
         else APPLY(float, false, op.D32, 0);
+        kt_end(c, slot, KF_COARSE, p, (double)Vc * nb, abytes);
 #undef APPLY
         const double2 *pin = part1;
         int npin = Vc;

@@ -113,7 +113,7 @@ struct Level2 {
 // Optional timing of kernel families with HIP events on the context's stream:
 // each launch is bracketed by an event pair from a fixed pool; durations are
 // added up when the pool is full or when the caller reads them.
-enum KernelFamily { KF_DIRAC = 0, KF_SAP = 1, KF_COUNT = 2 };
+enum KernelFamily { KF_DIRAC = 0, KF_SAP = 1, KF_COARSE = 2, KF_COUNT = 3 };
 struct KTimer {
     bool on = false;
     std::vector<hipEvent_t> ev;      // 2 per slot

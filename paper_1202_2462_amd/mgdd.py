@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ESHAPE, ERANK, ENOTREADY, ENOCONV, EBREAKDOWN, ENAN, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 F64, F32, F16 = 0, 1, 2
-KERNEL_DIRAC, KERNEL_SAP = 0, 1
+KERNEL_DIRAC, KERNEL_SAP, KERNEL_COARSE = 0, 1, 2
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ERANK", -4: "ENOTREADY", -5: "ENOCONV", -6: "EBREAKDOWN",
           -7: "ENAN", -8: "EHIP", -9: "ENOMEM"}
 

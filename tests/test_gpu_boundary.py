@@ -139,3 +139,38 @@ def test_links_outside_su3_use_full_rows():
     want_s = op.sap(block, x[0], np.zeros_like(x[0]), 1, 4)
     assert rel(lat.unpack(z)[0], want_s) < TOL32
     lat.close()
+
+
+def test_timing_families_count_their_bytes():
+    """mgdd_timing_read for the Schwarz colour kernel (FP32 and half storage,
+    two lanes per site: links as two rows) and for the coarse GMRES step on
+    the compact FP32 D_c: launches, site updates and algorithmic bytes as the
+    header states them."""
+    from paper_1202_2462_amd.mgdd import (F16, F32, F64, KERNEL_COARSE, KERNEL_SAP, mgdd_timing_enable,
+                                           mgdd_timing_read)
+    dims, block, agg, N = (8, 8, 8, 8), (4, 4, 4, 4), (4, 4, 4, 4), 8
+    say("timing families")
+    op = problem(dims, seed=31, m0=0.1)
+    lat = lattice(op, block)
+    lat.build_P(agg, lat.pack(latgen.gaussian_fields(dims, N, 32), F64))
+    V, Vc, n2, m = lat.V, lat.Vc, 2 * N, 12
+    for k in (KERNEL_SAP, KERNEL_COARSE):
+        for p in (F32, F16):
+            mgdd_timing_read(lat.ctx, k, p, reset=True)
+    mgdd_timing_enable(lat.ctx, True)
+    b = latgen.gaussian_fields(dims, 2, 33)
+    lat.sap(lat.pack(b, F32), lat.field(F32, 2), 1, 4)
+    lat.sap(lat.pack(b[:1], F16), lat.field(F16, 1), 1, 4)
+    cb = lat.torch.randn((1, Vc, 2, N, 2), dtype=lat.torch.float32, device="cuda")
+    lat.coarse_solve(cb, m)
+    res = {(k, p): mgdd_timing_read(lat.ctx, k, p) for k in (KERNEL_SAP, KERNEL_COARSE) for p in (F32, F16)}
+    mgdd_timing_enable(lat.ctx, False)
+    ms, units, n, nbytes = res[(KERNEL_SAP, F32)]
+    assert n == 2 and units == 2 * V and nbytes == V * (480 + 288 * 2) and ms > 0
+    ms, units, n, nbytes = res[(KERNEL_SAP, F16)]
+    assert n == 2 and units == V and nbytes == V * (480 + 144)
+    ms, units, n, nbytes = res[(KERNEL_COARSE, F32)]
+    want = sum(Vc * (5 * n2 * n2 * 8 + (3 + j) * n2 * 8) for j in range(m))
+    assert n == m and units == m * Vc and nbytes == want, (n, units, nbytes, want)
+    assert res[(KERNEL_COARSE, F16)][2] == 0
+    lat.close()

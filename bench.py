@@ -171,6 +171,41 @@ class Bench:
                          relres=stats[0].relres, converged=bool(stats[0].converged))
         return z, stats[0]
 
+    def learned_step(self, boot):
+        """The learned setup on this workload: the shipped network (trained on
+        16^3 x 32 fields; local and gauge covariant, so it applies at any
+        size) maps the random vectors the bootstrap step draws (the library's
+        seeded stream), then one Schwarz round and the
+        second setup part, then the same solve as the step. The plain
+        bootstrap is the fallback, judged by outer iterations: when the learned
+        setup's solve needs more than 10 % more of them than the bootstrap's
+        (`boot`, the step's split), the cost of the learned attempt is added to
+        a bootstrap step. The library itself falls back when the network's
+        vectors cannot form P (mgdd_setup_fallback)."""
+        mg, torch, w = self.mgdd, self.torch, self.w
+        d = np.load(os.path.join(ROOT, "paper_1202_2462_amd", "learned_weights_16x16x16x32.npz"))
+        widths = [int(t) for t in d["widths"]]
+        W = self.lat.weights_to_dev([d[f"W{l}"] for l in range(len(widths) - 1)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.lat.set_gauge(self.U_dev, self.m0, self.csw)
+        # the random vectors the bootstrap step draws (same stream and seed)
+        self.lat.setup_learned(widths, W, self.agg, None, self.start, nu=1, iota=w["iota"], mr_iters=w["mr"],
+                               n_part2=1, prec=mg.F32, ntv=self.N, seed=self.tv_seed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        z, stats = self.lat.solve(self.b, precision=mg.MIXED, restart=w["restart"], tol=w["tol"], maxit=3000,
+                                  coarse_iters=12, nu=1, mr_iters=w["mr"])
+        t2 = time.perf_counter()
+        del z
+        out = dict(network_widths=widths, setup_s=t1 - t0, solve_s=t2 - t1, iters=stats[0].iters,
+                   relres=stats[0].relres, converged=bool(stats[0].converged),
+                   library_fallback=self.lat.setup_fell_back(), bootstrap_iters=boot["iters"])
+        worse = (not stats[0].converged) or stats[0].iters > 1.1 * boot["iters"]
+        out["fallback"] = bool(worse)
+        out["seconds_with_fallback"] = (t2 - t0) + (boot["setup_s"] + boot["solve_s"] if worse else 0.0)
+        return out
+
     def comparator(self, solver):
         mg = self.mgdd
         t0 = time.perf_counter()
@@ -455,6 +490,14 @@ def main():
             s16 = {"error": str(e)}
         result["time_to_solution"]["mg_mixed_f16"] = s16
         lat.release_workspace()
+        log("learned setup (shipped network), the bootstrap as fallback")
+        try:
+            bench.learned_step(split)     # warm: the network's and the solve's workspaces
+            result["time_to_solution"]["mg_learned"] = bench.learned_step(split)
+        except mg.MgddError as e:
+            result["time_to_solution"]["mg_learned"] = {"error": str(e)}
+        lat.release_workspace()
+        torch.cuda.empty_cache()
         log("plain FP64 multilevel")
         s64 = {}
         try:

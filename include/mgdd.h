@@ -506,12 +506,22 @@ int mgdd_net_adam(mgdd_ctx *ctx, const mgdd_net_shape *shape, void *weights, con
                   int step, double lr);
 
 /* Setup with the network: the random vectors (params->ntv FP64 fine
- * fields) are mapped by the network, then the bootstrap setup continues
+ * fields, or NULL: drawn by the library from stream params->seed as for
+ * mgdd_setup_bootstrap) are mapped by the network, a few at a time in the
+ * context's test-vector storage, then the bootstrap setup continues
  * from the outputs as from its random vectors (params->nu part-1 rounds,
  * params->n_part2 second parts; with both 0 only P and D_c are built).
- * arnoldi_start may be NULL when n_part2 = 0. Synchronous. */
+ * The plain bootstrap setup is the fallback: when the network's vectors
+ * cannot serve (P rank deficient on an aggregate, or NaN / Inf on the way),
+ * the bootstrap runs from the caller's random vectors with the same
+ * parameters and the call returns its status (mgdd_setup_fallback then
+ * returns 1). arnoldi_start may be NULL when n_part2 = 0. Synchronous. */
 int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights,
                        const mgdd_setup_params *params, const void *random_vectors, const void *arnoldi_start);
+
+/* 1 if the last mgdd_setup_learned on this context fell back to the plain
+ * bootstrap setup, else 0 (also for a NULL context). */
+int mgdd_setup_fallback(const mgdd_ctx *ctx);
 
 /* Frees the context's solver / setup workspace and staging buffer (they grow
  * on demand and are otherwise kept until mgdd_destroy), for programs that

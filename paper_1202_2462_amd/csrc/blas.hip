@@ -290,6 +290,55 @@ __global__ __launch_bounds__(TPB) void update_dot2_kernel(size_t n, PtrListW xs,
     }
 }
 
+// multidot_kernel in FP64 for nvec <= 2 MAXV with four lanes per element,
+// grouped as in update_dot2_kernel: the lane of group g takes the vectors
+// g NG ... g NG + NG - 1 (a slot past nvec reads group 0's vector at the same
+// element, the address group 0's lane reads, and its sum is dropped). Fewer
+// accumulators per lane than one lane per element with all 32: more waves in
+// flight. Layout of part as multidot_kernel's.
+__global__ __launch_bounds__(TPB) void multidot4_kernel(size_t n, PtrListW xs, int nvec,
+                                                        const double2 *__restrict__ w, double2 *__restrict__ part) {
+    constexpr int G = 4, NG = 2 * MAXV / G, LG = 64 / G;
+    __shared__ double red[TPB / 64][4 * MAXV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, grp = lane / LG, gl = lane % LG;
+    const double2 *xp[NG];
+#pragma unroll
+    for (int i = 0; i < NG; i++) xp[i] = (const double2 *)(grp * NG + i < nvec ? xs.p[grp * NG + i] : xs.p[i]);
+    double2 acc[NG];
+#pragma unroll
+    for (int i = 0; i < NG; i++) acc[i] = make_double2(0, 0);
+    const size_t per = TPB / G, stride = (size_t)gridDim.x * per, so = (size_t)blockIdx.y * n;
+    for (size_t e = (size_t)blockIdx.x * per + wv * LG + gl; e < n; e += stride) {
+        const double2 wd = w[so + e];
+        double2 xv[NG];
+#pragma unroll
+        for (int i = 0; i < NG; i++) xv[i] = xp[i][so + e];
+#pragma unroll
+        for (int i = 0; i < NG; i++) cfmac(acc[i], xv[i], wd);
+    }
+#pragma unroll
+    for (int i = 0; i < NG; i++) {
+        double a = acc[i].x, b = acc[i].y;
+#pragma unroll
+        for (int m = LG / 2; m >= 1; m >>= 1) {
+            a += __shfl_xor(a, m, 64);
+            b += __shfl_xor(b, m, 64);
+        }
+        const int q = grp * NG + i;
+        if (gl == 0 && q < nvec) {
+            red[wv][2 * q] = a;
+            red[wv][2 * q + 1] = b;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nvec) {
+        const int q = threadIdx.x;
+        double a = 0, b = 0;
+        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * q]; b += red[k][2 * q + 1]; }
+        part[((size_t)q * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
+    }
+}
+
 // y = s * x with s = alpha * coef[0] (coef on the device), or
 // s = alpha / sqrt(re nrm2[0]) (0 when that is 0) when inv_norm, or s = alpha
 // when coef == nullptr; x and y may alias
@@ -692,14 +741,15 @@ static int update_dot_launch(Ctx *c, int p, size_t n, const void *const *xs, int
 
 int blas_multidot_wide(Ctx *c, size_t n, const void *const *xs, int nvec, const void *w, double2 *out, int nseg) {
     if (nvec < 1 || nvec > WIDE) return fail(c, MGDD_EINVAL, "multidot: bad vector count");
-    int nwg = red_grid(n);
+    // one element per group of four lanes, up to 2048 workgroups
+    size_t g = (n + TPB / 4 - 1) / (TPB / 4);
+    const int nwg = (int)(g > 2048 ? 2048 : g < 1 ? 1 : g);
     double2 *part = (double2 *)ensure_red(c, (size_t)2 * (WIDE + 1) * nseg * nwg + 16);
     if (!part) return MGDD_ENOMEM;
     PtrListW pl{};
     for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
     dim3 grid(nwg, nseg);
-    multidot_kernel<double, double, WIDE, PtrListW><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, (const double2 *)w,
-                                                                                 part);
+    multidot4_kernel<<<grid, TPB, 0, c->stream>>>(n, pl, nvec, (const double2 *)w, part);
     finish_kernel<<<nvec * nseg, 64, 0, c->stream>>>(nwg, part, out);
     return hip_check(c, hipGetLastError(), "multidot");
 }

@@ -882,7 +882,7 @@ int mgdd_net_adam(mgdd_ctx *ctx, const mgdd_net_shape *shape, void *weights, con
 
 int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *weights,
                        const mgdd_setup_params *params, const void *random_vectors, const void *arnoldi_start) {
-    if (!ctx || !shape || !weights || !params || !random_vectors) return MGDD_EINVAL;
+    if (!ctx || !shape || !weights || !params) return MGDD_EINVAL;
     if (!ctx->c.gauge_ready) return fail(&ctx->c, MGDD_ENOTREADY, "no gauge field");
     const mgdd_setup_params *sp = params;
     if (!valid_prec(sp->prec) || sp->nu < 0 || sp->iota < 0 || sp->mr_iters < 0 || sp->n_part2 < 0 || sp->arnoldi_m < 0 ||
@@ -901,6 +901,8 @@ int mgdd_setup_learned(mgdd_ctx *ctx, const mgdd_net_shape *shape, const void *w
     return rc;
     GUARD_END
 }
+
+int mgdd_setup_fallback(const mgdd_ctx *ctx) { return ctx && ctx->c.learned_fallback ? 1 : 0; }
 
 int mgdd_solve(mgdd_ctx *ctx, const mgdd_solve_params *params, int nrhs, const void *b, void *z,
                mgdd_solve_stats *stats) {

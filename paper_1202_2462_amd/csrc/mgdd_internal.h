@@ -143,6 +143,7 @@ struct Ctx {
     int dev = 0;
     size_t lds_max = 65536;                 // LDS bytes one workgroup may take
     int sap_lanes = 0;                      // mgdd_kernel_options: 0 automatic, 1, 2, 4
+    bool learned_fallback = false;          // the last learned setup fell back to the bootstrap
     int dirac_stage = 0;                    // 0 automatic, 1 staged, -1 not staged
     // geometry tables
     uint32_t *d_blk_coord = nullptr;

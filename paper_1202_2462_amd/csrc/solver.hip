@@ -1004,10 +1004,13 @@ int bootstrap(Ctx *c, const mgdd_setup_params *sp, const void *rv64, const void 
     double2 *gdev = (double2 *)A.take((size_t)4 * N * N * 16 + 256), *ydev = (double2 *)A.take((size_t)4 * N * N * 16 + 256);
     if (!ydev) return fail(c, MGDD_ENOMEM, "setup workspace");
     for (int i = 0; i < N; i++) Vt[i] = (char *)vt + (size_t)i * n * 16;
-    if (rv64)
+    if (rv64 == vt) {
+        // the caller (the learned setup) has put the starting vectors in place
+    } else if (rv64) {
         rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
-    else
+    } else {
         rc = launch_gaussian_fields(c, N, sp->seed, vt);
+    }
     if (!rc) rc = hip_check(c, hipMemsetAsync(zero, 0, (size_t)R * n * csize(p), c->stream), "memset");
     // part 1: nu rounds of (one SAP sweep with b = 0 on all vectors, global MGS)
     for (int it = 0; it < sp->nu && !rc; it++) {
@@ -1202,24 +1205,41 @@ int level2_bootstrap(Ctx *c, const mgdd_level2_params *lp, const void *random2) 
 // The network maps the caller's random vectors to test vectors; the bootstrap
 // setup then continues from them (sp->nu part-1 rounds, sp->n_part2 second
 // parts), so that with nu = n_part2 = 0 only P and D_c are built from the
-// network's vectors.
+// network's vectors. When the network's vectors cannot serve (P rank
+// deficient on an aggregate, or NaN / Inf on the way), the plain bootstrap
+// setup runs from the caller's random vectors with the same parameters, and
+// c->learned_fallback records it.
 int setup_learned(Ctx *c, const NetShape &sh, const double2 *W64, const mgdd_setup_params *sp, const void *rv64,
                   const void *start64) {
     const int N = sp->ntv;
     const size_t n = (size_t)12 * c->g.V;
-    void *tv = dalloc(c, (size_t)N * n * 16);
-    if (!tv) return MGDD_ENOMEM;
+    // the random vectors (the caller's, or drawn from the seeded stream) go
+    // to the context's test vectors, and the network maps them there in place,
+    // a few at a time (its workspace is that of the chunk, not of all N)
+    int rc = transfer_setup(c, sp->agg, N);
+    if (rc) return rc;
+    void *vt = c->c.tv64;
+    if (rv64)
+        rc = hip_check(c, hipMemcpyAsync(vt, rv64, (size_t)N * n * 16, hipMemcpyDeviceToDevice, c->stream), "copy");
+    else
+        rc = launch_gaussian_fields(c, N, sp->seed, vt);
+    const int R = std::min(N, 4);
     Arena A;
-    int rc = arena_open(c, net_forward_bytes(c, sh, N) + 2 * ((size_t)N * n * 8 + 256) + 4096, A);
-    void *in32 = rc ? nullptr : A.take((size_t)N * n * 8), *out32 = rc ? nullptr : A.take((size_t)N * n * 8);
+    if (!rc) rc = arena_open(c, net_forward_bytes(c, sh, R) + 2 * ((size_t)R * n * 8 + 256) + 4096, A);
+    void *in32 = rc ? nullptr : A.take((size_t)R * n * 8), *out32 = rc ? nullptr : A.take((size_t)R * n * 8);
     if (!rc && !out32) rc = fail(c, MGDD_ENOMEM, "learned setup workspace");
-    if (!rc) rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)N * n, rv64, in32);
-    if (!rc) rc = net_forward(c, sh, W64, N, in32, out32, A);
-    if (!rc) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)N * n, out32, tv);
+    for (int i0 = 0; i0 < N && !rc; i0 += R) {
+        const int r = std::min(R, N - i0);
+        void *vi = (char *)vt + (size_t)i0 * n * 16;
+        rc = launch_convert(c, MGDD_F64, MGDD_F32, (size_t)r * n, vi, in32);
+        if (!rc) rc = net_forward(c, sh, W64, r, in32, out32, A);
+        if (!rc) rc = launch_convert(c, MGDD_F32, MGDD_F64, (size_t)r * n, out32, vi);
+    }
     if (!rc) rc = hip_check(c, hipStreamSynchronize(c->stream), "sync");
-    if (!rc) rc = bootstrap(c, sp, tv, start64);
+    if (!rc) rc = bootstrap(c, sp, vt, start64);
     (void)hipStreamSynchronize(c->stream);
-    dfree(c, tv);
+    c->learned_fallback = rc == MGDD_ERANK || rc == MGDD_ENAN;
+    if (c->learned_fallback) rc = bootstrap(c, sp, rv64, start64);
     return rc;
 }
 

@@ -117,6 +117,7 @@ BLOCK_MR, BLOCK_GMRES = 0, 1
 PLAIN_F64, MIXED, MIXED_F16 = 0, 1, 2
 
 _sig("mgdd_set_kernel_options", ctypes.c_int, _vp, _vp)
+_sig("mgdd_setup_fallback", ctypes.c_int, _vp)
 _sig("mgdd_release_workspace", ctypes.c_int, _vp)
 _sig("mgdd_save_setup", ctypes.c_int, _vp, ctypes.c_char_p)
 _sig("mgdd_load_setup", ctypes.c_int, _vp, ctypes.c_char_p)
@@ -582,14 +583,20 @@ class Lattice:
         mgdd_net_adam(self.ctx, widths, weights, grad, m, v, step, lr)
 
     def setup_learned(self, widths, weights, agg, random_vectors, arnoldi_start=None, nu=0, iota=3, mr_iters=4,
-                      n_part2=0, prec=F32):
-        N = random_vectors.shape[0]
-        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, 0, n_part2, prec)
+                      n_part2=0, prec=F32, ntv=None, seed=0):
+        """random_vectors: N FP64 fields, or None to have the library draw ntv
+        of them from stream `seed`"""
+        N = random_vectors.shape[0] if random_vectors is not None else int(ntv)
+        sp = SetupParams((ctypes.c_int * 4)(*agg), N, nu, iota, mr_iters, 0, n_part2, prec, 0, seed)
         mgdd_setup_learned(self.ctx, widths, weights, sp, random_vectors, arnoldi_start)
         self.agg = tuple(agg)
         self.N = N
         self.cdims = tuple(d // a for d, a in zip(self.dims, self.agg))
         self.Vc = int(np.prod(self.cdims))
+
+    def setup_fell_back(self):
+        """True when the last setup_learned fell back to the plain bootstrap"""
+        return bool(_lib.mgdd_setup_fallback(self.ctx))
 
     def setup(self, agg, random_vectors, arnoldi_start, nu=3, iota=3, mr_iters=4, arnoldi_m=0, n_part2=1, prec=F64,
               chunk=0, ntv=None, seed=0):

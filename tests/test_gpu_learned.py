@@ -103,6 +103,38 @@ def test_learned_setup_builds_P_from_network_vectors_and_solves():
     assert np.linalg.norm(b[0] - op.apply(lat.unpack(z)[0])) <= 1.5e-10 * np.linalg.norm(b[0])
 
 
+def test_learned_setup_falls_back_to_the_bootstrap():
+    """A network whose outputs cannot form P (all weights zero: every test
+    vector is zero, so every aggregate's piece is rank deficient) makes the
+    learned setup run the plain bootstrap from the caller's random vectors
+    instead: mgdd_setup_fallback reports it, and the test vectors equal those
+    of mgdd_setup_bootstrap with the same vectors and parameters. Working
+    weights do not fall back."""
+    import torch
+    from paper_1202_2462_amd.mgdd import F32, F64
+    widths = [1, 4, 4, 1]
+    say("learned setup fallback")
+    op = problem(DIMS, seed=35, m0=0.1)
+    lat = lattice(op, BLOCK)
+    rnd = latgen.gaussian_fields(DIMS, N, 36)
+    Vc = int(np.prod(DIMS)) // int(np.prod(AGG))
+    st = latgen.gaussian_vector(Vc * 2 * N, 37)
+    start = torch.tensor(np.stack([st.real, st.imag], -1), dtype=torch.float64, device="cuda")
+    Wz = [0 * W for W in latgen.network_weights(widths, 38)]
+    lat.setup_learned(widths, lat.weights_to_dev(Wz), AGG, lat.pack(rnd, F64), start, nu=1, n_part2=1)
+    assert lat.setup_fell_back()
+    got = lat.unpack(lat.test_vectors())
+    ref = lattice(op, BLOCK)
+    ref.setup(AGG, ref.pack(rnd, F64), start, nu=1, iota=3, mr_iters=4, n_part2=1, prec=F32)
+    want = ref.unpack(ref.test_vectors())
+    assert rel(got, want) < 1e-12
+    lat.setup_learned(widths, lat.weights_to_dev(latgen.network_weights(widths, 38)), AGG, lat.pack(rnd, F64),
+                      start, nu=1, n_part2=1)
+    assert not lat.setup_fell_back()
+    lat.close()
+    ref.close()
+
+
 def test_short_training_lowers_the_loss():
     import torch
     from paper_1202_2462_amd.mgdd import F32

@@ -66,13 +66,14 @@ __device__ inline void sum_partials(const double2 *__restrict__ part, int nq, in
 // memory when the cache holds the rest.
 template <typename T, bool HC = false>
 __global__ __launch_bounds__(APB) void arnoldi_apply_kernel(int Vc, int N, const int *__restrict__ cnbr,
+                                                            const int *__restrict__ order,
                                                             const C<T> *__restrict__ Dc, const C<T> *__restrict__ w,
                                                             const double2 *__restrict__ npart, int nnp, VecList V,
                                                             int j, C<T> *__restrict__ vj, C<T> *__restrict__ y,
                                                             double2 *__restrict__ part1, double2 *__restrict__ nr) {
-    // consecutive coarse sites on one XCD: the x and y neighbours' blocks and
-    // vectors are read again from that XCD's L2
-    const int a = xcd_block(Vc), sg = blockIdx.y, nb = gridDim.y;
+    // consecutive entries of the visiting order on one XCD: the neighbours'
+    // blocks and vectors are read again from that XCD's L2
+    const int l = xcd_block(Vc), a = order ? order[l] : l, sg = blockIdx.y, nb = gridDim.y;
     const int n2 = 2 * N;
     const size_t so = (size_t)sg * Vc * n2;
     __shared__ double2 red[1];
@@ -370,7 +371,7 @@ int launch_coarse_arnoldi(Ctx *c, const StencilOp &op, int p, int m, int nb, con
             nrj = nullptr;
         }
 #define APPLY(T, HC, D, LDS)                                                                                       \
-    arnoldi_apply_kernel<T, HC><<<gapp, APB, LDS, c->stream>>>(Vc, N, op.nbr, (const C<T> *)(D), (const C<T> *)w, \
+    arnoldi_apply_kernel<T, HC><<<gapp, APB, LDS, c->stream>>>(Vc, N, op.nbr, op.order, (const C<T> *)(D), (const C<T> *)w, \
                                                                np, nnp, vl, j, (C<T> *)V[j], (C<T> *)y, part1, nrj)
         // algorithmic bytes: the blocks once per launch (5 per coarse site when
         // compact, else 9), per right-hand side w read, y and v_j written and

@@ -83,6 +83,7 @@ struct Level1 {  // coarse level of the current P
     // D_c(a, a + mu); the backward hops follow from gamma5^c-hermiticity
     void *Dh32 = nullptr;
     int *cnbr = nullptr;                    // [Vc][9] coarse neighbour (self first)
+    int *corder = nullptr;                  // [Vc] order in which the coarse step visits the coarse sites
     int *agg_sites = nullptr;               // [Vc][Va] device site of each local site of an aggregate
     int *site_agg = nullptr;                // [V] aggregate of each device site
     void *tv64 = nullptr;                   // the N test vectors P was built from

@@ -18,6 +18,7 @@ struct StencilOp {
     const int *nbr = nullptr;
     const void *D64 = nullptr, *D32 = nullptr;
     const void *H32 = nullptr;   // [V][5][col][row] FP32 self and forward blocks, or null
+    const int *order = nullptr;  // [V] visiting order of the sites (null: index order)
 };
 inline StencilOp level1_op(const Ctx *c) {
     StencilOp o;
@@ -27,6 +28,7 @@ inline StencilOp level1_op(const Ctx *c) {
     o.D64 = c->c.Dc64;
     o.D32 = c->c.Dc32;
     o.H32 = c->c.Dh32;
+    o.order = c->c.corder;
     return o;
 }
 inline StencilOp level2_op(const Ctx *c) {

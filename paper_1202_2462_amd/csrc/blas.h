@@ -6,7 +6,7 @@
 namespace mgdd {
 
 constexpr int MAXV = 16;  // vectors per kernel pass
-constexpr int WIDE = 2 * MAXV;  // vectors per pass of the FP64 outer Gram-Schmidt kernels
+constexpr int WIDE = 2 * MAXV;  // vectors per launch of the outer Gram-Schmidt kernels
 struct PtrList {
     const void *p[MAXV];
 };
@@ -22,15 +22,22 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
                  double beta, void *y, int nseg = 1);
 // y_s <- y_s - sum_i coef[i * nseg + s] x_i,s (same precision p for all), then
 // out[i * nseg + s] = <x_i, y>_s, or out[s] = ||y_s||^2 when norm_only;
-// nvec <= MAXV, or nvec <= 2 MAXV in FP64 (two lanes per element, each with
-// half of the vectors). The sums are deterministic.
+// nvec <= MAXV. The sums are deterministic.
 int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
                     double2 *out, int norm_only, int nseg = 1);
-// the same with both sums: out[i * nseg + s] = <x_i, y>_s and nrm[s] = ||y_s||^2
-int blas_update_dot_norm(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
-                         double2 *out, double2 *nrm, int nseg = 1);
-// FP64 only, nvec <= WIDE, in one pass: out[i * nseg + s] = <x_i, w>_s
-int blas_multidot_wide(Ctx *c, size_t n, const void *const *xs, int nvec, const void *w, double2 *out, int nseg = 1);
+// Outer Gram-Schmidt step with a lagged second pass (FP64), in two passes over
+// the basis instead of three:
+// pass A, in one pass over x_0 ... x_{nvec-1}:
+//   out_w[i * nseg + s] = <x_i, w>_s and out_v[i * nseg + s] = <x_i, v>_s;
+int blas_dots2(Ctx *c, size_t n, const void *const *xs, int nvec, const void *w, const void *v, double2 *out_w,
+               double2 *out_v, int nseg = 1);
+// pass B, in one pass over x_0 ... x_{nvec-1} (nvec >= 0; v and w are not
+// among them), coefficients of segment s at coef[q * nseg + s] (q = 0: a,
+// 1: c, 2 + i: -s_i, 2 + nvec + i: -t_i):
+//   v <- a (v - sum_i s_i x_i),   w <- w - sum_i t_i x_i + c v   (new v),
+// nrm[s] = ||w_s||^2 after.
+int blas_dcgs_update(Ctx *c, size_t n, const void *const *xs, int nvec, const double2 *coef, void *v, void *w,
+                     double2 *nrm, int nseg = 1);
 // y_s = (coef ? coef[s] * alpha : alpha) x_s   (x and y may alias)
 int blas_scale(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha, void *y,
                int nseg = 1);

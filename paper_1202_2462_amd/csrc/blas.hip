@@ -122,8 +122,7 @@ __global__ __launch_bounds__(TPB) void lincomb_kernel(size_t n, PtrList xs, int 
 }
 
 // y <- y - sum_i coef[i * nseg + s] x_i, then the partial sums of the new y
-// against every x_i (mode 0), of ||y||^2 (mode 1), or both (mode 2: the norm
-// after the nvec dot products) per workgroup into part, laid out as
+// against every x_i (mode 0) or of ||y||^2 (mode 1) per workgroup into part, laid out as
 // multidot's: one pass over the x_i instead of a lincomb and a multidot (the
 // later passes of classical Gram-Schmidt). The update arithmetic is that of
 // lincomb_kernel.
@@ -132,9 +131,8 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
                                                          const double2 *__restrict__ coef, C<T> *__restrict__ y,
                                                          int mode, double2 *__restrict__ part) {
     const int norm_only = mode == 1;
-    __shared__ double red[TPB / 64][2 * NV + 1];
+    __shared__ double red[TPB / 64][2 * NV];
     double2 c[NV], acc[NV];
-    double accn = 0;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         c[i] = i < nvec ? cscale(coef[(size_t)i * gridDim.y + blockIdx.y], -1.0) : make_double2(0, 0);
@@ -165,7 +163,6 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
         } else {
 #pragma unroll
             for (int i = 0; i < NV; i++) cfmac(acc[i], xv[i], ud);
-            if (mode == 2) accn += ud.x * ud.x + ud.y * ud.y;
         }
     }
     const int nout = norm_only ? 1 : nvec;
@@ -177,10 +174,6 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
             if (lane == 0) { red[wv][2 * i] = a; red[wv][2 * i + 1] = b; }
         }
     }
-    if (mode == 2) {
-        const double a = wave_sum(accn);
-        if (lane == 0) red[wv][2 * NV] = a;
-    }
     __syncthreads();
     if ((int)threadIdx.x < nout) {
         int i = threadIdx.x;
@@ -188,154 +181,139 @@ __global__ __launch_bounds__(TPB) void update_dot_kernel(size_t n, PtrList xs, i
         for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * i]; b += red[k][2 * i + 1]; }
         part[((size_t)i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
     }
-    if (mode == 2 && threadIdx.x == 0) {
-        double a = 0;
-        for (int k = 0; k < TPB / 64; k++) a += red[k][2 * NV];
-        part[((size_t)nvec * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, 0);
-    }
 }
 
 struct PtrListW {
     const void *p[WIDE];
 };
 
-// update_dot_kernel in FP64 for MAXV < nvec <= 2 MAXV with G lanes per
-// element, so that no lane holds more than 2 MAXV / G vectors' values and
-// sums. A wave is G groups of 64 / G lanes; lane l of group g takes element
-// l of the wave's range and the vectors g NG ... g NG + NG - 1 (NG =
-// 2 MAXV / G). The groups swap their partial updates in a butterfly, so that
-// every lane forms the same
-// y' = (u_0 + u_1) + (u_2 + u_3) (G = 4) or u_0 + u_1 (G = 2), with
-// u_0 = y - sum_{i < NG} c_i x_i and u_g = -sum c_i x_i over group g's vectors,
-// which the lane of group 0 stores. Modes and the layout of part are those of
-// update_dot_kernel.
-template <int G>
-__global__ __launch_bounds__(TPB) void update_dot2_kernel(size_t n, PtrListW xs, int nvec,
-                                                          const double2 *__restrict__ coef, double2 *__restrict__ y,
-                                                          int mode, double2 *__restrict__ part) {
-    constexpr int NG = 2 * MAXV / G, LG = 64 / G;
-    __shared__ double2 cs[2 * MAXV];
-    __shared__ double red[TPB / 64][4 * MAXV + 1];
-    if ((int)threadIdx.x < 2 * MAXV)
-        cs[threadIdx.x] = (int)threadIdx.x < nvec ? cscale(coef[(size_t)threadIdx.x * gridDim.y + blockIdx.y], -1.0)
-                                                  : make_double2(0, 0);
-    __syncthreads();
+// The two passes of the outer Gram-Schmidt step with a lagged second pass
+// (see blas.h). G lanes per element (fewer accumulators per lane than one
+// lane per element with all the vectors: more waves in flight), each a group
+// of 64 / G lanes of a wave; lane l of group g takes element l of the wave's
+// range and the vectors g NG ... g NG + NG - 1, NV = G NG vector slots; the
+// launcher fills the slots past nvec with vectors that group 0's lanes read
+// at the same element (no extra memory traffic), and their coefficients are
+// 0 or their sums dropped, so that no branch separates the loads.
+//
+// Pass A: partial sums of <x_i, w> (q = i) and <x_i, v> (q = nvec + i) per
+// workgroup into part, laid out as multidot's.
+template <int NG, int G>
+__global__ __launch_bounds__(TPB) void dots2_kernel(size_t n, PtrListW xs, int nvec, const double2 *__restrict__ w,
+                                                    const double2 *__restrict__ v, double2 *__restrict__ part) {
+    constexpr int LG = 64 / G, NV = NG * G;
+    __shared__ double red[TPB / 64][4 * NV];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, grp = lane / LG, gl = lane % LG;
-    const int norm_only = mode == 1;
-    // a lane whose group has run out of vectors reads vector i of group 0
-    // (the address group 0's lane reads, so no extra memory traffic) with
-    // coefficient 0: every lane issues all loads, without branches between
     const double2 *xp[NG];
 #pragma unroll
-    for (int i = 0; i < NG; i++) xp[i] = (const double2 *)(grp * NG + i < nvec ? xs.p[grp * NG + i] : xs.p[i]);
-    double2 acc[NG];
-    double accn = 0;
+    for (int i = 0; i < NG; i++) xp[i] = (const double2 *)xs.p[grp * NG + i];
+    double2 aw[NG], av[NG];
 #pragma unroll
-    for (int i = 0; i < NG; i++) acc[i] = make_double2(0, 0);
+    for (int i = 0; i < NG; i++) aw[i] = av[i] = make_double2(0, 0);
     const size_t per = TPB / G, stride = (size_t)gridDim.x * per, so = (size_t)blockIdx.y * n;
     for (size_t e = (size_t)blockIdx.x * per + wv * LG + gl; e < n; e += stride) {
-        const double2 yv = y[so + e];
+        const double2 wd = w[so + e], vd = v[so + e];
         double2 xv[NG];
 #pragma unroll
         for (int i = 0; i < NG; i++) xv[i] = xp[i][so + e];
-        double2 u = grp == 0 ? yv : make_double2(0, 0);
-#pragma unroll
-        for (int i = 0; i < NG; i++) cfma(u, cs[grp * NG + i], xv[i]);
-#pragma unroll
-        for (int m = LG; m < 64; m <<= 1) {
-            const double ox = __shfl_xor(u.x, m, 64), oy = __shfl_xor(u.y, m, 64);
-            u = make_double2(u.x + ox, u.y + oy);
-        }
-        if (grp == 0) {
-            y[so + e] = u;
-            if (mode != 0) accn += u.x * u.x + u.y * u.y;
-        }
-        if (!norm_only) {
-#pragma unroll
-            for (int i = 0; i < NG; i++) cfmac(acc[i], xv[i], u);
-        }
-    }
-    if (!norm_only) {
 #pragma unroll
         for (int i = 0; i < NG; i++) {
-            double a = acc[i].x, b = acc[i].y;
-#pragma unroll
-            for (int m = LG / 2; m >= 1; m >>= 1) {
-                a += __shfl_xor(a, m, 64);
-                b += __shfl_xor(b, m, 64);
-            }
-            const int q = grp * NG + i;
-            if (gl == 0 && q < nvec) {
-                red[wv][2 * q] = a;
-                red[wv][2 * q + 1] = b;
-            }
+            cfmac(aw[i], xv[i], wd);
+            cfmac(av[i], xv[i], vd);
         }
-    }
-    if (mode != 0) {
-        const double a = wave_sum(accn);
-        if (lane == 0) red[wv][4 * MAXV] = a;
-    }
-    __syncthreads();
-    const int nout = norm_only ? 0 : nvec;
-    if ((int)threadIdx.x < nout) {
-        const int q = threadIdx.x;
-        double a = 0, b = 0;
-        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * q]; b += red[k][2 * q + 1]; }
-        part[((size_t)q * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
-    }
-    if (mode != 0 && threadIdx.x == 0) {
-        double a = 0;
-        for (int k = 0; k < TPB / 64; k++) a += red[k][4 * MAXV];
-        part[((size_t)nout * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, 0);
-    }
-}
-
-// multidot_kernel in FP64 for nvec <= 2 MAXV with four lanes per element,
-// grouped as in update_dot2_kernel: the lane of group g takes the vectors
-// g NG ... g NG + NG - 1 (a slot past nvec reads group 0's vector at the same
-// element, the address group 0's lane reads, and its sum is dropped). Fewer
-// accumulators per lane than one lane per element with all 32: more waves in
-// flight. Layout of part as multidot_kernel's.
-__global__ __launch_bounds__(TPB) void multidot4_kernel(size_t n, PtrListW xs, int nvec,
-                                                        const double2 *__restrict__ w, double2 *__restrict__ part) {
-    constexpr int G = 4, NG = 2 * MAXV / G, LG = 64 / G;
-    __shared__ double red[TPB / 64][4 * MAXV];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, grp = lane / LG, gl = lane % LG;
-    const double2 *xp[NG];
-#pragma unroll
-    for (int i = 0; i < NG; i++) xp[i] = (const double2 *)(grp * NG + i < nvec ? xs.p[grp * NG + i] : xs.p[i]);
-    double2 acc[NG];
-#pragma unroll
-    for (int i = 0; i < NG; i++) acc[i] = make_double2(0, 0);
-    const size_t per = TPB / G, stride = (size_t)gridDim.x * per, so = (size_t)blockIdx.y * n;
-    for (size_t e = (size_t)blockIdx.x * per + wv * LG + gl; e < n; e += stride) {
-        const double2 wd = w[so + e];
-        double2 xv[NG];
-#pragma unroll
-        for (int i = 0; i < NG; i++) xv[i] = xp[i][so + e];
-#pragma unroll
-        for (int i = 0; i < NG; i++) cfmac(acc[i], xv[i], wd);
     }
 #pragma unroll
     for (int i = 0; i < NG; i++) {
-        double a = acc[i].x, b = acc[i].y;
+        double a = aw[i].x, b = aw[i].y, c = av[i].x, d = av[i].y;
 #pragma unroll
         for (int m = LG / 2; m >= 1; m >>= 1) {
             a += __shfl_xor(a, m, 64);
             b += __shfl_xor(b, m, 64);
+            c += __shfl_xor(c, m, 64);
+            d += __shfl_xor(d, m, 64);
         }
         const int q = grp * NG + i;
         if (gl == 0 && q < nvec) {
             red[wv][2 * q] = a;
             red[wv][2 * q + 1] = b;
+            red[wv][2 * (NV + q)] = c;
+            red[wv][2 * (NV + q) + 1] = d;
         }
     }
     __syncthreads();
-    if ((int)threadIdx.x < nvec) {
-        const int q = threadIdx.x;
+    if ((int)threadIdx.x < 2 * nvec) {
+        const int q = threadIdx.x, slot = q < nvec ? q : NV + q - nvec;
         double a = 0, b = 0;
-        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * q]; b += red[k][2 * q + 1]; }
+        for (int k = 0; k < TPB / 64; k++) { a += red[k][2 * slot]; b += red[k][2 * slot + 1]; }
         part[((size_t)q * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = make_double2(a, b);
+    }
+}
+
+// Pass B, for the vectors i0 ... i0 + nvec - 1 of ntot, with the coefficients
+// of segment s at coef[q * nseg + s] (q = 0: a, 1: c, 2 + i: -s_i,
+// 2 + ntot + i: -t_i):
+//   v <- v + sum_i (-s_i) x_i,  w <- w + sum_i (-t_i) x_i,
+// and in the last launch (last != 0) then v <- a v, w <- w + c v and the
+// partial sums of ||w||^2 per workgroup into part.
+template <int NG, int G>
+__global__ __launch_bounds__(TPB) void dcgs_update_kernel(size_t n, PtrListW xs, int nvec, int i0, int ntot,
+                                                          const double2 *__restrict__ coef, int last,
+                                                          double2 *__restrict__ v, double2 *__restrict__ w,
+                                                          double2 *__restrict__ part) {
+    constexpr int LG = 64 / G, NV = NG * G;
+    __shared__ double2 cs[2 * NV + 2];
+    __shared__ double red[TPB / 64];
+    const int nseg = gridDim.y, sg = blockIdx.y;
+    if ((int)threadIdx.x < 2 * NV) {
+        const int i = threadIdx.x % NV, q = 2 + ((int)threadIdx.x >= NV ? ntot : 0) + i0 + i;
+        cs[threadIdx.x] = i < nvec ? coef[(size_t)q * nseg + sg] : make_double2(0, 0);
+    }
+    if (threadIdx.x == 0) {
+        cs[2 * NV] = last ? coef[sg] : make_double2(1, 0);
+        cs[2 * NV + 1] = last ? coef[(size_t)nseg + sg] : make_double2(0, 0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, grp = lane / LG, gl = lane % LG;
+    const double2 *xp[NG];
+#pragma unroll
+    for (int i = 0; i < NG; i++) xp[i] = (const double2 *)xs.p[grp * NG + i];
+    const double a = cs[2 * NV].x;
+    const double2 cv = cs[2 * NV + 1];
+    double accn = 0;
+    const size_t per = TPB / G, stride = (size_t)gridDim.x * per, so = (size_t)blockIdx.y * n;
+    for (size_t e = (size_t)blockIdx.x * per + wv * LG + gl; e < n; e += stride) {
+        const double2 vd = v[so + e], wd = w[so + e];
+        double2 xv[NG];
+#pragma unroll
+        for (int i = 0; i < NG; i++) xv[i] = xp[i][so + e];
+        double2 uv = make_double2(0, 0), uw = make_double2(0, 0);
+#pragma unroll
+        for (int i = 0; i < NG; i++) {
+            cfma(uv, cs[grp * NG + i], xv[i]);
+            cfma(uw, cs[NV + grp * NG + i], xv[i]);
+        }
+#pragma unroll
+        for (int m = LG; m < 64; m <<= 1) {
+            uv = make_double2(uv.x + __shfl_xor(uv.x, m, 64), uv.y + __shfl_xor(uv.y, m, 64));
+            uw = make_double2(uw.x + __shfl_xor(uw.x, m, 64), uw.y + __shfl_xor(uw.y, m, 64));
+        }
+        if (grp == 0) {
+            const double2 vn = cscale(cadd(vd, uv), a);
+            double2 wn = cadd(wd, uw);
+            cfma(wn, cv, vn);
+            v[so + e] = vn;
+            w[so + e] = wn;
+            accn += wn.x * wn.x + wn.y * wn.y;
+        }
+    }
+    if (!last) return;
+    const double s = wave_sum(accn);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int k = 0; k < TPB / 64; k++) t += red[k];
+        part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(t, 0);
     }
 }
 
@@ -689,38 +667,14 @@ int blas_lincomb(Ctx *c, int px, int py, size_t n, const void *const *xs, int nv
     return MGDD_OK;
 }
 
-#ifndef UPDATE_DOT2_LANES
-#define UPDATE_DOT2_LANES 4
-#endif
-static int update_dot2_launch(Ctx *c, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
-                              double2 *out, int mode, double2 *nrm, int nseg) {
-    constexpr int G = UPDATE_DOT2_LANES;
-    size_t g = (n + TPB / G - 1) / (TPB / G);   // one element per lane group
-    const int nwg = (int)(g > 4096 ? 4096 : g < 1 ? 1 : g);
-    double2 *part = (double2 *)ensure_red(c, (size_t)2 * (WIDE + 1) * nseg * nwg + 16);
-    if (!part) return MGDD_ENOMEM;
-    PtrListW pl{};
-    for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
-    dim3 grid(nwg, nseg);
-    update_dot2_kernel<G><<<grid, TPB, 0, c->stream>>>(n, pl, nvec, coef, (double2 *)y, mode, part);
-    if (mode == 1) {
-        finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part, out);
-    } else {
-        finish_kernel<<<nvec * nseg, 64, 0, c->stream>>>(nwg, part, out);
-        if (mode == 2) finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part + (size_t)nvec * nseg * nwg, nrm);
-    }
-    return hip_check(c, hipGetLastError(), "update_dot");
-}
-
-static int update_dot_launch(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
-                             double2 *out, int mode, double2 *nrm, int nseg) {
-    if (p == MGDD_F64 && nvec > MAXV && nvec <= 2 * MAXV)
-        return update_dot2_launch(c, n, xs, nvec, coef, y, out, mode, nrm, nseg);
+int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
+                    double2 *out, int norm_only, int nseg) {
+    const int mode = norm_only ? 1 : 0;
     if (nvec < 1 || nvec > MAXV) return fail(c, MGDD_EINVAL, "update_dot: bad vector count");
     // about two elements per thread: every load of the update in flight at once
     size_t g = (n + 2 * TPB - 1) / (2 * TPB);
     const int nwg = (int)(g > 4096 ? 4096 : g < 1 ? 1 : g);
-    double2 *part = (double2 *)ensure_red(c, (size_t)2 * (MAXV + 1) * nseg * nwg + 16);
+    double2 *part = (double2 *)ensure_red(c, (size_t)2 * MAXV * nseg * nwg + 16);
     if (!part) return MGDD_ENOMEM;
     PtrList pl{};
     for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
@@ -735,33 +689,69 @@ static int update_dot_launch(Ctx *c, int p, size_t n, const void *const *xs, int
 #undef UD1
     const int nout = mode == 1 ? 1 : nvec;
     finish_kernel<<<nout * nseg, 64, 0, c->stream>>>(nwg, part, out);
-    if (mode == 2) finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part + (size_t)nvec * nseg * nwg, nrm);
     return hip_check(c, hipGetLastError(), "update_dot");
 }
 
-int blas_multidot_wide(Ctx *c, size_t n, const void *const *xs, int nvec, const void *w, double2 *out, int nseg) {
-    if (nvec < 1 || nvec > WIDE) return fail(c, MGDD_EINVAL, "multidot: bad vector count");
-    // one element per group of four lanes, up to 2048 workgroups
-    size_t g = (n + TPB / 4 - 1) / (TPB / 4);
-    const int nwg = (int)(g > 2048 ? 2048 : g < 1 ? 1 : g);
-    double2 *part = (double2 *)ensure_red(c, (size_t)2 * (WIDE + 1) * nseg * nwg + 16);
-    if (!part) return MGDD_ENOMEM;
+// pointer list of one launch of the lagged Gram-Schmidt kernels: vectors
+// i0 ... i0 + nv - 1, the slots past nv filled as the kernels expect (the
+// vector group 0 reads in that slot, else the first one, else fill)
+static PtrListW dcgs_slots(const void *const *xs, int i0, int nv, int NG, const void *fill) {
     PtrListW pl{};
-    for (int i = 0; i < nvec; i++) pl.p[i] = xs[i];
-    dim3 grid(nwg, nseg);
-    multidot4_kernel<<<grid, TPB, 0, c->stream>>>(n, pl, nvec, (const double2 *)w, part);
-    finish_kernel<<<nvec * nseg, 64, 0, c->stream>>>(nwg, part, out);
-    return hip_check(c, hipGetLastError(), "multidot");
+    for (int q = 0; q < WIDE; q++) {
+        const int r = q % NG;
+        pl.p[q] = q < nv ? xs[i0 + q] : r < nv ? xs[i0 + r] : nv > 0 ? xs[i0] : fill;
+    }
+    return pl;
 }
 
-int blas_update_dot(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
-                    double2 *out, int norm_only, int nseg) {
-    return update_dot_launch(c, p, n, xs, nvec, coef, y, out, norm_only ? 1 : 0, nullptr, nseg);
+static int dcgs_grid(size_t n, int G) {
+    size_t g = (n + TPB / G - 1) / (TPB / G);
+    return (int)(g > 4096 ? 4096 : g < 1 ? 1 : g);
 }
 
-int blas_update_dot_norm(Ctx *c, int p, size_t n, const void *const *xs, int nvec, const double2 *coef, void *y,
-                         double2 *out, double2 *nrm, int nseg) {
-    return update_dot_launch(c, p, n, xs, nvec, coef, y, out, 2, nrm, nseg);
+int blas_dots2(Ctx *c, size_t n, const void *const *xs, int nvec, const void *w, const void *v, double2 *out_w,
+               double2 *out_v, int nseg) {
+    if (nvec < 1) return fail(c, MGDD_EINVAL, "dots2: bad vector count");
+    for (int i0 = 0; i0 < nvec; i0 += WIDE) {
+        const int nv = nvec - i0 < WIDE ? nvec - i0 : WIDE;
+        const int G = nv <= 8 ? 1 : nv <= 16 ? 2 : 4, NG = nv <= 4 ? 4 : 8;
+        const int nwg = dcgs_grid(n, G);
+        double2 *part = (double2 *)ensure_red(c, (size_t)4 * WIDE * nseg * nwg + 16);
+        if (!part) return MGDD_ENOMEM;
+        const PtrListW pl = dcgs_slots(xs, i0, nv, NG, w);
+        dim3 grid(nwg, nseg);
+#define D2(NGT, GT)     dots2_kernel<NGT, GT><<<grid, TPB, 0, c->stream>>>(n, pl, nv, (const double2 *)w, (const double2 *)v, part)
+        if (nv <= 4) D2(4, 1); else if (nv <= 8) D2(8, 1); else if (nv <= 16) D2(8, 2); else D2(8, 4);
+#undef D2
+        finish_kernel<<<nv * nseg, 64, 0, c->stream>>>(nwg, part, out_w + (size_t)i0 * nseg);
+        finish_kernel<<<nv * nseg, 64, 0, c->stream>>>(nwg, part + (size_t)nv * nseg * nwg, out_v + (size_t)i0 * nseg);
+        int rc = hip_check(c, hipGetLastError(), "dots2");
+        if (rc) return rc;
+    }
+    return MGDD_OK;
+}
+
+int blas_dcgs_update(Ctx *c, size_t n, const void *const *xs, int nvec, const double2 *coef, void *v, void *w,
+                     double2 *nrm, int nseg) {
+    if (nvec < 0) return fail(c, MGDD_EINVAL, "dcgs_update: bad vector count");
+    int i0 = 0;
+    do {
+        const int nv = nvec - i0 < WIDE ? nvec - i0 : WIDE, last = i0 + nv >= nvec;
+        const int G = nv <= 8 ? 1 : nv <= 16 ? 2 : 4, NG = nv <= 4 ? 4 : 8;
+        const int nwg = dcgs_grid(n, G);
+        double2 *part = (double2 *)ensure_red(c, (size_t)2 * nseg * nwg + 16);
+        if (!part) return MGDD_ENOMEM;
+        const PtrListW pl = dcgs_slots(xs, i0, nv, NG, v);
+        dim3 grid(nwg, nseg);
+#define DU(NGT, GT)                                                                                                      dcgs_update_kernel<NGT, GT><<<grid, TPB, 0, c->stream>>>(n, pl, nv, i0, nvec, coef, last, (double2 *)v,                                                                      (double2 *)w, part)
+        if (nv <= 4) DU(4, 1); else if (nv <= 8) DU(8, 1); else if (nv <= 16) DU(8, 2); else DU(8, 4);
+#undef DU
+        if (last) finish_kernel<<<nseg, 64, 0, c->stream>>>(nwg, part, nrm);
+        int rc = hip_check(c, hipGetLastError(), "dcgs_update");
+        if (rc) return rc;
+        i0 += nv;
+    } while (i0 < nvec);
+    return MGDD_OK;
 }
 
 static int scale_launch(Ctx *c, int px, int py, size_t n, const void *x, const double2 *coef, double2 alpha,

@@ -82,8 +82,9 @@ static int write_dev(Ctx *c, const cd *src, size_t n, double2 *dst) {
 static bool finite(cd z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
 
 // Solves min || beta e1 - H y || for the (k+1) x k upper Hessenberg H (column
-// major, ld = ldh) by Givens rotations; returns y (k values).
-static void hessenberg_lsq(int k, const std::vector<cd> &Hcol, int ldh, double beta, std::vector<cd> &y) {
+// major, ld = ldh) by Givens rotations: y (k values) when y is given; returns
+// the minimum, |g_k| after the rotations.
+static double hessenberg_lsq(int k, const std::vector<cd> &Hcol, int ldh, double beta, std::vector<cd> *y) {
     std::vector<cd> R((size_t)(k + 1) * k);
     for (int j = 0; j < k; j++)
         for (int i = 0; i <= j + 1; i++) R[(size_t)j * (k + 1) + i] = Hcol[(size_t)j * ldh + i];
@@ -107,12 +108,15 @@ static void hessenberg_lsq(int k, const std::vector<cd> &Hcol, int ldh, double b
             cl[j + 1] = -std::conj(s) * a + c * b;
         }
     }
-    y.assign(k, 0.0);
-    for (int i = k - 1; i >= 0; i--) {
-        cd s = g[i];
-        for (int l = i + 1; l < k; l++) s -= R[(size_t)l * (k + 1) + i] * y[l];
-        y[i] = s / R[(size_t)i * (k + 1) + i];
+    if (y) {
+        y->assign(k, 0.0);
+        for (int i = k - 1; i >= 0; i--) {
+            cd s = g[i];
+            for (int l = i + 1; l < k; l++) s -= R[(size_t)l * (k + 1) + i] * (*y)[l];
+            (*y)[i] = s / R[(size_t)i * (k + 1) + i];
+        }
     }
+    return std::abs(g[k]);
 }
 
 // ---------------------------------------------------------------- Gram-Schmidt steps on the device
@@ -142,45 +146,6 @@ static int cgs2(Ctx *c, int p, size_t n, void *const *V, int k, void *w, double2
     if (!rc) rc = blas_multidot(c, p, p, n, &wp, 1, w, nrm, nb);
     return rc;
 }
-
-// Outer Gram-Schmidt step of the flexible GMRES (FP64, long vectors):
-// classical Gram-Schmidt whose second pass runs only where the first leaves a
-// measurable component in span(V). First part: h1 = V^H w, then
-// w' = w - V h1 with h2 = V^H w' and ||w'||^2 summed in the same pass over V.
-// Second part (only when the caller's test asks for it): w'' = w' - V h2 and
-// ||w''||^2. The caller reads h1, h2 and the norm between the two parts.
-static int cgs_first(Ctx *c, size_t n, void *const *V, int k, void *w, double2 *h1, double2 *h2, double2 *nrm,
-                     int nb) {
-    if (k > MAXV && k <= 2 * MAXV) {
-        // one pass for h1 (all k vectors at once), one for the update, h2
-        // and the norm
-        int rc = blas_multidot_wide(c, n, V, k, w, h1, nb);
-        if (!rc) rc = blas_update_dot_norm(c, MGDD_F64, n, V, k, h1, w, h2, nrm, nb);
-        return rc;
-    }
-    int rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, V, k, w, h1, nb);
-    if (rc) return rc;
-    if (k <= MAXV) return blas_update_dot_norm(c, MGDD_F64, n, V, k, h1, w, h2, nrm, nb);
-    rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, V, k, h1, -1.0, 1.0, w, nb);
-    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, V, k, w, h2, nb);
-    const void *wp = w;
-    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &wp, 1, w, nrm, nb);
-    return rc;
-}
-
-static int cgs_second(Ctx *c, size_t n, void *const *V, int k, void *w, const double2 *h2, double2 *nrm, int nb) {
-    if (k <= 2 * MAXV) return blas_update_dot(c, MGDD_F64, n, V, k, h2, w, nrm, 1, nb);
-    int rc = blas_lincomb(c, MGDD_F64, MGDD_F64, n, V, k, h2, -1.0, 1.0, w, nb);
-    const void *wp = w;
-    if (!rc) rc = blas_multidot(c, MGDD_F64, MGDD_F64, n, &wp, 1, w, nrm, nb);
-    return rc;
-}
-
-// the second pass is taken when the component the first pass left in span(V)
-// exceeds this fraction of the new vector, ||V^H w'|| > REORTH_TOL ||w'||
-// (the basis then stays orthonormal to about this level; the test follows
-// Daniel, Gragg, Kaufman and Stewart, 1976, with the measured component)
-constexpr double REORTH_TOL = 1e-12;
 
 // Orthonormalisation of nv FP64 vectors in index order (global
 // orthonormalisation): the Q of X = Q R with R upper triangular and a
@@ -276,7 +241,7 @@ static int hessenberg_combine(Ctx *c, int p, int m, int nb, size_t n, const doub
             Hc[(size_t)j * (m + 1) + j + 1] = hn;
             if (hn == 0.0) { k = j + 1; break; }
         }
-        hessenberg_lsq(k, Hc, m + 1, beta, y);
+        hessenberg_lsq(k, Hc, m + 1, beta, &y);
         for (int i = 0; i < k; i++) {
             if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the coarse solve");
             yb[(size_t)i * nb + sg] = y[i];
@@ -491,11 +456,11 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
     // copies, so that each Arnoldi step reads them back in one copy
     double2 *h1 = (double2 *)A.take((size_t)(2 * (m + 1) + 1) * nb * 16);
     double2 *h2 = h1 ? h1 + (size_t)(m + 1) * nb : nullptr, *nr = h1 ? h2 + (size_t)(m + 1) * nb : nullptr;
-    double2 *coef = (double2 *)A.take((size_t)(m + 2) * nb * 16);
+    double2 *coef = (double2 *)A.take((size_t)(2 * m + 2) * nb * 16);
     double2 *pm = (double2 *)A.take((size_t)2 * nb * 16);
     if (!pm) return fail(c, MGDD_ENOMEM, "FGMRES workspace");
-    // pinned scalars: [pm 2nb | h1 (m+1)nb | h2 (m+1)nb | norms nb | coefficients (m+1)nb]
-    cd *hb = host_buf(c, (size_t)nb * (3 * (size_t)m + 6));
+    // pinned scalars: [pm 2nb | h1 (m+1)nb | h2 (m+1)nb | norms nb | coefficients (2m+2)nb]
+    cd *hb = host_buf(c, (size_t)nb * (4 * (size_t)m + 7));
     if (!hb) return fail(c, MGDD_ENOMEM, "pinned buffer (too many right-hand sides for this restart length)");
     cd *Hb1 = hb + 2 * nb, *Hb2 = Hb1 + (size_t)(m + 1) * nb, *Nb = Hb2 + (size_t)(m + 1) * nb,
        *Cb = Nb + nb;
@@ -529,8 +494,8 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
         if (!rc) rc = blas_scale(c, MGDD_F64, MGDD_F64, n, z, coef, make_double2(1, 0), z, nb);
         if (rc) return rc;
     }
-    std::vector<std::vector<cd>> Hc(nb), g(nb), sn(nb);
-    std::vector<std::vector<double>> cs_(nb);
+    std::vector<std::vector<cd>> Hc(nb);   // Hessenberg columns as formed (ld m + 1)
+    std::vector<double> beta0(nb);
     std::vector<int> k(nb);
     for (;;) {
         // true residuals r = b - D z
@@ -565,10 +530,7 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
         for (int sg = 0; sg < nb; sg++) {
             incycle[sg] = active[sg];
             Hc[sg].assign((size_t)m * (m + 1), 0.0);
-            g[sg].assign(m + 1, 0.0);
-            g[sg][0] = std::sqrt(Nb[sg].real());
-            sn[sg].assign(m, 0.0);
-            cs_[sg].assign(m, 0.0);
+            beta0[sg] = std::sqrt(Nb[sg].real());
             k[sg] = 0;
         }
         int kmax = 0;
@@ -579,51 +541,70 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
             } else if (!rc) {
                 rc = launch_dirac(c, MGDD_F64, nb, Z[j], w);
             }
-            if (!rc) rc = cgs_first(c, n, V.data(), j + 1, w, h1, h2, nr, nb);
+            // Gram-Schmidt with the second pass of v_j lagged into this step
+            // (V[j] holds v_j after one pass, normalised): pass A,
+            // t = V[0..j]^H w and s = V[0..j]^H V[j] in one pass over the basis
+            if (!rc) rc = blas_dots2(c, n, V.data(), j + 1, w, V[j], h1, h2, nb);
+            if (!rc) rc = read_dev(c, h1, (size_t)2 * (m + 1) * nb, Hb1);
             if (rc) return rc;
-            rc = read_dev(c, h1, (size_t)(2 * (m + 1) + 1) * nb, Hb1);   // h1, h2 and the norms
-            if (rc) return rc;
-            // second pass when any right-hand side of the cycle needs it
-            // (then for all of them: it is the second pass of CGS2)
-            bool reorth = false;
-            for (int sg = 0; sg < nb && !reorth; sg++) {
+            // v_j = (V[j] - V s) / alpha with alpha^2 = ||V[j]||^2 - ||s||^2; column
+            // j - 1 gains the component of V[j] in span(V[0..j-1]) (D z_{j-1} =
+            // sum h_i v_i + beta V[j]); column j: <v_i, w> (i < j) and
+            // <v_j, w> = (t_j - s^H t) / alpha
+            for (size_t q = 0; q < (size_t)(2 + 2 * j) * nb; q++) Cb[q] = 0.0;
+            for (int sg = 0; sg < nb; sg++) {
+                Cb[sg] = 1.0;   // right-hand sides outside the cycle: v and w unchanged
                 if (!incycle[sg]) continue;
+                const cd *S = Hb2 + sg, *T = Hb1 + sg;
                 double s2 = 0.0;
-                for (int i = 0; i <= j; i++) s2 += std::norm(Hb2[(size_t)i * nb + sg]);
-                const double w2 = Nb[sg].real();
-                if (!(s2 <= REORTH_TOL * REORTH_TOL * w2)) reorth = true;
+                cd st_ = 0.0;
+                for (int i = 0; i < j; i++) {
+                    s2 += std::norm(S[(size_t)i * nb]);
+                    st_ += std::conj(S[(size_t)i * nb]) * T[(size_t)i * nb];
+                }
+                const double a2 = S[(size_t)j * nb].real() - s2;
+                if (!std::isfinite(a2) || !finite(st_)) return fail(c, MGDD_ENAN, "NaN in the Arnoldi step");
+                cd *prev = j > 0 ? &Hc[sg][(size_t)(j - 1) * (m + 1)] : nullptr;
+                const double beta = prev ? prev[j].real() : 0.0;
+                if (prev)
+                    for (int i = 0; i < j; i++) prev[i] += beta * S[(size_t)i * nb];
+                if (!(a2 > 0.0)) {   // V[j] lies in span(V[0..j-1]): the cycle ends at column j - 1
+                    if (prev) prev[j] = 0.0;
+                    incycle[sg] = 0;
+                    continue;
+                }
+                const double alpha = std::sqrt(a2);
+                if (prev) prev[j] = beta * alpha;
+                cd *col = &Hc[sg][(size_t)j * (m + 1)];
+                for (int i = 0; i < j; i++) col[i] = T[(size_t)i * nb];
+                col[j] = (T[(size_t)j * nb] - st_) / alpha;
+                Cb[sg] = 1.0 / alpha;
+                Cb[nb + sg] = -col[j];
+                for (int i = 0; i < j; i++) {
+                    Cb[(size_t)(2 + i) * nb + sg] = -S[(size_t)i * nb];
+                    Cb[(size_t)(2 + j + i) * nb + sg] = -T[(size_t)i * nb];
+                }
             }
-            if (reorth) {
-                rc = cgs_second(c, n, V.data(), j + 1, w, h2, nr, nb);
-                if (!rc) rc = read_dev(c, nr, nb, Nb);
-                if (rc) return rc;
-            }
-            kmax = j + 1;
+            // pass B: V[j] <- v_j and w <- w - V[0..j] col (one pass over the
+            // basis), ||w||^2; w's own second pass comes with v_{j+1}
+            rc = write_dev(c, Cb, (size_t)(2 + 2 * j) * nb, coef);
+            if (!rc) rc = blas_dcgs_update(c, n, V.data(), j, coef, V[j], w, nr, nb);
+            if (!rc) rc = read_dev(c, nr, nb, Nb);
+            if (rc) return rc;
             bool more = false;
             for (int sg = 0; sg < nb; sg++) {
                 Cb[sg] = 0.0;
                 if (!incycle[sg]) continue;
-                cd *col = &Hc[sg][(size_t)j * (m + 1)];
-                for (int i = 0; i <= j; i++)
-                    col[i] = reorth ? Hb1[(size_t)i * nb + sg] + Hb2[(size_t)i * nb + sg] : Hb1[(size_t)i * nb + sg];
                 const double h = std::sqrt(std::max(Nb[sg].real(), 0.0));
                 if (!std::isfinite(h)) return fail(c, MGDD_ENAN, "NaN in the Arnoldi step");
-                col[j + 1] = h;
-                for (int i = 0; i < j; i++) {
-                    cd a = col[i], bb = col[i + 1];
-                    col[i] = cs_[sg][i] * a + sn[sg][i] * bb;
-                    col[i + 1] = -std::conj(sn[sg][i]) * a + cs_[sg][i] * bb;
-                }
-                cd rho;
-                la::givens(col[j], col[j + 1], cs_[sg][j], sn[sg][j], rho);
-                col[j] = rho;
-                col[j + 1] = 0.0;
-                cd gj = g[sg][j];
-                g[sg][j] = cs_[sg][j] * gj;
-                g[sg][j + 1] = -std::conj(sn[sg][j]) * gj;
+                Hc[sg][(size_t)j * (m + 1) + j + 1] = h;
                 st[sg].iters++;
                 k[sg] = j + 1;
-                if (std::abs(g[sg][j + 1]) <= sp->tol * bn[sg] || h == 0.0 || st[sg].iters >= sp->maxit) {
+                kmax = std::max(kmax, j + 1);
+                // the residual estimate from the columns so far (the last one
+                // still without the second pass of v_{j+1}, a rounding-level change)
+                const double est = hessenberg_lsq(j + 1, Hc[sg], m + 1, beta0[sg], nullptr);
+                if (est <= sp->tol * bn[sg] || h == 0.0 || st[sg].iters >= sp->maxit) {
                     incycle[sg] = 0;
                 } else {
                     Cb[sg] = 1.0 / h;
@@ -640,14 +621,12 @@ static int fgmres(Ctx *c, const mgdd_solve_params *sp, int nb, const void *b, vo
         for (int sg = 0; sg < nb; sg++) {
             if (!active[sg]) continue;
             const int kk = k[sg];
-            std::vector<cd> y(kk);
-            for (int i = kk - 1; i >= 0; i--) {
-                cd sacc = g[sg][i];
-                for (int l = i + 1; l < kk; l++) sacc -= Hc[sg][(size_t)l * (m + 1) + i] * y[l];
-                y[i] = sacc / Hc[sg][(size_t)i * (m + 1) + i];
+            std::vector<cd> y;
+            hessenberg_lsq(kk, Hc[sg], m + 1, beta0[sg], &y);
+            for (int i = 0; i < kk; i++) {
                 if (!finite(y[i])) return fail(c, MGDD_ENAN, "NaN in the least-squares solve");
+                Cb[(size_t)i * nb + sg] = y[i];
             }
-            for (int i = 0; i < kk; i++) Cb[(size_t)i * nb + sg] = y[i];
             st[sg].restarts++;
         }
         rc = write_dev(c, Cb, (size_t)kmax * nb, coef);

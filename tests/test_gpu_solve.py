@@ -38,6 +38,31 @@ def test_fgmres_plain_matches_oracle():
     assert rel(got, z_or) < 1e-8
 
 
+def test_fgmres_long_cycles_match_oracle():
+    """FGMRES(40) with a weak preconditioner (2 test vectors, one coarse GMRES
+    step, one MR step per block): the cycles run past 32 basis vectors, where
+    the outer Gram-Schmidt passes go over the basis in two launches."""
+    from paper_1202_2462_amd.mgdd import F64, PLAIN_F64
+    dims, block, agg, _, op = small_problem()
+    say("fgmres(40) long cycles", dims)
+    lat = lattice(op, block)
+    tv = latgen.gaussian_fields(dims, 2, 77)
+    lat.build_P(agg, lat.pack(tv, F64))
+    tl = solvers.TwoLevel(op, agg, tv, block, mr_iters=1, coarse_iters=1)
+    b = latgen.gaussian_fields(dims, 1, 3)
+    z_or, st_or = solvers.fgmres(op.apply, tl.precond, b[0], 40, 1e-10, 400)
+    assert st_or.converged and st_or.iters > 40
+    z, stats = lat.solve(lat.pack(b, F64), precision=PLAIN_F64, restart=40, tol=1e-10, maxit=400,
+                         coarse_iters=1, mr_iters=1)
+    got = lat.unpack(z)[0]
+    st = stats[0]
+    say("gpu iters", st.iters, "oracle iters", st_or.iters, "relres", st.relres)
+    assert st.converged and st.relres <= 1e-10
+    assert np.linalg.norm(b[0] - op.apply(got)) <= 1e-10 * np.linalg.norm(b[0])
+    assert abs(st.iters - st_or.iters) <= 1
+    assert rel(got, z_or) < 1e-8
+
+
 def test_fgmres_mixed_reaches_tolerance():
     from paper_1202_2462_amd.mgdd import F64, MIXED
     dims, block, agg, N, op = small_problem(seed=5)
@@ -113,6 +138,24 @@ def test_gcr_and_even_odd_gcr(solver):
     lat = lattice(op, (4, 4, 4, 4))
     b = latgen.gaussian_fields(dims, 1, 5)
     z, stats = lat.solve(lat.pack(b, F64), solver=solver, restart=16, tol=1e-10, maxit=3000)
+    got = lat.unpack(z)[0]
+    assert stats[0].converged
+    assert np.linalg.norm(b[0] - op.apply(got)) <= 1e-10 * np.linalg.norm(b[0])
+    z_or, st_or = solvers.gcr(op.apply, b[0], 16, 1e-12, 5000)
+    assert rel(got, z_or) < 1e-7
+
+
+def test_even_odd_gcr_with_an_indefinite_clover_term():
+    """m0 = -9 makes every clover block negative definite: the clover inverse
+    of the even-odd operator then comes from the Gauss-Jordan fallback
+    instead of the Cholesky factorisation (D itself stays well conditioned)."""
+    from paper_1202_2462_amd.mgdd import F64, SOLVER_GCR_EO
+    dims = (8, 8, 4, 8)
+    say("even-odd gcr, clover term not positive definite", dims)
+    op = problem(dims, seed=9, m0=-9.0)
+    lat = lattice(op, (4, 4, 4, 4))
+    b = latgen.gaussian_fields(dims, 1, 5)
+    z, stats = lat.solve(lat.pack(b, F64), solver=SOLVER_GCR_EO, restart=16, tol=1e-10, maxit=3000)
     got = lat.unpack(z)[0]
     assert stats[0].converged
     assert np.linalg.norm(b[0] - op.apply(got)) <= 1e-10 * np.linalg.norm(b[0])

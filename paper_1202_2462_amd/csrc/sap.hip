@@ -755,6 +755,10 @@ __global__ __launch_bounds__(2 * VB) __attribute__((amdgpu_waves_per_eu(4))) voi
     // from memory)
     float2 rho[6], e[6];
     {
+        // half of the clover rows before the hops, as in the MR steps below
+        float2 ap0[18];
+#pragma unroll
+        for (int k = 0; k < 9; k++) ap0[k] = Aall.ld_lane(k, d, aoff);
         float2 up[6], L[6];
 #pragma unroll
         for (int k = 0; k < 6; k++) up[k] = L[k] = make_float2(0.f, 0.f);
@@ -795,12 +799,9 @@ __global__ __launch_bounds__(2 * VB) __attribute__((amdgpu_waves_per_eu(4))) voi
         exchange_chirality(h, up, L, hs);
 #pragma unroll
         for (int c = 0; c < 6; c++) zc[c] = rho_lds[(6 * h + c) * RS + l];
-        {
-            float2 ap[18];
 #pragma unroll
-            for (int k = 0; k < 18; k++) ap[k] = Aall.ld_lane(k, d, aoff);
-            herm6_mv<float>(ap, zc, az);
-        }
+        for (int k = 9; k < 18; k++) ap0[k] = Aall.ld_lane(k, d, aoff);
+        herm6_mv<float>(ap0, zc, az);
 #pragma unroll
         for (int c = 0; c < 6; c++) {
             const float2 bs = bf.template ld_lane<true>(c, d, coff);
@@ -820,15 +821,17 @@ __global__ __launch_bounds__(2 * VB) __attribute__((amdgpu_waves_per_eu(4))) voi
         float2 up[6], L[6];
 #pragma unroll
         for (int k = 0; k < 6; k++) up[k] = L[k] = make_float2(0.f, 0.f);
+        // half of the clover rows (from L2) are loaded before the hops,
+        // which hide their latency (all 18 would not fit the registers)
+        float2 ap[18];
+#pragma unroll
+        for (int k = 0; k < 9; k++) ap[k] = Aall.ld_lane(k, d, aoff, salt);
         block_hops<RS, LS>(rho_lds, lnk, h, l, lnf, lnb, src0, src1, sig, sgf, sgb, up, L);
         float2 hs[6], ax[6], q[6];
         exchange_chirality(h, up, L, hs);
-        {
-            float2 ap[18];
 #pragma unroll
-            for (int k = 0; k < 18; k++) ap[k] = Aall.ld_lane(k, d, aoff, salt);
-            herm6_mv<float>(ap, rho, ax);
-        }
+        for (int k = 9; k < 18; k++) ap[k] = Aall.ld_lane(k, d, aoff, salt);
+        herm6_mv<float>(ap, rho, ax);
         Red3<float> part{0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 6; c++) {

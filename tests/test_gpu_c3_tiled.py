@@ -19,6 +19,7 @@ repeat as well, and inside a block the MR iteration is odd in the residual
 also commutes with the repetition. The oracle's result on 16^3 x 32,
 repeated with the signs, is therefore the exact expected result on 48^3 x 96:
 a full-size comparison whose host work is that of the small lattice."""
+import gc
 import json
 import os
 import time
@@ -156,6 +157,10 @@ def test_c3_multilevel_solve_residual(levels):
     m0 = tuned_m0("c1")
     U = repeat_links(latgen.workload_gauge("c1"))
     say("48^3x96 solve,", levels, "levels, m0", m0)
+    # device memory held in torch's cache by earlier tests is of no use to
+    # the library's own allocations (this test needs most of the 288 GB)
+    gc.collect()
+    torch.cuda.empty_cache()
     lat = Lattice(dims, block)
     lat.set_gauge(U, m0, w["csw"])
     gen = torch.Generator(device="cuda")
@@ -168,6 +173,7 @@ def test_c3_multilevel_solve_residual(levels):
     t0 = time.perf_counter()
     lat.setup(agg, rnd, start, nu=w["nu"], iota=w["iota"], mr_iters=w["mr"], prec=F32)
     del rnd
+    torch.cuda.empty_cache()
     l3 = {}
     if levels == 3:
         q = LEVEL3

@@ -804,8 +804,9 @@ static int MFMA_MIN_RHS = 4;
 // 4, 3 or 2, whichever divides the coarse extent first; in time, when 8
 // divides the time extent, it is one eighth of it (so that each XCD's range
 // is a whole number of time slices, their tiles complete: at 12^3 x 24
-// coarse sites, 4 x 4 x 4 x 3 tiles took the coarse step from 850 to 793 us,
-// where 4^4 tiles gained nothing), else 4, 3 or 2 as in space.
+// coarse sites, 4 x 4 x 4 x 3 tiles cut the coarse step's reads from memory
+// by 5 % and its time by about 3 %, where 4^4 tiles gained nothing), else 4,
+// 3 or 2 as in space.
 static std::vector<int> coarse_visit_order(const int *Lc) {
     int e[4], nt[4];
     for (int m = 0; m < 4; m++) {
